@@ -1,0 +1,509 @@
+"""CPU FP64 reference implementation of Exp-ParaDiag -- test infrastructure only.
+
+This module is the oracle the GPU library is checked against.  Only the test
+suite, the smoke check and the CPU-baseline leg of the benchmark may import
+it; the product path never does.  It shares no code with the GPU library.
+
+It is deliberately plain: numpy FP64, the paper's steps in the paper's order,
+no blocking or fusion.  Library primitives used as steps: numpy's FFT (for
+functions of the periodic spectral operator and for the unitary time DFT F),
+numpy.linalg (dense checks).
+
+Reference: Garai & Chamakuri, "Exp-ParaDiag: Time-Parallel Exponential
+Integrators for Parabolic PDEs" (arXiv 2603.04350).  Citations below name the
+section / equation of that paper.
+
+Readings taken where the paper is silent (also listed in the design doc):
+  * Spatial operator: Fourier collocation on periodic [0,2pi)^d, n even,
+    L = a*Lap - c with symbol mu_k = -a|k|^2 - c (the analysis of Sec. 2-3
+    only needs L_h diagonalisable with non-positive spectrum).
+  * ETD1 = explicit exponential Euler,
+        u_n = A u_{n-1} + dt*phi1(dt L) N(u_{n-1}),
+    the ETD variant Sec. 5 allows; the all-at-once iteration lags the
+    nonlinearity exactly as in the IMEX-type iteration of Sec. 6.2
+    (eq. disc_imextype_scheme), here with the phi1-weighted term.
+  * ETD2 = Cox-Matthews multistep,
+        u_n = A u_{n-1} + dt[(phi1+phi2) N(u_{n-1}) - phi2 N(u_{n-2})],
+    with u_{-1} := u_0 (so step 1 equals ETD1).
+  * N(u) = n1 u + n2 u^2 + n3 u^3 evaluated pointwise on the grid, no
+    dealiasing.
+  * The fixed point is written in residual-correction form
+    u^{k+1} = u^k + Q_alpha^{-1}(f + G(u^k) - Q u^k)  (eq. pcond-1st-order),
+    which equals the paper's b^{k-1} form in exact arithmetic.
+
+parity: every function here is pinned by tests/test_oracle_pins.py (closed
+forms, dense LU, mpmath, textbook GMRES, convergence order).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "Setup", "phi1", "phi2", "sequential", "residual", "precond_apply",
+    "fixed_point", "q_apply", "qalpha_apply", "gprime_apply", "gmres",
+    "gmres_solve", "newton_gmres", "rel_err", "dense_operators",
+    "dense_solve", "dense_newton", "time_dft", "time_idft",
+]
+
+
+# ---------------------------------------------------------------------------
+# phi functions (exponential-integrator weights)
+# ---------------------------------------------------------------------------
+def phi1(z):
+    """phi1(z) = (e^z - 1)/z, phi1(0) = 1 (exponential Euler weight)."""
+    z = np.asarray(z, dtype=np.float64)
+    out = np.ones_like(z)
+    nz = z != 0.0
+    out[nz] = np.expm1(z[nz]) / z[nz]
+    return out
+
+
+def phi2(z):
+    """phi2(z) = (e^z - 1 - z)/z^2, phi2(0) = 1/2.
+
+    For |z| < 1 the direct formula cancels, so the Taylor series
+    sum_{j>=0} z^j/(j+2)! with 30 terms is used there.
+    """
+    z = np.asarray(z, dtype=np.float64)
+    out = np.empty_like(z)
+    small = np.abs(z) < 1.0
+    zs = z[small]
+    acc = np.zeros_like(zs)
+    for j in range(29, -1, -1):
+        acc = acc * zs + 1.0 / math.factorial(j + 2)
+    out[small] = acc
+    zb = z[~small]
+    out[~small] = (np.expm1(zb) - zb) / (zb * zb)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# problem setup: symbols of A = exp(dt L), phi-weights, alpha-circulant data
+# ---------------------------------------------------------------------------
+@dataclass
+class Setup:
+    """Symbols and time tables of one Exp-ParaDiag instance.
+
+    A = exp(dt L_h) acts per Fourier mode as E_k = exp(dt mu_k) (Sec. 2,
+    eq. disc_wr).  Gamma_alpha = diag(alpha^{l/Nt}), lambda_{0,m} =
+    alpha^{1/Nt} exp(2 pi i m/Nt) (Sec. 2, diagonalisation of C_0^alpha).
+    """
+    dim: int
+    n: int
+    Nt: int
+    dt: float
+    alpha: float
+    a: float
+    c: float = 0.0
+    n1: float = 0.0
+    n2: float = 0.0
+    n3: float = 0.0
+    scheme: int = 1
+    mu: np.ndarray = field(init=False, repr=False)
+    E: np.ndarray = field(init=False, repr=False)
+    w1: np.ndarray = field(init=False, repr=False)
+    w2: np.ndarray = field(init=False, repr=False)
+    gamma: np.ndarray = field(init=False, repr=False)
+    lam: np.ndarray = field(init=False, repr=False)
+
+    def __post_init__(self):
+        k = np.fft.fftfreq(self.n, 1.0 / self.n)
+        grids = np.meshgrid(*([k] * self.dim), indexing="ij")
+        k2 = sum(g * g for g in grids)
+        self.mu = -self.a * k2 - self.c
+        z = self.dt * self.mu
+        self.E = np.exp(z)
+        self.w1 = self.dt * phi1(z)
+        self.w2 = self.dt * phi2(z)
+        l = np.arange(self.Nt, dtype=np.float64)
+        self.gamma = self.alpha ** (l / self.Nt)
+        self.lam = self.alpha ** (1.0 / self.Nt) * np.exp(
+            2j * np.pi * l / self.Nt)
+
+    @classmethod
+    def from_instance(cls, inst):
+        return cls(inst.dim, inst.n, inst.Nt, inst.dt, inst.alpha, inst.a,
+                   inst.c, inst.n1, inst.n2, inst.n3, inst.scheme)
+
+    @property
+    def axes(self):
+        """Spatial axes of a space-time array shaped (Nt, n, ..., n)."""
+        return tuple(range(1, self.dim + 1))
+
+    @property
+    def nonlinear(self):
+        return (self.n1, self.n2, self.n3) != (0.0, 0.0, 0.0)
+
+    # -- functions of the spatial operator, applied through the spectrum --
+    def spectral_apply(self, v, g):
+        """g(L_h) v for one field v (shape (n,)*dim) or a stack (Nt, ...)."""
+        axes = tuple(range(v.ndim - self.dim, v.ndim))
+        return np.fft.ifftn(g * np.fft.fftn(v, axes=axes), axes=axes)
+
+    def A(self, v):
+        """A v with A = exp(dt L_h); real in, real out."""
+        return self.spectral_apply(v, self.E).real
+
+    def W1(self, v):
+        return self.spectral_apply(v, self.w1).real
+
+    def W2(self, v):
+        return self.spectral_apply(v, self.w2).real
+
+    def N(self, u):
+        return self.n1 * u + self.n2 * u * u + self.n3 * u * u * u
+
+    def dN(self, u):
+        return self.n1 + 2.0 * self.n2 * u + 3.0 * self.n3 * u * u
+
+
+# ---------------------------------------------------------------------------
+# O1: sequential time stepping (the plain definition of the result)
+# ---------------------------------------------------------------------------
+def sequential(st: Setup, u0):
+    """u_1..u_Nt by sequential ETD1 / ETD2 stepping.
+
+    Linear part: u_n = A u_{n-1} (Sec. 2, eq. disc_wr).  The all-at-once
+    system Q u = f of Sec. 3 (eq. all_at_once_1storder) has exactly this
+    block forward substitution as its solution.
+    """
+    U = np.empty((st.Nt,) + u0.shape)
+    prev2, prev = u0, u0
+    for j in range(st.Nt):
+        un = st.A(prev)
+        if st.nonlinear:
+            if st.scheme == 1:
+                un = un + st.W1(st.N(prev))
+            else:
+                un = un + st.W1(st.N(prev)) + st.W2(st.N(prev) - st.N(prev2))
+        U[j] = un
+        prev2, prev = prev, un
+    return U
+
+
+# ---------------------------------------------------------------------------
+# all-at-once residual and the alpha-circulant preconditioner
+# ---------------------------------------------------------------------------
+def _shift(st, U, u_first):
+    """(u_{n-1})_{n=1..Nt} with u_0 := u_first."""
+    P = np.empty_like(U)
+    P[0] = u_first
+    P[1:] = U[:-1]
+    return P
+
+
+def nonlinear_term(st: Setup, u0, U):
+    """G(U) + (nonlinear part of f): the slice-n term built from u_{n-1},
+    u_{n-2} (u_{-1} := u_0), i.e. the lagged nonlinearity of Sec. 6.2."""
+    if not st.nonlinear:
+        return np.zeros_like(U)
+    P1 = _shift(st, U, u0)
+    N1 = st.N(P1)
+    if st.scheme == 1:
+        return st.W1(N1)
+    P2 = _shift(st, P1, u0)
+    N2 = st.N(P2)
+    return st.W1(N1) + st.W2(N1 - N2)
+
+
+def residual(st: Setup, u0, U):
+    """R(U) = f + G(U) - Q U  (right-hand side of eq. pcond-1st-order).
+
+    Q = I_t (x) I_x - C_0 (x) A, f = (A u_0 + [dt phi1 N(u_0)], 0, ..., 0).
+    Slice n of R is A u_{n-1} + G_n - u_n with u_0 the initial condition.
+    """
+    P1 = _shift(st, U, u0)
+    return st.A(P1) + nonlinear_term(st, u0, U) - U
+
+
+def q_apply(st: Setup, V):
+    """Q V with Q = I_t (x) I_x - C_0 (x) A (eq. all_at_once_1storder)."""
+    return V - st.A(_shift(st, V, np.zeros_like(V[0])))
+
+
+def qalpha_apply(st: Setup, V):
+    """Q_alpha V with Q_alpha = I_t (x) I_x - C_0^alpha (x) A
+    (eq. pcond-1st-order, C_0^alpha of eq. alpha_circ)."""
+    P = _shift(st, V, st.alpha * V[-1])
+    return V - st.A(P)
+
+
+def time_dft(X):
+    """(F (x) I_x) X with F = Nt^{-1/2} [omega^{(l1-1)(l2-1)}],
+    omega = exp(+2 pi i/Nt) (Sec. 2)."""
+    return np.fft.ifft(X, axis=0, norm="ortho")
+
+
+def time_idft(X):
+    """(F^* (x) I_x) X."""
+    return np.fft.fft(X, axis=0, norm="ortho")
+
+
+def precond_apply(st: Setup, R):
+    """S = Q_alpha^{-1} R by the three steps of Sec. 3 (eq.
+    exp_ParaDiag_steps):
+      (a) S_a = (F (x) I)(Gamma_alpha (x) I) R
+      (b) S_b,m = (I - lambda_{0,m} A)^{-1} S_a,m,  m = 1..Nt
+      (c) S = (Gamma_alpha^{-1} (x) I)(F^* (x) I) S_b
+    """
+    g = st.gamma.reshape((st.Nt,) + (1,) * st.dim)
+    Sa = time_dft(g * R)
+    Sb = np.empty_like(Sa)
+    for m in range(st.Nt):
+        Sb[m] = st.spectral_apply(Sa[m], 1.0 / (1.0 - st.lam[m] * st.E))
+    S = time_idft(Sb) / g
+    return S.real
+
+
+def rel_err(U, V):
+    """max_n ||u_n - v_n||_2 / max_n ||v_n||_2: the L_inf(0,T; L2) error
+    of Sec. 6, normalised by the reference's norm."""
+    ax = tuple(range(1, U.ndim))
+    num = np.sqrt(np.sum((U - V) ** 2, axis=ax)).max()
+    den = np.sqrt(np.sum(V ** 2, axis=ax)).max()
+    return num / den
+
+
+# ---------------------------------------------------------------------------
+# O2: the preconditioned fixed point (Richardson) iteration
+# ---------------------------------------------------------------------------
+def fixed_point(st: Setup, u0, U0=None, max_iter=200, tol=1e-11, ref=None,
+                ref_tol=None, record=False):
+    """u^{k+1} = u^k + s^k,  Q_alpha s^k = f + G(u^k) - Q u^k.
+
+    Eq. pcond-1st-order (linear) with the nonlinearity lagged one iteration
+    (Sec. 6.2).  U^0 = 0 unless given (Sec. 6 starts from zeros).
+    Stops when ||s^k|| <= tol ||u^{k+1}||, or, if `ref` is given and
+    ref_tol is set, when rel_err(u^{k+1}, ref) <= ref_tol.
+    Returns (U, iterations, history) where history holds
+    (||s||/||u||, rel_err vs ref or nan) per iteration and, if record,
+    the iterates themselves.
+    """
+    U = np.zeros((st.Nt,) + u0.shape) if U0 is None else U0.copy()
+    hist, iterates = [], []
+    for k in range(max_iter):
+        R = residual(st, u0, U)
+        S = precond_apply(st, R)
+        U = U + S
+        upd = np.linalg.norm(S) / max(np.linalg.norm(U), 1e-300)
+        err = rel_err(U, ref) if ref is not None else float("nan")
+        hist.append((upd, err))
+        if record:
+            iterates.append(U.copy())
+        if ref is not None and ref_tol is not None:
+            if err <= ref_tol:
+                return U, k + 1, (hist, iterates)
+        elif upd <= tol:
+            return U, k + 1, (hist, iterates)
+    return U, max_iter, (hist, iterates)
+
+
+# ---------------------------------------------------------------------------
+# O3: GMRES (left-preconditioned) and Newton-Krylov
+# ---------------------------------------------------------------------------
+def gmres(matvec, b, x0, restart=20, tol=1e-10, max_iter=200):
+    """Restarted GMRES(m): Arnoldi with modified Gram-Schmidt and Givens
+    rotations on the (m+1) x m Hessenberg matrix (Saad, Iterative Methods
+    for Sparse Linear Systems, Alg. 6.9 with restarts).
+
+    Stops when ||b - A x|| <= tol ||b||.  Returns (x, iterations, history of
+    residual norms ||b - A x_k||, one per inner iteration, starting at k=0).
+    """
+    x = x0.copy()
+    bnorm = np.linalg.norm(b)
+    if bnorm == 0.0:
+        return np.zeros_like(b), 0, [0.0]
+    r = b - matvec(x)
+    beta = np.linalg.norm(r)
+    hist = [beta]
+    total = 0
+    while total < max_iter and beta > tol * bnorm:
+        m = restart
+        V = np.zeros((m + 1, b.size))
+        H = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        V[0] = r.ravel() / beta
+        j_end = 0
+        for j in range(m):
+            w = matvec(V[j].reshape(b.shape)).ravel()
+            for i in range(j + 1):
+                H[i, j] = np.dot(w, V[i])
+                w = w - H[i, j] * V[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            den = math.hypot(H[j, j], H[j + 1, j])
+            cs[j] = H[j, j] / den
+            sn[j] = H[j + 1, j] / den
+            H[j, j] = den
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            total += 1
+            j_end = j + 1
+            hist.append(abs(g[j + 1]))
+            if abs(g[j + 1]) <= tol * bnorm or total >= max_iter:
+                break
+            nrm = np.linalg.norm(w)
+            if nrm == 0.0:
+                break
+            V[j + 1] = w / nrm
+        y = np.zeros(j_end)
+        for i in range(j_end - 1, -1, -1):
+            y[i] = (g[i] - np.dot(H[i, i + 1:j_end], y[i + 1:])) / H[i, i]
+        x = x + (V[:j_end].T @ y).reshape(b.shape)
+        r = b - matvec(x)
+        beta = np.linalg.norm(r)
+    return x, total, hist
+
+
+def gmres_solve(st: Setup, u0, restart=20, tol=1e-10, max_iter=200):
+    """Linear problems: GMRES on Q_alpha^{-1} Q u = Q_alpha^{-1} f
+    (Sec. 3.2, Theorem thm_gmres1 system), u^0 = 0."""
+    zeros = np.zeros((st.Nt,) + u0.shape)
+    f = residual(st, u0, zeros)          # f - Q*0
+    b = precond_apply(st, f)
+    op = lambda v: precond_apply(st, q_apply(st, v))
+    return gmres(op, b, zeros, restart, tol, max_iter)
+
+
+def gprime_apply(st: Setup, u0, U, V):
+    """G'(U) V: derivative of the lagged nonlinear term with u_0 fixed."""
+    if not st.nonlinear:
+        return np.zeros_like(V)
+    P1 = _shift(st, U, u0)
+    V1 = _shift(st, V, np.zeros_like(u0))
+    J1 = st.dN(P1) * V1
+    if st.scheme == 1:
+        return st.W1(J1)
+    P2 = _shift(st, P1, u0)
+    V2 = _shift(st, V1, np.zeros_like(u0))
+    J2 = st.dN(P2) * V2
+    return st.W1(J1) + st.W2(J1 - J2)
+
+
+def newton_gmres(st: Setup, u0, restart=20, tol=1e-10, max_newton=30,
+                 max_inner=200, eta_max=1e-3):
+    """Newton on R(U) = 0 with inner GMRES(restart) on
+    Q_alpha^{-1}(Q - G'(U)) d = Q_alpha^{-1} R(U), left-preconditioned by
+    the Exp-ParaDiag step.  Forcing term eta_j = min(eta_max, ||R_j||/||R_0||).
+    Stops when ||R_j|| <= tol ||R_0||.  Returns (U, newton_steps, inner_total,
+    history of ||R_j||)."""
+    U = np.zeros((st.Nt,) + u0.shape)
+    R = residual(st, u0, U)
+    r0 = np.linalg.norm(R)
+    hist = [r0]
+    inner_total = 0
+    for j in range(max_newton):
+        rn = np.linalg.norm(R)
+        if rn <= tol * r0:
+            return U, j, inner_total, hist
+        eta = min(eta_max, rn / r0)
+        Uc = U
+        op = lambda v: precond_apply(st, q_apply(st, v)
+                                     - gprime_apply(st, u0, Uc, v))
+        b = precond_apply(st, R)
+        d, it, _ = gmres(op, b, np.zeros_like(U), restart, eta, max_inner)
+        inner_total += it
+        U = U + d
+        R = residual(st, u0, U)
+        hist.append(np.linalg.norm(R))
+    return U, max_newton, inner_total, hist
+
+
+# ---------------------------------------------------------------------------
+# O4: dense assembled operators for tiny sizes (brute force)
+# ---------------------------------------------------------------------------
+def _dft_matrix(n):
+    j = np.arange(n)
+    return np.exp(-2j * np.pi * np.outer(j, j) / n)
+
+
+def dense_operators(st: Setup):
+    """Assemble A, Q, Q_alpha and the phi-weight matrices as dense real
+    matrices from the definitions (Sec. 2 eq. st_system, Sec. 3 eq.
+    all_at_once_1storder).  Only for n^dim * Nt up to a few thousand."""
+    Fx = _dft_matrix(st.n)
+    F = Fx
+    for _ in range(st.dim - 1):
+        F = np.kron(F, Fx)
+    Finv = F.conj().T / F.shape[0]
+
+    def dense_of(sym):
+        return (Finv @ np.diag(sym.ravel()) @ F).real
+
+    A = dense_of(st.E)
+    Ns = A.shape[0]
+    C0 = np.diag(np.ones(st.Nt - 1), -1)
+    C0a = C0.copy()
+    C0a[0, -1] = st.alpha
+    I = np.eye(st.Nt * Ns)
+    return {
+        "A": A, "W1": dense_of(st.w1), "W2": dense_of(st.w2),
+        "C0": C0, "C0a": C0a,
+        "Q": I - np.kron(C0, A), "Qa": I - np.kron(C0a, A),
+    }
+
+
+def dense_solve(st: Setup, u0, D=None):
+    """Linear all-at-once solve Q u = f by LU (numpy.linalg.solve)."""
+    D = D or dense_operators(st)
+    Ns = u0.size
+    f = np.zeros(st.Nt * Ns)
+    f[:Ns] = D["A"] @ u0.ravel()
+    return np.linalg.solve(D["Q"], f).reshape((st.Nt,) + u0.shape)
+
+
+def dense_newton(st: Setup, u0, tol=1e-14, max_iter=50, D=None):
+    """Nonlinear all-at-once system R(U)=0 by dense Newton with LU."""
+    D = D or dense_operators(st)
+    Ns = u0.size
+    Nt = st.Nt
+    u0f = u0.ravel()
+    U = np.zeros(Nt * Ns)
+
+    def R_of(Uf):
+        Us = Uf.reshape(Nt, Ns)
+        P1 = np.vstack([u0f[None], Us[:-1]])
+        P2 = np.vstack([u0f[None], P1[:-1]])
+        out = (D["A"] @ P1.T).T - Us
+        N1 = st.N(P1)
+        if st.scheme == 1:
+            out = out + (D["W1"] @ N1.T).T
+        else:
+            N2 = st.N(P2)
+            out = out + (D["W1"] @ N1.T).T + (D["W2"] @ (N1 - N2).T).T
+        return out.ravel()
+
+    def J_of(Uf):
+        Us = Uf.reshape(Nt, Ns)
+        P1 = np.vstack([u0f[None], Us[:-1]])
+        P2 = np.vstack([u0f[None], P1[:-1]])
+        J = -np.eye(Nt * Ns) + np.kron(np.diag(np.ones(Nt - 1), -1), D["A"])
+        for nn in range(1, Nt):
+            d1 = st.dN(P1[nn])
+            if st.scheme == 1:
+                blk = D["W1"] * d1[None, :]
+            else:
+                blk = (D["W1"] + D["W2"]) * d1[None, :]
+            J[nn * Ns:(nn + 1) * Ns, (nn - 1) * Ns:nn * Ns] += blk
+            if st.scheme == 2 and nn >= 2:
+                d2 = st.dN(P2[nn])
+                J[nn * Ns:(nn + 1) * Ns, (nn - 2) * Ns:(nn - 1) * Ns] -= \
+                    D["W2"] * d2[None, :]
+        return J
+
+    for _ in range(max_iter):
+        R = R_of(U)
+        if np.linalg.norm(R) <= tol * max(1.0, np.linalg.norm(U)):
+            break
+        U = U - np.linalg.solve(J_of(U), R)
+    return U.reshape((Nt,) + u0.shape)
