@@ -1,0 +1,899 @@
+// Host side of the Exp-ParaDiag library: handle, tables, launch dispatch
+// and the C ABI declared in include/expdiag.h.
+//
+// Spectral state.  Inside a handle the space-time iterate lives in Fourier
+// space as its half spectrum Uh[l][kappa], l = 0..Nt-1 (slices 1..Nt),
+// kappa = 0..Nk-1 in rfftn order; the ABI is physical, so each solve does
+// one forward batched FFT on entry and one inverse on exit.
+//
+// One fixed-point iteration (Sec. 3, eq. pcond-1st-order with the lagged
+// nonlinearity of Sec. 6.2) is
+//   pass A (nonlinear only, per slice):  N^_{l} = FFT N(IFFT Uh_{l-1})
+//   pass B (per kappa tile, all Nt rows): residual, steps (a)-(c), update
+//   reduce: norms and the convergence flag (device side).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/expdiag.h"
+#include "kernels_fft.hpp"
+#include "kernels_krylov.hpp"
+#include "kernels_passb.hpp"
+
+using namespace expdiag;
+
+namespace {
+
+constexpr int HIST_CAP = 4096;
+constexpr int NPROF = 5;
+enum ProfClass { P_COL = 0, P_ROW = 1, P_PASSB = 2, P_RED = 3, P_KRY = 4 };
+
+struct EventPair {
+  hipEvent_t a, b;
+  int cls;
+};
+
+}  // namespace
+
+struct expdiag_ctx {
+  int dim = 1;
+  int n[3] = {0, 0, 0};
+  int Nt = 0;
+  double dt = 0, alpha = 0;
+  int scheme = 1;
+  expdiag_problem p{};
+  hipStream_t stream = nullptr;
+  long Ns = 0, Nk = 0;
+  int nh = 0;
+  bool nonlinear = false;
+  bool mixed = false;
+  int restart_cap = 0;
+
+  // device buffers
+  cx<double>* Uh = nullptr;   // [Nt][Nk]
+  cx<double>* Nh = nullptr;   // [Nt][Nk] (nonlinear); float view in bulk
+  cx<double>* T = nullptr;    // [Nt][Nk] scratch
+  cx<double>* T2 = nullptr;   // [Nt][Nk] scratch (GMRES / Newton)
+  double* Uphys = nullptr;    // [Nt][Ns] physical iterate (Newton)
+  cx<double>* u0h = nullptr;  // [Nk]
+  double *E = nullptr, *c1 = nullptr, *c2 = nullptr;  // [Nk]
+  double *gam = nullptr, *igam = nullptr;             // [Nt]
+  cx<double>* lam = nullptr;                          // [Nt]
+  cx<double>* tw64 = nullptr;                         // [TW_N]
+  cx<float>* tw32 = nullptr;                          // [TW_N]
+  double* partials = nullptr;                         // [maxblocks][4]
+  int max_partials = 0;
+  double* red_out = nullptr;  // [8]
+  Ctl* ctl = nullptr;
+  double* hist = nullptr;     // [HIST_CAP][2]
+  cx<double>* V = nullptr;    // Krylov basis [(restart+1)][Nt][Nk]
+  double* kdots = nullptr;    // [restart+2] dot results
+  double* kpart = nullptr;    // [maxblocks][restart+2]
+  int kpart_blocks = 0;
+
+  // pinned host mirrors
+  Ctl* h_ctl = nullptr;
+  double* h_red = nullptr;
+
+  // profiling
+  bool prof = false;
+  std::vector<EventPair> events;
+  size_t ev_used = 0;
+  double prof_ms[NPROF] = {0, 0, 0, 0, 0};
+  long prof_cnt[NPROF] = {0, 0, 0, 0, 0};
+  double prof_bytes[NPROF] = {0, 0, 0, 0, 0};
+
+  std::string err;
+  size_t bytes = 0;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+int fail(expdiag_ctx* h, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (h != nullptr)
+    h->err = buf;
+  else
+    g_create_err = buf;
+  return code;
+}
+
+#define HIPCHK(h, expr)                                                   \
+  do {                                                                    \
+    hipError_t e_ = (expr);                                               \
+    if (e_ != hipSuccess)                                                 \
+      return fail((h), EXPDIAG_EHIP, "%s: %s (%s:%d)", #expr,             \
+                  hipGetErrorString(e_), __FILE__, __LINE__);             \
+  } while (0)
+
+bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
+
+template <int LO, int HI, typename F>
+bool dispatch_pow2(int v, F&& f) {
+  if constexpr (LO > HI) {
+    return false;
+  } else {
+    if (v == LO) {
+      f(std::integral_constant<int, LO>{});
+      return true;
+    }
+    return dispatch_pow2<LO * 2, HI>(v, f);
+  }
+}
+
+// ---------------------------------------------------------------- profiling
+// Brackets one launch with events when profiling is on and accounts the
+// launch's algorithmic bytes (what the kernel must read and write once).
+struct ProfScope {
+  expdiag_ctx* h;
+  int cls;
+  EventPair* ep = nullptr;
+  ProfScope(expdiag_ctx* h_, int c, double bytes) : h(h_), cls(c) {
+    if (h->prof) h->prof_bytes[c] += bytes;
+    if (h->prof && h->ev_used < h->events.size()) {
+      ep = &h->events[h->ev_used++];
+      ep->cls = cls;
+      (void)hipEventRecord(ep->a, h->stream);
+    }
+  }
+  ~ProfScope() {
+    if (ep != nullptr) (void)hipEventRecord(ep->b, h->stream);
+  }
+};
+
+// ------------------------------------------------------------------ launches
+template <typename T>
+const cx<T>* twid_table(expdiag_ctx* h) {
+  if constexpr (std::is_same<T, double>::value)
+    return h->tw64;
+  else
+    return h->tw32;
+}
+
+template <typename T, int MODE, typename TI, typename TO>
+int launch_row(expdiag_ctx* h, const TI* in, TO* out, long nrows,
+               long in_pitch, long out_pitch, double scale,
+               const TI* aux = nullptr, long aux_pitch = 0) {
+  const int M = h->n[h->dim - 1] / 2;
+  NonlinCoef nc{h->p.n1, h->p.n2, h->p.n3};
+  const double realb = static_cast<double>(nrows) * 2 * M;
+  const double cplxb = static_cast<double>(nrows) * (M + 1) * 2;
+  double bytes = 0;
+  if (MODE == ROW_R2C || MODE == ROW_NR2C)
+    bytes = realb * sizeof(TI) + cplxb * sizeof(TO);
+  else if (MODE == ROW_C2R)
+    bytes = cplxb * sizeof(TI) + realb * sizeof(TO);
+  else
+    bytes = cplxb * (sizeof(TI) + sizeof(TO)) +
+            (MODE == ROW_JVP ? realb * sizeof(TI) : 0.0);
+  ProfScope ps(h, P_ROW, bytes);
+  bool ok = dispatch_pow2<2, 512>(M, [&](auto Mc) {
+    constexpr int MM = decltype(Mc)::value;
+    using S = RowShape<MM>;
+    const long blocks = (nrows + S::RPB - 1) / S::RPB;
+    hipLaunchKernelGGL((row_kernel<T, MM, MODE, TI, TO>), dim3(blocks),
+                       dim3(S::THREADS), 0, h->stream, in, out, nrows,
+                       in_pitch, out_pitch, static_cast<T>(scale), nc, aux,
+                       aux_pitch, twid_table<T>(h));
+  });
+  if (!ok) return fail(h, EXPDIAG_EUNSUPPORTED, "row length %d", 2 * M);
+  HIPCHK(h, hipGetLastError());
+  return 0;
+}
+
+template <typename T, int S, typename TI, typename TO>
+int launch_col(expdiag_ctx* h, int L, const cx<TI>* in, cx<TO>* out,
+               long outer, long inner, double scale) {
+  const double elems = static_cast<double>(outer) * L * inner;
+  ProfScope ps(h, P_COL, elems * 2 * (sizeof(TI) + sizeof(TO)));
+  bool ok = dispatch_pow2<4, 1024>(L, [&](auto Lc) {
+    constexpr int LL = decltype(Lc)::value;
+    using SH = ColShape<LL>;
+    const long tiles = (inner + SH::C - 1) / SH::C;
+    hipLaunchKernelGGL((col_kernel<T, LL, S, TI, TO>), dim3(outer * tiles),
+                       dim3(SH::THREADS), 0, h->stream, in, out, outer,
+                       inner, LL * inner, LL * inner, static_cast<T>(scale),
+                       twid_table<T>(h));
+  });
+  if (!ok) return fail(h, EXPDIAG_EUNSUPPORTED, "column length %d", L);
+  HIPCHK(h, hipGetLastError());
+  return 0;
+}
+
+#define RCHK(expr)          \
+  do {                      \
+    int r_ = (expr);        \
+    if (r_ != 0) return r_; \
+  } while (0)
+
+// real physical slices [ns][Ns] -> half spectra [ns][Nk].  ROWMODE is
+// ROW_R2C or ROW_NR2C (apply N pointwise first).  Uses h->T as scratch.
+template <int ROWMODE>
+int fwd_slices(expdiag_ctx* h, const double* src, cx<double>* dst, long ns) {
+  const int d = h->dim;
+  const long nh2 = 2L * h->nh;
+  if (d == 1)
+    return launch_row<double, ROWMODE, double, double>(
+        h, src, reinterpret_cast<double*>(dst), ns, h->n[0], nh2, 1.0);
+  double* Tr = reinterpret_cast<double*>(h->T);
+  const long rows = ns * (h->Ns / h->n[d - 1]);
+  RCHK((launch_row<double, ROWMODE, double, double>(h, src, Tr, rows,
+                                                     h->n[d - 1], nh2, 1.0)));
+  if (d == 2)
+    return launch_col<double, -1, double, double>(h, h->n[0], h->T, dst, ns,
+                                                  h->nh, 1.0);
+  RCHK((launch_col<double, -1, double, double>(h, h->n[1], h->T, h->T,
+                                               ns * h->n[0], h->nh, 1.0)));
+  return launch_col<double, -1, double, double>(
+      h, h->n[0], h->T, dst, ns, static_cast<long>(h->n[1]) * h->nh, 1.0);
+}
+
+// half spectra [ns][Nk] -> real physical slices [ns][Ns] (normalised).
+// `src` may be h->T.
+template <typename T>
+int inv_slices(expdiag_ctx* h, const cx<double>* src, double* dst, long ns) {
+  const int d = h->dim;
+  const long nh2 = 2L * h->nh;
+  const double sc = 1.0 / static_cast<double>(h->Ns);
+  if (d == 1)
+    return launch_row<double, ROW_C2R, double, double>(
+        h, reinterpret_cast<const double*>(src), dst, ns, nh2, h->n[0], sc);
+  if (d == 2) {
+    RCHK((launch_col<double, 1, double, double>(h, h->n[0], src, h->T, ns,
+                                                h->nh, 1.0)));
+  } else {
+    RCHK((launch_col<double, 1, double, double>(
+        h, h->n[0], src, h->T, ns, static_cast<long>(h->n[1]) * h->nh, 1.0)));
+    RCHK((launch_col<double, 1, double, double>(h, h->n[1], h->T, h->T,
+                                                ns * h->n[0], h->nh, 1.0)));
+  }
+  const long rows = ns * (h->Ns / h->n[d - 1]);
+  return launch_row<double, ROW_C2R, double, double>(
+      h, reinterpret_cast<const double*>(h->T), dst, rows, nh2, h->n[d - 1],
+      sc);
+}
+
+// Storage of N^ in precision T.  The fp64 array fills the allocation; the
+// fp32 array of the mixed bulk phase lives in its second half, so writing
+// the fp32 slot 0 never overlaps the fp64 slot 0 it is narrowed from
+// (Nt >= 2).
+template <typename T>
+cx<T>* nh_view(expdiag_ctx* h) {
+  if constexpr (std::is_same<T, double>::value) {
+    return h->Nh;
+  } else {
+    return reinterpret_cast<cx<float>*>(reinterpret_cast<char*>(h->Nh) +
+                                        static_cast<size_t>(h->Nt) * h->Nk *
+                                            sizeof(cx<float>));
+  }
+}
+
+// Pass A: N^_{l} = FFT N(IFFT Uh_{l-1}) for l = 1..Nt-1, in precision T
+// (TN = storage type of N^: double, or float in the mixed bulk phase).
+template <typename T>
+int pass_a(expdiag_ctx* h) {
+  const int d = h->dim;
+  const long ns = h->Nt - 1;
+  const long nh2 = 2L * h->nh;
+  const double sc = 1.0 / static_cast<double>(h->Ns);
+  cx<T>* Tt = reinterpret_cast<cx<T>*>(h->T);
+  cx<T>* Nt_ = nh_view<T>(h) + h->Nk;  // slot 1
+  if (d == 1)
+    return launch_row<T, ROW_FUSED, double, T>(
+        h, reinterpret_cast<const double*>(h->Uh),
+        reinterpret_cast<T*>(Nt_), ns, nh2, nh2, sc);
+  if (d == 2) {
+    RCHK((launch_col<T, 1, double, T>(h, h->n[0], h->Uh, Tt, ns, h->nh,
+                                      1.0)));
+  } else {
+    const long in2 = static_cast<long>(h->n[1]) * h->nh;
+    RCHK((launch_col<T, 1, double, T>(h, h->n[0], h->Uh, Tt, ns, in2, 1.0)));
+    RCHK((launch_col<T, 1, T, T>(h, h->n[1], Tt, Tt, ns * h->n[0], h->nh,
+                                 1.0)));
+  }
+  const long rows = ns * (h->Ns / h->n[d - 1]);
+  RCHK((launch_row<T, ROW_FUSED, T, T>(h, reinterpret_cast<const T*>(Tt),
+                                       reinterpret_cast<T*>(Tt), rows, nh2,
+                                       nh2, sc)));
+  if (d == 2)
+    return launch_col<T, -1, T, T>(h, h->n[0], Tt, Nt_, ns, h->nh, 1.0);
+  RCHK((launch_col<T, -1, T, T>(h, h->n[1], Tt, Tt, ns * h->n[0], h->nh,
+                                1.0)));
+  return launch_col<T, -1, T, T>(h, h->n[0], Tt, Nt_, ns,
+                                 static_cast<long>(h->n[1]) * h->nh, 1.0);
+}
+
+int passb_blocks(expdiag_ctx* h) {
+  int blocks = 0;
+  dispatch_pow2<2, 512>(h->Nt, [&](auto Nc) {
+    constexpr int NN = decltype(Nc)::value;
+    blocks = static_cast<int>((h->Nk + PassBShape<NN>::C - 1) /
+                              PassBShape<NN>::C);
+  });
+  return blocks;
+}
+
+template <int MODE, typename TN>
+int launch_passb(expdiag_ctx* h, PassBArgs a) {
+  const double ent = static_cast<double>(h->Nt) * h->Nk;
+  double bytes = static_cast<double>(h->Nk) * (sizeof(double) * 3 + 16);
+  const double nb = a.nonlinear ? sizeof(cx<TN>) : 0.0;
+  if (MODE == PB_ITERATE)
+    bytes += ent * (16 + 16 + nb);
+  else if (MODE == PB_PRECOND)
+    bytes += ent * (16 + 16);
+  else if (MODE == PB_RESIDUAL)
+    bytes += ent * (16 + 16 + nb);
+  else
+    bytes += ent * (16 + 16 + nb);
+  ProfScope ps(h, P_PASSB, bytes);
+  bool ok = dispatch_pow2<2, 512>(h->Nt, [&](auto Nc) {
+    constexpr int NN = decltype(Nc)::value;
+    using SH = PassBShape<NN>;
+    const long blocks = (h->Nk + SH::C - 1) / SH::C;
+    hipLaunchKernelGGL((passb_kernel<NN, MODE, TN>), dim3(blocks),
+                       dim3(SH::THREADS), 0, h->stream, a);
+  });
+  if (!ok) return fail(h, EXPDIAG_EUNSUPPORTED, "Nt %d", h->Nt);
+  HIPCHK(h, hipGetLastError());
+  return 0;
+}
+
+PassBArgs passb_args(expdiag_ctx* h) {
+  PassBArgs a{};
+  a.U = h->Uh;
+  a.Nh = h->Nh;
+  a.u0h = h->u0h;
+  a.E = h->E;
+  a.c1 = h->c1;
+  a.c2 = h->c2;
+  a.gam = h->gam;
+  a.igam = h->igam;
+  a.lam = h->lam;
+  a.partials = h->partials;
+  a.ctl = nullptr;
+  a.tw = h->tw64;
+  a.Nk = h->Nk;
+  a.nh = h->nh;
+  a.nonlinear = h->nonlinear ? 1 : 0;
+  return a;
+}
+
+int launch_reduce(expdiag_ctx* h, int nblocks, bool update_ctl) {
+  ProfScope ps(h, P_RED, static_cast<double>(nblocks) * 32);
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, h->stream,
+                     h->partials, nblocks, 1.0 / static_cast<double>(h->Ns),
+                     h->red_out, h->ctl, update_ctl ? 1 : 0, h->hist);
+  HIPCHK(h, hipGetLastError());
+  return 0;
+}
+
+// u0 -> u0h and N^_0 = FFT N(u0) (slot 0 of Nh, fp64)
+int prepare_u0(expdiag_ctx* h, const double* u0) {
+  RCHK(fwd_slices<ROW_R2C>(h, u0, h->u0h, 1));
+  if (h->nonlinear) RCHK(fwd_slices<ROW_NR2C>(h, u0, h->Nh, 1));
+  return 0;
+}
+
+// N^_0 in fp32 storage (slot 0 of the float view of Nh) from the fp64 one.
+__global__ void narrow_kernel(const cx<double>* __restrict__ in,
+                              cx<float>* __restrict__ out, long n) {
+  const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = cvt<float>(in[i]);
+}
+
+// ------------------------------------------------------------------ tables
+long double phi1l(long double z) {
+  if (z == 0.0L) return 1.0L;
+  return expm1l(z) / z;
+}
+long double phi2l(long double z) {
+  if (fabsl(z) < 1.0L) {
+    // sum_{j>=0} z^j / (j+2)!, Horner from the tail
+    long double fact[40];
+    fact[0] = 1.0L;
+    for (int i = 1; i < 40; ++i) fact[i] = fact[i - 1] * i;
+    long double acc = 0.0L;
+    for (int j = 35; j >= 0; --j) acc = acc * z + 1.0L / fact[j + 2];
+    return acc;
+  }
+  return (expm1l(z) - z) / (z * z);
+}
+
+int build_tables(expdiag_ctx* h) {
+  const int d = h->dim;
+  const long Nk = h->Nk;
+  std::vector<double> E(Nk), c1(Nk), c2(Nk);
+  const long double a = h->p.a, c = h->p.c, dt = h->dt;
+  long idx = 0;
+  const int n0 = h->n[0], n1 = d >= 2 ? h->n[1] : 1;
+  const int nlast = h->n[d - 1];
+  auto wn = [](int j, int n) { return j <= n / 2 ? j : j - n; };
+  const int outer0 = d >= 2 ? n0 : 1;
+  const int outer1 = d >= 3 ? n1 : 1;
+  for (int i0 = 0; i0 < outer0; ++i0) {
+    for (int i1 = 0; i1 < outer1; ++i1) {
+      for (int kl = 0; kl < h->nh; ++kl) {
+        long double k2 = static_cast<long double>(kl) * kl;
+        if (d >= 2) {
+          const long double k0 = wn(i0, n0);
+          k2 += k0 * k0;
+        }
+        if (d >= 3) {
+          const long double k1 = wn(i1, n1);
+          k2 += k1 * k1;
+        }
+        const long double mu = -a * k2 - c;
+        const long double z = dt * mu;
+        const long double w1 = dt * phi1l(z);
+        const long double w2 = dt * phi2l(z);
+        E[idx] = static_cast<double>(expl(z));
+        if (h->scheme == EXPDIAG_ETD1) {
+          c1[idx] = static_cast<double>(w1);
+          c2[idx] = 0.0;
+        } else {
+          c1[idx] = static_cast<double>(w1 + w2);
+          c2[idx] = static_cast<double>(-w2);
+        }
+        ++idx;
+      }
+    }
+  }
+  (void)nlast;
+  const int Nt = h->Nt;
+  std::vector<double> gam(Nt), igam(Nt);
+  std::vector<cx<double>> lam(Nt);
+  const long double la = logl(static_cast<long double>(h->alpha));
+  const long double pi = 3.141592653589793238462643383279502884L;
+  const long double root = expl(la / Nt);
+  for (int l = 0; l < Nt; ++l) {
+    const long double g = expl(la * l / Nt);
+    gam[l] = static_cast<double>(g);
+    igam[l] = static_cast<double>(1.0L / g);
+    const long double th = 2.0L * pi * l / Nt;
+    lam[l] = mk<double>(static_cast<double>(root * cosl(th)),
+                        static_cast<double>(root * sinl(th)));
+  }
+  std::vector<cx<double>> tw(TW_N);
+  std::vector<cx<float>> tw32(TW_N);
+  for (int j = 0; j < TW_N; ++j) {
+    const long double th = -2.0L * pi * j / TW_N;
+    const long double cr = cosl(th), si = sinl(th);
+    tw[j] = mk<double>(static_cast<double>(cr), static_cast<double>(si));
+    tw32[j] = mk<float>(static_cast<float>(cr), static_cast<float>(si));
+  }
+  HIPCHK(h, hipMemcpy(h->E, E.data(), Nk * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->c1, c1.data(), Nk * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->c2, c2.data(), Nk * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->gam, gam.data(), Nt * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->igam, igam.data(), Nt * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->lam, lam.data(), Nt * sizeof(cx<double>), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->tw64, tw.data(), TW_N * sizeof(cx<double>), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->tw32, tw32.data(), TW_N * sizeof(cx<float>), hipMemcpyHostToDevice));
+  return 0;
+}
+
+struct Sizes {
+  long Ns, Nk, nh;
+};
+
+int check_grid(const expdiag_grid* g, Sizes* sz) {
+  if (g == nullptr || g->dim < 1 || g->dim > 3) return EXPDIAG_EINVAL;
+  long Ns = 1;
+  for (int i = 0; i < g->dim; ++i) {
+    if (g->n[i] < 4 || (g->n[i] & 1)) return EXPDIAG_EINVAL;
+    if (!is_pow2(g->n[i]) || g->n[i] > 1024) return EXPDIAG_EUNSUPPORTED;
+    Ns *= g->n[i];
+  }
+  const long nh = g->n[g->dim - 1] / 2 + 1;
+  sz->Ns = Ns;
+  sz->nh = nh;
+  sz->Nk = Ns / g->n[g->dim - 1] * nh;
+  return 0;
+}
+
+size_t footprint(const Sizes& s, int Nt, bool nonlinear, int restart) {
+  const size_t st = static_cast<size_t>(Nt) * s.Nk * sizeof(cx<double>);
+  size_t b = 2 * st;                   // Uh, T
+  if (nonlinear) b += st;              // Nh
+  if (restart > 0) {
+    b += st;                                          // T2
+    b += static_cast<size_t>(restart + 1) * st;       // Krylov basis
+    if (nonlinear) b += static_cast<size_t>(Nt) * s.Ns * sizeof(double);
+  }
+  b += s.Nk * (sizeof(cx<double>) + 3 * sizeof(double));
+  b += TW_N * (sizeof(cx<double>) + sizeof(cx<float>));
+  return b;
+}
+
+template <typename P>
+int dalloc(expdiag_ctx* h, P** ptr, size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(h, EXPDIAG_ENOMEM, "hipMalloc(%zu): %s", bytes,
+                hipGetErrorString(e));
+  }
+  *ptr = static_cast<P*>(p);
+  h->bytes += bytes;
+  return 0;
+}
+
+void release(expdiag_ctx* h) {
+  auto fr = [](void* p) {
+    if (p != nullptr) (void)hipFree(p);
+  };
+  fr(h->Uh);
+  fr(h->Nh);
+  fr(h->T);
+  fr(h->T2);
+  fr(h->Uphys);
+  fr(h->u0h);
+  fr(h->E);
+  fr(h->c1);
+  fr(h->c2);
+  fr(h->gam);
+  fr(h->igam);
+  fr(h->lam);
+  fr(h->tw64);
+  fr(h->tw32);
+  fr(h->partials);
+  fr(h->red_out);
+  fr(h->ctl);
+  fr(h->hist);
+  fr(h->V);
+  fr(h->kdots);
+  fr(h->kpart);
+  if (h->h_ctl != nullptr) (void)hipHostFree(h->h_ctl);
+  if (h->h_red != nullptr) (void)hipHostFree(h->h_red);
+  for (auto& e : h->events) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  h->events.clear();
+}
+
+int sync_ctl(expdiag_ctx* h) {
+  HIPCHK(h, hipMemcpyAsync(h->h_ctl, h->ctl, sizeof(Ctl),
+                           hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return 0;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+const char* expdiag_strerror(int code) {
+  switch (code) {
+    case EXPDIAG_OK:
+      return "ok";
+    case EXPDIAG_NOT_CONVERGED:
+      return "tolerance not reached within the iteration cap";
+    case EXPDIAG_EINVAL:
+      return "invalid argument";
+    case EXPDIAG_ENOMEM:
+      return "device memory allocation failed";
+    case EXPDIAG_EHIP:
+      return "HIP runtime error";
+    case EXPDIAG_EDIVERGED:
+      return "iteration diverged (non-finite residual)";
+    case EXPDIAG_EUNSUPPORTED:
+      return "size not supported by this build";
+    default:
+      return "unknown error code";
+  }
+}
+
+const char* expdiag_last_error(expdiag_t h) {
+  if (h == nullptr) return g_create_err.c_str();
+  return h->err.c_str();
+}
+
+size_t expdiag_footprint_bytes(const expdiag_grid* g, int Nt, int scheme,
+                               int precision, int gmres_restart) {
+  Sizes s{};
+  if (check_grid(g, &s) != 0) return 0;
+  if (!is_pow2(Nt) || Nt < 2 || Nt > 512) return 0;
+  if (scheme != EXPDIAG_ETD1 && scheme != EXPDIAG_ETD2) return 0;
+  (void)precision;
+  // nonlinearity unknown here: report the nonlinear (larger) footprint
+  return footprint(s, Nt, true, gmres_restart);
+}
+
+int expdiag_create(const expdiag_grid* g, int Nt, double dt, double alpha,
+                   int scheme, const expdiag_problem* p, void* hip_stream,
+                   expdiag_t* out) {
+  g_create_err.clear();
+  if (out == nullptr || p == nullptr || g == nullptr)
+    return fail(nullptr, EXPDIAG_EINVAL, "null pointer argument");
+  *out = nullptr;
+  Sizes s{};
+  const int gc = check_grid(g, &s);
+  if (gc != 0)
+    return fail(nullptr, gc, "grid: dim 1..3, n even, power of two, 4..1024");
+  if (Nt < 2) return fail(nullptr, EXPDIAG_EINVAL, "Nt must be >= 2");
+  if (!is_pow2(Nt) || Nt > 512)
+    return fail(nullptr, EXPDIAG_EUNSUPPORTED, "Nt must be a power of two <= 512");
+  if (!(dt > 0.0) || !std::isfinite(dt))
+    return fail(nullptr, EXPDIAG_EINVAL, "dt must be > 0");
+  if (!(alpha > 0.0 && alpha < 1.0))
+    return fail(nullptr, EXPDIAG_EINVAL, "alpha must lie in (0, 1)");
+  if (scheme != EXPDIAG_ETD1 && scheme != EXPDIAG_ETD2)
+    return fail(nullptr, EXPDIAG_EINVAL, "unknown scheme %d", scheme);
+  if (!(p->a >= 0.0) || !(p->c >= 0.0) || !std::isfinite(p->a) ||
+      !std::isfinite(p->c) || !std::isfinite(p->n1) ||
+      !std::isfinite(p->n2) || !std::isfinite(p->n3))
+    return fail(nullptr, EXPDIAG_EINVAL, "a, c must be finite and >= 0");
+  if (p->precision != EXPDIAG_FP64 && p->precision != EXPDIAG_MIXED)
+    return fail(nullptr, EXPDIAG_EINVAL, "unknown precision %d", p->precision);
+  if (p->gmres_restart < 0 || p->gmres_restart > 64)
+    return fail(nullptr, EXPDIAG_EINVAL, "gmres_restart must be 0..64");
+
+  expdiag_ctx* h = new (std::nothrow) expdiag_ctx();
+  if (h == nullptr) return fail(nullptr, EXPDIAG_ENOMEM, "host allocation");
+  h->dim = g->dim;
+  for (int i = 0; i < 3; ++i) h->n[i] = i < g->dim ? g->n[i] : 1;
+  h->Nt = Nt;
+  h->dt = dt;
+  h->alpha = alpha;
+  h->scheme = scheme;
+  h->p = *p;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  h->Ns = s.Ns;
+  h->Nk = s.Nk;
+  h->nh = static_cast<int>(s.nh);
+  h->nonlinear = (p->n1 != 0.0 || p->n2 != 0.0 || p->n3 != 0.0);
+  h->mixed = p->precision == EXPDIAG_MIXED;
+  h->restart_cap = p->gmres_restart;
+
+  const size_t st = static_cast<size_t>(Nt) * h->Nk * sizeof(cx<double>);
+  int rc = 0;
+  auto A = [&](auto** ptr, size_t bytes) {
+    if (rc == 0) rc = dalloc(h, ptr, bytes);
+  };
+  A(&h->Uh, st);
+  A(&h->T, st);
+  if (h->nonlinear) A(&h->Nh, st);
+  A(&h->u0h, h->Nk * sizeof(cx<double>));
+  A(&h->E, h->Nk * sizeof(double));
+  A(&h->c1, h->Nk * sizeof(double));
+  A(&h->c2, h->Nk * sizeof(double));
+  A(&h->gam, Nt * sizeof(double));
+  A(&h->igam, Nt * sizeof(double));
+  A(&h->lam, Nt * sizeof(cx<double>));
+  A(&h->tw64, TW_N * sizeof(cx<double>));
+  A(&h->tw32, TW_N * sizeof(cx<float>));
+  // partial sums: the largest grid of any reducing kernel
+  h->max_partials = std::max(passb_blocks(h), 1);
+  h->max_partials = std::max<int>(h->max_partials,
+                                  static_cast<int>(krylov_blocks(Nt * h->Nk)));
+  A(&h->partials, static_cast<size_t>(h->max_partials) * 4 * sizeof(double));
+  A(&h->red_out, 8 * sizeof(double));
+  A(&h->ctl, sizeof(Ctl));
+  A(&h->hist, HIST_CAP * 2 * sizeof(double));
+  if (h->restart_cap > 0) {
+    A(&h->T2, st);
+    A(&h->V, static_cast<size_t>(h->restart_cap + 1) * st);
+    h->kpart_blocks = static_cast<int>(krylov_blocks(Nt * h->Nk));
+    A(&h->kpart, static_cast<size_t>(h->kpart_blocks) *
+                     (h->restart_cap + 2) * sizeof(double));
+    A(&h->kdots, (h->restart_cap + 2) * sizeof(double));
+    if (h->nonlinear)
+      A(&h->Uphys, static_cast<size_t>(Nt) * h->Ns * sizeof(double));
+  }
+  if (rc == 0) {
+    if (hipHostMalloc(&h->h_ctl, sizeof(Ctl)) != hipSuccess ||
+        hipHostMalloc(&h->h_red, 8 * sizeof(double)) != hipSuccess)
+      rc = fail(h, EXPDIAG_ENOMEM, "pinned host allocation");
+  }
+  if (rc == 0) rc = build_tables(h);
+  if (rc != 0) {
+    g_create_err = h->err;
+    release(h);
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return EXPDIAG_OK;
+}
+
+int expdiag_destroy(expdiag_t h) {
+  if (h == nullptr) return EXPDIAG_OK;
+  (void)hipStreamSynchronize(h->stream);
+  release(h);
+  delete h;
+  return EXPDIAG_OK;
+}
+
+int expdiag_set_stream(expdiag_t h, void* hip_stream) {
+  if (h == nullptr) return EXPDIAG_EINVAL;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  return EXPDIAG_OK;
+}
+
+int expdiag_residual(expdiag_t h, const double* u0, const double* U,
+                     double* R, double* rnorm) {
+  if (h == nullptr) return EXPDIAG_EINVAL;
+  if (u0 == nullptr || U == nullptr || R == nullptr)
+    return fail(h, EXPDIAG_EINVAL, "null device pointer");
+  if (static_cast<const void*>(U) == static_cast<const void*>(R))
+    return fail(h, EXPDIAG_EINVAL, "U and R must be distinct");
+  RCHK(prepare_u0(h, u0));
+  RCHK(fwd_slices<ROW_R2C>(h, U, h->Uh, h->Nt));
+  if (h->nonlinear) RCHK(pass_a<double>(h));
+  PassBArgs a = passb_args(h);
+  a.Sout = h->T;
+  RCHK((launch_passb<PB_RESIDUAL, double>(h, a)));
+  RCHK(launch_reduce(h, passb_blocks(h), false));
+  RCHK(inv_slices<double>(h, h->T, R, h->Nt));
+  if (rnorm != nullptr) {
+    HIPCHK(h, hipMemcpyAsync(h->h_red, h->red_out, 4 * sizeof(double),
+                             hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    *rnorm = std::sqrt(h->h_red[0]);
+  }
+  return EXPDIAG_OK;
+}
+
+int expdiag_precond_apply(expdiag_t h, const double* R, double* S) {
+  if (h == nullptr) return EXPDIAG_EINVAL;
+  if (R == nullptr || S == nullptr)
+    return fail(h, EXPDIAG_EINVAL, "null device pointer");
+  RCHK(fwd_slices<ROW_R2C>(h, R, h->T, h->Nt));
+  PassBArgs a = passb_args(h);
+  a.Rin = h->T;
+  a.Sout = h->T;
+  RCHK((launch_passb<PB_PRECOND, double>(h, a)));
+  RCHK(inv_slices<double>(h, h->T, S, h->Nt));
+  return EXPDIAG_OK;
+}
+
+int expdiag_iterate(expdiag_t h, const double* u0, double* U, int max_iter,
+                    double tol, int* iters, double* rel_update) {
+  if (h == nullptr) return EXPDIAG_EINVAL;
+  if (u0 == nullptr || U == nullptr)
+    return fail(h, EXPDIAG_EINVAL, "null device pointer");
+  if (max_iter < 1 || max_iter > HIST_CAP)
+    return fail(h, EXPDIAG_EINVAL, "max_iter must be 1..%d", HIST_CAP);
+  if (!(tol >= 0.0)) return fail(h, EXPDIAG_EINVAL, "tol must be >= 0");
+  RCHK(prepare_u0(h, u0));
+  RCHK(fwd_slices<ROW_R2C>(h, U, h->Uh, h->Nt));
+
+  Ctl c0{};
+  c0.max_iter = max_iter;
+  c0.tol = tol;
+  *h->h_ctl = c0;
+  HIPCHK(h, hipMemcpyAsync(h->ctl, h->h_ctl, sizeof(Ctl),
+                           hipMemcpyHostToDevice, h->stream));
+  const int nb = passb_blocks(h);
+  // mixed precision: bulk phase with fp32 pass A until ||S||/||U|| <= 1e-6
+  bool bulk = h->mixed && h->nonlinear;
+  const double bulk_tol = 1e-6;
+  if (bulk) {
+    const long n0 = h->Nk;
+    hipLaunchKernelGGL(narrow_kernel, dim3((n0 + 255) / 256), dim3(256), 0,
+                       h->stream, h->Nh, nh_view<float>(h), n0);
+    HIPCHK(h, hipGetLastError());
+  }
+  int enqueued = 0;
+  int chunk = 4;
+  double rel_prev = -1.0;
+  int it_prev = 0;
+  while (true) {
+    const int todo = std::min(chunk, max_iter - enqueued);
+    for (int i = 0; i < todo; ++i) {
+      PassBArgs a = passb_args(h);
+      a.ctl = h->ctl;
+      if (bulk) {
+        RCHK(pass_a<float>(h));
+        a.Nh = nh_view<float>(h);
+        RCHK((launch_passb<PB_ITERATE, float>(h, a)));
+      } else {
+        if (h->nonlinear) RCHK(pass_a<double>(h));
+        RCHK((launch_passb<PB_ITERATE, double>(h, a)));
+      }
+      RCHK(launch_reduce(h, nb, true));
+    }
+    enqueued += todo;
+    RCHK(sync_ctl(h));
+    const Ctl& c = *h->h_ctl;
+    if (c.done == 2) break;
+    if (bulk && (c.last_rel <= bulk_tol || c.done == 1)) {
+      // switch to the fp64 residual: rebuild N^_0 in fp64 storage
+      bulk = false;
+      RCHK(fwd_slices<ROW_NR2C>(h, u0, h->Nh, 1));
+      if (c.done == 1 && c.iters < max_iter) {
+        // converged in the bulk phase: keep refining in fp64
+        h->h_ctl->done = 0;
+        HIPCHK(h, hipMemcpyAsync(h->ctl, h->h_ctl, sizeof(Ctl),
+                                 hipMemcpyHostToDevice, h->stream));
+      }
+      if (c.iters >= max_iter) break;
+      continue;
+    }
+    if (c.done != 0 || enqueued >= max_iter) break;
+    // next chunk: iterations the observed contraction predicts to reach
+    // the active tolerance (device-side flags make overshoot harmless)
+    const double goal = bulk ? bulk_tol : tol;
+    int next = 8;
+    if (rel_prev > 0.0 && c.last_rel > 0.0 && c.iters > it_prev &&
+        c.last_rel < rel_prev) {
+      const double rho =
+          std::pow(c.last_rel / rel_prev, 1.0 / (c.iters - it_prev));
+      const double need = std::log(goal / c.last_rel) / std::log(rho);
+      next = static_cast<int>(std::ceil(need > 0 ? need : 1.0));
+    }
+    chunk = std::max(1, std::min(next, 64));
+    rel_prev = c.last_rel;
+    it_prev = c.iters;
+  }
+  RCHK(inv_slices<double>(h, h->Uh, U, h->Nt));
+  RCHK(sync_ctl(h));
+  const Ctl& c = *h->h_ctl;
+  if (iters != nullptr) *iters = c.iters;
+  if (rel_update != nullptr) *rel_update = c.last_rel;
+  if (c.done == 2) return fail(h, EXPDIAG_EDIVERGED, "non-finite residual");
+  return c.last_rel <= tol ? EXPDIAG_OK : EXPDIAG_NOT_CONVERGED;
+}
+
+int expdiag_profile_enable(expdiag_t h, int on) {
+  if (h == nullptr) return EXPDIAG_EINVAL;
+  if (on) {
+    if (h->events.empty()) {
+      h->events.resize(16384);
+      for (auto& e : h->events) {
+        HIPCHK(h, hipEventCreate(&e.a));
+        HIPCHK(h, hipEventCreate(&e.b));
+      }
+    }
+    h->ev_used = 0;
+    for (int i = 0; i < NPROF; ++i) {
+      h->prof_ms[i] = 0;
+      h->prof_cnt[i] = 0;
+      h->prof_bytes[i] = 0;
+    }
+  }
+  h->prof = on != 0;
+  return EXPDIAG_OK;
+}
+
+int expdiag_profile_read(expdiag_t h, double* ms, long* launches,
+                         double* bytes, int nclass) {
+  if (h == nullptr || ms == nullptr || nclass < 1) return EXPDIAG_EINVAL;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (size_t i = 0; i < h->ev_used; ++i) {
+    float t = 0;
+    HIPCHK(h, hipEventElapsedTime(&t, h->events[i].a, h->events[i].b));
+    h->prof_ms[h->events[i].cls] += t;
+    h->prof_cnt[h->events[i].cls] += 1;
+  }
+  h->ev_used = 0;
+  for (int i = 0; i < nclass && i < NPROF; ++i) {
+    ms[i] = h->prof_ms[i];
+    if (launches != nullptr) launches[i] = h->prof_cnt[i];
+    if (bytes != nullptr) bytes[i] = h->prof_bytes[i];
+  }
+  return EXPDIAG_OK;
+}
+
+}  // extern "C"
+
+#include "gmres.inc"

@@ -1,0 +1,266 @@
+// Pass B: everything of one Exp-ParaDiag iteration that is pointwise in the
+// spatial wavevector kappa, fused into one kernel per tile of C kappa
+// columns x all Nt time rows.
+//
+// For each kappa (spectral state U^_l, l = 0..Nt-1 <-> slices 1..Nt):
+//   residual   R_l = E U_{l-1} + c1 N_l + c2 N_{l-1} - U_l
+//              (U_{-1} = u0^, N_{-1} = N_0; eq. pcond-1st-order with the
+//               lagged nonlinearity of Sec. 6.2; ETD1: c1 = dt phi1, c2 = 0;
+//               ETD2: c1 = dt(phi1+phi2), c2 = -dt phi2)
+//   step (a)   Y_m = sum_l e^{+2 pi i ml/Nt} gamma_l R_l       (F Gamma_alpha)
+//   step (b)   X_m = Y_m / (Nt (1 - lambda_m E))                 shifted solves
+//   step (c)   S_l = gamma_l^{-1} sum_m e^{-2 pi i ml/Nt} X_m  (Gamma^-1 F^*)
+//   update     U_l += S_l
+// (Sec. 3, eq. exp_ParaDiag_steps; the unitary 1/sqrt(Nt) factors of F and
+// F^* are folded into the single 1/Nt of step (b).)
+//
+// The time transforms are length-Nt Stockham FFTs held in registers and LDS
+// (fft_core.hpp).  Norm partials use Parseval with the half-spectrum weight
+// (1 for the k_last = 0 and Nyquist planes, 2 otherwise).
+#pragma once
+#include "fft_core.hpp"
+
+namespace expdiag {
+
+enum PassBMode : int {
+  PB_ITERATE = 0,   // residual + precond + update of U
+  PB_PRECOND = 1,   // Sout = Q_alpha^{-1} Rin
+  PB_RESIDUAL = 2,  // Sout = R(U)
+  PB_OPAPPLY = 3,   // Sout = Q_alpha^{-1} (Q v - Gv), v in U, Gv in N (opt.)
+};
+
+struct Ctl {
+  int done;      // 0 running, 1 converged or max_iter, 2 diverged
+  int iters;     // iterations completed
+  int max_iter;
+  int pad;
+  double tol;
+  double last_rel;   // ||S|| / ||U||
+  double last_rnorm; // ||R|| (L2 over space-time, physical scaling)
+  double last_unorm;
+};
+
+struct PassBArgs {
+  cx<double>* U;          // [Nt][Nk]
+  const void* Nh;         // [Nt][Nk] of TN, or null (linear)
+  const cx<double>* u0h;  // [Nk]
+  const double* E;        // [Nk]
+  const double* c1;       // [Nk]
+  const double* c2;       // [Nk]
+  const double* gam;      // [Nt]
+  const double* igam;     // [Nt]
+  const cx<double>* lam;  // [Nt]
+  const cx<double>* Rin;  // [Nt][Nk] (PB_PRECOND)
+  cx<double>* Sout;       // [Nt][Nk] (PB_PRECOND / PB_RESIDUAL / PB_OPAPPLY)
+  double* partials;       // [gridDim.x][4]
+  const Ctl* ctl;         // skip the launch when ctl->done (may be null)
+  const cx<double>* tw;
+  long Nk;
+  int nh;
+  int nonlinear;
+};
+
+template <int NT>
+struct PassBShape {
+  static constexpr int R = FftShape<NT>::R;
+  static constexpr int TPL = FftShape<NT>::TPL;
+  static constexpr int C = (256 / TPL) >= 4 ? 256 / TPL : 4;
+  static constexpr int THREADS = C * TPL;
+  static constexpr int LS = C + 1;
+};
+
+// Sum NV doubles over the block; thread 0 writes them to out[0..NV).
+template <int NV, int THREADS>
+__device__ __forceinline__ void block_sum(double (&acc)[NV], double* red,
+                                          double* out) {
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    double a = acc[j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+    acc[j] = a;
+  }
+  constexpr int NW = (THREADS + 63) / 64;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) red[wid * NV + j] = acc[j];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      double s = 0;
+      for (int w = 0; w < NW; ++w) s += red[w * NV + j];
+      out[j] = s;
+    }
+  }
+}
+
+template <int NT, int MODE, typename TN>
+__global__ void __launch_bounds__(PassBShape<NT>::THREADS)
+    passb_kernel(PassBArgs a) {
+  using SH = PassBShape<NT>;
+  constexpr int R = SH::R;
+  constexpr int TPL = SH::TPL;
+  constexpr int C = SH::C;
+  constexpr int LS = SH::LS;
+  __shared__ cx<double> lds[NT * LS];
+  __shared__ double red[((SH::THREADS + 63) / 64) * 4];
+  if (a.ctl != nullptr && a.ctl->done) return;
+
+  const int c = threadIdx.x % C;
+  const int t = threadIdx.x / C;
+  const long kap = static_cast<long>(blockIdx.x) * C + c;
+  const bool valid = kap < a.Nk;
+  const long Nk = a.Nk;
+  const double E = valid ? a.E[kap] : 0.0;
+  const int kl = static_cast<int>(kap % a.nh);
+  const double pw = (!valid) ? 0.0 : ((kl == 0 || kl == a.nh - 1) ? 1.0 : 2.0);
+
+  cx<double> u[R];  // current iterate rows (ITERATE) / input rows
+  cx<double> v[R];
+  double nrm_r = 0.0, nrm_s = 0.0, nrm_u = 0.0;
+
+  if constexpr (MODE == PB_PRECOND) {
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      const int l = t + s * TPL;
+      const cx<double> r = valid ? a.Rin[l * Nk + kap] : mk(0.0, 0.0);
+      nrm_r += pw * norm2(r);
+      v[s] = r * a.gam[l];
+    }
+  } else {
+    // rows of U (or of the Krylov vector v for PB_OPAPPLY)
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      const int l = t + s * TPL;
+      u[s] = valid ? a.U[l * Nk + kap] : mk(0.0, 0.0);
+      lds[l * LS + c] = u[s];
+    }
+    __syncthreads();
+    const cx<double> first =
+        (MODE == PB_OPAPPLY || !valid) ? mk(0.0, 0.0) : a.u0h[kap];
+    const double c1 = (valid && a.nonlinear) ? a.c1[kap] : 0.0;
+    const double c2 = (valid && a.nonlinear) ? a.c2[kap] : 0.0;
+    const TN* Nh = reinterpret_cast<const TN*>(a.Nh);
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      const int l = t + s * TPL;
+      const cx<double> prev = (l == 0) ? first : lds[(l - 1) * LS + c];
+      cx<double> r;
+      if constexpr (MODE == PB_OPAPPLY) {
+        // Q v - G'v : v_l - E v_{l-1} - Gv_l
+        r = u[s] - prev * E;
+        if (a.nonlinear && valid) {
+          const cx<TN> g =
+              reinterpret_cast<const cx<TN>*>(Nh)[l * Nk + kap];
+          r = r - cvt<double>(g);
+        }
+      } else {
+        r = prev * E - u[s];
+        if (a.nonlinear && valid) {
+          const cx<double> nl =
+              cvt<double>(reinterpret_cast<const cx<TN>*>(Nh)[l * Nk + kap]);
+          const cx<double> nlp = cvt<double>(reinterpret_cast<const cx<TN>*>(
+              Nh)[(l == 0 ? 0 : l - 1) * Nk + kap]);
+          r = r + nl * c1 + nlp * c2;
+        }
+      }
+      nrm_r += pw * norm2(r);
+      v[s] = r * a.gam[l];
+    }
+    if constexpr (MODE == PB_RESIDUAL) {
+      if (valid) {
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+          const int l = t + s * TPL;
+          a.Sout[l * Nk + kap] = v[s] * a.igam[l];
+        }
+      }
+      double acc[4] = {nrm_r, 0.0, 0.0, 0.0};
+      block_sum<4, SH::THREADS>(acc, red, a.partials + blockIdx.x * 4);
+      return;
+    }
+    __syncthreads();
+  }
+
+  // step (a): forward time transform with the + sign
+  fft_line<double, NT, 1>(v, lds + c, LS, t, a.tw);
+  // step (b): shifted solves, 1/(Nt (1 - lambda_m E))
+#pragma unroll
+  for (int s = 0; s < R; ++s) {
+    const int m = t + s * TPL;
+    const cx<double> lam = a.lam[m];
+    const double dr = 1.0 - lam.x * E, di = -lam.y * E;
+    const double inv = 1.0 / (NT * (dr * dr + di * di));
+    v[s] = cmul(v[s], mk(dr * inv, -di * inv));
+  }
+  __syncthreads();
+  // step (c): inverse time transform with the - sign, then Gamma^{-1}
+  fft_line<double, NT, -1>(v, lds + c, LS, t, a.tw);
+
+  if constexpr (MODE == PB_ITERATE) {
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      const int l = t + s * TPL;
+      const cx<double> sv = v[s] * a.igam[l];
+      const cx<double> un = u[s] + sv;
+      nrm_s += pw * norm2(sv);
+      nrm_u += pw * norm2(un);
+      if (valid) a.U[l * Nk + kap] = un;
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      const int l = t + s * TPL;
+      const cx<double> sv = v[s] * a.igam[l];
+      nrm_s += pw * norm2(sv);
+      if (valid) a.Sout[l * Nk + kap] = sv;
+    }
+  }
+  double acc[4] = {nrm_r, nrm_s, nrm_u, 0.0};
+  block_sum<4, SH::THREADS>(acc, red, a.partials + blockIdx.x * 4);
+}
+
+// Deterministic final reduction of per-block partials (fixed order), and the
+// convergence bookkeeping of the fixed point.  One block of 256 threads.
+// out[j] = sum_b partials[b][j] / Ns  (Parseval: physical squared norms).
+__global__ void __launch_bounds__(256)
+    reduce_kernel(const double* __restrict__ partials, int nblocks,
+                  double inv_ns, double* __restrict__ out, Ctl* ctl,
+                  int update_ctl, double* hist) {
+  if (update_ctl && ctl->done) return;
+  __shared__ double red[4 * 4];
+  double acc[4] = {0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nblocks; b += 256) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] += partials[b * 4 + j];
+  }
+  double tot[4];
+  block_sum<4, 256>(acc, red, tot);
+  if (threadIdx.x != 0) return;
+  for (int j = 0; j < 4; ++j) out[j] = tot[j] * inv_ns;
+  if (!update_ctl) return;
+  const double rn = sqrt(tot[0] * inv_ns);
+  const double sn = sqrt(tot[1] * inv_ns);
+  const double un = sqrt(tot[2] * inv_ns);
+  const double rel = un > 0 ? sn / un : sn;
+  const int it = ctl->iters + 1;
+  ctl->iters = it;
+  ctl->last_rel = rel;
+  ctl->last_rnorm = rn;
+  ctl->last_unorm = un;
+  if (hist != nullptr && it <= ctl->max_iter) {
+    hist[2 * (it - 1)] = rel;
+    hist[2 * (it - 1) + 1] = rn;
+  }
+  if (!(rel == rel) || !(rn == rn) || rel > 1e300) {
+    ctl->done = 2;
+  } else if (rel <= ctl->tol || it >= ctl->max_iter) {
+    ctl->done = 1;
+  }
+}
+
+}  // namespace expdiag

@@ -1,0 +1,274 @@
+"""Thin ctypes binding of libexpdiag.so (include/expdiag.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+Device arrays are torch tensors (float64, contiguous, on a HIP device); the
+stream is torch's current stream unless one is given.  The library must
+have been built (``__graft_entry__.build()``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+LIB_NAME = "libexpdiag.so"
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), LIB_NAME)
+
+EXPDIAG_OK = 0
+EXPDIAG_NOT_CONVERGED = 1
+EXPDIAG_EINVAL = -1
+EXPDIAG_ENOMEM = -2
+EXPDIAG_EHIP = -3
+EXPDIAG_EDIVERGED = -4
+EXPDIAG_EUNSUPPORTED = -5
+EXPDIAG_ETD1 = 1
+EXPDIAG_ETD2 = 2
+EXPDIAG_FP64 = 0
+EXPDIAG_MIXED = 1
+
+EXPORTED = (
+    "expdiag_create", "expdiag_destroy", "expdiag_set_stream",
+    "expdiag_footprint_bytes", "expdiag_residual", "expdiag_precond_apply",
+    "expdiag_iterate", "expdiag_gmres", "expdiag_profile_enable",
+    "expdiag_profile_read", "expdiag_strerror", "expdiag_last_error",
+)
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double), ("c", ctypes.c_double),
+                ("n1", ctypes.c_double), ("n2", ctypes.c_double),
+                ("n3", ctypes.c_double), ("precision", ctypes.c_int),
+                ("gmres_restart", ctypes.c_int)]
+
+
+class ExpdiagError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"expdiag error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build it with __graft_entry__.build(); "
+            "there is no CPU fallback")
+    L = ctypes.CDLL(path)
+    vp, cd, ci, sz = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, \
+        ctypes.c_size_t
+    L.expdiag_create.argtypes = [ctypes.POINTER(Grid), ci, cd, cd, ci,
+                                 ctypes.POINTER(Problem), vp,
+                                 ctypes.POINTER(vp)]
+    L.expdiag_destroy.argtypes = [vp]
+    L.expdiag_set_stream.argtypes = [vp, vp]
+    L.expdiag_footprint_bytes.argtypes = [ctypes.POINTER(Grid), ci, ci, ci,
+                                          ci]
+    L.expdiag_footprint_bytes.restype = sz
+    L.expdiag_residual.argtypes = [vp, vp, vp, vp,
+                                   ctypes.POINTER(cd)]
+    L.expdiag_precond_apply.argtypes = [vp, vp, vp]
+    L.expdiag_iterate.argtypes = [vp, vp, vp, ci, cd,
+                                  ctypes.POINTER(ci), ctypes.POINTER(cd)]
+    L.expdiag_gmres.argtypes = [vp, vp, vp, ci, ci, cd,
+                                ctypes.POINTER(ci), ctypes.POINTER(cd)]
+    L.expdiag_profile_enable.argtypes = [vp, ci]
+    L.expdiag_profile_read.argtypes = [vp, ctypes.POINTER(cd),
+                                       ctypes.POINTER(ctypes.c_long),
+                                       ctypes.POINTER(cd), ci]
+    L.expdiag_strerror.argtypes = [ci]
+    L.expdiag_strerror.restype = ctypes.c_char_p
+    L.expdiag_last_error.argtypes = [vp]
+    L.expdiag_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        getattr(L, name).restype = getattr(L, name).restype or ci
+    _lib = L
+    return L
+
+
+def make_grid(shape: Sequence[int]) -> Grid:
+    g = Grid()
+    g.dim = len(shape)
+    for i in range(3):
+        g.n[i] = int(shape[i]) if i < len(shape) else 1
+    return g
+
+
+def make_problem(a, c=0.0, n1=0.0, n2=0.0, n3=0.0, precision=EXPDIAG_FP64,
+                 gmres_restart=0) -> Problem:
+    return Problem(float(a), float(c), float(n1), float(n2), float(n3),
+                   int(precision), int(gmres_restart))
+
+
+def _ptr(t, numel=None, name="array"):
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError(f"{name} must be a contiguous float64 GPU tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def strerror(code: int) -> str:
+    return load().expdiag_strerror(code).decode()
+
+
+def _check(rc, h=None, ok=(EXPDIAG_OK,)):
+    if rc in ok:
+        return rc
+    L = load()
+    msg = L.expdiag_last_error(h).decode() if h is not None else \
+        L.expdiag_last_error(None).decode()
+    raise ExpdiagError(rc, f"{strerror(rc)}: {msg}")
+
+
+# -- the C ABI, one Python function per entry point ------------------------
+def expdiag_create(shape, Nt, dt, alpha, scheme, problem: Problem,
+                   stream=None):
+    L = load()
+    h = ctypes.c_void_p()
+    g = make_grid(shape)
+    rc = L.expdiag_create(ctypes.byref(g), int(Nt), float(dt), float(alpha),
+                          int(scheme), ctypes.byref(problem),
+                          _stream(stream), ctypes.byref(h))
+    _check(rc)
+    return h
+
+
+def expdiag_destroy(h):
+    return load().expdiag_destroy(h)
+
+
+def expdiag_set_stream(h, stream):
+    return _check(load().expdiag_set_stream(h, _stream(stream)), h)
+
+
+def expdiag_footprint_bytes(shape, Nt, scheme, precision=EXPDIAG_FP64,
+                            gmres_restart=0) -> int:
+    g = make_grid(shape)
+    return int(load().expdiag_footprint_bytes(ctypes.byref(g), int(Nt),
+                                              int(scheme), int(precision),
+                                              int(gmres_restart)))
+
+
+def expdiag_residual(h, u0, U, R, want_norm=True):
+    nrm = ctypes.c_double(0.0)
+    rc = load().expdiag_residual(h, _ptr(u0, name="u0"), _ptr(U, name="U"),
+                                 _ptr(R, U.numel(), "R"),
+                                 ctypes.byref(nrm) if want_norm else None)
+    _check(rc, h)
+    return nrm.value if want_norm else None
+
+
+def expdiag_precond_apply(h, R, S):
+    return _check(load().expdiag_precond_apply(
+        h, _ptr(R, name="R"), _ptr(S, R.numel(), "S")), h)
+
+
+def expdiag_iterate(h, u0, U, max_iter, tol):
+    it = ctypes.c_int(0)
+    rel = ctypes.c_double(0.0)
+    rc = load().expdiag_iterate(h, _ptr(u0, name="u0"), _ptr(U, name="U"),
+                                int(max_iter), float(tol), ctypes.byref(it),
+                                ctypes.byref(rel))
+    _check(rc, h, ok=(EXPDIAG_OK, EXPDIAG_NOT_CONVERGED))
+    return rc, it.value, rel.value
+
+
+def expdiag_gmres(h, u0, U, restart, max_iter, tol):
+    it = ctypes.c_int(0)
+    rel = ctypes.c_double(0.0)
+    rc = load().expdiag_gmres(h, _ptr(u0, name="u0"), _ptr(U, name="U"),
+                              int(restart), int(max_iter), float(tol),
+                              ctypes.byref(it), ctypes.byref(rel))
+    _check(rc, h, ok=(EXPDIAG_OK, EXPDIAG_NOT_CONVERGED))
+    return rc, it.value, rel.value
+
+
+def expdiag_profile_enable(h, on=True):
+    return _check(load().expdiag_profile_enable(h, 1 if on else 0), h)
+
+
+PROFILE_CLASSES = ("col_fft", "row_fft", "passb", "reduce", "krylov")
+
+
+def expdiag_profile_read(h, nclass=5):
+    """Returns (ms, launches, bytes) per kernel class since enable."""
+    ms = (ctypes.c_double * nclass)()
+    cnt = (ctypes.c_long * nclass)()
+    by = (ctypes.c_double * nclass)()
+    _check(load().expdiag_profile_read(h, ms, cnt, by, nclass), h)
+    return list(ms), list(cnt), list(by)
+
+
+class Solver:
+    """Owns one handle; convenience wrapper around the functions above."""
+
+    def __init__(self, shape, Nt, dt, alpha, scheme=EXPDIAG_ETD1, a=1.0,
+                 c=0.0, n1=0.0, n2=0.0, n3=0.0, precision=EXPDIAG_FP64,
+                 gmres_restart=0, stream=None):
+        self.shape = tuple(int(v) for v in shape)
+        self.Nt = int(Nt)
+        self.problem = make_problem(a, c, n1, n2, n3, precision,
+                                    gmres_restart)
+        self.h = expdiag_create(self.shape, Nt, dt, alpha, scheme,
+                                self.problem, stream)
+
+    @classmethod
+    def from_instance(cls, inst, gmres_restart=0, stream=None,
+                      precision=None):
+        return cls(inst.shape, inst.Nt, inst.dt, inst.alpha, inst.scheme,
+                   inst.a, inst.c, inst.n1, inst.n2, inst.n3,
+                   inst.precision if precision is None else precision,
+                   gmres_restart, stream)
+
+    def close(self):
+        if self.h is not None:
+            expdiag_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def residual(self, u0, U, R):
+        return expdiag_residual(self.h, u0, U, R)
+
+    def precond_apply(self, R, S):
+        return expdiag_precond_apply(self.h, R, S)
+
+    def iterate(self, u0, U, max_iter=200, tol=1e-11):
+        return expdiag_iterate(self.h, u0, U, max_iter, tol)
+
+    def gmres(self, u0, U, restart=20, max_iter=400, tol=1e-10):
+        return expdiag_gmres(self.h, u0, U, restart, max_iter, tol)
