@@ -63,6 +63,7 @@ struct expdiag_ctx {
   cx<double>* T = nullptr;    // [Nt][Nk] scratch
   cx<double>* T2 = nullptr;   // [Nt][Nk] scratch (GMRES / Newton)
   double* Uphys = nullptr;    // [Nt][Ns] physical iterate (Newton)
+  float* Uphys32 = nullptr;   // [Nt][Ns] its fp32 copy (mixed Newton)
   cx<double>* u0h = nullptr;  // [Nk]
   double *E = nullptr, *c1 = nullptr, *c2 = nullptr;  // [Nk]
   double *gam = nullptr, *igam = nullptr;             // [Nt]
@@ -82,6 +83,7 @@ struct expdiag_ctx {
   // pinned host mirrors
   Ctl* h_ctl = nullptr;
   double* h_red = nullptr;
+  double* h_kdots = nullptr;  // [3 (restart+2)]
 
   // profiling
   bool prof = false;
@@ -513,7 +515,7 @@ size_t footprint(const Sizes& s, int Nt, bool nonlinear, int restart) {
   if (restart > 0) {
     b += st;                                          // T2
     b += static_cast<size_t>(restart + 1) * st;       // Krylov basis
-    if (nonlinear) b += static_cast<size_t>(Nt) * s.Ns * sizeof(double);
+    if (nonlinear) b += static_cast<size_t>(Nt) * s.Ns * sizeof(double) * 3 / 2;
   }
   b += s.Nk * (sizeof(cx<double>) + 3 * sizeof(double));
   b += TW_N * (sizeof(cx<double>) + sizeof(cx<float>));
@@ -544,6 +546,7 @@ void release(expdiag_ctx* h) {
   fr(h->T);
   fr(h->T2);
   fr(h->Uphys);
+  fr(h->Uphys32);
   fr(h->u0h);
   fr(h->E);
   fr(h->c1);
@@ -562,6 +565,7 @@ void release(expdiag_ctx* h) {
   fr(h->kpart);
   if (h->h_ctl != nullptr) (void)hipHostFree(h->h_ctl);
   if (h->h_red != nullptr) (void)hipHostFree(h->h_red);
+  if (h->h_kdots != nullptr) (void)hipHostFree(h->h_kdots);
   for (auto& e : h->events) {
     (void)hipEventDestroy(e.a);
     (void)hipEventDestroy(e.b);
@@ -695,13 +699,17 @@ int expdiag_create(const expdiag_grid* g, int Nt, double dt, double alpha,
     h->kpart_blocks = static_cast<int>(krylov_blocks(Nt * h->Nk));
     A(&h->kpart, static_cast<size_t>(h->kpart_blocks) *
                      (h->restart_cap + 2) * sizeof(double));
-    A(&h->kdots, (h->restart_cap + 2) * sizeof(double));
+    A(&h->kdots, 3 * (h->restart_cap + 2) * sizeof(double));
     if (h->nonlinear)
       A(&h->Uphys, static_cast<size_t>(Nt) * h->Ns * sizeof(double));
+    if (h->nonlinear && h->mixed)
+      A(&h->Uphys32, static_cast<size_t>(Nt) * h->Ns * sizeof(float));
   }
   if (rc == 0) {
     if (hipHostMalloc(&h->h_ctl, sizeof(Ctl)) != hipSuccess ||
-        hipHostMalloc(&h->h_red, 8 * sizeof(double)) != hipSuccess)
+        hipHostMalloc(&h->h_red, 8 * sizeof(double)) != hipSuccess ||
+        hipHostMalloc(&h->h_kdots, 3 * (h->restart_cap + 2) *
+                                       sizeof(double)) != hipSuccess)
       rc = fail(h, EXPDIAG_ENOMEM, "pinned host allocation");
   }
   if (rc == 0) rc = build_tables(h);

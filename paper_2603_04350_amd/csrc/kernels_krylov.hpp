@@ -1,4 +1,11 @@
 // Krylov-vector kernels for GMRES on spectral space-time vectors.
+//
+// A Krylov vector is a half-spectrum space-time array [Nt][Nk] of complex
+// fp64.  The real inner product of the physical fields it represents is,
+// by Parseval, <x, y> = (1/Ns) sum_{l,kappa} w(kappa) Re(conj(x) y) with the
+// half-spectrum weight w = 1 on the k_last = 0 and Nyquist planes, 2 else.
+// All reductions are two-level with a fixed order, so results do not depend
+// on scheduling.
 #pragma once
 #include "cx.hpp"
 
@@ -6,11 +13,127 @@ namespace expdiag {
 
 constexpr int KRY_THREADS = 256;
 constexpr int KRY_PER_THREAD = 4;
+constexpr int KRY_PER_BLOCK = KRY_THREADS * KRY_PER_THREAD;
 
 inline long krylov_blocks(long n) {
-  const long per = static_cast<long>(KRY_THREADS) * KRY_PER_THREAD;
-  long b = (n + per - 1) / per;
+  long b = (n + KRY_PER_BLOCK - 1) / KRY_PER_BLOCK;
   return b < 1 ? 1 : b;
+}
+
+__device__ __forceinline__ double half_weight(long e, long Nk, int nh) {
+  const long kap = e % Nk;
+  const int kl = static_cast<int>(kap % nh);
+  return (kl == 0 || kl == nh - 1) ? 1.0 : 2.0;
+}
+
+// Sum one double over the block; the result is valid in thread 0.
+__device__ __forceinline__ double kry_block_sum(double a, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = a;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < KRY_THREADS / 64; ++w) s += red[w];
+  }
+  return s;
+}
+
+// part[b*ld + i] = block-partial <V_i, w> for i < nv; part[b*ld + nv] =
+// block-partial <w, w>.  V_i = V + i*vstride.
+__global__ void __launch_bounds__(KRY_THREADS)
+    kdot_kernel(const cx<double>* __restrict__ V, long vstride, int nv,
+                const cx<double>* __restrict__ w, long n, long Nk, int nh,
+                double* __restrict__ part, int ld) {
+  __shared__ double red[KRY_THREADS / 64];
+  const long base = static_cast<long>(blockIdx.x) * KRY_PER_BLOCK;
+  cx<double> wv[KRY_PER_THREAD];
+  double pw[KRY_PER_THREAD];
+#pragma unroll
+  for (int q = 0; q < KRY_PER_THREAD; ++q) {
+    const long e = base + threadIdx.x + q * KRY_THREADS;
+    const bool ok = e < n;
+    wv[q] = ok ? w[e] : mk(0.0, 0.0);
+    pw[q] = ok ? half_weight(e, Nk, nh) : 0.0;
+  }
+  for (int i = 0; i <= nv; ++i) {
+    double acc = 0.0;
+    if (i < nv) {
+      const cx<double>* vi = V + i * vstride;
+#pragma unroll
+      for (int q = 0; q < KRY_PER_THREAD; ++q) {
+        const long e = base + threadIdx.x + q * KRY_THREADS;
+        if (e < n) {
+          const cx<double> x = vi[e];
+          acc += pw[q] * (x.x * wv[q].x + x.y * wv[q].y);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < KRY_PER_THREAD; ++q) acc += pw[q] * norm2(wv[q]);
+    }
+    const double s = kry_block_sum(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x * ld + i] = s;
+  }
+}
+
+// out[i] = scale * sum_b part[b*ld + i], one block per i, fixed order.
+__global__ void __launch_bounds__(KRY_THREADS)
+    kreduce_kernel(const double* __restrict__ part, int nblocks, int ld,
+                   double scale, double* __restrict__ out) {
+  __shared__ double red[KRY_THREADS / 64];
+  const int i = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += KRY_THREADS)
+    acc += part[b * ld + i];
+  const double s = kry_block_sum(acc, red);
+  if (threadIdx.x == 0) out[i] = s * scale;
+}
+
+// w += sign * sum_{i<nv} coef[i] V_i ; optionally block partials of <w,w>
+// (after the update) into part[b*ld].
+__global__ void __launch_bounds__(KRY_THREADS)
+    kaxpy_kernel(cx<double>* __restrict__ w, const cx<double>* __restrict__ V,
+                 long vstride, int nv, const double* __restrict__ coef,
+                 double sign, long n, long Nk, int nh,
+                 double* __restrict__ part, int ld) {
+  __shared__ double red[KRY_THREADS / 64];
+  __shared__ double cf[72];
+  if (threadIdx.x < nv) cf[threadIdx.x] = sign * coef[threadIdx.x];
+  __syncthreads();
+  const long base = static_cast<long>(blockIdx.x) * KRY_PER_BLOCK;
+  double acc = 0.0;
+#pragma unroll
+  for (int q = 0; q < KRY_PER_THREAD; ++q) {
+    const long e = base + threadIdx.x + q * KRY_THREADS;
+    if (e < n) {
+      cx<double> x = w[e];
+      for (int i = 0; i < nv; ++i) x = x + V[i * vstride + e] * cf[i];
+      w[e] = x;
+      if (part != nullptr) acc += half_weight(e, Nk, nh) * norm2(x);
+    }
+  }
+  if (part != nullptr) {
+    const double s = kry_block_sum(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x * ld] = s;
+  }
+}
+
+// out = in * s (out may equal in)
+__global__ void __launch_bounds__(KRY_THREADS)
+    kscale_kernel(cx<double>* out, const cx<double>* in, double s, long n) {
+  const long e = static_cast<long>(blockIdx.x) * KRY_THREADS + threadIdx.x;
+  if (e < n) out[e] = in[e] * s;
+}
+
+// zero fill (a plain kernel rather than a memset so that it can sit in a
+// captured graph)
+__global__ void __launch_bounds__(KRY_THREADS)
+    kzero_kernel(cx<double>* out, long n) {
+  const long e = static_cast<long>(blockIdx.x) * KRY_THREADS + threadIdx.x;
+  if (e < n) out[e] = mk(0.0, 0.0);
 }
 
 }  // namespace expdiag

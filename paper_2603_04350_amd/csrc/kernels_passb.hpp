@@ -26,7 +26,7 @@ enum PassBMode : int {
   PB_ITERATE = 0,   // residual + precond + update of U
   PB_PRECOND = 1,   // Sout = Q_alpha^{-1} Rin
   PB_RESIDUAL = 2,  // Sout = R(U)
-  PB_OPAPPLY = 3,   // Sout = Q_alpha^{-1} (Q v - Gv), v in U, Gv in N (opt.)
+  PB_OPAPPLY = 3,   // Sout = Q_alpha^{-1} (Q - G'(U)) v, v in U, J in Nh
 };
 
 struct Ctl {
@@ -151,12 +151,13 @@ __global__ void __launch_bounds__(PassBShape<NT>::THREADS)
       const cx<double> prev = (l == 0) ? first : lds[(l - 1) * LS + c];
       cx<double> r;
       if constexpr (MODE == PB_OPAPPLY) {
-        // Q v - G'v : v_l - E v_{l-1} - Gv_l
+        // (Q - G'(U)) v : v_l - E v_{l-1} - (c1 J_l + c2 J_{l-1}), where
+        // J_l = FFT[N'(u_{l-1}) v_{l-1}] (J_0 = J_{-1} = 0: u_0 is fixed)
         r = u[s] - prev * E;
         if (a.nonlinear && valid) {
-          const cx<TN> g =
-              reinterpret_cast<const cx<TN>*>(Nh)[l * Nk + kap];
-          r = r - cvt<double>(g);
+          const cx<TN>* J = reinterpret_cast<const cx<TN>*>(Nh);
+          if (l >= 1) r = r - cvt<double>(J[l * Nk + kap]) * c1;
+          if (l >= 2) r = r - cvt<double>(J[(l - 1) * Nk + kap]) * c2;
         }
       } else {
         r = prev * E - u[s];

@@ -1,0 +1,99 @@
+"""GPU GMRES and Newton-GMRES vs the oracle, through the C ABI.
+
+Results are compared, not iteration counts, except where a theorem fixes
+the count (finite termination) or bounds it; GPU Arnoldi uses classical
+Gram-Schmidt twice (CGS2), the oracle modified Gram-Schmidt.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(
+        "cuda:0")
+
+
+def _solver(st, precision=0, restart=20):
+    from paper_2603_04350_amd import Solver
+    return Solver((st.n,) * st.dim, st.Nt, st.dt, st.alpha, st.scheme,
+                  st.a, st.c, st.n1, st.n2, st.n3, precision, restart)
+
+
+def _zeros(st):
+    import torch
+    return torch.zeros((st.Nt,) + (st.n,) * st.dim, dtype=torch.float64,
+                       device="cuda:0")
+
+
+LINEAR = {
+    "heat1d_C1": (1, 64, 16, 1e-2, 1.0, 0.0),
+    "heat2d": (2, 32, 32, 1e-3, 0.1, 0.1),
+    "heat3d": (3, 16, 8, 1e-2, 1.0, 0.0),
+    "heat1d_alpha02": (1, 32, 64, 0.2, 0.05, 0.0),
+}
+
+
+@pytest.mark.parametrize("case", sorted(LINEAR))
+def test_linear_gmres_solution(case):
+    dim, n, Nt, alpha, a, c = LINEAR[case]
+    st = O.Setup(dim, n, Nt, 1.0 / Nt, alpha, a, c)
+    rng = np.random.default_rng([n, Nt])
+    u0 = rng.uniform(-0.9, 0.9, size=(n,) * dim)
+    ref = O.sequential(st, u0)
+    Uo, it_o, _ = O.gmres_solve(st, u0, restart=20, tol=1e-13)
+    with _solver(st) as s:
+        U = _zeros(st)
+        rc, it, rel = s.gmres(_dev(u0), U, restart=20, max_iter=200,
+                              tol=1e-13)
+    assert rel <= 1e-13
+    assert O.rel_err(U.cpu().numpy(), ref) < 1e-12
+    assert abs(it - it_o) <= 1, (it, it_o)
+
+
+def test_gmres_residual_bound_gmres3_thm():
+    """||r_k|| <= (4 alpha (1 - alpha))^{k/2} ||r_0||: after k iterations
+    the GPU's relative preconditioned residual respects the bound."""
+    import math
+    st = O.Setup(1, 32, 8, 0.1, 0.1, a=0.3)
+    u0 = np.random.default_rng(3).uniform(-0.9, 0.9, size=32)
+    with _solver(st) as s:
+        for k in (1, 2, 3):
+            U = _zeros(st)
+            rc, it, rel = s.gmres(_dev(u0), U, restart=k, max_iter=k,
+                                  tol=1e-15)
+            assert rel <= math.sqrt(4 * 0.1 * 0.9) ** k * (1 + 1e-8)
+
+
+@pytest.mark.parametrize("scheme", [1, 2])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_newton_gmres_reaches_sequential(scheme, precision):
+    inst = W.scaled(W.rd2d(), n=32, Nt=32)
+    inst.scheme = scheme
+    st = O.Setup.from_instance(inst)
+    ref = O.sequential(st, inst.u0)
+    with _solver(st, precision=precision) as s:
+        U = _zeros(st)
+        rc, it, rel = s.gmres(_dev(inst.u0), U, restart=20, max_iter=400,
+                              tol=1e-12)
+    err = O.rel_err(U.cpu().numpy(), ref)
+    assert err < 1e-10, (it, rel, err)
+    assert it // 1000 <= 12
+
+
+def test_newton_gmres_3d_and_1d():
+    for dim, n in ((1, 64), (3, 16)):
+        st = O.Setup(dim, n, 16, 1.0 / 16, 1e-3, a=0.05, n1=1.0, n3=-1.0,
+                     scheme=2)
+        u0 = np.random.default_rng(dim).uniform(-0.9, 0.9, size=(n,) * dim)
+        ref = O.sequential(st, u0)
+        with _solver(st) as s:
+            U = _zeros(st)
+            rc, it, rel = s.gmres(_dev(u0), U, restart=20, max_iter=400,
+                                  tol=1e-12)
+        assert O.rel_err(U.cpu().numpy(), ref) < 1e-10
