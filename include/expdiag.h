@@ -167,6 +167,68 @@ int expdiag_profile_enable(expdiag_t h, int on);
 int expdiag_profile_read(expdiag_t h, double* ms, long* launches,
                          double* bytes, int nclass);
 
+/* Choose between replaying the captured hipGraph of one iteration (on, the
+ * default) and launching the same kernels one by one (off). */
+int expdiag_set_graph(expdiag_t h, int on);
+
+/* ---- Batching: many independent instances in one iteration plan ------
+ * Groups `count` handles (any grids, Nt, coefficients, alpha, precision;
+ * each keeps its own workspace and stays owned by the caller) so that one
+ * fixed-point iteration of all of them is one launch per kernel signature,
+ * captured as one hipGraph.  Every instance has its own control block:
+ * converged instances drop out, mixed-precision instances switch to the
+ * fp64 residual independently, and each result is the one its handle gives
+ * alone (same kernels, same per-instance reduction order).  The handles must
+ * not be used concurrently outside the batch. */
+typedef struct expdiag_batch* expdiag_batch_t;
+int expdiag_batch_create(const expdiag_t* handles, int count,
+                         void* hip_stream, expdiag_batch_t* out);
+int expdiag_batch_destroy(expdiag_batch_t b);
+/* Solve every instance by the fixed point of expdiag_iterate.
+ *   u0s[i], Us[i]  device pointers of instance i (as in expdiag_iterate)
+ *   iters, rel_update, status  host arrays of count entries (nullable):
+ *   per-instance iterations, last ||S||/||U||, and return code.
+ * Returns the worst per-instance code.  Synchronises the stream. */
+int expdiag_batch_iterate(expdiag_batch_t b, const double* const* u0s,
+                          double* const* Us, int max_iter, double tol,
+                          int* iters, double* rel_update, int* status);
+const char* expdiag_batch_last_error(expdiag_batch_t b);
+
+/* ---- Serving: continuous batching of solve requests -------------------
+ * A server owns a host thread that admits submitted requests in arrival
+ * order while the sum of their device footprints (expdiag_footprint_bytes)
+ * stays within hbm_budget and fewer than max_active are in flight, keeps
+ * each admitted solve's space-time state on the device, runs all admitted
+ * solves together (the batch plan above, rebuilt when membership changes),
+ * and retires each as it converges.  Requests arriving while others run
+ * join at the next iteration chunk. */
+typedef struct expdiag_server* expdiag_server_t;
+typedef struct {
+  long long id;
+  int status;         /* expdiag_iterate's return code for this request */
+  int iters;
+  double rel_update;
+  double t_submit, t_admit, t_done;  /* seconds since server creation */
+} expdiag_result;
+int expdiag_server_create(size_t hbm_budget, int max_active,
+                          void* hip_stream, expdiag_server_t* out);
+/* Queue one solve; u0 (Ns doubles) and U (Nt*Ns doubles, in: initial
+ * iterate, out: result) are device pointers that must stay valid, and U
+ * untouched by the caller, until the request is reported by poll. */
+int expdiag_server_submit(expdiag_server_t s, const expdiag_grid* g, int Nt,
+                          double dt, double alpha, int scheme,
+                          const expdiag_problem* p, const double* u0,
+                          double* U, int max_iter, double tol,
+                          long long* id);
+/* Move up to cap finished results into out (host array); *n receives the
+ * count, *outstanding (nullable) the requests not yet reported. */
+int expdiag_server_poll(expdiag_server_t s, expdiag_result* out, int cap,
+                        int* n, int* outstanding);
+int expdiag_server_stats(expdiag_server_t s, size_t* bytes_in_use,
+                         int* active, int* pending, double* busy_seconds);
+/* Finish every queued request, then stop the thread and free. */
+int expdiag_server_destroy(expdiag_server_t s);
+
 /* Static description of an error code. */
 const char* expdiag_strerror(int code);
 

@@ -1,5 +1,5 @@
-// Host side of the Exp-ParaDiag library: handle, tables, launch dispatch
-// and the C ABI declared in include/expdiag.h.
+// Host side of the Exp-ParaDiag library: handles, symbol tables, launch
+// plans, hipGraph capture, and the C ABI declared in include/expdiag.h.
 //
 // Spectral state.  Inside a handle the space-time iterate lives in Fourier
 // space as its half spectrum Uh[l][kappa], l = 0..Nt-1 (slices 1..Nt),
@@ -8,18 +8,30 @@
 //
 // One fixed-point iteration (Sec. 3, eq. pcond-1st-order with the lagged
 // nonlinearity of Sec. 6.2) is
-//   pass A (nonlinear only, per slice):  N^_{l} = FFT N(IFFT Uh_{l-1})
-//   pass B (per kappa tile, all Nt rows): residual, steps (a)-(c), update
-//   reduce: norms and the convergence flag (device side).
+//   pass A (nonlinear only, per slice):  N^_l = FFT N(IFFT Uh_{l-1})
+//   pass B (per kappa tile, all Nt rows): residual, steps (a)-(c), update,
+//          norms, convergence state (device side).
+// An iteration is a fixed list of launches (a "plan"): launches are grouped
+// by stage and kernel signature and each carries a device job table, so a
+// batch of instances of any shapes costs one launch per group.  The plan is
+// captured once into a hipGraph and replayed; finished instances and
+// off-phase jobs exit at their first instruction.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <thread>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
@@ -34,11 +46,36 @@ namespace {
 
 constexpr int HIST_CAP = 4096;
 constexpr int NPROF = 5;
+constexpr double BULK_TOL = 1e-6;
 enum ProfClass { P_COL = 0, P_ROW = 1, P_PASSB = 2, P_RED = 3, P_KRY = 4 };
 
 struct EventPair {
   hipEvent_t a, b;
   int cls;
+};
+
+enum Kind { K_ROW = 0, K_COL = 1, K_PASSB = 2 };
+
+// One launch of a plan: jobs of the same kernel signature.
+struct Group {
+  int stage, kind, tcode, len, mode, ti, to;  // signature
+  std::vector<RowJob> rj;
+  std::vector<ColJob> cj;
+  std::vector<PassBArgs> pj;
+  std::vector<int> start;  // njobs + 1
+  double bytes = 0;        // algorithmic bytes of one full launch
+  void* djobs = nullptr;
+  int* dstart = nullptr;
+  int grid() const { return start.empty() ? 0 : start.back(); }
+  int njobs() const { return static_cast<int>(start.size()) - 1; }
+  std::tuple<int, int, int, int, int, int, int> key() const {
+    return std::make_tuple(stage, kind, tcode, len, mode, ti, to);
+  }
+};
+
+struct Plan {
+  std::vector<Group> groups;
+  bool uploaded = false;
 };
 
 }  // namespace
@@ -51,6 +88,7 @@ struct expdiag_ctx {
   int scheme = 1;
   expdiag_problem p{};
   hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream for graph capture
   long Ns = 0, Nk = 0;
   int nh = 0;
   bool nonlinear = false;
@@ -59,7 +97,7 @@ struct expdiag_ctx {
 
   // device buffers
   cx<double>* Uh = nullptr;   // [Nt][Nk]
-  cx<double>* Nh = nullptr;   // [Nt][Nk] (nonlinear); float view in bulk
+  cx<double>* Nh = nullptr;   // [Nt][Nk] fp64; fp32 view in its 2nd half
   cx<double>* T = nullptr;    // [Nt][Nk] scratch
   cx<double>* T2 = nullptr;   // [Nt][Nk] scratch (GMRES / Newton)
   double* Uphys = nullptr;    // [Nt][Ns] physical iterate (Newton)
@@ -76,14 +114,22 @@ struct expdiag_ctx {
   Ctl* ctl = nullptr;
   double* hist = nullptr;     // [HIST_CAP][2]
   cx<double>* V = nullptr;    // Krylov basis [(restart+1)][Nt][Nk]
-  double* kdots = nullptr;    // [restart+2] dot results
-  double* kpart = nullptr;    // [maxblocks][restart+2]
+  double* kdots = nullptr;    // [3 (restart+2)]
+  double* kpart = nullptr;    // [blocks][restart+2]
   int kpart_blocks = 0;
 
-  // pinned host mirrors
-  Ctl* h_ctl = nullptr;
+  // pinned host memory
+  Ctl* h_ctl = nullptr;       // staging for control-block uploads
+  Ctl* h_mirror = nullptr;    // host-mapped mirror written by the device
+  Ctl* d_mirror = nullptr;    // its device address
   double* h_red = nullptr;
-  double* h_kdots = nullptr;  // [3 (restart+2)]
+  double* h_kdots = nullptr;
+
+  // iteration plan and its graph
+  Plan plan;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool use_graph = true;
 
   // profiling
   bool prof = false;
@@ -122,6 +168,12 @@ int fail(expdiag_ctx* h, int code, const char* fmt, ...) {
                   hipGetErrorString(e_), __FILE__, __LINE__);             \
   } while (0)
 
+#define RCHK(expr)          \
+  do {                      \
+    int r_ = (expr);        \
+    if (r_ != 0) return r_; \
+  } while (0)
+
 bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
 
 template <int LO, int HI, typename F>
@@ -137,6 +189,11 @@ bool dispatch_pow2(int v, F&& f) {
   }
 }
 
+template <typename T>
+constexpr int tcode_of() {
+  return std::is_same<T, double>::value ? 0 : 1;
+}
+
 // ---------------------------------------------------------------- profiling
 // Brackets one launch with events when profiling is on and accounts the
 // launch's algorithmic bytes (what the kernel must read and write once).
@@ -145,8 +202,9 @@ struct ProfScope {
   int cls;
   EventPair* ep = nullptr;
   ProfScope(expdiag_ctx* h_, int c, double bytes) : h(h_), cls(c) {
-    if (h->prof) h->prof_bytes[c] += bytes;
-    if (h->prof && h->ev_used < h->events.size()) {
+    if (h == nullptr || !h->prof) return;
+    h->prof_bytes[c] += bytes;
+    if (h->ev_used < h->events.size()) {
       ep = &h->events[h->ev_used++];
       ep->cls = cls;
       (void)hipEventRecord(ep->a, h->stream);
@@ -157,7 +215,6 @@ struct ProfScope {
   }
 };
 
-// ------------------------------------------------------------------ launches
 template <typename T>
 const cx<T>* twid_table(expdiag_ctx* h) {
   if constexpr (std::is_same<T, double>::value)
@@ -166,31 +223,111 @@ const cx<T>* twid_table(expdiag_ctx* h) {
     return h->tw32;
 }
 
-template <typename T, int MODE, typename TI, typename TO>
-int launch_row(expdiag_ctx* h, const TI* in, TO* out, long nrows,
-               long in_pitch, long out_pitch, double scale,
-               const TI* aux = nullptr, long aux_pitch = 0) {
-  const int M = h->n[h->dim - 1] / 2;
-  NonlinCoef nc{h->p.n1, h->p.n2, h->p.n3};
+// ------------------------------------------------------- job constructors
+int row_blocks(int M, long nrows) {
+  long b = 0;
+  dispatch_pow2<2, 512>(M, [&](auto Mc) {
+    constexpr int MM = decltype(Mc)::value;
+    b = (nrows + RowShape<MM>::RPB - 1) / RowShape<MM>::RPB;
+  });
+  return static_cast<int>(b);
+}
+int col_blocks(int L, long outer, long inner) {
+  long b = 0;
+  dispatch_pow2<4, 1024>(L, [&](auto Lc) {
+    constexpr int LL = decltype(Lc)::value;
+    b = outer * ((inner + ColShape<LL>::C - 1) / ColShape<LL>::C);
+  });
+  return static_cast<int>(b);
+}
+int passb_blocks_nt(int Nt, long Nk) {
+  long b = 0;
+  dispatch_pow2<2, 512>(Nt, [&](auto Nc) {
+    constexpr int NN = decltype(Nc)::value;
+    b = (Nk + PassBShape<NN>::C - 1) / PassBShape<NN>::C;
+  });
+  return static_cast<int>(b);
+}
+int passb_blocks(expdiag_ctx* h) { return passb_blocks_nt(h->Nt, h->Nk); }
+
+double row_bytes(int M, int mode, long nrows, size_t si, size_t so) {
   const double realb = static_cast<double>(nrows) * 2 * M;
   const double cplxb = static_cast<double>(nrows) * (M + 1) * 2;
-  double bytes = 0;
-  if (MODE == ROW_R2C || MODE == ROW_NR2C)
-    bytes = realb * sizeof(TI) + cplxb * sizeof(TO);
-  else if (MODE == ROW_C2R)
-    bytes = cplxb * sizeof(TI) + realb * sizeof(TO);
-  else
-    bytes = cplxb * (sizeof(TI) + sizeof(TO)) +
-            (MODE == ROW_JVP ? realb * sizeof(TI) : 0.0);
-  ProfScope ps(h, P_ROW, bytes);
+  if (mode == ROW_R2C || mode == ROW_NR2C) return realb * si + cplxb * so;
+  if (mode == ROW_C2R) return cplxb * si + realb * so;
+  return cplxb * (si + so) + (mode == ROW_JVP ? realb * si : 0.0);
+}
+
+RowJob make_row(expdiag_ctx* h, const void* in, void* out, long nrows,
+                long in_pitch, long out_pitch, double scale, const Ctl* ctl,
+                int phase_req, const void* aux = nullptr, long aux_pitch = 0) {
+  RowJob j{};
+  j.in = in;
+  j.out = out;
+  j.aux = aux;
+  j.nrows = nrows;
+  j.in_pitch = in_pitch;
+  j.out_pitch = out_pitch;
+  j.aux_pitch = aux_pitch;
+  j.scale = scale;
+  j.n1 = h->p.n1;
+  j.n2 = h->p.n2;
+  j.n3 = h->p.n3;
+  j.ctl = ctl;
+  j.phase_req = phase_req;
+  return j;
+}
+
+ColJob make_col(const void* in, void* out, long outer, long inner,
+                double scale, const Ctl* ctl, int phase_req) {
+  ColJob j{};
+  j.in = in;
+  j.out = out;
+  j.outer = outer;
+  j.inner = inner;
+  j.scale = scale;
+  j.ctl = ctl;
+  j.phase_req = phase_req;
+  return j;
+}
+
+PassBArgs passb_args(expdiag_ctx* h) {
+  PassBArgs a{};
+  a.U = h->Uh;
+  a.Nh = h->Nh;
+  a.Nh32 = nullptr;
+  a.u0h = h->u0h;
+  a.E = h->E;
+  a.c1 = h->c1;
+  a.c2 = h->c2;
+  a.gam = h->gam;
+  a.igam = h->igam;
+  a.lam = h->lam;
+  a.partials = h->partials;
+  a.ctl = nullptr;
+  a.hmirror = nullptr;
+  a.hist = nullptr;
+  a.tw = h->tw64;
+  a.Nk = h->Nk;
+  a.nh = h->nh;
+  a.nonlinear = h->nonlinear ? 1 : 0;
+  a.etd2 = h->scheme == EXPDIAG_ETD2 ? 1 : 0;
+  a.nblocks = passb_blocks(h);
+  a.inv_ns = 1.0 / static_cast<double>(h->Ns);
+  return a;
+}
+
+// ------------------------------------------------------ single launches
+template <typename T, int MODE, typename TI, typename TO>
+int launch_row1(expdiag_ctx* h, const RowJob& jb) {
+  const int M = h->n[h->dim - 1] / 2;
+  ProfScope ps(h, P_ROW, row_bytes(M, MODE, jb.nrows, sizeof(TI), sizeof(TO)));
   bool ok = dispatch_pow2<2, 512>(M, [&](auto Mc) {
     constexpr int MM = decltype(Mc)::value;
     using S = RowShape<MM>;
-    const long blocks = (nrows + S::RPB - 1) / S::RPB;
-    hipLaunchKernelGGL((row_kernel<T, MM, MODE, TI, TO>), dim3(blocks),
-                       dim3(S::THREADS), 0, h->stream, in, out, nrows,
-                       in_pitch, out_pitch, static_cast<T>(scale), nc, aux,
-                       aux_pitch, twid_table<T>(h));
+    const long blocks = (jb.nrows + S::RPB - 1) / S::RPB;
+    hipLaunchKernelGGL((row_kernel1<T, MM, MODE, TI, TO>), dim3(blocks),
+                       dim3(S::THREADS), 0, h->stream, jb, twid_table<T>(h));
   });
   if (!ok) return fail(h, EXPDIAG_EUNSUPPORTED, "row length %d", 2 * M);
   HIPCHK(h, hipGetLastError());
@@ -198,29 +335,53 @@ int launch_row(expdiag_ctx* h, const TI* in, TO* out, long nrows,
 }
 
 template <typename T, int S, typename TI, typename TO>
-int launch_col(expdiag_ctx* h, int L, const cx<TI>* in, cx<TO>* out,
-               long outer, long inner, double scale) {
-  const double elems = static_cast<double>(outer) * L * inner;
-  ProfScope ps(h, P_COL, elems * 2 * (sizeof(TI) + sizeof(TO)));
+int launch_col1(expdiag_ctx* h, int L, const ColJob& jb) {
+  ProfScope ps(h, P_COL, static_cast<double>(jb.outer) * L * jb.inner * 2 *
+                             (sizeof(TI) + sizeof(TO)));
   bool ok = dispatch_pow2<4, 1024>(L, [&](auto Lc) {
     constexpr int LL = decltype(Lc)::value;
     using SH = ColShape<LL>;
-    const long tiles = (inner + SH::C - 1) / SH::C;
-    hipLaunchKernelGGL((col_kernel<T, LL, S, TI, TO>), dim3(outer * tiles),
-                       dim3(SH::THREADS), 0, h->stream, in, out, outer,
-                       inner, LL * inner, LL * inner, static_cast<T>(scale),
-                       twid_table<T>(h));
+    const long tiles = (jb.inner + SH::C - 1) / SH::C;
+    hipLaunchKernelGGL((col_kernel1<T, LL, S, TI, TO>),
+                       dim3(jb.outer * tiles), dim3(SH::THREADS), 0,
+                       h->stream, jb, twid_table<T>(h));
   });
   if (!ok) return fail(h, EXPDIAG_EUNSUPPORTED, "column length %d", L);
   HIPCHK(h, hipGetLastError());
   return 0;
 }
 
-#define RCHK(expr)          \
-  do {                      \
-    int r_ = (expr);        \
-    if (r_ != 0) return r_; \
-  } while (0)
+double passb_bytes(const PassBArgs& a, int Nt, int mode, size_t nb) {
+  const double ent = static_cast<double>(Nt) * a.Nk;
+  double bytes = static_cast<double>(a.Nk) * (sizeof(double) * 3 + 16);
+  const double nbytes = a.nonlinear ? static_cast<double>(nb) : 0.0;
+  if (mode == PB_PRECOND) return bytes + ent * 32;
+  return bytes + ent * (32 + nbytes);
+}
+
+template <int MODE, typename TN>
+int launch_passb1(expdiag_ctx* h, const PassBArgs& a) {
+  ProfScope ps(h, P_PASSB, passb_bytes(a, h->Nt, MODE, sizeof(cx<TN>)));
+  bool ok = dispatch_pow2<2, 512>(h->Nt, [&](auto Nc) {
+    constexpr int NN = decltype(Nc)::value;
+    using SH = PassBShape<NN>;
+    const long blocks = (h->Nk + SH::C - 1) / SH::C;
+    hipLaunchKernelGGL((passb_kernel1<NN, MODE, TN>), dim3(blocks),
+                       dim3(SH::THREADS), 0, h->stream, a);
+  });
+  if (!ok) return fail(h, EXPDIAG_EUNSUPPORTED, "Nt %d", h->Nt);
+  HIPCHK(h, hipGetLastError());
+  return 0;
+}
+
+int launch_reduce(expdiag_ctx* h, int nblocks) {
+  ProfScope ps(h, P_RED, static_cast<double>(nblocks) * 32);
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, h->stream,
+                     h->partials, nblocks, 1.0 / static_cast<double>(h->Ns),
+                     h->red_out);
+  HIPCHK(h, hipGetLastError());
+  return 0;
+}
 
 // real physical slices [ns][Ns] -> half spectra [ns][Nk].  ROWMODE is
 // ROW_R2C or ROW_NR2C (apply N pointwise first).  Uses h->T as scratch.
@@ -228,51 +389,54 @@ template <int ROWMODE>
 int fwd_slices(expdiag_ctx* h, const double* src, cx<double>* dst, long ns) {
   const int d = h->dim;
   const long nh2 = 2L * h->nh;
+  const int nl = h->n[d - 1];
   if (d == 1)
-    return launch_row<double, ROWMODE, double, double>(
-        h, src, reinterpret_cast<double*>(dst), ns, h->n[0], nh2, 1.0);
-  double* Tr = reinterpret_cast<double*>(h->T);
-  const long rows = ns * (h->Ns / h->n[d - 1]);
-  RCHK((launch_row<double, ROWMODE, double, double>(h, src, Tr, rows,
-                                                     h->n[d - 1], nh2, 1.0)));
+    return launch_row1<double, ROWMODE, double, double>(
+        h, make_row(h, src, dst, ns, nl, nh2, 1.0, nullptr, -1));
+  const long rows = ns * (h->Ns / nl);
+  RCHK((launch_row1<double, ROWMODE, double, double>(
+      h, make_row(h, src, h->T, rows, nl, nh2, 1.0, nullptr, -1))));
   if (d == 2)
-    return launch_col<double, -1, double, double>(h, h->n[0], h->T, dst, ns,
-                                                  h->nh, 1.0);
-  RCHK((launch_col<double, -1, double, double>(h, h->n[1], h->T, h->T,
-                                               ns * h->n[0], h->nh, 1.0)));
-  return launch_col<double, -1, double, double>(
-      h, h->n[0], h->T, dst, ns, static_cast<long>(h->n[1]) * h->nh, 1.0);
+    return launch_col1<double, -1, double, double>(
+        h, h->n[0], make_col(h->T, dst, ns, h->nh, 1.0, nullptr, -1));
+  RCHK((launch_col1<double, -1, double, double>(
+      h, h->n[1], make_col(h->T, h->T, ns * h->n[0], h->nh, 1.0, nullptr, -1))));
+  return launch_col1<double, -1, double, double>(
+      h, h->n[0],
+      make_col(h->T, dst, ns, static_cast<long>(h->n[1]) * h->nh, 1.0,
+               nullptr, -1));
 }
 
 // half spectra [ns][Nk] -> real physical slices [ns][Ns] (normalised).
 // `src` may be h->T.
-template <typename T>
 int inv_slices(expdiag_ctx* h, const cx<double>* src, double* dst, long ns) {
   const int d = h->dim;
   const long nh2 = 2L * h->nh;
+  const int nl = h->n[d - 1];
   const double sc = 1.0 / static_cast<double>(h->Ns);
   if (d == 1)
-    return launch_row<double, ROW_C2R, double, double>(
-        h, reinterpret_cast<const double*>(src), dst, ns, nh2, h->n[0], sc);
+    return launch_row1<double, ROW_C2R, double, double>(
+        h, make_row(h, src, dst, ns, nh2, nl, sc, nullptr, -1));
   if (d == 2) {
-    RCHK((launch_col<double, 1, double, double>(h, h->n[0], src, h->T, ns,
-                                                h->nh, 1.0)));
+    RCHK((launch_col1<double, 1, double, double>(
+        h, h->n[0], make_col(src, h->T, ns, h->nh, 1.0, nullptr, -1))));
   } else {
-    RCHK((launch_col<double, 1, double, double>(
-        h, h->n[0], src, h->T, ns, static_cast<long>(h->n[1]) * h->nh, 1.0)));
-    RCHK((launch_col<double, 1, double, double>(h, h->n[1], h->T, h->T,
-                                                ns * h->n[0], h->nh, 1.0)));
+    RCHK((launch_col1<double, 1, double, double>(
+        h, h->n[0],
+        make_col(src, h->T, ns, static_cast<long>(h->n[1]) * h->nh, 1.0,
+                 nullptr, -1))));
+    RCHK((launch_col1<double, 1, double, double>(
+        h, h->n[1],
+        make_col(h->T, h->T, ns * h->n[0], h->nh, 1.0, nullptr, -1))));
   }
-  const long rows = ns * (h->Ns / h->n[d - 1]);
-  return launch_row<double, ROW_C2R, double, double>(
-      h, reinterpret_cast<const double*>(h->T), dst, rows, nh2, h->n[d - 1],
-      sc);
+  const long rows = ns * (h->Ns / nl);
+  return launch_row1<double, ROW_C2R, double, double>(
+      h, make_row(h, h->T, dst, rows, nh2, nl, sc, nullptr, -1));
 }
 
 // Storage of N^ in precision T.  The fp64 array fills the allocation; the
-// fp32 array of the mixed bulk phase lives in its second half, so writing
-// the fp32 slot 0 never overlaps the fp64 slot 0 it is narrowed from
-// (Nt >= 2).
+// fp32 array of the mixed bulk phase lives in its second half, so it never
+// overlaps fp64 slot 0 (N^_0 of the initial condition; Nt >= 2).
 template <typename T>
 cx<T>* nh_view(expdiag_ctx* h) {
   if constexpr (std::is_same<T, double>::value) {
@@ -284,118 +448,246 @@ cx<T>* nh_view(expdiag_ctx* h) {
   }
 }
 
-// Pass A: N^_{l} = FFT N(IFFT Uh_{l-1}) for l = 1..Nt-1, in precision T
-// (TN = storage type of N^: double, or float in the mixed bulk phase).
-template <typename T>
-int pass_a(expdiag_ctx* h) {
-  const int d = h->dim;
-  const long ns = h->Nt - 1;
-  const long nh2 = 2L * h->nh;
-  const double sc = 1.0 / static_cast<double>(h->Ns);
-  cx<T>* Tt = reinterpret_cast<cx<T>*>(h->T);
-  cx<T>* Nt_ = nh_view<T>(h) + h->Nk;  // slot 1
-  if (d == 1)
-    return launch_row<T, ROW_FUSED, double, T>(
-        h, reinterpret_cast<const double*>(h->Uh),
-        reinterpret_cast<T*>(Nt_), ns, nh2, nh2, sc);
-  if (d == 2) {
-    RCHK((launch_col<T, 1, double, T>(h, h->n[0], h->Uh, Tt, ns, h->nh,
-                                      1.0)));
-  } else {
-    const long in2 = static_cast<long>(h->n[1]) * h->nh;
-    RCHK((launch_col<T, 1, double, T>(h, h->n[0], h->Uh, Tt, ns, in2, 1.0)));
-    RCHK((launch_col<T, 1, T, T>(h, h->n[1], Tt, Tt, ns * h->n[0], h->nh,
-                                 1.0)));
-  }
-  const long rows = ns * (h->Ns / h->n[d - 1]);
-  RCHK((launch_row<T, ROW_FUSED, T, T>(h, reinterpret_cast<const T*>(Tt),
-                                       reinterpret_cast<T*>(Tt), rows, nh2,
-                                       nh2, sc)));
-  if (d == 2)
-    return launch_col<T, -1, T, T>(h, h->n[0], Tt, Nt_, ns, h->nh, 1.0);
-  RCHK((launch_col<T, -1, T, T>(h, h->n[1], Tt, Tt, ns * h->n[0], h->nh,
-                                1.0)));
-  return launch_col<T, -1, T, T>(h, h->n[0], Tt, Nt_, ns,
-                                 static_cast<long>(h->n[1]) * h->nh, 1.0);
-}
-
-int passb_blocks(expdiag_ctx* h) {
-  int blocks = 0;
-  dispatch_pow2<2, 512>(h->Nt, [&](auto Nc) {
-    constexpr int NN = decltype(Nc)::value;
-    blocks = static_cast<int>((h->Nk + PassBShape<NN>::C - 1) /
-                              PassBShape<NN>::C);
-  });
-  return blocks;
-}
-
-template <int MODE, typename TN>
-int launch_passb(expdiag_ctx* h, PassBArgs a) {
-  const double ent = static_cast<double>(h->Nt) * h->Nk;
-  double bytes = static_cast<double>(h->Nk) * (sizeof(double) * 3 + 16);
-  const double nb = a.nonlinear ? sizeof(cx<TN>) : 0.0;
-  if (MODE == PB_ITERATE)
-    bytes += ent * (16 + 16 + nb);
-  else if (MODE == PB_PRECOND)
-    bytes += ent * (16 + 16);
-  else if (MODE == PB_RESIDUAL)
-    bytes += ent * (16 + 16 + nb);
-  else
-    bytes += ent * (16 + 16 + nb);
-  ProfScope ps(h, P_PASSB, bytes);
-  bool ok = dispatch_pow2<2, 512>(h->Nt, [&](auto Nc) {
-    constexpr int NN = decltype(Nc)::value;
-    using SH = PassBShape<NN>;
-    const long blocks = (h->Nk + SH::C - 1) / SH::C;
-    hipLaunchKernelGGL((passb_kernel<NN, MODE, TN>), dim3(blocks),
-                       dim3(SH::THREADS), 0, h->stream, a);
-  });
-  if (!ok) return fail(h, EXPDIAG_EUNSUPPORTED, "Nt %d", h->Nt);
-  HIPCHK(h, hipGetLastError());
-  return 0;
-}
-
-PassBArgs passb_args(expdiag_ctx* h) {
-  PassBArgs a{};
-  a.U = h->Uh;
-  a.Nh = h->Nh;
-  a.u0h = h->u0h;
-  a.E = h->E;
-  a.c1 = h->c1;
-  a.c2 = h->c2;
-  a.gam = h->gam;
-  a.igam = h->igam;
-  a.lam = h->lam;
-  a.partials = h->partials;
-  a.ctl = nullptr;
-  a.tw = h->tw64;
-  a.Nk = h->Nk;
-  a.nh = h->nh;
-  a.nonlinear = h->nonlinear ? 1 : 0;
-  return a;
-}
-
-int launch_reduce(expdiag_ctx* h, int nblocks, bool update_ctl) {
-  ProfScope ps(h, P_RED, static_cast<double>(nblocks) * 32);
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, h->stream,
-                     h->partials, nblocks, 1.0 / static_cast<double>(h->Ns),
-                     h->red_out, h->ctl, update_ctl ? 1 : 0, h->hist);
-  HIPCHK(h, hipGetLastError());
-  return 0;
-}
-
-// u0 -> u0h and N^_0 = FFT N(u0) (slot 0 of Nh, fp64)
-int prepare_u0(expdiag_ctx* h, const double* u0) {
-  RCHK(fwd_slices<ROW_R2C>(h, u0, h->u0h, 1));
-  if (h->nonlinear) RCHK(fwd_slices<ROW_NR2C>(h, u0, h->Nh, 1));
-  return 0;
-}
-
-// N^_0 in fp32 storage (slot 0 of the float view of Nh) from the fp64 one.
 __global__ void narrow_kernel(const cx<double>* __restrict__ in,
                               cx<float>* __restrict__ out, long n) {
   const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) out[i] = cvt<float>(in[i]);
+}
+
+// u0 -> u0h, N^_0 = FFT N(u0) (fp64 slot 0) and, for mixed precision, its
+// fp32 copy in slot 0 of the fp32 view.
+int prepare_u0(expdiag_ctx* h, const double* u0) {
+  RCHK(fwd_slices<ROW_R2C>(h, u0, h->u0h, 1));
+  if (!h->nonlinear) return 0;
+  RCHK(fwd_slices<ROW_NR2C>(h, u0, h->Nh, 1));
+  if (h->mixed) {
+    hipLaunchKernelGGL(narrow_kernel, dim3((h->Nk + 255) / 256), dim3(256), 0,
+                       h->stream, h->Nh, nh_view<float>(h), h->Nk);
+    HIPCHK(h, hipGetLastError());
+  }
+  return 0;
+}
+
+// ----------------------------------------------------------------- plans
+Group& plan_group(Plan& P, int stage, int kind, int tcode, int len, int mode,
+                  int ti, int to) {
+  for (auto& g : P.groups)
+    if (g.key() == std::make_tuple(stage, kind, tcode, len, mode, ti, to))
+      return g;
+  Group g{};
+  g.stage = stage;
+  g.kind = kind;
+  g.tcode = tcode;
+  g.len = len;
+  g.mode = mode;
+  g.ti = ti;
+  g.to = to;
+  g.start.push_back(0);
+  P.groups.push_back(g);
+  return P.groups.back();
+}
+
+template <typename T, typename TI, typename TO>
+void plan_row(Plan& P, int stage, int M, int mode, const RowJob& j) {
+  Group& g = plan_group(P, stage, K_ROW, tcode_of<T>(), M, mode,
+                        tcode_of<TI>(), tcode_of<TO>());
+  g.rj.push_back(j);
+  g.start.push_back(g.start.back() + row_blocks(M, j.nrows));
+  g.bytes += row_bytes(M, mode, j.nrows, sizeof(TI), sizeof(TO));
+}
+
+template <typename T, int S, typename TI, typename TO>
+void plan_col(Plan& P, int stage, int L, const ColJob& j) {
+  Group& g = plan_group(P, stage, K_COL, tcode_of<T>(), L, S,
+                        tcode_of<TI>(), tcode_of<TO>());
+  g.cj.push_back(j);
+  g.start.push_back(g.start.back() + col_blocks(L, j.outer, j.inner));
+  g.bytes += static_cast<double>(j.outer) * L * j.inner * 2 *
+             (sizeof(TI) + sizeof(TO));
+}
+
+void plan_passb(Plan& P, int stage, int Nt, const PassBArgs& a, size_t nb) {
+  Group& g = plan_group(P, stage, K_PASSB, 0, Nt, PB_ITERATE, 0, 0);
+  g.pj.push_back(a);
+  g.start.push_back(g.start.back() + a.nblocks);
+  g.bytes += passb_bytes(a, Nt, PB_ITERATE, nb);
+}
+
+// pass A of one instance in precision T, gated on phase `ph`
+template <typename T>
+void plan_pass_a(Plan& P, expdiag_ctx* h, const Ctl* ctl, int ph) {
+  const int d = h->dim;
+  const long ns = h->Nt - 1;
+  const long nh2 = 2L * h->nh;
+  const int nl = h->n[d - 1];
+  const double sc = 1.0 / static_cast<double>(h->Ns);
+  cx<T>* Tt = reinterpret_cast<cx<T>*>(h->T);
+  cx<T>* N1 = nh_view<T>(h) + h->Nk;  // slot 1
+  if (d == 1) {
+    plan_row<T, double, T>(P, 2, nl / 2, ROW_FUSED,
+                           make_row(h, h->Uh, N1, ns, nh2, nh2, sc, ctl, ph));
+    return;
+  }
+  const long in2 = d == 3 ? static_cast<long>(h->n[1]) * h->nh : h->nh;
+  plan_col<T, 1, double, T>(P, 0, h->n[0],
+                            make_col(h->Uh, Tt, ns, in2, 1.0, ctl, ph));
+  if (d == 3)
+    plan_col<T, 1, T, T>(P, 1, h->n[1],
+                         make_col(Tt, Tt, ns * h->n[0], h->nh, 1.0, ctl, ph));
+  plan_row<T, T, T>(P, 2, nl / 2, ROW_FUSED,
+                    make_row(h, Tt, Tt, ns * (h->Ns / nl), nh2, nh2, sc, ctl,
+                             ph));
+  if (d == 3)
+    plan_col<T, -1, T, T>(P, 3, h->n[1],
+                          make_col(Tt, Tt, ns * h->n[0], h->nh, 1.0, ctl, ph));
+  plan_col<T, -1, T, T>(P, 4, h->n[0], make_col(Tt, N1, ns, in2, 1.0, ctl, ph));
+}
+
+// All launches of one fixed-point iteration of instance h, with control
+// block `ctl` (device) and host mirror `mirror` (device address).
+void plan_iteration(Plan& P, expdiag_ctx* h, Ctl* ctl, Ctl* mirror,
+                    double* hist) {
+  if (h->nonlinear) {
+    plan_pass_a<double>(P, h, ctl, 1);
+    if (h->mixed) plan_pass_a<float>(P, h, ctl, 0);
+  }
+  PassBArgs a = passb_args(h);
+  a.ctl = ctl;
+  a.hmirror = mirror;
+  a.hist = hist;
+  if (h->nonlinear && h->mixed) a.Nh32 = nh_view<float>(h);
+  plan_passb(P, 5, h->Nt, a, sizeof(cx<double>));
+}
+
+int plan_upload(expdiag_ctx* h, Plan& P) {
+  std::stable_sort(P.groups.begin(), P.groups.end(),
+                   [](const Group& x, const Group& y) {
+                     return x.stage < y.stage;
+                   });
+  for (auto& g : P.groups) {
+    size_t jb = 0;
+    const void* src = nullptr;
+    if (g.kind == K_ROW) {
+      jb = g.rj.size() * sizeof(RowJob);
+      src = g.rj.data();
+    } else if (g.kind == K_COL) {
+      jb = g.cj.size() * sizeof(ColJob);
+      src = g.cj.data();
+    } else {
+      jb = g.pj.size() * sizeof(PassBArgs);
+      src = g.pj.data();
+    }
+    HIPCHK(h, hipMalloc(&g.djobs, jb));
+    HIPCHK(h, hipMalloc(&g.dstart, g.start.size() * sizeof(int)));
+    HIPCHK(h, hipMemcpy(g.djobs, src, jb, hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(g.dstart, g.start.data(), g.start.size() * sizeof(int),
+                        hipMemcpyHostToDevice));
+  }
+  P.uploaded = true;
+  return 0;
+}
+
+void plan_free(Plan& P) {
+  for (auto& g : P.groups) {
+    if (g.djobs != nullptr) (void)hipFree(g.djobs);
+    if (g.dstart != nullptr) (void)hipFree(g.dstart);
+    g.djobs = nullptr;
+    g.dstart = nullptr;
+  }
+  P.groups.clear();
+  P.uploaded = false;
+}
+
+// Launch every group of the plan on `st` in stage order.  `ph` is the handle
+// used for profiling and error text (nullable).
+int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st, const cx<double>* tw64,
+                const cx<float>* tw32) {
+  for (auto& g : P.groups) {
+    const int grid = g.grid();
+    if (grid == 0) continue;
+    const int nj = g.njobs();
+    bool ok = false;
+    if (g.kind == K_ROW) {
+      ProfScope ps(ph, P_ROW, g.bytes);
+      const RowJob* J = static_cast<const RowJob*>(g.djobs);
+      ok = dispatch_pow2<2, 512>(g.len, [&](auto Mc) {
+        constexpr int MM = decltype(Mc)::value;
+        const dim3 th(RowShape<MM>::THREADS);
+        if (g.tcode == 0) {
+          hipLaunchKernelGGL((row_kernel<double, MM, ROW_FUSED, double, double>),
+                             dim3(grid), th, 0, st, J, g.dstart, nj, tw64);
+        } else if (g.ti == 0) {
+          hipLaunchKernelGGL((row_kernel<float, MM, ROW_FUSED, double, float>),
+                             dim3(grid), th, 0, st, J, g.dstart, nj, tw32);
+        } else {
+          hipLaunchKernelGGL((row_kernel<float, MM, ROW_FUSED, float, float>),
+                             dim3(grid), th, 0, st, J, g.dstart, nj, tw32);
+        }
+      });
+    } else if (g.kind == K_COL) {
+      ProfScope ps(ph, P_COL, g.bytes);
+      const ColJob* J = static_cast<const ColJob*>(g.djobs);
+      ok = dispatch_pow2<4, 1024>(g.len, [&](auto Lc) {
+        constexpr int LL = decltype(Lc)::value;
+        const dim3 th(ColShape<LL>::THREADS);
+        if (g.tcode == 0) {
+          if (g.mode == 1)
+            hipLaunchKernelGGL((col_kernel<double, LL, 1, double, double>),
+                               dim3(grid), th, 0, st, J, g.dstart, nj, tw64);
+          else
+            hipLaunchKernelGGL((col_kernel<double, LL, -1, double, double>),
+                               dim3(grid), th, 0, st, J, g.dstart, nj, tw64);
+        } else if (g.ti == 0) {
+          hipLaunchKernelGGL((col_kernel<float, LL, 1, double, float>),
+                             dim3(grid), th, 0, st, J, g.dstart, nj, tw32);
+        } else if (g.mode == 1) {
+          hipLaunchKernelGGL((col_kernel<float, LL, 1, float, float>),
+                             dim3(grid), th, 0, st, J, g.dstart, nj, tw32);
+        } else {
+          hipLaunchKernelGGL((col_kernel<float, LL, -1, float, float>),
+                             dim3(grid), th, 0, st, J, g.dstart, nj, tw32);
+        }
+      });
+    } else {
+      ProfScope ps(ph, P_PASSB, g.bytes);
+      const PassBArgs* J = static_cast<const PassBArgs*>(g.djobs);
+      ok = dispatch_pow2<2, 512>(g.len, [&](auto Nc) {
+        constexpr int NN = decltype(Nc)::value;
+        hipLaunchKernelGGL((passb_kernel<NN, PB_ITERATE, double>), dim3(grid),
+                           dim3(PassBShape<NN>::THREADS), 0, st, J, g.dstart,
+                           nj);
+      });
+    }
+    if (!ok) return fail(ph, EXPDIAG_EUNSUPPORTED, "plan length %d", g.len);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+      return fail(ph, EXPDIAG_EHIP, "plan launch: %s", hipGetErrorString(e));
+  }
+  return 0;
+}
+
+// Capture one iteration of plan P into an executable graph.
+int plan_capture(expdiag_ctx* h, Plan& P, hipStream_t cap,
+                 const cx<double>* tw64, const cx<float>* tw32,
+                 hipGraph_t* graph, hipGraphExec_t* exec) {
+  HIPCHK(h, hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  int rc = plan_launch(nullptr, P, cap, tw64, tw32);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(cap, &g);
+  if (rc != 0) {
+    if (g != nullptr) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess)
+    return fail(h, EXPDIAG_EHIP, "graph capture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(h, EXPDIAG_EHIP, "graph instantiate: %s",
+                hipGetErrorString(e));
+  }
+  *graph = g;
+  return 0;
 }
 
 // ------------------------------------------------------------------ tables
@@ -423,7 +715,6 @@ int build_tables(expdiag_ctx* h) {
   const long double a = h->p.a, c = h->p.c, dt = h->dt;
   long idx = 0;
   const int n0 = h->n[0], n1 = d >= 2 ? h->n[1] : 1;
-  const int nlast = h->n[d - 1];
   auto wn = [](int j, int n) { return j <= n / 2 ? j : j - n; };
   const int outer0 = d >= 2 ? n0 : 1;
   const int outer1 = d >= 3 ? n1 : 1;
@@ -455,7 +746,6 @@ int build_tables(expdiag_ctx* h) {
       }
     }
   }
-  (void)nlast;
   const int Nt = h->Nt;
   std::vector<double> gam(Nt), igam(Nt);
   std::vector<cx<double>> lam(Nt);
@@ -515,10 +805,12 @@ size_t footprint(const Sizes& s, int Nt, bool nonlinear, int restart) {
   if (restart > 0) {
     b += st;                                          // T2
     b += static_cast<size_t>(restart + 1) * st;       // Krylov basis
-    if (nonlinear) b += static_cast<size_t>(Nt) * s.Ns * sizeof(double) * 3 / 2;
+    if (nonlinear)
+      b += static_cast<size_t>(Nt) * s.Ns * (sizeof(double) + sizeof(float));
   }
   b += s.Nk * (sizeof(cx<double>) + 3 * sizeof(double));
   b += TW_N * (sizeof(cx<double>) + sizeof(cx<float>));
+  b += static_cast<size_t>(passb_blocks_nt(Nt, s.Nk)) * 4 * sizeof(double);
   return b;
 }
 
@@ -541,6 +833,9 @@ void release(expdiag_ctx* h) {
   auto fr = [](void* p) {
     if (p != nullptr) (void)hipFree(p);
   };
+  if (h->gexec != nullptr) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph != nullptr) (void)hipGraphDestroy(h->graph);
+  plan_free(h->plan);
   fr(h->Uh);
   fr(h->Nh);
   fr(h->T);
@@ -564,8 +859,10 @@ void release(expdiag_ctx* h) {
   fr(h->kdots);
   fr(h->kpart);
   if (h->h_ctl != nullptr) (void)hipHostFree(h->h_ctl);
+  if (h->h_mirror != nullptr) (void)hipHostFree(h->h_mirror);
   if (h->h_red != nullptr) (void)hipHostFree(h->h_red);
   if (h->h_kdots != nullptr) (void)hipHostFree(h->h_kdots);
+  if (h->cap_stream != nullptr) (void)hipStreamDestroy(h->cap_stream);
   for (auto& e : h->events) {
     (void)hipEventDestroy(e.a);
     (void)hipEventDestroy(e.b);
@@ -573,11 +870,26 @@ void release(expdiag_ctx* h) {
   h->events.clear();
 }
 
-int sync_ctl(expdiag_ctx* h) {
-  HIPCHK(h, hipMemcpyAsync(h->h_ctl, h->ctl, sizeof(Ctl),
-                           hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(h, hipStreamSynchronize(h->stream));
-  return 0;
+// Snapshot of a host-mapped control block written by the device (read
+// after the stream that writes it has been synchronised).
+Ctl read_mirror(const Ctl* p) {
+  Ctl c;
+  std::memcpy(&c, static_cast<const void*>(p), sizeof(Ctl));
+  return c;
+}
+
+Ctl initial_ctl(expdiag_ctx* h, int max_iter, double tol) {
+  Ctl c{};
+  c.done = 0;
+  c.iters = 0;
+  c.max_iter = max_iter;
+  c.phase = (h->mixed && h->nonlinear) ? 0 : 1;
+  c.tol = tol;
+  c.bulk_tol = BULK_TOL;
+  c.last_rel = 0.0;
+  c.arrive = 0;
+  c.nblocks = passb_blocks(h);
+  return c;
 }
 
 }  // namespace
@@ -617,8 +929,9 @@ size_t expdiag_footprint_bytes(const expdiag_grid* g, int Nt, int scheme,
   if (check_grid(g, &s) != 0) return 0;
   if (!is_pow2(Nt) || Nt < 2 || Nt > 512) return 0;
   if (scheme != EXPDIAG_ETD1 && scheme != EXPDIAG_ETD2) return 0;
-  (void)precision;
-  // nonlinearity unknown here: report the nonlinear (larger) footprint
+  if (precision != EXPDIAG_FP64 && precision != EXPDIAG_MIXED) return 0;
+  if (gmres_restart < 0 || gmres_restart > 64) return 0;
+  // the nonlinearity is not known here: report the nonlinear footprint
   return footprint(s, Nt, true, gmres_restart);
 }
 
@@ -635,7 +948,8 @@ int expdiag_create(const expdiag_grid* g, int Nt, double dt, double alpha,
     return fail(nullptr, gc, "grid: dim 1..3, n even, power of two, 4..1024");
   if (Nt < 2) return fail(nullptr, EXPDIAG_EINVAL, "Nt must be >= 2");
   if (!is_pow2(Nt) || Nt > 512)
-    return fail(nullptr, EXPDIAG_EUNSUPPORTED, "Nt must be a power of two <= 512");
+    return fail(nullptr, EXPDIAG_EUNSUPPORTED,
+                "Nt must be a power of two <= 512");
   if (!(dt > 0.0) || !std::isfinite(dt))
     return fail(nullptr, EXPDIAG_EINVAL, "dt must be > 0");
   if (!(alpha > 0.0 && alpha < 1.0))
@@ -647,7 +961,8 @@ int expdiag_create(const expdiag_grid* g, int Nt, double dt, double alpha,
       !std::isfinite(p->n2) || !std::isfinite(p->n3))
     return fail(nullptr, EXPDIAG_EINVAL, "a, c must be finite and >= 0");
   if (p->precision != EXPDIAG_FP64 && p->precision != EXPDIAG_MIXED)
-    return fail(nullptr, EXPDIAG_EINVAL, "unknown precision %d", p->precision);
+    return fail(nullptr, EXPDIAG_EINVAL, "unknown precision %d",
+                p->precision);
   if (p->gmres_restart < 0 || p->gmres_restart > 64)
     return fail(nullptr, EXPDIAG_EINVAL, "gmres_restart must be 0..64");
 
@@ -685,10 +1000,7 @@ int expdiag_create(const expdiag_grid* g, int Nt, double dt, double alpha,
   A(&h->lam, Nt * sizeof(cx<double>));
   A(&h->tw64, TW_N * sizeof(cx<double>));
   A(&h->tw32, TW_N * sizeof(cx<float>));
-  // partial sums: the largest grid of any reducing kernel
   h->max_partials = std::max(passb_blocks(h), 1);
-  h->max_partials = std::max<int>(h->max_partials,
-                                  static_cast<int>(krylov_blocks(Nt * h->Nk)));
   A(&h->partials, static_cast<size_t>(h->max_partials) * 4 * sizeof(double));
   A(&h->red_out, 8 * sizeof(double));
   A(&h->ctl, sizeof(Ctl));
@@ -707,12 +1019,34 @@ int expdiag_create(const expdiag_grid* g, int Nt, double dt, double alpha,
   }
   if (rc == 0) {
     if (hipHostMalloc(&h->h_ctl, sizeof(Ctl)) != hipSuccess ||
+        hipHostMalloc(&h->h_mirror, sizeof(Ctl), hipHostMallocMapped) !=
+            hipSuccess ||
         hipHostMalloc(&h->h_red, 8 * sizeof(double)) != hipSuccess ||
         hipHostMalloc(&h->h_kdots, 3 * (h->restart_cap + 2) *
                                        sizeof(double)) != hipSuccess)
       rc = fail(h, EXPDIAG_ENOMEM, "pinned host allocation");
   }
+  if (rc == 0 &&
+      hipHostGetDevicePointer(reinterpret_cast<void**>(&h->d_mirror),
+                              h->h_mirror, 0) != hipSuccess)
+    rc = fail(h, EXPDIAG_EHIP, "host-mapped control block");
+  if (rc == 0 && hipStreamCreateWithFlags(&h->cap_stream,
+                                          hipStreamNonBlocking) != hipSuccess)
+    rc = fail(h, EXPDIAG_EHIP, "capture stream");
   if (rc == 0) rc = build_tables(h);
+  if (rc == 0) {
+    plan_iteration(h->plan, h, h->ctl, h->d_mirror, h->hist);
+    rc = plan_upload(h, h->plan);
+  }
+  if (rc == 0) {
+    if (plan_capture(h, h->plan, h->cap_stream, h->tw64, h->tw32, &h->graph,
+                     &h->gexec) != 0) {
+      // plain launches of the same plan remain available
+      h->use_graph = false;
+      h->err.clear();
+      (void)hipGetLastError();
+    }
+  }
   if (rc != 0) {
     g_create_err = h->err;
     release(h);
@@ -737,6 +1071,71 @@ int expdiag_set_stream(expdiag_t h, void* hip_stream) {
   return EXPDIAG_OK;
 }
 
+int expdiag_set_graph(expdiag_t h, int on) {
+  if (h == nullptr) return EXPDIAG_EINVAL;
+  h->use_graph = on != 0 && h->gexec != nullptr;
+  return EXPDIAG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// nonlinear pass A outside the iteration plan (residual / GMRES paths)
+int pass_a_now(expdiag_ctx* h) {
+  Plan P;
+  plan_pass_a<double>(P, h, nullptr, -1);
+  std::stable_sort(P.groups.begin(), P.groups.end(),
+                   [](const Group& x, const Group& y) {
+                     return x.stage < y.stage;
+                   });
+  for (auto& g : P.groups) {
+    if (g.kind == K_ROW) {
+      for (auto& j : g.rj)
+        RCHK((launch_row1<double, ROW_FUSED, double, double>(h, j)));
+    } else {
+      for (auto& j : g.cj) {
+        if (g.mode == 1)
+          RCHK((launch_col1<double, 1, double, double>(h, g.len, j)));
+        else
+          RCHK((launch_col1<double, -1, double, double>(h, g.len, j)));
+      }
+    }
+  }
+  return 0;
+}
+
+// run `chunk` iterations of the handle's plan (graph replay or launches)
+int run_iterations(expdiag_ctx* h, int chunk) {
+  for (int i = 0; i < chunk; ++i) {
+    if (h->use_graph && !h->prof) {
+      HIPCHK(h, hipGraphLaunch(h->gexec, h->stream));
+    } else {
+      RCHK(plan_launch(h, h->plan, h->stream, h->tw64, h->tw32));
+    }
+  }
+  return 0;
+}
+
+// Iterations to request next: what the observed contraction predicts to
+// reach the active target (flags make overshoot harmless), at least 1.
+int next_chunk(const Ctl& c, double rel_prev, int it_prev) {
+  const double goal = c.phase == 0 ? c.bulk_tol : c.tol;
+  int next = 8;
+  if (rel_prev > 0.0 && c.last_rel > 0.0 && c.iters > it_prev &&
+      c.last_rel < rel_prev) {
+    const double rho =
+        std::pow(c.last_rel / rel_prev, 1.0 / (c.iters - it_prev));
+    const double need = std::log(goal / c.last_rel) / std::log(rho);
+    next = static_cast<int>(std::ceil(need > 0 ? need : 1.0));
+  }
+  return std::max(1, std::min(next, 64));
+}
+
+}  // namespace
+
+extern "C" {
+
 int expdiag_residual(expdiag_t h, const double* u0, const double* U,
                      double* R, double* rnorm) {
   if (h == nullptr) return EXPDIAG_EINVAL;
@@ -746,12 +1145,12 @@ int expdiag_residual(expdiag_t h, const double* u0, const double* U,
     return fail(h, EXPDIAG_EINVAL, "U and R must be distinct");
   RCHK(prepare_u0(h, u0));
   RCHK(fwd_slices<ROW_R2C>(h, U, h->Uh, h->Nt));
-  if (h->nonlinear) RCHK(pass_a<double>(h));
+  if (h->nonlinear) RCHK(pass_a_now(h));
   PassBArgs a = passb_args(h);
   a.Sout = h->T;
-  RCHK((launch_passb<PB_RESIDUAL, double>(h, a)));
-  RCHK(launch_reduce(h, passb_blocks(h), false));
-  RCHK(inv_slices<double>(h, h->T, R, h->Nt));
+  RCHK((launch_passb1<PB_RESIDUAL, double>(h, a)));
+  RCHK(launch_reduce(h, passb_blocks(h)));
+  RCHK(inv_slices(h, h->T, R, h->Nt));
   if (rnorm != nullptr) {
     HIPCHK(h, hipMemcpyAsync(h->h_red, h->red_out, 4 * sizeof(double),
                              hipMemcpyDeviceToHost, h->stream));
@@ -769,8 +1168,8 @@ int expdiag_precond_apply(expdiag_t h, const double* R, double* S) {
   PassBArgs a = passb_args(h);
   a.Rin = h->T;
   a.Sout = h->T;
-  RCHK((launch_passb<PB_PRECOND, double>(h, a)));
-  RCHK(inv_slices<double>(h, h->T, S, h->Nt));
+  RCHK((launch_passb1<PB_PRECOND, double>(h, a)));
+  RCHK(inv_slices(h, h->T, S, h->Nt));
   return EXPDIAG_OK;
 }
 
@@ -784,82 +1183,33 @@ int expdiag_iterate(expdiag_t h, const double* u0, double* U, int max_iter,
   if (!(tol >= 0.0)) return fail(h, EXPDIAG_EINVAL, "tol must be >= 0");
   RCHK(prepare_u0(h, u0));
   RCHK(fwd_slices<ROW_R2C>(h, U, h->Uh, h->Nt));
-
-  Ctl c0{};
-  c0.max_iter = max_iter;
-  c0.tol = tol;
-  *h->h_ctl = c0;
+  *h->h_ctl = initial_ctl(h, max_iter, tol);
+  *h->h_mirror = *h->h_ctl;
   HIPCHK(h, hipMemcpyAsync(h->ctl, h->h_ctl, sizeof(Ctl),
                            hipMemcpyHostToDevice, h->stream));
-  const int nb = passb_blocks(h);
-  // mixed precision: bulk phase with fp32 pass A until ||S||/||U|| <= 1e-6
-  bool bulk = h->mixed && h->nonlinear;
-  const double bulk_tol = 1e-6;
-  if (bulk) {
-    const long n0 = h->Nk;
-    hipLaunchKernelGGL(narrow_kernel, dim3((n0 + 255) / 256), dim3(256), 0,
-                       h->stream, h->Nh, nh_view<float>(h), n0);
-    HIPCHK(h, hipGetLastError());
-  }
   int enqueued = 0;
-  int chunk = 4;
+  int chunk = std::min(8, max_iter);
   double rel_prev = -1.0;
   int it_prev = 0;
   while (true) {
-    const int todo = std::min(chunk, max_iter - enqueued);
-    for (int i = 0; i < todo; ++i) {
-      PassBArgs a = passb_args(h);
-      a.ctl = h->ctl;
-      if (bulk) {
-        RCHK(pass_a<float>(h));
-        a.Nh = nh_view<float>(h);
-        RCHK((launch_passb<PB_ITERATE, float>(h, a)));
-      } else {
-        if (h->nonlinear) RCHK(pass_a<double>(h));
-        RCHK((launch_passb<PB_ITERATE, double>(h, a)));
-      }
-      RCHK(launch_reduce(h, nb, true));
-    }
-    enqueued += todo;
-    RCHK(sync_ctl(h));
-    const Ctl& c = *h->h_ctl;
-    if (c.done == 2) break;
-    if (bulk && (c.last_rel <= bulk_tol || c.done == 1)) {
-      // switch to the fp64 residual: rebuild N^_0 in fp64 storage
-      bulk = false;
-      RCHK(fwd_slices<ROW_NR2C>(h, u0, h->Nh, 1));
-      if (c.done == 1 && c.iters < max_iter) {
-        // converged in the bulk phase: keep refining in fp64
-        h->h_ctl->done = 0;
-        HIPCHK(h, hipMemcpyAsync(h->ctl, h->h_ctl, sizeof(Ctl),
-                                 hipMemcpyHostToDevice, h->stream));
-      }
-      if (c.iters >= max_iter) break;
-      continue;
-    }
-    if (c.done != 0 || enqueued >= max_iter) break;
-    // next chunk: iterations the observed contraction predicts to reach
-    // the active tolerance (device-side flags make overshoot harmless)
-    const double goal = bulk ? bulk_tol : tol;
-    int next = 8;
-    if (rel_prev > 0.0 && c.last_rel > 0.0 && c.iters > it_prev &&
-        c.last_rel < rel_prev) {
-      const double rho =
-          std::pow(c.last_rel / rel_prev, 1.0 / (c.iters - it_prev));
-      const double need = std::log(goal / c.last_rel) / std::log(rho);
-      next = static_cast<int>(std::ceil(need > 0 ? need : 1.0));
-    }
-    chunk = std::max(1, std::min(next, 64));
+    RCHK(run_iterations(h, chunk));
+    enqueued += chunk;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    const Ctl c = read_mirror(h->h_mirror);
+    if (c.done != 0 || c.iters >= max_iter) break;
+    if (enqueued >= max_iter + 64) break;  // safety: device state stalled
+    chunk = next_chunk(c, rel_prev, it_prev);
     rel_prev = c.last_rel;
     it_prev = c.iters;
   }
-  RCHK(inv_slices<double>(h, h->Uh, U, h->Nt));
-  RCHK(sync_ctl(h));
-  const Ctl& c = *h->h_ctl;
+  RCHK(inv_slices(h, h->Uh, U, h->Nt));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  const Ctl c = read_mirror(h->h_mirror);
   if (iters != nullptr) *iters = c.iters;
   if (rel_update != nullptr) *rel_update = c.last_rel;
   if (c.done == 2) return fail(h, EXPDIAG_EDIVERGED, "non-finite residual");
-  return c.last_rel <= tol ? EXPDIAG_OK : EXPDIAG_NOT_CONVERGED;
+  return (c.phase == 1 && c.last_rel <= tol) ? EXPDIAG_OK
+                                             : EXPDIAG_NOT_CONVERGED;
 }
 
 int expdiag_profile_enable(expdiag_t h, int on) {
@@ -905,3 +1255,4 @@ int expdiag_profile_read(expdiag_t h, double* ms, long* launches,
 }  // extern "C"
 
 #include "gmres.inc"
+#include "batch.inc"

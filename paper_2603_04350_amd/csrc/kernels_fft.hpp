@@ -12,10 +12,54 @@
 // Column kernel: length-L transforms along a strided axis of an array viewed
 // as [outer][L][inner]; a workgroup owns C adjacent `inner` columns so each
 // global access is a contiguous run of C elements.
+//
+// Every launch walks a job table: job j owns blocks [start[j], start[j+1])
+// of the grid, so one launch serves any number of instances of the same
+// transform length (a single solve is a table of one job).  A job carries a
+// pointer to its instance's control block and is skipped when that instance
+// has finished or is not in the precision phase the job belongs to.
 #pragma once
 #include "fft_core.hpp"
 
 namespace expdiag {
+
+// Per-instance control block, device resident (kernels_passb.hpp updates it).
+struct Ctl {
+  int done;      // 0 running, 1 finished (tolerance or max_iter), 2 diverged
+  int iters;     // iterations completed
+  int max_iter;
+  int phase;     // 0: fp32 bulk residual (mixed precision), 1: fp64
+  double tol;       // ||S|| / ||U|| target
+  double bulk_tol;  // switch from phase 0 to 1 below this
+  double last_rel;
+  double last_rnorm;
+  double last_unorm;
+  unsigned int arrive;  // pass B blocks arrived this launch
+  int nblocks;          // pass B blocks per launch of this instance
+};
+
+// True when the job's instance still needs this work.  phase_req < 0: any
+// phase.
+__device__ __forceinline__ bool job_live(const Ctl* c, int phase_req) {
+  if (c == nullptr) return true;
+  if (c->done) return false;
+  return phase_req < 0 || c->phase == phase_req;
+}
+
+// Job index of this block: largest j with start[j] <= blockIdx.x.
+__device__ __forceinline__ int find_job(const int* __restrict__ start,
+                                        int njobs) {
+  int lo = 0, hi = njobs - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
 
 enum RowMode : int {
   ROW_R2C = 0,    // real rows -> half spectrum
@@ -43,18 +87,21 @@ struct RowShape {
   static constexpr int LS = M + 1;  // LDS complex slots per row
 };
 
-struct NonlinCoef {
+struct RowJob {
+  const void* in;   // scalar array of the input type
+  void* out;        // scalar array of the output type
+  const void* aux;  // ROW_JVP: real field u (input type)
+  long nrows, in_pitch, out_pitch, aux_pitch;  // pitches in scalars
+  double scale;
   double n1, n2, n3;
+  const Ctl* ctl;
+  int phase_req;
 };
 
-// in / out are scalar pointers; pitches are in scalars.  For ROW_JVP, `aux`
-// holds the real field u (pitch aux_pitch) at which N' is evaluated.
+// One block of the row transform: rows [lb*RPB, lb*RPB + RPB) of job `jb`.
 template <typename T, int M, int MODE, typename TI, typename TO>
-__global__ void __launch_bounds__(RowShape<M>::THREADS)
-    row_kernel(const TI* __restrict__ in, TO* __restrict__ out, long nrows,
-               long in_pitch, long out_pitch, T scale, NonlinCoef nc,
-               const TI* __restrict__ aux, long aux_pitch,
-               const cx<T>* __restrict__ tw) {
+__device__ __forceinline__ void row_body(const RowJob& jb, long lb,
+                                         const cx<T>* __restrict__ tw) {
   using S = RowShape<M>;
   constexpr int R = S::R;
   constexpr int TPR = S::TPR;
@@ -62,15 +109,18 @@ __global__ void __launch_bounds__(RowShape<M>::THREADS)
   __shared__ cx<T> lds[S::RPB * S::LS];
   const int rl = threadIdx.x / TPR;
   const int t = threadIdx.x % TPR;
-  const long row = static_cast<long>(blockIdx.x) * S::RPB + rl;
-  const bool valid = row < nrows;
+  const long row = lb * S::RPB + rl;
+  const bool valid = row < jb.nrows;
   cx<T>* lrow = lds + rl * S::LS;
-  const T n1 = static_cast<T>(nc.n1), n2 = static_cast<T>(nc.n2),
-          n3 = static_cast<T>(nc.n3);
+  const TI* in = static_cast<const TI*>(jb.in);
+  TO* out = static_cast<TO*>(jb.out);
+  const T n1 = static_cast<T>(jb.n1), n2 = static_cast<T>(jb.n2),
+          n3 = static_cast<T>(jb.n3);
+  const T scale = static_cast<T>(jb.scale);
   cx<T> v[R];
 
   if constexpr (MODE == ROW_R2C || MODE == ROW_NR2C) {
-    const TI* src = in + row * in_pitch;
+    const TI* src = in + row * jb.in_pitch;
 #pragma unroll
     for (int s = 0; s < R; ++s) {
       const int j = t + s * TPR;
@@ -84,7 +134,7 @@ __global__ void __launch_bounds__(RowShape<M>::THREADS)
     }
   } else {
     // load X_0..X_M of the half-spectrum row into LDS
-    const TI* src = in + row * in_pitch;
+    const TI* src = in + row * jb.in_pitch;
 #pragma unroll
     for (int s = 0; s < R; ++s) {
       const int k = t + s * TPR;
@@ -117,7 +167,7 @@ __global__ void __launch_bounds__(RowShape<M>::THREADS)
     // v[s] = z_j = x_{2j} + i x_{2j+1},  j = t + s*TPR
     if constexpr (MODE == ROW_C2R) {
       if (valid) {
-        TO* dst = out + row * out_pitch;
+        TO* dst = out + row * jb.out_pitch;
 #pragma unroll
         for (int s = 0; s < R; ++s) {
           const int j = t + s * TPR;
@@ -132,7 +182,7 @@ __global__ void __launch_bounds__(RowShape<M>::THREADS)
         v[s].y = nonlin(v[s].y, n1, n2, n3);
       }
     } else {  // ROW_JVP
-      const TI* ua = aux + row * aux_pitch;
+      const TI* ua = static_cast<const TI*>(jb.aux) + row * jb.aux_pitch;
 #pragma unroll
       for (int s = 0; s < R; ++s) {
         const int j = t + s * TPR;
@@ -148,7 +198,7 @@ __global__ void __launch_bounds__(RowShape<M>::THREADS)
   // forward: Z = FFT_M(z), then X_k = E_k + W^k O_k
   fft_line<T, M, -1>(v, lrow, 1, t, tw);
   if (!valid) return;
-  TO* dst = out + row * out_pitch;
+  TO* dst = out + row * jb.out_pitch;
   cx<T> x0e, x0o;
 #pragma unroll
   for (int s = 0; s < R; ++s) {
@@ -167,6 +217,24 @@ __global__ void __launch_bounds__(RowShape<M>::THREADS)
   if (t == 0) *reinterpret_cast<cx<TO>*>(dst + 2 * M) = cvt<TO>(x0e - x0o);
 }
 
+template <typename T, int M, int MODE, typename TI, typename TO>
+__global__ void __launch_bounds__(RowShape<M>::THREADS)
+    row_kernel(const RowJob* __restrict__ jobs, const int* __restrict__ start,
+               int njobs, const cx<T>* __restrict__ tw) {
+  const int j = find_job(start, njobs);
+  const RowJob jb = jobs[j];
+  if (!job_live(jb.ctl, jb.phase_req)) return;
+  row_body<T, M, MODE, TI, TO>(jb, blockIdx.x - start[j], tw);
+}
+
+// single job passed by value (per-call boundary transforms)
+template <typename T, int M, int MODE, typename TI, typename TO>
+__global__ void __launch_bounds__(RowShape<M>::THREADS)
+    row_kernel1(RowJob jb, const cx<T>* __restrict__ tw) {
+  if (!job_live(jb.ctl, jb.phase_req)) return;
+  row_body<T, M, MODE, TI, TO>(jb, blockIdx.x, tw);
+}
+
 template <int L>
 struct ColShape {
   static constexpr int R = FftShape<L>::R;
@@ -176,26 +244,34 @@ struct ColShape {
   static constexpr int LS = C + 1;  // padded LDS row (complex slots)
 };
 
+struct ColJob {
+  const void* in;  // cx<TI>
+  void* out;       // cx<TO>
+  long outer, inner;
+  double scale;
+  const Ctl* ctl;
+  int phase_req;
+};
+
 // Length-L transform along the middle axis of [outer][L][inner]; element
-// (o, p, c) at o*ostride + p*inner + c.  out = scale * FFT_S(in).
+// (o, p, c) at (o*L + p)*inner + c.  out = scale * FFT_S(in); in-place safe.
 template <typename T, int L, int S, typename TI, typename TO>
-__global__ void __launch_bounds__(ColShape<L>::THREADS)
-    col_kernel(const cx<TI>* __restrict__ in, cx<TO>* __restrict__ out,
-               long outer, long inner, long in_ostride, long out_ostride,
-               T scale, const cx<T>* __restrict__ tw) {
+__device__ __forceinline__ void col_body(const ColJob& jb, long lb,
+                                         const cx<T>* __restrict__ tw) {
   using SH = ColShape<L>;
   constexpr int R = SH::R;
   constexpr int TPL = SH::TPL;
   constexpr int C = SH::C;
   __shared__ cx<T> lds[L * SH::LS];
+  const long inner = jb.inner;
   const long tiles = (inner + C - 1) / C;
-  const long o = blockIdx.x / tiles;
-  const long tile = blockIdx.x % tiles;
+  const long o = lb / tiles;
+  const long tile = lb % tiles;
   const int c = threadIdx.x % C;
   const int t = threadIdx.x / C;
   const long col = tile * C + c;
-  const bool valid = (col < inner) && (o < outer);
-  const cx<TI>* src = in + o * in_ostride + col;
+  const bool valid = (col < inner) && (o < jb.outer);
+  const cx<TI>* src = static_cast<const cx<TI>*>(jb.in) + o * L * inner + col;
   cx<T> v[R];
 #pragma unroll
   for (int s = 0; s < R; ++s) {
@@ -204,12 +280,30 @@ __global__ void __launch_bounds__(ColShape<L>::THREADS)
   }
   fft_line<T, L, S>(v, lds + c, SH::LS, t, tw);
   if (!valid) return;
-  cx<TO>* dst = out + o * out_ostride + col;
+  cx<TO>* dst = static_cast<cx<TO>*>(jb.out) + o * L * inner + col;
+  const T scale = static_cast<T>(jb.scale);
 #pragma unroll
   for (int s = 0; s < R; ++s) {
     const long p = t + s * TPL;
     dst[p * inner] = cvt<TO>(v[s] * scale);
   }
+}
+
+template <typename T, int L, int S, typename TI, typename TO>
+__global__ void __launch_bounds__(ColShape<L>::THREADS)
+    col_kernel(const ColJob* __restrict__ jobs, const int* __restrict__ start,
+               int njobs, const cx<T>* __restrict__ tw) {
+  const int j = find_job(start, njobs);
+  const ColJob jb = jobs[j];
+  if (!job_live(jb.ctl, jb.phase_req)) return;
+  col_body<T, L, S, TI, TO>(jb, blockIdx.x - start[j], tw);
+}
+
+template <typename T, int L, int S, typename TI, typename TO>
+__global__ void __launch_bounds__(ColShape<L>::THREADS)
+    col_kernel1(ColJob jb, const cx<T>* __restrict__ tw) {
+  if (!job_live(jb.ctl, jb.phase_req)) return;
+  col_body<T, L, S, TI, TO>(jb, blockIdx.x, tw);
 }
 
 }  // namespace expdiag

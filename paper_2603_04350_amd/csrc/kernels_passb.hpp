@@ -15,10 +15,13 @@
 // F^* are folded into the single 1/Nt of step (b).)
 //
 // The time transforms are length-Nt Stockham FFTs held in registers and LDS
-// (fft_core.hpp).  Norm partials use Parseval with the half-spectrum weight
-// (1 for the k_last = 0 and Nyquist planes, 2 otherwise).
+// (fft_core.hpp).  Norms use Parseval with the half-spectrum weight (1 for
+// the k_last = 0 and Nyquist planes, 2 otherwise).  In the iterate mode the
+// last block of an instance to finish (arrival counter in its control block)
+// reduces all block partials in a fixed order, so the result does not depend
+// on scheduling, and advances the instance's convergence state.
 #pragma once
-#include "fft_core.hpp"
+#include "kernels_fft.hpp"
 
 namespace expdiag {
 
@@ -29,20 +32,10 @@ enum PassBMode : int {
   PB_OPAPPLY = 3,   // Sout = Q_alpha^{-1} (Q - G'(U)) v, v in U, J in Nh
 };
 
-struct Ctl {
-  int done;      // 0 running, 1 converged or max_iter, 2 diverged
-  int iters;     // iterations completed
-  int max_iter;
-  int pad;
-  double tol;
-  double last_rel;   // ||S|| / ||U||
-  double last_rnorm; // ||R|| (L2 over space-time, physical scaling)
-  double last_unorm;
-};
-
 struct PassBArgs {
   cx<double>* U;          // [Nt][Nk]
-  const void* Nh;         // [Nt][Nk] of TN, or null (linear)
+  const void* Nh;         // [Nt][Nk] fp64 N^ (or J for PB_OPAPPLY), or null
+  const void* Nh32;       // [Nt][Nk] fp32 N^ of the mixed bulk phase
   const cx<double>* u0h;  // [Nk]
   const double* E;        // [Nk]
   const double* c1;       // [Nk]
@@ -52,12 +45,17 @@ struct PassBArgs {
   const cx<double>* lam;  // [Nt]
   const cx<double>* Rin;  // [Nt][Nk] (PB_PRECOND)
   cx<double>* Sout;       // [Nt][Nk] (PB_PRECOND / PB_RESIDUAL / PB_OPAPPLY)
-  double* partials;       // [gridDim.x][4]
-  const Ctl* ctl;         // skip the launch when ctl->done (may be null)
+  double* partials;       // [nblocks][4]
+  Ctl* ctl;               // iterate mode: convergence state (else null)
+  Ctl* hmirror;           // host-mapped copy of *ctl (nullable)
+  double* hist;           // [max_iter][2] (rel, ||R||) history (nullable)
   const cx<double>* tw;
   long Nk;
   int nh;
   int nonlinear;
+  int etd2;
+  int nblocks;
+  double inv_ns;
 };
 
 template <int NT>
@@ -98,28 +96,73 @@ __device__ __forceinline__ void block_sum(double (&acc)[NV], double* red,
   }
 }
 
+__device__ __forceinline__ void store_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_agent(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Convergence bookkeeping of one fixed-point iteration (thread 0 of the
+// last block).  tot = {||R||^2, ||S||^2, ||U||^2} (Parseval-weighted sums).
+__device__ inline void advance_ctl(const PassBArgs& a, const double* tot) {
+  Ctl* c = a.ctl;
+  const double rn = sqrt(tot[0] * a.inv_ns);
+  const double sn = sqrt(tot[1] * a.inv_ns);
+  const double un = sqrt(tot[2] * a.inv_ns);
+  const double rel = un > 0 ? sn / un : sn;
+  const int it = c->iters + 1;
+  c->iters = it;
+  c->last_rel = rel;
+  c->last_rnorm = rn;
+  c->last_unorm = un;
+  if (a.hist != nullptr && it <= c->max_iter) {
+    a.hist[2 * (it - 1)] = rel;
+    a.hist[2 * (it - 1) + 1] = rn;
+  }
+  int done = 0;
+  if (!(rel == rel) || !(rn == rn) || rel > 1e300) {
+    done = 2;
+  } else if (c->phase == 0) {
+    if (rel <= c->bulk_tol) c->phase = 1;
+    if (it >= c->max_iter) done = 1;
+  } else if (rel <= c->tol || it >= c->max_iter) {
+    done = 1;
+  }
+  c->done = done;
+  c->arrive = 0;
+  if (a.hmirror != nullptr) {
+    volatile Ctl* m = a.hmirror;
+    m->iters = it;
+    m->phase = c->phase;
+    m->last_rel = rel;
+    m->last_rnorm = rn;
+    m->last_unorm = un;
+    m->done = done;
+  }
+}
+
 template <int NT, int MODE, typename TN>
-__global__ void __launch_bounds__(PassBShape<NT>::THREADS)
-    passb_kernel(PassBArgs a) {
+__device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
+                                           const TN* Nh, cx<double>* lds,
+                                           double* red) {
   using SH = PassBShape<NT>;
   constexpr int R = SH::R;
   constexpr int TPL = SH::TPL;
   constexpr int C = SH::C;
   constexpr int LS = SH::LS;
-  __shared__ cx<double> lds[NT * LS];
-  __shared__ double red[((SH::THREADS + 63) / 64) * 4];
-  if (a.ctl != nullptr && a.ctl->done) return;
 
   const int c = threadIdx.x % C;
   const int t = threadIdx.x / C;
-  const long kap = static_cast<long>(blockIdx.x) * C + c;
+  const long kap = lb * C + c;
   const bool valid = kap < a.Nk;
   const long Nk = a.Nk;
   const double E = valid ? a.E[kap] : 0.0;
   const int kl = static_cast<int>(kap % a.nh);
   const double pw = (!valid) ? 0.0 : ((kl == 0 || kl == a.nh - 1) ? 1.0 : 2.0);
 
-  cx<double> u[R];  // current iterate rows (ITERATE) / input rows
+  cx<double> u[R];
   cx<double> v[R];
   double nrm_r = 0.0, nrm_s = 0.0, nrm_u = 0.0;
 
@@ -142,9 +185,10 @@ __global__ void __launch_bounds__(PassBShape<NT>::THREADS)
     __syncthreads();
     const cx<double> first =
         (MODE == PB_OPAPPLY || !valid) ? mk(0.0, 0.0) : a.u0h[kap];
-    const double c1 = (valid && a.nonlinear) ? a.c1[kap] : 0.0;
-    const double c2 = (valid && a.nonlinear) ? a.c2[kap] : 0.0;
-    const TN* Nh = reinterpret_cast<const TN*>(a.Nh);
+    const bool nl_on = valid && a.nonlinear;
+    const double c1 = nl_on ? a.c1[kap] : 0.0;
+    const double c2 = (nl_on && a.etd2) ? a.c2[kap] : 0.0;
+    const cx<TN>* Nc = reinterpret_cast<const cx<TN>*>(Nh);
 #pragma unroll
     for (int s = 0; s < R; ++s) {
       const int l = t + s * TPL;
@@ -154,19 +198,17 @@ __global__ void __launch_bounds__(PassBShape<NT>::THREADS)
         // (Q - G'(U)) v : v_l - E v_{l-1} - (c1 J_l + c2 J_{l-1}), where
         // J_l = FFT[N'(u_{l-1}) v_{l-1}] (J_0 = J_{-1} = 0: u_0 is fixed)
         r = u[s] - prev * E;
-        if (a.nonlinear && valid) {
-          const cx<TN>* J = reinterpret_cast<const cx<TN>*>(Nh);
-          if (l >= 1) r = r - cvt<double>(J[l * Nk + kap]) * c1;
-          if (l >= 2) r = r - cvt<double>(J[(l - 1) * Nk + kap]) * c2;
+        if (nl_on) {
+          if (l >= 1) r = r - cvt<double>(Nc[l * Nk + kap]) * c1;
+          if (a.etd2 && l >= 2)
+            r = r - cvt<double>(Nc[(l - 1) * Nk + kap]) * c2;
         }
       } else {
         r = prev * E - u[s];
-        if (a.nonlinear && valid) {
-          const cx<double> nl =
-              cvt<double>(reinterpret_cast<const cx<TN>*>(Nh)[l * Nk + kap]);
-          const cx<double> nlp = cvt<double>(reinterpret_cast<const cx<TN>*>(
-              Nh)[(l == 0 ? 0 : l - 1) * Nk + kap]);
-          r = r + nl * c1 + nlp * c2;
+        if (nl_on) {
+          r = r + cvt<double>(Nc[l * Nk + kap]) * c1;
+          if (a.etd2)
+            r = r + cvt<double>(Nc[(l == 0 ? 0 : l - 1) * Nk + kap]) * c2;
         }
       }
       nrm_r += pw * norm2(r);
@@ -181,7 +223,7 @@ __global__ void __launch_bounds__(PassBShape<NT>::THREADS)
         }
       }
       double acc[4] = {nrm_r, 0.0, 0.0, 0.0};
-      block_sum<4, SH::THREADS>(acc, red, a.partials + blockIdx.x * 4);
+      block_sum<4, SH::THREADS>(acc, red, a.partials + lb * 4);
       return;
     }
     __syncthreads();
@@ -222,17 +264,77 @@ __global__ void __launch_bounds__(PassBShape<NT>::THREADS)
     }
   }
   double acc[4] = {nrm_r, nrm_s, nrm_u, 0.0};
-  block_sum<4, SH::THREADS>(acc, red, a.partials + blockIdx.x * 4);
+  double tot[4];
+  block_sum<4, SH::THREADS>(acc, red, tot);
+  if constexpr (MODE != PB_ITERATE) {
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a.partials[lb * 4 + j] = tot[j];
+    }
+    return;
+  } else {
+    // publish this block's partials; the last block of the instance
+    // reduces them in block order and advances the control block
+    __shared__ int s_last;
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) store_agent(a.partials + lb * 4 + j, tot[j]);
+      __threadfence();
+      const unsigned prev = atomicAdd(&a.ctl->arrive, 1u);
+      s_last = (prev == static_cast<unsigned>(a.nblocks - 1)) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    double fin[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < a.nblocks; b += SH::THREADS) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) fin[j] += load_agent(a.partials + b * 4 + j);
+    }
+    double all[4];
+    block_sum<4, SH::THREADS>(fin, red, all);
+    if (threadIdx.x == 0) advance_ctl(a, all);
+  }
 }
 
-// Deterministic final reduction of per-block partials (fixed order), and the
-// convergence bookkeeping of the fixed point.  One block of 256 threads.
-// out[j] = sum_b partials[b][j] / Ns  (Parseval: physical squared norms).
+template <int NT, int MODE, typename TN>
+__global__ void __launch_bounds__(PassBShape<NT>::THREADS)
+    passb_kernel(const PassBArgs* __restrict__ jobs,
+                 const int* __restrict__ start, int njobs) {
+  using SH = PassBShape<NT>;
+  __shared__ cx<double> lds[NT * SH::LS];
+  __shared__ double red[((SH::THREADS + 63) / 64) * 4];
+  const int j = find_job(start, njobs);
+  const PassBArgs& a = jobs[j];
+  const long lb = blockIdx.x - start[j];
+  if constexpr (MODE == PB_ITERATE) {
+    if (a.ctl->done) return;
+    if (a.Nh32 != nullptr && a.ctl->phase == 0)
+      passb_body<NT, MODE, float>(a, lb, static_cast<const float*>(a.Nh32),
+                                  lds, red);
+    else
+      passb_body<NT, MODE, double>(a, lb, static_cast<const double*>(a.Nh),
+                                   lds, red);
+  } else {
+    passb_body<NT, MODE, TN>(a, lb, static_cast<const TN*>(a.Nh), lds, red);
+  }
+}
+
+template <int NT, int MODE, typename TN>
+__global__ void __launch_bounds__(PassBShape<NT>::THREADS)
+    passb_kernel1(PassBArgs a) {
+  using SH = PassBShape<NT>;
+  __shared__ cx<double> lds[NT * SH::LS];
+  __shared__ double red[((SH::THREADS + 63) / 64) * 4];
+  passb_body<NT, MODE, TN>(a, blockIdx.x, static_cast<const TN*>(a.Nh), lds,
+                           red);
+}
+
+// Fixed-order final reduction of per-block partials for the non-iterate
+// modes: out[j] = inv_ns * sum_b partials[b][j].  One block of 256 threads.
 __global__ void __launch_bounds__(256)
     reduce_kernel(const double* __restrict__ partials, int nblocks,
-                  double inv_ns, double* __restrict__ out, Ctl* ctl,
-                  int update_ctl, double* hist) {
-  if (update_ctl && ctl->done) return;
+                  double inv_ns, double* __restrict__ out) {
   __shared__ double red[4 * 4];
   double acc[4] = {0, 0, 0, 0};
   for (int b = threadIdx.x; b < nblocks; b += 256) {
@@ -243,25 +345,6 @@ __global__ void __launch_bounds__(256)
   block_sum<4, 256>(acc, red, tot);
   if (threadIdx.x != 0) return;
   for (int j = 0; j < 4; ++j) out[j] = tot[j] * inv_ns;
-  if (!update_ctl) return;
-  const double rn = sqrt(tot[0] * inv_ns);
-  const double sn = sqrt(tot[1] * inv_ns);
-  const double un = sqrt(tot[2] * inv_ns);
-  const double rel = un > 0 ? sn / un : sn;
-  const int it = ctl->iters + 1;
-  ctl->iters = it;
-  ctl->last_rel = rel;
-  ctl->last_rnorm = rn;
-  ctl->last_unorm = un;
-  if (hist != nullptr && it <= ctl->max_iter) {
-    hist[2 * (it - 1)] = rel;
-    hist[2 * (it - 1) + 1] = rn;
-  }
-  if (!(rel == rel) || !(rn == rn) || rel > 1e300) {
-    ctl->done = 2;
-  } else if (rel <= ctl->tol || it >= ctl->max_iter) {
-    ctl->done = 1;
-  }
 }
 
 }  // namespace expdiag

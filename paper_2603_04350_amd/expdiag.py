@@ -31,6 +31,10 @@ EXPORTED = (
     "expdiag_footprint_bytes", "expdiag_residual", "expdiag_precond_apply",
     "expdiag_iterate", "expdiag_gmres", "expdiag_profile_enable",
     "expdiag_profile_read", "expdiag_strerror", "expdiag_last_error",
+    "expdiag_set_graph", "expdiag_batch_create", "expdiag_batch_destroy",
+    "expdiag_batch_iterate", "expdiag_batch_last_error",
+    "expdiag_server_create", "expdiag_server_submit", "expdiag_server_poll",
+    "expdiag_server_stats", "expdiag_server_destroy",
 )
 
 
@@ -43,6 +47,13 @@ class Problem(ctypes.Structure):
                 ("n1", ctypes.c_double), ("n2", ctypes.c_double),
                 ("n3", ctypes.c_double), ("precision", ctypes.c_int),
                 ("gmres_restart", ctypes.c_int)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_longlong), ("status", ctypes.c_int),
+                ("iters", ctypes.c_int), ("rel_update", ctypes.c_double),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
 
 
 class ExpdiagError(RuntimeError):
@@ -85,6 +96,28 @@ def load(path: str = LIB_PATH):
     L.expdiag_profile_read.argtypes = [vp, ctypes.POINTER(cd),
                                        ctypes.POINTER(ctypes.c_long),
                                        ctypes.POINTER(cd), ci]
+    L.expdiag_set_graph.argtypes = [vp, ci]
+    pp = ctypes.POINTER(vp)
+    L.expdiag_batch_create.argtypes = [pp, ci, vp, pp]
+    L.expdiag_batch_destroy.argtypes = [vp]
+    L.expdiag_batch_iterate.argtypes = [vp, pp, pp, ci, cd,
+                                        ctypes.POINTER(ci),
+                                        ctypes.POINTER(cd),
+                                        ctypes.POINTER(ci)]
+    L.expdiag_batch_last_error.argtypes = [vp]
+    L.expdiag_batch_last_error.restype = ctypes.c_char_p
+    L.expdiag_server_create.argtypes = [sz, ci, vp, pp]
+    L.expdiag_server_submit.argtypes = [vp, ctypes.POINTER(Grid), ci, cd, cd,
+                                        ci, ctypes.POINTER(Problem), vp, vp,
+                                        ci, cd,
+                                        ctypes.POINTER(ctypes.c_longlong)]
+    L.expdiag_server_poll.argtypes = [vp, ctypes.POINTER(Result), ci,
+                                      ctypes.POINTER(ci), ctypes.POINTER(ci)]
+    L.expdiag_server_stats.argtypes = [vp, ctypes.POINTER(sz),
+                                       ctypes.POINTER(ci),
+                                       ctypes.POINTER(ci),
+                                       ctypes.POINTER(cd)]
+    L.expdiag_server_destroy.argtypes = [vp]
     L.expdiag_strerror.argtypes = [ci]
     L.expdiag_strerror.restype = ctypes.c_char_p
     L.expdiag_last_error.argtypes = [vp]
@@ -272,3 +305,112 @@ class Solver:
 
     def gmres(self, u0, U, restart=20, max_iter=400, tol=1e-10):
         return expdiag_gmres(self.h, u0, U, restart, max_iter, tol)
+
+
+def expdiag_set_graph(h, on=True):
+    return _check(load().expdiag_set_graph(h, 1 if on else 0), h)
+
+
+# -- batching -----------------------------------------------------------------
+def expdiag_batch_create(handles, stream=None):
+    L = load()
+    arr = (ctypes.c_void_p * len(handles))(*[h.value for h in handles])
+    b = ctypes.c_void_p()
+    rc = L.expdiag_batch_create(arr, len(handles), _stream(stream),
+                                ctypes.byref(b))
+    _check(rc)
+    return b
+
+
+def expdiag_batch_destroy(b):
+    return load().expdiag_batch_destroy(b)
+
+
+def expdiag_batch_iterate(b, u0s, Us, max_iter, tol):
+    """Returns (rc, iters[], rel_update[], status[])."""
+    L = load()
+    n = len(u0s)
+    if len(Us) != n:
+        raise ValueError("u0s and Us differ in length")
+    pu = (ctypes.c_void_p * n)(*[_ptr(t, name="u0").value for t in u0s])
+    pU = (ctypes.c_void_p * n)(*[_ptr(t, name="U").value for t in Us])
+    it = (ctypes.c_int * n)()
+    rel = (ctypes.c_double * n)()
+    st = (ctypes.c_int * n)()
+    rc = L.expdiag_batch_iterate(b, pu, pU, int(max_iter), float(tol), it,
+                                 rel, st)
+    if rc < 0 and rc != EXPDIAG_EDIVERGED:
+        raise ExpdiagError(rc, f"{strerror(rc)}: "
+                           f"{L.expdiag_batch_last_error(b).decode()}")
+    return rc, list(it), list(rel), list(st)
+
+
+class Batch:
+    """Owns a batch over existing Solvers (which stay owned by the caller)."""
+
+    def __init__(self, solvers, stream=None):
+        self.solvers = list(solvers)
+        self.b = expdiag_batch_create([s.h for s in self.solvers], stream)
+
+    def iterate(self, u0s, Us, max_iter=400, tol=1e-11):
+        return expdiag_batch_iterate(self.b, u0s, Us, max_iter, tol)
+
+    def close(self):
+        if self.b is not None:
+            expdiag_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# -- serving ------------------------------------------------------------------
+def expdiag_server_create(hbm_budget, max_active, stream=None):
+    s = ctypes.c_void_p()
+    _check(load().expdiag_server_create(int(hbm_budget), int(max_active),
+                                        _stream(stream), ctypes.byref(s)))
+    return s
+
+
+def expdiag_server_submit(s, shape, Nt, dt, alpha, scheme, problem, u0, U,
+                          max_iter, tol):
+    rid = ctypes.c_longlong(0)
+    g = make_grid(shape)
+    rc = load().expdiag_server_submit(s, ctypes.byref(g), int(Nt), float(dt),
+                                      float(alpha), int(scheme),
+                                      ctypes.byref(problem),
+                                      _ptr(u0, name="u0"), _ptr(U, name="U"),
+                                      int(max_iter), float(tol),
+                                      ctypes.byref(rid))
+    _check(rc)
+    return rid.value
+
+
+def expdiag_server_poll(s, cap=256):
+    out = (Result * cap)()
+    n = ctypes.c_int(0)
+    pending = ctypes.c_int(0)
+    _check(load().expdiag_server_poll(s, out, cap, ctypes.byref(n),
+                                      ctypes.byref(pending)))
+    res = [dict(id=r.id, status=r.status, iters=r.iters,
+                rel_update=r.rel_update, t_submit=r.t_submit,
+                t_admit=r.t_admit, t_done=r.t_done) for r in out[:n.value]]
+    return res, pending.value
+
+
+def expdiag_server_stats(s):
+    b = ctypes.c_size_t(0)
+    a = ctypes.c_int(0)
+    p = ctypes.c_int(0)
+    busy = ctypes.c_double(0.0)
+    _check(load().expdiag_server_stats(s, ctypes.byref(b), ctypes.byref(a),
+                                       ctypes.byref(p), ctypes.byref(busy)))
+    return dict(bytes_in_use=b.value, active=a.value, pending=p.value,
+                busy_s=busy.value)
+
+
+def expdiag_server_destroy(s):
+    return load().expdiag_server_destroy(s)

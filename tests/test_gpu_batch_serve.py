@@ -1,0 +1,151 @@
+"""Batched solves and the continuous-batching server vs solo solves and the
+oracle, through the C ABI.
+
+Inside a batch an instance runs the same kernels on the same data with its
+own reduction order, so its result must equal its solo result bit for bit;
+against the oracle the usual bars apply (1e-12 fp64, 1e-10 mixed).
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(
+        "cuda:0")
+
+
+def _zeros(inst):
+    import torch
+    return torch.zeros((inst.Nt,) + inst.shape, dtype=torch.float64,
+                       device="cuda:0")
+
+
+def _mix(count, seed=3):
+    insts = W.batch(count, seed=seed, ns=(16, 32, 64), nts=(8, 16, 32),
+                    precision=1)
+    # half fp64, a 1D heat and a 3D Allen-Cahn instance in the mix too
+    for i, inst in enumerate(insts):
+        inst.precision = i % 2
+    rng = np.random.default_rng(seed)
+    insts.append(W.Instance("heat1d", 1, 64, 16, 1.0, 1e-2, a=1.0,
+                            u0=rng.uniform(-1, 1, 64)))
+    insts.append(W.Instance("ac3d", 3, 16, 8, 1.0, 1e-3, a=0.0025, n1=1.0,
+                            n3=-1.0, precision=1,
+                            u0=rng.uniform(-0.9, 0.9, (16, 16, 16))))
+    return insts
+
+
+def test_graph_replay_equals_plain_launches():
+    from paper_2603_04350_amd import Solver
+    from paper_2603_04350_amd import expdiag as X
+    inst = W.scaled(W.allen_cahn2d(precision=1), n=32, Nt=16)
+    outs = []
+    with Solver.from_instance(inst) as s:
+        for graph in (True, False, True):
+            X.expdiag_set_graph(s.h, graph)
+            U = _zeros(inst)
+            rc, it, rel = s.iterate(_dev(inst.u0), U, max_iter=200,
+                                    tol=1e-12)
+            outs.append((it, U.cpu().numpy()))
+    for it, U in outs[1:]:
+        assert it == outs[0][0]
+        assert np.array_equal(U, outs[0][1])
+
+
+def test_batch_equals_solo_and_oracle():
+    from paper_2603_04350_amd import Batch, Solver
+    insts = _mix(12)
+    solvers = [Solver.from_instance(i) for i in insts]
+    solo = []
+    for s, inst in zip(solvers, insts):
+        U = _zeros(inst)
+        rc, it, rel = s.iterate(_dev(inst.u0), U, max_iter=300, tol=1e-12)
+        solo.append((it, U.cpu().numpy()))
+    b = Batch(solvers)
+    u0s = [_dev(i.u0) for i in insts]
+    Us = [_zeros(i) for i in insts]
+    rc, its, rels, sts = b.iterate(u0s, Us, max_iter=300, tol=1e-12)
+    b.close()
+    for k, inst in enumerate(insts):
+        got = Us[k].cpu().numpy()
+        assert its[k] == solo[k][0], (k, its[k], solo[k][0])
+        assert np.array_equal(got, solo[k][1]), k
+        st = O.Setup.from_instance(inst)
+        ref = O.sequential(st, inst.u0)
+        bar = 1e-10 if (inst.precision == 1 and inst.nonlinear) else 1e-12
+        assert O.rel_err(got, ref) < bar, (k, inst.name)
+    for s in solvers:
+        s.close()
+
+
+def test_batch_reused_twice():
+    from paper_2603_04350_amd import Batch, Solver
+    insts = _mix(4, seed=5)
+    solvers = [Solver.from_instance(i) for i in insts]
+    b = Batch(solvers)
+    res = []
+    for _ in range(2):
+        Us = [_zeros(i) for i in insts]
+        b.iterate([_dev(i.u0) for i in insts], Us, max_iter=300, tol=1e-12)
+        res.append([u.cpu().numpy() for u in Us])
+    b.close()
+    for a, c in zip(res[0], res[1]):
+        assert np.array_equal(a, c)
+
+
+def test_server_continuous_batching():
+    """Requests arrive while others run; every result equals its solo
+    result, admission keeps the footprint within budget, timestamps are
+    ordered."""
+    import torch
+    from paper_2603_04350_amd import Solver
+    from paper_2603_04350_amd import expdiag as X
+    insts = _mix(14, seed=11)
+    solo = []
+    for inst in insts:
+        with Solver.from_instance(inst) as s:
+            U = _zeros(inst)
+            s.iterate(_dev(inst.u0), U, max_iter=300, tol=1e-12)
+            solo.append(U.cpu().numpy())
+    fps = [X.expdiag_footprint_bytes(i.shape, i.Nt, i.scheme, i.precision)
+           for i in insts]
+    budget = int(3.5 * max(fps))
+    srv = X.expdiag_server_create(budget, 8)
+    u0s = [_dev(i.u0) for i in insts]
+    Us = [_zeros(i) for i in insts]
+    torch.cuda.synchronize()
+    ids = {}
+    peak = 0
+    rng = np.random.default_rng(0)
+    for k, inst in enumerate(insts):
+        prob = X.make_problem(inst.a, inst.c, inst.n1, inst.n2, inst.n3,
+                              inst.precision)
+        rid = X.expdiag_server_submit(srv, inst.shape, inst.Nt, inst.dt,
+                                      inst.alpha, inst.scheme, prob, u0s[k],
+                                      Us[k], 300, 1e-12)
+        ids[rid] = k
+        time.sleep(float(rng.exponential(0.002)))
+        peak = max(peak, X.expdiag_server_stats(srv)["bytes_in_use"])
+    done = []
+    t_end = time.time() + 60
+    while len(done) < len(insts) and time.time() < t_end:
+        res, pending = X.expdiag_server_poll(srv)
+        done.extend(res)
+        peak = max(peak, X.expdiag_server_stats(srv)["bytes_in_use"])
+        time.sleep(0.001)
+    X.expdiag_server_destroy(srv)
+    assert len(done) == len(insts)
+    assert peak <= budget
+    for r in done:
+        k = ids[r["id"]]
+        assert r["status"] == 0, r
+        assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
+        assert np.array_equal(Us[k].cpu().numpy(), solo[k]), k
