@@ -1,20 +1,32 @@
 #!/usr/bin/env python3
 """Exp-ParaDiag benchmark on one MI355X.
 
-Workload: 2D Allen-Cahn u_t = eps^2 Lap u + u - u^3, eps = 0.05, periodic
-[0,2pi)^2 on 256^2 points, Nt = 64 steps over T = 2, ETD1, alpha = 1e-3,
-u0 ~ U[-0.9, 0.9] i.i.d. (seed 0), synthetic.
+Headline workload: 2D Allen-Cahn u_t = eps^2 Lap u + u - u^3, eps = 0.05,
+periodic [0,2pi)^2 on 256^2 points, Nt = 64 steps over T = 2, ETD1,
+alpha = 1e-3, u0 ~ U[-0.9, 0.9] i.i.d. (seed 0), synthetic.
 
 One step = one complete Exp-ParaDiag solve from U = 0 to the run-time
 tolerance ||S||/||U|| <= 1e-11 (which lands within 1e-10 of sequential
-stepping), inputs already resident in HBM: boundary FFTs, every fixed-point
-iteration (pass A: spatial FFTs + nonlinearity; pass B: residual, alpha-scaled
-time transform, shifted solves, inverse transform, update; reduction).
+stepping), inputs already resident in HBM: boundary FFTs and every
+fixed-point iteration (pass A: spatial FFTs + nonlinearity; pass B:
+residual, alpha-scaled time transform, shifted solves, inverse transform,
+update, norms), replayed as a captured hipGraph.
 
 value = space-time DOF-iterations per second of the plain FP64 solve
-(S = 256^2 * 64 DOF times iterations, over wall time).  The mixed-precision
-solve (fp32 bulk phase, fp64 refinement) is timed the same way beside it and
-reported with its time-to-tolerance against the FP64 path.
+(S = 256^2 * 64 DOF times iterations, over wall time).  Beside it:
+  * the mixed-precision solve (fp32 bulk residual, fp64 refinement) timed
+    the same way, with its time-to-tolerance against the FP64 path;
+  * per-kernel durations from HIP events recorded on the library's stream
+    around every launch during a second timed region of the same solves
+    (plain launches, so each kernel can be bracketed), and the roofline of
+    the dominant kernel from its algorithmic bytes per launch;
+  * batched: 256 heterogeneous Allen-Cahn instances (n in {64,128,256},
+    Nt in {16..128}, eps ~ U[0.02,0.1], alpha in {1e-2,1e-3}) solved in one
+    batched plan in mixed precision, against the same instances solved one
+    after another by the plain FP64 single-instance path;
+  * served: Poisson arrivals of batch-shaped 2D requests mixed with 3D
+    128^3 x 32 heat / Allen-Cahn requests into the continuous-batching
+    server; p50/p99 latency and solves/s per arrival rate.
 """
 import argparse
 import hashlib
@@ -30,10 +42,15 @@ HBM_PEAK_GBS = 8000.0
 TOL = 1e-11
 
 
+DEVICE_SOURCES = ("cx.hpp", "fft_core.hpp", "kernels_fft.hpp",
+                  "kernels_passb.hpp", "kernels_krylov.hpp")
+
+
 def _src_hash():
+    """Hash of the device-code sources (what the counters depend on)."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2603_04350_amd", "csrc")
-    for name in sorted(os.listdir(d)):
+    for name in DEVICE_SOURCES:
         with open(os.path.join(d, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
@@ -55,68 +72,189 @@ def _traffic(kernel, src_hash):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def run_gpu(args):
-    import numpy as np
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def bench_single(inst, prec, steps, warmup):
     import torch
-
-    import workloads as W
     from paper_2603_04350_amd import expdiag as X
-
     dev = "cuda:0"
-    inst = W.allen_cahn2d()
-    S_dof = inst.dof
     u0 = torch.from_numpy(inst.u0).to(dev)
     U = torch.zeros((inst.Nt,) + inst.shape, dtype=torch.float64, device=dev)
-    out = {}
-    for mode, prec in (("fp64", X.EXPDIAG_FP64), ("mixed", X.EXPDIAG_MIXED)):
-        s = X.Solver.from_instance(inst, precision=prec)
+    s = X.Solver.from_instance(inst, precision=prec)
 
-        def step():
-            U.zero_()
-            rc, it, rel = s.iterate(u0, U, max_iter=400, tol=TOL)
-            return it, rel
+    def step():
+        U.zero_()
+        return s.iterate(u0, U, max_iter=400, tol=TOL)
 
-        for _ in range(args.warmup):
-            step()
-        X.expdiag_profile_enable(s.h, True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        iters = []
-        for _ in range(args.steps):
-            it, rel = step()
-            iters.append(it)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        ms, cnt, by = X.expdiag_profile_read(s.h)
-        X.expdiag_profile_enable(s.h, False)
-        wall = t1 - t0
-        total_iters = sum(iters)
-        out[mode] = {
-            "ms_per_solve": 1e3 * wall / args.steps,
-            "iters": iters[-1],
-            "rel_update": rel,
-            "dof_iters_per_s": S_dof * total_iters / wall,
-            "us_per_iter": 1e6 * wall / total_iters,
-            "kernels": {
-                X.PROFILE_CLASSES[i]: {
-                    "launches": cnt[i], "ms_total": ms[i],
-                    "avg_us": 1e3 * ms[i] / cnt[i] if cnt[i] else 0.0,
-                    "bytes_per_launch": by[i] / cnt[i] if cnt[i] else 0.0,
-                    "GBps": (by[i] / (ms[i] * 1e-3) / 1e9) if ms[i] else 0.0,
-                } for i in range(len(ms))
-            },
-            "U": U.cpu().numpy().copy(),
-        }
+    for _ in range(warmup):
+        step()
+    # timed region 1: graph replay, no instrumentation -> value
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    for _ in range(steps):
+        rc, it, rel = step()
+        iters += it
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = {
+        "ms_per_solve": 1e3 * wall / steps,
+        "iters": it,
+        "rel_update": rel,
+        "dof_iters_per_s": inst.dof * iters / wall,
+        "us_per_iter": 1e6 * wall / iters,
+        "U": U.cpu().numpy().copy(),
+    }
+    # which kernel class dominates: one pass with events around every launch
+    X.expdiag_profile_enable(s.h, 0x1F)
+    for _ in range(2):
+        step()
+    ms, cnt, by, tm = X.expdiag_profile_read(s.h)
+    dom = max(range(len(ms)), key=lambda i: ms[i])
+    # timed region 2: the same solves with HIP events around every launch of
+    # the dominant class only (on the library's stream)
+    X.expdiag_profile_enable(s.h, 1 << dom)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall2 = time.perf_counter() - t0
+    ms2, cnt2, by2, tm2 = X.expdiag_profile_read(s.h)
+    X.expdiag_profile_enable(s.h, 0)
+    out["ms_per_solve_instrumented"] = 1e3 * wall2 / steps
+    out["dominant"] = X.PROFILE_CLASSES[dom]
+    out["kernels"] = {}
+    for i in range(len(ms)):
+        d = {"launches_per_solve": cnt[i] / 2,
+             "bytes_per_launch": by[i] / cnt[i] if cnt[i] else 0.0,
+             "avg_us_all_classes_timed": 1e3 * ms[i] / tm[i] if tm[i] else 0.0}
+        if i == dom:
+            d["avg_us"] = 1e3 * ms2[i] / tm2[i]
+            d["timed_launches"] = tm2[i]
+            d["GBps"] = d["bytes_per_launch"] / (d["avg_us"] * 1e-6) / 1e9
+        out["kernels"][X.PROFILE_CLASSES[i]] = d
+    s.close()
+    return out
+
+
+def bench_batched(count):
+    import torch
+    import workloads as W
+    from paper_2603_04350_amd import expdiag as X
+    dev = "cuda:0"
+    insts = W.batch(count, seed=0, precision=1)
+    u0s = [torch.from_numpy(i.u0).to(dev) for i in insts]
+    Us = [torch.zeros((i.Nt,) + i.shape, dtype=torch.float64, device=dev)
+          for i in insts]
+    t0 = time.perf_counter()
+    solvers = [X.Solver.from_instance(i, precision=1) for i in insts]
+    b = X.Batch(solvers)
+    setup_s = time.perf_counter() - t0
+    b.iterate(u0s, Us, max_iter=400, tol=TOL)  # warmup
+    for u in Us:
+        u.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, its, rels, sts = b.iterate(u0s, Us, max_iter=400, tol=TOL)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    dof_iters = sum(i.dof * k for i, k in zip(insts, its))
+    b.close()
+    for s in solvers:
         s.close()
-    return inst, out
+    # the same instances one after another on the plain FP64 path
+    solos = [X.Solver.from_instance(i, precision=0) for i in insts]
+    V = [torch.zeros_like(u) for u in Us]
+    for s, i, u0, v in zip(solos[:4], insts[:4], u0s[:4], V[:4]):
+        s.iterate(u0, v, max_iter=400, tol=TOL)  # warmup
+    for v in V:
+        v.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its64 = []
+    for s, u0, v in zip(solos, u0s, V):
+        rc, it, rel = s.iterate(u0, v, max_iter=400, tol=TOL)
+        its64.append(it)
+    torch.cuda.synchronize()
+    t_solo = time.perf_counter() - t0
+    diff = max(float((a - c).abs().max() / c.abs().max())
+               for a, c in zip(Us, V))
+    for s in solos:
+        s.close()
+    return {
+        "instances": count,
+        "total_dof": sum(i.dof for i in insts),
+        "setup_s": setup_s,
+        "time_to_tol_s_batched_mixed": t_batch,
+        "time_to_tol_s_solo_fp64_sequential": t_solo,
+        "speedup_vs_solo_fp64": t_solo / t_batch,
+        "dof_iters_per_s": dof_iters / t_batch,
+        "iters_min_max": [min(its), max(its)],
+        "iters_fp64_min_max": [min(its64), max(its64)],
+        "all_converged": all(s == 0 for s in sts),
+        "max_rel_diff_batched_mixed_vs_solo_fp64": diff,
+    }
+
+
+def bench_served(rates_frac, n_req, sat_solves_per_s):
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2603_04350_amd import expdiag as X
+    dev = "cuda:0"
+    out = []
+    for frac in rates_frac:
+        rate = frac * sat_solves_per_s
+        times, insts = W.served_stream(n_req, rate, seed=1)
+        u0s = [torch.from_numpy(i.u0).to(dev) for i in insts]
+        Us = [torch.zeros((i.Nt,) + i.shape, dtype=torch.float64,
+                          device=dev) for i in insts]
+        torch.cuda.synchronize()
+        srv = X.expdiag_server_create(64 << 30, 128)
+        ids = {}
+        t0 = time.perf_counter()
+        done = []
+        for k, (ta, inst) in enumerate(zip(times, insts)):
+            while time.perf_counter() - t0 < ta:
+                res, _ = X.expdiag_server_poll(srv)
+                done.extend(res)
+                time.sleep(0.0005)
+            prob = X.make_problem(inst.a, inst.c, inst.n1, inst.n2, inst.n3,
+                                  inst.precision)
+            rid = X.expdiag_server_submit(srv, inst.shape, inst.Nt, inst.dt,
+                                          inst.alpha, inst.scheme, prob,
+                                          u0s[k], Us[k], 400, TOL)
+            ids[rid] = k
+        while len(done) < n_req:
+            res, _ = X.expdiag_server_poll(srv)
+            done.extend(res)
+            time.sleep(0.0005)
+        wall = time.perf_counter() - t0
+        X.expdiag_server_destroy(srv)
+        lat = np.array([r["t_done"] - r["t_submit"] for r in done])
+        ok = sum(1 for r in done if r["status"] == 0)
+        out.append({
+            "rate_solves_per_s": rate,
+            "rate_frac_of_batched_throughput": frac,
+            "requests": n_req,
+            "requests_3d": sum(1 for i in insts if i.dim == 3),
+            "converged": ok,
+            "p50_latency_ms": 1e3 * float(np.percentile(lat, 50)),
+            "p99_latency_ms": 1e3 * float(np.percentile(lat, 99)),
+            "throughput_solves_per_s": n_req / wall,
+        })
+        del Us, u0s
+        torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(inst, U_fp64, U_mixed, sample_iters):
     """The oracle timed on the host cores on a bounded sample: a few of its
     fixed-point iterations of the same instance, scaled to DOF-iters/s.  The
     oracle's sequential solution also checks the GPU answers."""
-    import numpy as np
-
     import oracle as O
     st = O.Setup.from_instance(inst)
     t0 = time.perf_counter()
@@ -141,18 +279,30 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-iters", type=int, default=4)
+    ap.add_argument("--cpu-iters", type=int, default=10)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--quick", action="store_true",
+                    help="fp64 single-instance solves only (profiler runs)")
     args = ap.parse_args()
+    if args.quick:
+        args.no_batch = args.no_serve = args.no_cpu_baseline = True
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
-    inst, res = run_gpu(args)
-    fp, mx = res["fp64"], res["mixed"]
+    import workloads as W
+    inst = W.allen_cahn2d()
+    _log("single-instance fp64")
+    fp = bench_single(inst, 0, args.steps, args.warmup)
+    _log("single-instance mixed")
+    mx = fp if args.quick else bench_single(inst, 1, args.steps, args.warmup)
     kern = fp["kernels"]
-    dom = max(kern, key=lambda k: kern[k]["ms_total"])
+    dom = fp["dominant"]
     src_hash = _src_hash()
     achieved = kern[dom]["GBps"]
     roof = {
@@ -197,12 +347,24 @@ def main():
                 fp["ms_per_solve"] / mx["ms_per_solve"],
         },
         "us_per_iter": {"fp64": fp["us_per_iter"], "mixed": mx["us_per_iter"]},
+        "ms_per_solve_instrumented": fp["ms_per_solve_instrumented"],
         "kernels_fp64": {k: {kk: round(vv, 3) for kk, vv in v.items()}
                          for k, v in kern.items()},
+        "kernels_mixed": {k: {kk: round(vv, 3) for kk, vv in v.items()}
+                          for k, v in mx["kernels"].items()},
         "roofline": roof,
         "src_hash": src_hash,
     }
+    if not args.no_batch:
+        _log(f"batched: {args.batch} instances")
+        line["batched"] = bench_batched(args.batch)
+        if not args.no_serve:
+            sat = args.batch / line["batched"]["time_to_tol_s_batched_mixed"]
+            _log("served")
+            line["served"] = bench_served((0.5, 0.9), args.serve_requests,
+                                          sat)
     if not args.no_cpu_baseline and rank == 0:
+        _log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(inst, fp["U"], mx["U"],
                                             args.cpu_iters)
     if rank == 0:

@@ -156,16 +156,19 @@ int expdiag_iterate(expdiag_t h, const double* u0, double* U, int max_iter,
 int expdiag_gmres(expdiag_t h, const double* u0, double* U, int restart,
                   int max_iter, double tol, int* iters, double* rel_resid);
 
-/* Kernel-class timing with HIP events recorded on the handle's stream
- * around every launch while enabled.  Classes: 0 column FFT, 1 row FFT /
- * nonlinearity, 2 pass B (residual + time transform + shifted solve +
- * update), 3 reductions, 4 Krylov vector kernels.  read() synchronises and
- * returns, per class (host arrays of nclass entries, launches and bytes
- * nullable): total milliseconds, launch counts, and algorithmic bytes (the
- * data each launch must read and write once) since enable. */
-int expdiag_profile_enable(expdiag_t h, int on);
+/* Kernel-class timing.  While enabled (mask != 0) every launch's
+ * algorithmic bytes (the data it must read and write once) and count are
+ * accounted per class, and launches of the classes whose bit is set in
+ * mask are bracketed by HIP events recorded on the handle's stream (those
+ * solves run as plain launches rather than a graph replay).  Classes: 0
+ * column FFT, 1 row FFT / nonlinearity, 2 pass B (residual + time
+ * transform + shifted solve + update), 3 reductions, 4 Krylov vector
+ * kernels.  read() synchronises and returns per class (host arrays of
+ * nclass entries; all but ms nullable): milliseconds summed over the timed
+ * launches, launches, bytes, and timed launches, since enable. */
+int expdiag_profile_enable(expdiag_t h, int mask);
 int expdiag_profile_read(expdiag_t h, double* ms, long* launches,
-                         double* bytes, int nclass);
+                         double* bytes, long* timed, int nclass);
 
 /* Choose between replaying the captured hipGraph of one iteration (on, the
  * default) and launching the same kernels one by one (off). */

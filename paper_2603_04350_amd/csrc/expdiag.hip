@@ -76,6 +76,11 @@ struct Group {
 struct Plan {
   std::vector<Group> groups;
   bool uploaded = false;
+  // one device arena (and pinned staging) for every group's job table,
+  // grown on demand and reused across rebuilds
+  char* arena = nullptr;
+  char* staging = nullptr;
+  size_t cap = 0;
 };
 
 }  // namespace
@@ -133,6 +138,8 @@ struct expdiag_ctx {
 
   // profiling
   bool prof = false;
+  int prof_mask = 0;  // classes whose launches are bracketed by events
+  long prof_all[NPROF] = {0, 0, 0, 0, 0};  // launches of every class
   std::vector<EventPair> events;
   size_t ev_used = 0;
   double prof_ms[NPROF] = {0, 0, 0, 0, 0};
@@ -204,7 +211,8 @@ struct ProfScope {
   ProfScope(expdiag_ctx* h_, int c, double bytes) : h(h_), cls(c) {
     if (h == nullptr || !h->prof) return;
     h->prof_bytes[c] += bytes;
-    if (h->ev_used < h->events.size()) {
+    h->prof_all[c] += 1;
+    if (((h->prof_mask >> c) & 1) && h->ev_used < h->events.size()) {
       ep = &h->events[h->ev_used++];
       ep->cls = cls;
       (void)hipEventRecord(ep->a, h->stream);
@@ -559,11 +567,35 @@ void plan_iteration(Plan& P, expdiag_ctx* h, Ctl* ctl, Ctl* mirror,
   plan_passb(P, 5, h->Nt, a, sizeof(cx<double>));
 }
 
-int plan_upload(expdiag_ctx* h, Plan& P) {
+size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
+
+// Copy every group's job table into the plan's device arena (stream-ordered
+// on `st`; the staging buffer is reused only after `st` has synchronised,
+// which every caller does before rebuilding a plan).
+int plan_upload(expdiag_ctx* h, Plan& P, hipStream_t st) {
   std::stable_sort(P.groups.begin(), P.groups.end(),
                    [](const Group& x, const Group& y) {
                      return x.stage < y.stage;
                    });
+  size_t need = 0;
+  for (auto& g : P.groups) {
+    const size_t jb = g.kind == K_ROW   ? g.rj.size() * sizeof(RowJob)
+                      : g.kind == K_COL ? g.cj.size() * sizeof(ColJob)
+                                        : g.pj.size() * sizeof(PassBArgs);
+    need += align256(jb) + align256(g.start.size() * sizeof(int));
+  }
+  if (need > P.cap) {
+    if (P.arena != nullptr) (void)hipFree(P.arena);
+    if (P.staging != nullptr) (void)hipHostFree(P.staging);
+    P.arena = nullptr;
+    P.staging = nullptr;
+    P.cap = 0;
+    const size_t cap = std::max<size_t>(need * 2, 64 << 10);
+    HIPCHK(h, hipMalloc(&P.arena, cap));
+    HIPCHK(h, hipHostMalloc(&P.staging, cap));
+    P.cap = cap;
+  }
+  size_t off = 0;
   for (auto& g : P.groups) {
     size_t jb = 0;
     const void* src = nullptr;
@@ -577,26 +609,33 @@ int plan_upload(expdiag_ctx* h, Plan& P) {
       jb = g.pj.size() * sizeof(PassBArgs);
       src = g.pj.data();
     }
-    HIPCHK(h, hipMalloc(&g.djobs, jb));
-    HIPCHK(h, hipMalloc(&g.dstart, g.start.size() * sizeof(int)));
-    HIPCHK(h, hipMemcpy(g.djobs, src, jb, hipMemcpyHostToDevice));
-    HIPCHK(h, hipMemcpy(g.dstart, g.start.data(), g.start.size() * sizeof(int),
-                        hipMemcpyHostToDevice));
+    std::memcpy(P.staging + off, src, jb);
+    g.djobs = P.arena + off;
+    off += align256(jb);
+    const size_t sb = g.start.size() * sizeof(int);
+    std::memcpy(P.staging + off, g.start.data(), sb);
+    g.dstart = reinterpret_cast<int*>(P.arena + off);
+    off += align256(sb);
   }
+  HIPCHK(h, hipMemcpyAsync(P.arena, P.staging, off, hipMemcpyHostToDevice, st));
   P.uploaded = true;
   return 0;
 }
 
-void plan_free(Plan& P) {
-  for (auto& g : P.groups) {
-    if (g.djobs != nullptr) (void)hipFree(g.djobs);
-    if (g.dstart != nullptr) (void)hipFree(g.dstart);
-    g.djobs = nullptr;
-    g.dstart = nullptr;
-  }
+// Drop the plan's groups; keep (keep_arena) or free its arena.
+void plan_clear(Plan& P, bool keep_arena) {
   P.groups.clear();
   P.uploaded = false;
+  if (!keep_arena) {
+    if (P.arena != nullptr) (void)hipFree(P.arena);
+    if (P.staging != nullptr) (void)hipHostFree(P.staging);
+    P.arena = nullptr;
+    P.staging = nullptr;
+    P.cap = 0;
+  }
 }
+
+void plan_free(Plan& P) { plan_clear(P, false); }
 
 // Launch every group of the plan on `st` in stage order.  `ph` is the handle
 // used for profiling and error text (nullable).
@@ -649,14 +688,25 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st, const cx<double>* tw64
         }
       });
     } else {
-      ProfScope ps(ph, P_PASSB, g.bytes);
       const PassBArgs* J = static_cast<const PassBArgs*>(g.djobs);
-      ok = dispatch_pow2<2, 512>(g.len, [&](auto Nc) {
-        constexpr int NN = decltype(Nc)::value;
-        hipLaunchKernelGGL((passb_kernel<NN, PB_ITERATE, double>), dim3(grid),
-                           dim3(PassBShape<NN>::THREADS), 0, st, J, g.dstart,
+      {
+        ProfScope ps(ph, P_PASSB, g.bytes);
+        ok = dispatch_pow2<2, 512>(g.len, [&](auto Nc) {
+          constexpr int NN = decltype(Nc)::value;
+          hipLaunchKernelGGL((passb_kernel<NN, PB_ITERATE, double>),
+                             dim3(grid), dim3(PassBShape<NN>::THREADS), 0, st,
+                             J, g.dstart, nj);
+        });
+      }
+      if (ok) {
+        hipError_t e0 = hipGetLastError();
+        if (e0 != hipSuccess)
+          return fail(ph, EXPDIAG_EHIP, "plan launch: %s",
+                      hipGetErrorString(e0));
+        ProfScope pr(ph, P_RED, static_cast<double>(grid) * 32);
+        hipLaunchKernelGGL(ctl_reduce_kernel, dim3(nj), dim3(256), 0, st, J,
                            nj);
-      });
+      }
     }
     if (!ok) return fail(ph, EXPDIAG_EUNSUPPORTED, "plan length %d", g.len);
     hipError_t e = hipGetLastError();
@@ -887,8 +937,6 @@ Ctl initial_ctl(expdiag_ctx* h, int max_iter, double tol) {
   c.tol = tol;
   c.bulk_tol = BULK_TOL;
   c.last_rel = 0.0;
-  c.arrive = 0;
-  c.nblocks = passb_blocks(h);
   return c;
 }
 
@@ -935,17 +983,12 @@ size_t expdiag_footprint_bytes(const expdiag_grid* g, int Nt, int scheme,
   return footprint(s, Nt, true, gmres_restart);
 }
 
-int expdiag_create(const expdiag_grid* g, int Nt, double dt, double alpha,
-                   int scheme, const expdiag_problem* p, void* hip_stream,
-                   expdiag_t* out) {
-  g_create_err.clear();
-  if (out == nullptr || p == nullptr || g == nullptr)
-    return fail(nullptr, EXPDIAG_EINVAL, "null pointer argument");
-  *out = nullptr;
-  Sizes s{};
-  const int gc = check_grid(g, &s);
-  if (gc != 0)
-    return fail(nullptr, gc, "grid: dim 1..3, n even, power of two, 4..1024");
+}  // extern "C"
+
+namespace {
+
+int validate_params(int Nt, double dt, double alpha, int scheme,
+                    const expdiag_problem* p) {
   if (Nt < 2) return fail(nullptr, EXPDIAG_EINVAL, "Nt must be >= 2");
   if (!is_pow2(Nt) || Nt > 512)
     return fail(nullptr, EXPDIAG_EUNSUPPORTED,
@@ -965,6 +1008,36 @@ int expdiag_create(const expdiag_grid* g, int Nt, double dt, double alpha,
                 p->precision);
   if (p->gmres_restart < 0 || p->gmres_restart > 64)
     return fail(nullptr, EXPDIAG_EINVAL, "gmres_restart must be 0..64");
+  return 0;
+}
+
+// New coefficients for an existing handle of the same grid, Nt,
+// nonlinearity and precision (buffers unchanged; tables rebuilt).
+int reinit_params(expdiag_ctx* h, double dt, double alpha, int scheme,
+                  const expdiag_problem* p) {
+  RCHK(validate_params(h->Nt, dt, alpha, scheme, p));
+  h->dt = dt;
+  h->alpha = alpha;
+  h->scheme = scheme;
+  h->p = *p;
+  h->p.gmres_restart = h->restart_cap;
+  return build_tables(h);
+}
+
+// light: no iteration plan or graph of its own (handles driven by a batch
+// or the server).
+int create_impl(const expdiag_grid* g, int Nt, double dt, double alpha,
+                int scheme, const expdiag_problem* p, void* hip_stream,
+                expdiag_t* out, bool light) {
+  g_create_err.clear();
+  if (out == nullptr || p == nullptr || g == nullptr)
+    return fail(nullptr, EXPDIAG_EINVAL, "null pointer argument");
+  *out = nullptr;
+  Sizes s{};
+  const int gc = check_grid(g, &s);
+  if (gc != 0)
+    return fail(nullptr, gc, "grid: dim 1..3, n even, power of two, 4..1024");
+  RCHK(validate_params(Nt, dt, alpha, scheme, p));
 
   expdiag_ctx* h = new (std::nothrow) expdiag_ctx();
   if (h == nullptr) return fail(nullptr, EXPDIAG_ENOMEM, "host allocation");
@@ -1034,11 +1107,14 @@ int expdiag_create(const expdiag_grid* g, int Nt, double dt, double alpha,
                                           hipStreamNonBlocking) != hipSuccess)
     rc = fail(h, EXPDIAG_EHIP, "capture stream");
   if (rc == 0) rc = build_tables(h);
-  if (rc == 0) {
+  if (rc == 0 && light) h->use_graph = false;
+  if (rc == 0 && !light) {
     plan_iteration(h->plan, h, h->ctl, h->d_mirror, h->hist);
-    rc = plan_upload(h, h->plan);
+    rc = plan_upload(h, h->plan, h->cap_stream);
+    if (rc == 0 && hipStreamSynchronize(h->cap_stream) != hipSuccess)
+      rc = fail(h, EXPDIAG_EHIP, "plan upload");
   }
-  if (rc == 0) {
+  if (rc == 0 && !light) {
     if (plan_capture(h, h->plan, h->cap_stream, h->tw64, h->tw32, &h->graph,
                      &h->gexec) != 0) {
       // plain launches of the same plan remain available
@@ -1055,6 +1131,16 @@ int expdiag_create(const expdiag_grid* g, int Nt, double dt, double alpha,
   }
   *out = h;
   return EXPDIAG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int expdiag_create(const expdiag_grid* g, int Nt, double dt, double alpha,
+                   int scheme, const expdiag_problem* p, void* hip_stream,
+                   expdiag_t* out) {
+  return create_impl(g, Nt, dt, alpha, scheme, p, hip_stream, out, false);
 }
 
 int expdiag_destroy(expdiag_t h) {
@@ -1212,9 +1298,9 @@ int expdiag_iterate(expdiag_t h, const double* u0, double* U, int max_iter,
                                              : EXPDIAG_NOT_CONVERGED;
 }
 
-int expdiag_profile_enable(expdiag_t h, int on) {
+int expdiag_profile_enable(expdiag_t h, int mask) {
   if (h == nullptr) return EXPDIAG_EINVAL;
-  if (on) {
+  if (mask) {
     if (h->events.empty()) {
       h->events.resize(16384);
       for (auto& e : h->events) {
@@ -1227,14 +1313,16 @@ int expdiag_profile_enable(expdiag_t h, int on) {
       h->prof_ms[i] = 0;
       h->prof_cnt[i] = 0;
       h->prof_bytes[i] = 0;
+      h->prof_all[i] = 0;
     }
   }
-  h->prof = on != 0;
+  h->prof = mask != 0;
+  h->prof_mask = mask;
   return EXPDIAG_OK;
 }
 
 int expdiag_profile_read(expdiag_t h, double* ms, long* launches,
-                         double* bytes, int nclass) {
+                         double* bytes, long* timed, int nclass) {
   if (h == nullptr || ms == nullptr || nclass < 1) return EXPDIAG_EINVAL;
   HIPCHK(h, hipStreamSynchronize(h->stream));
   for (size_t i = 0; i < h->ev_used; ++i) {
@@ -1246,8 +1334,9 @@ int expdiag_profile_read(expdiag_t h, double* ms, long* launches,
   h->ev_used = 0;
   for (int i = 0; i < nclass && i < NPROF; ++i) {
     ms[i] = h->prof_ms[i];
-    if (launches != nullptr) launches[i] = h->prof_cnt[i];
+    if (launches != nullptr) launches[i] = h->prof_all[i];
     if (bytes != nullptr) bytes[i] = h->prof_bytes[i];
+    if (timed != nullptr) timed[i] = h->prof_cnt[i];
   }
   return EXPDIAG_OK;
 }

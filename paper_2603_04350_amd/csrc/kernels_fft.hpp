@@ -34,8 +34,6 @@ struct Ctl {
   double last_rel;
   double last_rnorm;
   double last_unorm;
-  unsigned int arrive;  // pass B blocks arrived this launch
-  int nblocks;          // pass B blocks per launch of this instance
 };
 
 // True when the job's instance still needs this work.  phase_req < 0: any

@@ -16,10 +16,12 @@
 //
 // The time transforms are length-Nt Stockham FFTs held in registers and LDS
 // (fft_core.hpp).  Norms use Parseval with the half-spectrum weight (1 for
-// the k_last = 0 and Nyquist planes, 2 otherwise).  In the iterate mode the
-// last block of an instance to finish (arrival counter in its control block)
-// reduces all block partials in a fixed order, so the result does not depend
-// on scheduling, and advances the instance's convergence state.
+// the k_last = 0 and Nyquist planes, 2 otherwise).  Each block writes its
+// partial sums; ctl_reduce_kernel then reduces an instance's partials in a
+// fixed order (so the result does not depend on scheduling) and advances
+// its convergence state.  (Doing that in the last-arriving pass B block
+// needs a device-scope release fence in every block, which on this GPU
+// writes back L2 and costs more than the extra launch.)
 #pragma once
 #include "kernels_fft.hpp"
 
@@ -96,16 +98,8 @@ __device__ __forceinline__ void block_sum(double (&acc)[NV], double* red,
   }
 }
 
-__device__ __forceinline__ void store_agent(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double load_agent(const double* p) {
-  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Convergence bookkeeping of one fixed-point iteration (thread 0 of the
-// last block).  tot = {||R||^2, ||S||^2, ||U||^2} (Parseval-weighted sums).
+// instance's reduction block).  tot = {||R||^2, ||S||^2, ||U||^2} (Parseval-weighted sums).
 __device__ inline void advance_ctl(const PassBArgs& a, const double* tot) {
   Ctl* c = a.ctl;
   const double rn = sqrt(tot[0] * a.inv_ns);
@@ -121,6 +115,7 @@ __device__ inline void advance_ctl(const PassBArgs& a, const double* tot) {
     a.hist[2 * (it - 1)] = rel;
     a.hist[2 * (it - 1) + 1] = rn;
   }
+  const int phase0 = c->phase;
   int done = 0;
   if (!(rel == rel) || !(rn == rn) || rel > 1e300) {
     done = 2;
@@ -130,9 +125,9 @@ __device__ inline void advance_ctl(const PassBArgs& a, const double* tot) {
   } else if (rel <= c->tol || it >= c->max_iter) {
     done = 1;
   }
+  const bool publish = done != 0 || (it & 3) == 0 || c->phase != phase0;
   c->done = done;
-  c->arrive = 0;
-  if (a.hmirror != nullptr) {
+  if (a.hmirror != nullptr && publish) {
     volatile Ctl* m = a.hmirror;
     m->iters = it;
     m->phase = c->phase;
@@ -266,34 +261,9 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
   double acc[4] = {nrm_r, nrm_s, nrm_u, 0.0};
   double tot[4];
   block_sum<4, SH::THREADS>(acc, red, tot);
-  if constexpr (MODE != PB_ITERATE) {
-    if (threadIdx.x == 0) {
+  if (threadIdx.x == 0) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) a.partials[lb * 4 + j] = tot[j];
-    }
-    return;
-  } else {
-    // publish this block's partials; the last block of the instance
-    // reduces them in block order and advances the control block
-    __shared__ int s_last;
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) store_agent(a.partials + lb * 4 + j, tot[j]);
-      __threadfence();
-      const unsigned prev = atomicAdd(&a.ctl->arrive, 1u);
-      s_last = (prev == static_cast<unsigned>(a.nblocks - 1)) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    double fin[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < a.nblocks; b += SH::THREADS) {
-#pragma unroll
-      for (int j = 0; j < 3; ++j) fin[j] += load_agent(a.partials + b * 4 + j);
-    }
-    double all[4];
-    block_sum<4, SH::THREADS>(fin, red, all);
-    if (threadIdx.x == 0) advance_ctl(a, all);
+    for (int j = 0; j < 4; ++j) a.partials[lb * 4 + j] = tot[j];
   }
 }
 
@@ -305,7 +275,7 @@ __global__ void __launch_bounds__(PassBShape<NT>::THREADS)
   __shared__ cx<double> lds[NT * SH::LS];
   __shared__ double red[((SH::THREADS + 63) / 64) * 4];
   const int j = find_job(start, njobs);
-  const PassBArgs& a = jobs[j];
+  const PassBArgs a = jobs[j];  // by value: the kernel stores through a.U
   const long lb = blockIdx.x - start[j];
   if constexpr (MODE == PB_ITERATE) {
     if (a.ctl->done) return;
@@ -318,6 +288,23 @@ __global__ void __launch_bounds__(PassBShape<NT>::THREADS)
   } else {
     passb_body<NT, MODE, TN>(a, lb, static_cast<const TN*>(a.Nh), lds, red);
   }
+}
+
+// One block per job of a pass B job table: fixed-order sum of that
+// instance's block partials, then its convergence bookkeeping.
+__global__ void __launch_bounds__(256)
+    ctl_reduce_kernel(const PassBArgs* __restrict__ jobs, int njobs) {
+  __shared__ double red[4 * 4];
+  const PassBArgs a = jobs[blockIdx.x];
+  if (a.ctl->done) return;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < a.nblocks; b += 256) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) acc[j] += a.partials[b * 4 + j];
+  }
+  double tot[4];
+  block_sum<4, 256>(acc, red, tot);
+  if (threadIdx.x == 0) advance_ctl(a, tot);
 }
 
 template <int NT, int MODE, typename TN>

@@ -95,7 +95,8 @@ def load(path: str = LIB_PATH):
     L.expdiag_profile_enable.argtypes = [vp, ci]
     L.expdiag_profile_read.argtypes = [vp, ctypes.POINTER(cd),
                                        ctypes.POINTER(ctypes.c_long),
-                                       ctypes.POINTER(cd), ci]
+                                       ctypes.POINTER(cd),
+                                       ctypes.POINTER(ctypes.c_long), ci]
     L.expdiag_set_graph.argtypes = [vp, ci]
     pp = ctypes.POINTER(vp)
     L.expdiag_batch_create.argtypes = [pp, ci, vp, pp]
@@ -240,20 +241,22 @@ def expdiag_gmres(h, u0, U, restart, max_iter, tol):
     return rc, it.value, rel.value
 
 
-def expdiag_profile_enable(h, on=True):
-    return _check(load().expdiag_profile_enable(h, 1 if on else 0), h)
+def expdiag_profile_enable(h, mask=0x1F):
+    """mask: bit i brackets launches of class i with events; 0 disables."""
+    return _check(load().expdiag_profile_enable(h, int(mask)), h)
 
 
 PROFILE_CLASSES = ("col_fft", "row_fft", "passb", "reduce", "krylov")
 
 
 def expdiag_profile_read(h, nclass=5):
-    """Returns (ms, launches, bytes) per kernel class since enable."""
+    """Returns (ms, launches, bytes, timed_launches) per kernel class."""
     ms = (ctypes.c_double * nclass)()
     cnt = (ctypes.c_long * nclass)()
     by = (ctypes.c_double * nclass)()
-    _check(load().expdiag_profile_read(h, ms, cnt, by, nclass), h)
-    return list(ms), list(cnt), list(by)
+    tm = (ctypes.c_long * nclass)()
+    _check(load().expdiag_profile_read(h, ms, cnt, by, tm, nclass), h)
+    return list(ms), list(cnt), list(by), list(tm)
 
 
 class Solver:
