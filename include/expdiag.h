@@ -174,6 +174,23 @@ int expdiag_profile_read(expdiag_t h, double* ms, long* launches,
  * default) and launching the same kernels one by one (off). */
 int expdiag_set_graph(expdiag_t h, int on);
 
+/* Time transform of steps (a) and (c): 0 = radix-8/4/2 FFT along time in
+ * registers and LDS (any Nt), 1 = dense complex Nt x Nt GEMM on FP64 MFMA
+ * (8 <= Nt <= 128).  Both compute the same operator; results agree to
+ * rounding.  set() rebuilds the handle's plan (EUNSUPPORTED if the variant
+ * does not cover Nt); get() returns the current one. */
+int expdiag_set_time_variant(expdiag_t h, int variant);
+int expdiag_get_time_variant(expdiag_t h);
+
+/* Autotuner: times both variants of pass B on this handle's shape (its own
+ * buffers and stream, 20 launches each after warm-up), keeps the faster and
+ * records it in the JSON cache file `cache_path` (nullable) under the key
+ * gfx950/d<d>/<n0>x<n1>x<n2>/Nt<Nt>/<fp64|mixed>; a cached entry is used
+ * without measuring.  variant, us_fft, us_dense (host, nullable) receive
+ * the choice and the per-launch times (us_dense = -1 when not applicable). */
+int expdiag_autotune(expdiag_t h, const char* cache_path, int* variant,
+                     double* us_fft, double* us_dense);
+
 /* ---- Batching: many independent instances in one iteration plan ------
  * Groups `count` handles (any grids, Nt, coefficients, alpha, precision;
  * each keeps its own workspace and stays owned by the caller) so that one

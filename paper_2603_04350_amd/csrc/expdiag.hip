@@ -36,6 +36,7 @@
 #include <vector>
 
 #include "../../include/expdiag.h"
+#include "kernels_dense.hpp"
 #include "kernels_fft.hpp"
 #include "kernels_krylov.hpp"
 #include "kernels_passb.hpp"
@@ -99,6 +100,8 @@ struct expdiag_ctx {
   bool nonlinear = false;
   bool mixed = false;
   int restart_cap = 0;
+  int tvariant = 0;  // time transform: 0 radix FFT, 1 dense MFMA GEMM
+  bool light = false;  // no plan / graph of its own (batch, server)
 
   // device buffers
   cx<double>* Uh = nullptr;   // [Nt][Nk]
@@ -113,6 +116,7 @@ struct expdiag_ctx {
   cx<double>* lam = nullptr;                          // [Nt]
   cx<double>* tw64 = nullptr;                         // [TW_N]
   cx<float>* tw32 = nullptr;                          // [TW_N]
+  double *Wf = nullptr, *Wi = nullptr;  // dense time transform [2Nt][2Nt]
   double* partials = nullptr;                         // [maxblocks][4]
   int max_partials = 0;
   double* red_out = nullptr;  // [8]
@@ -256,7 +260,14 @@ int passb_blocks_nt(int Nt, long Nk) {
   });
   return static_cast<int>(b);
 }
-int passb_blocks(expdiag_ctx* h) { return passb_blocks_nt(h->Nt, h->Nk); }
+constexpr int DENSE_NT_MIN = 8, DENSE_NT_MAX = 128;
+bool dense_ok(int Nt) { return Nt >= DENSE_NT_MIN && Nt <= DENSE_NT_MAX; }
+int dense_blocks(long Nk) {
+  return static_cast<int>((Nk + DENSE_C - 1) / DENSE_C);
+}
+int passb_blocks(expdiag_ctx* h) {
+  return h->tvariant == 1 ? dense_blocks(h->Nk) : passb_blocks_nt(h->Nt, h->Nk);
+}
 
 double row_bytes(int M, int mode, long nrows, size_t si, size_t so) {
   const double realb = static_cast<double>(nrows) * 2 * M;
@@ -316,6 +327,8 @@ PassBArgs passb_args(expdiag_ctx* h) {
   a.hmirror = nullptr;
   a.hist = nullptr;
   a.tw = h->tw64;
+  a.Wf = h->Wf;
+  a.Wi = h->Wi;
   a.Nk = h->Nk;
   a.nh = h->nh;
   a.nonlinear = h->nonlinear ? 1 : 0;
@@ -370,6 +383,17 @@ double passb_bytes(const PassBArgs& a, int Nt, int mode, size_t nb) {
 template <int MODE, typename TN>
 int launch_passb1(expdiag_ctx* h, const PassBArgs& a) {
   ProfScope ps(h, P_PASSB, passb_bytes(a, h->Nt, MODE, sizeof(cx<TN>)));
+  if (MODE == PB_PRECOND && h->tvariant == 1) {
+    const bool ok = dispatch_pow2<DENSE_NT_MIN, DENSE_NT_MAX>(h->Nt, [&](auto Nc) {
+      constexpr int NN = decltype(Nc)::value;
+      hipLaunchKernelGGL((passb_dense_kernel1<NN, PB_PRECOND, double>),
+                         dim3(dense_blocks(h->Nk)), dim3(DENSE_THREADS), 0,
+                         h->stream, a);
+    });
+    if (!ok) return fail(h, EXPDIAG_EUNSUPPORTED, "dense Nt %d", h->Nt);
+    HIPCHK(h, hipGetLastError());
+    return 0;
+  }
   bool ok = dispatch_pow2<2, 512>(h->Nt, [&](auto Nc) {
     constexpr int NN = decltype(Nc)::value;
     using SH = PassBShape<NN>;
@@ -514,8 +538,9 @@ void plan_col(Plan& P, int stage, int L, const ColJob& j) {
              (sizeof(TI) + sizeof(TO));
 }
 
-void plan_passb(Plan& P, int stage, int Nt, const PassBArgs& a, size_t nb) {
-  Group& g = plan_group(P, stage, K_PASSB, 0, Nt, PB_ITERATE, 0, 0);
+void plan_passb(Plan& P, int stage, int Nt, const PassBArgs& a, size_t nb,
+                int variant) {
+  Group& g = plan_group(P, stage, K_PASSB, variant, Nt, PB_ITERATE, 0, 0);
   g.pj.push_back(a);
   g.start.push_back(g.start.back() + a.nblocks);
   g.bytes += passb_bytes(a, Nt, PB_ITERATE, nb);
@@ -564,7 +589,7 @@ void plan_iteration(Plan& P, expdiag_ctx* h, Ctl* ctl, Ctl* mirror,
   a.hmirror = mirror;
   a.hist = hist;
   if (h->nonlinear && h->mixed) a.Nh32 = nh_view<float>(h);
-  plan_passb(P, 5, h->Nt, a, sizeof(cx<double>));
+  plan_passb(P, 5, h->Nt, a, sizeof(cx<double>), h->tvariant);
 }
 
 size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
@@ -691,12 +716,21 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st, const cx<double>* tw64
       const PassBArgs* J = static_cast<const PassBArgs*>(g.djobs);
       {
         ProfScope ps(ph, P_PASSB, g.bytes);
-        ok = dispatch_pow2<2, 512>(g.len, [&](auto Nc) {
-          constexpr int NN = decltype(Nc)::value;
-          hipLaunchKernelGGL((passb_kernel<NN, PB_ITERATE, double>),
-                             dim3(grid), dim3(PassBShape<NN>::THREADS), 0, st,
-                             J, g.dstart, nj);
-        });
+        if (g.tcode == 1) {
+          ok = dispatch_pow2<DENSE_NT_MIN, DENSE_NT_MAX>(g.len, [&](auto Nc) {
+            constexpr int NN = decltype(Nc)::value;
+            hipLaunchKernelGGL((passb_dense_kernel<NN, PB_ITERATE, double>),
+                               dim3(grid), dim3(DENSE_THREADS), 0, st, J,
+                               g.dstart, nj);
+          });
+        } else {
+          ok = dispatch_pow2<2, 512>(g.len, [&](auto Nc) {
+            constexpr int NN = decltype(Nc)::value;
+            hipLaunchKernelGGL((passb_kernel<NN, PB_ITERATE, double>),
+                               dim3(grid), dim3(PassBShape<NN>::THREADS), 0,
+                               st, J, g.dstart, nj);
+          });
+        }
       }
       if (ok) {
         hipError_t e0 = hipGetLastError();
@@ -810,6 +844,33 @@ int build_tables(expdiag_ctx* h) {
     lam[l] = mk<double>(static_cast<double>(root * cosl(th)),
                         static_cast<double>(root * sinl(th)));
   }
+  if (h->Wf != nullptr) {
+    // [[Re, -Im], [Im, Re]] of Wf[m][l] = gamma_l e^{+2 pi i ml/Nt} / Nt and
+    // Wi[l][m] = gamma_l^{-1} e^{-2 pi i ml/Nt}
+    const int K = 2 * Nt;
+    std::vector<double> wf(static_cast<size_t>(K) * K), wi(wf.size());
+    for (int m = 0; m < Nt; ++m) {
+      for (int l = 0; l < Nt; ++l) {
+        const long double th = 2.0L * pi * ((static_cast<long>(m) * l) % Nt) / Nt;
+        const long double g = expl(la * l / Nt);
+        const long double fr = g * cosl(th) / Nt, fi = g * sinl(th) / Nt;
+        wf[m * K + l] = static_cast<double>(fr);
+        wf[m * K + Nt + l] = static_cast<double>(-fi);
+        wf[(Nt + m) * K + l] = static_cast<double>(fi);
+        wf[(Nt + m) * K + Nt + l] = static_cast<double>(fr);
+        // Wi row l, column m
+        const long double ir = cosl(th) / g, ii = -sinl(th) / g;
+        wi[l * K + m] = static_cast<double>(ir);
+        wi[l * K + Nt + m] = static_cast<double>(-ii);
+        wi[(Nt + l) * K + m] = static_cast<double>(ii);
+        wi[(Nt + l) * K + Nt + m] = static_cast<double>(ir);
+      }
+    }
+    HIPCHK(h, hipMemcpy(h->Wf, wf.data(), wf.size() * sizeof(double),
+                        hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(h->Wi, wi.data(), wi.size() * sizeof(double),
+                        hipMemcpyHostToDevice));
+  }
   std::vector<cx<double>> tw(TW_N);
   std::vector<cx<float>> tw32(TW_N);
   for (int j = 0; j < TW_N; ++j) {
@@ -860,7 +921,9 @@ size_t footprint(const Sizes& s, int Nt, bool nonlinear, int restart) {
   }
   b += s.Nk * (sizeof(cx<double>) + 3 * sizeof(double));
   b += TW_N * (sizeof(cx<double>) + sizeof(cx<float>));
-  b += static_cast<size_t>(passb_blocks_nt(Nt, s.Nk)) * 4 * sizeof(double);
+  b += static_cast<size_t>(std::max(passb_blocks_nt(Nt, s.Nk),
+                                    dense_blocks(s.Nk))) * 4 * sizeof(double);
+  if (dense_ok(Nt)) b += 8 * static_cast<size_t>(Nt) * Nt * sizeof(double);
   return b;
 }
 
@@ -901,6 +964,8 @@ void release(expdiag_ctx* h) {
   fr(h->lam);
   fr(h->tw64);
   fr(h->tw32);
+  fr(h->Wf);
+  fr(h->Wi);
   fr(h->partials);
   fr(h->red_out);
   fr(h->ctl);
@@ -1073,7 +1138,12 @@ int create_impl(const expdiag_grid* g, int Nt, double dt, double alpha,
   A(&h->lam, Nt * sizeof(cx<double>));
   A(&h->tw64, TW_N * sizeof(cx<double>));
   A(&h->tw32, TW_N * sizeof(cx<float>));
-  h->max_partials = std::max(passb_blocks(h), 1);
+  if (dense_ok(Nt)) {
+    A(&h->Wf, 4 * static_cast<size_t>(Nt) * Nt * sizeof(double));
+    A(&h->Wi, 4 * static_cast<size_t>(Nt) * Nt * sizeof(double));
+  }
+  h->max_partials = std::max(passb_blocks_nt(Nt, h->Nk), 1);
+  if (dense_ok(Nt)) h->max_partials = std::max(h->max_partials, dense_blocks(h->Nk));
   A(&h->partials, static_cast<size_t>(h->max_partials) * 4 * sizeof(double));
   A(&h->red_out, 8 * sizeof(double));
   A(&h->ctl, sizeof(Ctl));
@@ -1107,7 +1177,10 @@ int create_impl(const expdiag_grid* g, int Nt, double dt, double alpha,
                                           hipStreamNonBlocking) != hipSuccess)
     rc = fail(h, EXPDIAG_EHIP, "capture stream");
   if (rc == 0) rc = build_tables(h);
-  if (rc == 0 && light) h->use_graph = false;
+  if (rc == 0 && light) {
+    h->use_graph = false;
+    h->light = true;
+  }
   if (rc == 0 && !light) {
     plan_iteration(h->plan, h, h->ctl, h->d_mirror, h->hist);
     rc = plan_upload(h, h->plan, h->cap_stream);
@@ -1345,3 +1418,4 @@ int expdiag_profile_read(expdiag_t h, double* ms, long* launches,
 
 #include "gmres.inc"
 #include "batch.inc"
+#include "autotune.inc"

@@ -52,6 +52,8 @@ struct PassBArgs {
   Ctl* hmirror;           // host-mapped copy of *ctl (nullable)
   double* hist;           // [max_iter][2] (rel, ||R||) history (nullable)
   const cx<double>* tw;
+  const double* Wf;  // dense time transform [2Nt][2Nt] (dense variant)
+  const double* Wi;
   long Nk;
   int nh;
   int nonlinear;

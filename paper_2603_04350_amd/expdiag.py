@@ -35,6 +35,8 @@ EXPORTED = (
     "expdiag_batch_iterate", "expdiag_batch_last_error",
     "expdiag_server_create", "expdiag_server_submit", "expdiag_server_poll",
     "expdiag_server_stats", "expdiag_server_destroy",
+    "expdiag_set_time_variant", "expdiag_get_time_variant",
+    "expdiag_autotune",
 )
 
 
@@ -98,6 +100,10 @@ def load(path: str = LIB_PATH):
                                        ctypes.POINTER(cd),
                                        ctypes.POINTER(ctypes.c_long), ci]
     L.expdiag_set_graph.argtypes = [vp, ci]
+    L.expdiag_set_time_variant.argtypes = [vp, ci]
+    L.expdiag_get_time_variant.argtypes = [vp]
+    L.expdiag_autotune.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ci),
+                                   ctypes.POINTER(cd), ctypes.POINTER(cd)]
     pp = ctypes.POINTER(vp)
     L.expdiag_batch_create.argtypes = [pp, ci, vp, pp]
     L.expdiag_batch_destroy.argtypes = [vp]
@@ -417,3 +423,27 @@ def expdiag_server_stats(s):
 
 def expdiag_server_destroy(s):
     return load().expdiag_server_destroy(s)
+
+
+# -- time-transform variant and autotuning ---------------------------------
+TIME_FFT = 0
+TIME_DENSE_MFMA = 1
+
+
+def expdiag_set_time_variant(h, variant):
+    return _check(load().expdiag_set_time_variant(h, int(variant)), h)
+
+
+def expdiag_get_time_variant(h):
+    return load().expdiag_get_time_variant(h)
+
+
+def expdiag_autotune(h, cache_path=None):
+    """Returns (variant, us_fft, us_dense) and applies the variant."""
+    v = ctypes.c_int(0)
+    a = ctypes.c_double(0.0)
+    b = ctypes.c_double(0.0)
+    path = None if cache_path is None else str(cache_path).encode()
+    _check(load().expdiag_autotune(h, path, ctypes.byref(v), ctypes.byref(a),
+                                   ctypes.byref(b)), h)
+    return v.value, a.value, b.value

@@ -1,0 +1,123 @@
+"""Dense-MFMA time transform and the autotuner, through the C ABI.
+
+The dense variant applies the same operator as the radix-FFT variant with
+another rounding order, so it meets the same bars against the oracle
+(max(1e-12, 50 eps/alpha) per apply, 1e-12 at convergence in fp64).
+"""
+import json
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+EPS = 2.220446049250313e-16
+
+CASES = {
+    "heat1d_Nt16": (1, 64, 16, 1e-2, 1.0, 0.0, 0, 0, 0, 1),
+    "ac2d_Nt8_ragged": (2, 8, 8, 1e-3, 0.0025, 0.0, 1.0, 0, -1.0, 1),
+    "ac2d_Nt32": (2, 32, 32, 1e-3, 0.0025, 0.0, 1.0, 0, -1.0, 1),
+    "rd2d_etd2_Nt64": (2, 32, 64, 1e-3, 0.1, 0.0, 1.0, 0, -1.0, 2),
+    "heat3d_Nt128": (3, 8, 128, 1e-2, 1.0, 0.1, 0, 0, 0, 1),
+}
+
+
+def _setup(case, T=1.0):
+    dim, n, Nt, alpha, a, c, n1, n2, n3, scheme = CASES[case]
+    return O.Setup(dim, n, Nt, T / Nt, alpha, a, c, n1, n2, n3, scheme)
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(
+        "cuda:0")
+
+
+def _solver(st, precision=0):
+    from paper_2603_04350_amd import Solver
+    from paper_2603_04350_amd import expdiag as X
+    s = Solver((st.n,) * st.dim, st.Nt, st.dt, st.alpha, st.scheme, st.a,
+               st.c, st.n1, st.n2, st.n3, precision)
+    X.expdiag_set_time_variant(s.h, X.TIME_DENSE_MFMA)
+    assert X.expdiag_get_time_variant(s.h) == X.TIME_DENSE_MFMA
+    return s
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_dense_precond_parity(case):
+    import torch
+    st = _setup(case)
+    Rv = np.random.default_rng(2).standard_normal((st.Nt,) + (st.n,) * st.dim)
+    with _solver(st) as s:
+        S = torch.empty_like(_dev(Rv))
+        s.precond_apply(_dev(Rv), S)
+        torch.cuda.synchronize()
+    Sr = O.precond_apply(st, Rv)
+    err = np.max(np.abs(S.cpu().numpy() - Sr)) / np.max(np.abs(Sr))
+    assert err < max(1e-12, 50 * EPS / st.alpha), err
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_dense_iterate_converges_to_sequential(case):
+    import torch
+    st = _setup(case)
+    u0 = np.random.default_rng([st.n, st.Nt]).uniform(-0.9, 0.9,
+                                                      (st.n,) * st.dim)
+    ref = O.sequential(st, u0)
+    _, _, (_, its) = O.fixed_point(st, u0, max_iter=2, tol=0.0, record=True)
+    with _solver(st) as s:
+        U = torch.zeros((st.Nt,) + (st.n,) * st.dim, dtype=torch.float64,
+                        device="cuda:0")
+        s.iterate(_dev(u0), U, max_iter=2, tol=0.0)
+        assert O.rel_err(U.cpu().numpy(), its[1]) < max(1e-12, 50 * EPS /
+                                                       st.alpha)
+        U.zero_()
+        rc, it, rel = s.iterate(_dev(u0), U, max_iter=400, tol=1e-14)
+    assert O.rel_err(U.cpu().numpy(), ref) < 1e-12
+
+
+def test_dense_in_batch_with_fft_instances():
+    """A batch mixing both variants: each instance equals its solo solve."""
+    import torch
+    from paper_2603_04350_amd import Batch, Solver
+    from paper_2603_04350_amd import expdiag as X
+    insts = W.batch(6, seed=2, ns=(16, 32), nts=(16, 32), precision=1)
+    solvers = [Solver.from_instance(i) for i in insts]
+    for k, s in enumerate(solvers):
+        X.expdiag_set_time_variant(s.h, k % 2)
+    solo = []
+    for s, inst in zip(solvers, insts):
+        U = torch.zeros((inst.Nt,) + inst.shape, dtype=torch.float64,
+                        device="cuda:0")
+        s.iterate(_dev(inst.u0), U, max_iter=300, tol=1e-12)
+        solo.append(U.cpu().numpy())
+    b = Batch(solvers)
+    Us = [torch.zeros((i.Nt,) + i.shape, dtype=torch.float64,
+                      device="cuda:0") for i in insts]
+    b.iterate([_dev(i.u0) for i in insts], Us, max_iter=300, tol=1e-12)
+    b.close()
+    for k in range(len(insts)):
+        assert np.array_equal(Us[k].cpu().numpy(), solo[k])
+    for s in solvers:
+        s.close()
+
+
+def test_autotune_writes_and_reuses_cache(tmp_path):
+    from paper_2603_04350_amd import Solver
+    from paper_2603_04350_amd import expdiag as X
+    inst = W.scaled(W.allen_cahn2d(), n=64, Nt=32)
+    cache = tmp_path / "tune.json"
+    with Solver.from_instance(inst) as s:
+        v, tf, td = X.expdiag_autotune(s.h, cache)
+        assert v in (0, 1) and tf > 0 and td > 0
+        assert X.expdiag_get_time_variant(s.h) == v
+    data = json.loads(cache.read_text())
+    key = "gfx950/d2/64x64x1/Nt32/fp64"
+    assert data[key]["variant"] == v
+    with Solver.from_instance(inst) as s:
+        v2, tf2, td2 = X.expdiag_autotune(s.h, cache)
+        assert (v2, tf2, td2) == (v, data[key]["us_fft"],
+                                  data[key]["us_dense"])
