@@ -80,22 +80,22 @@ __device__ __forceinline__ cx<T> twid(const cx<T>* tw, int j) {
 
 constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
 
-// Elements per thread for a line of length L.
-template <int L>
+// Elements per thread for a line of length L (at most RMAX).
+template <int L, int RMAX = 8>
 struct FftShape {
-  static constexpr int R = L >= 8 ? 8 : L;
+  static constexpr int R = L >= RMAX ? RMAX : L;
   static constexpr int TPL = L / R;
 };
 
 // One Stockham stage with span NS, then recurse.  `lds` points at element 0
-// of this thread's line; element p lives at lds[p * stride].
-template <typename T, int L, int S, int NS>
-__device__ __forceinline__ void fft_stages(cx<T> (&v)[FftShape<L>::R],
-                                           cx<T>* lds, int stride, int t,
+// of this thread's line; element p lives at lds[p * stride].  R elements
+// per thread (a power of two, 2..8).
+template <typename T, int L, int R, int S, int NS>
+__device__ __forceinline__ void fft_stages(cx<T> (&v)[R], cx<T>* lds,
+                                           int stride, int t,
                                            const cx<T>* tw) {
   if constexpr (NS < L) {
-    constexpr int R = FftShape<L>::R;
-    constexpr int TPL = FftShape<L>::TPL;
+    constexpr int TPL = L / R;
     constexpr int rem = L / NS;
     constexpr int r = (rem % R == 0) ? R : rem;
     constexpr int NB = R / r;
@@ -121,7 +121,7 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[FftShape<L>::R],
 #pragma unroll
     for (int s = 0; s < R; ++s) v[s] = lds[(t + s * TPL) * stride];
     if constexpr (NS * r < L) __syncthreads();
-    fft_stages<T, L, S, NS * r>(v, lds, stride, t, tw);
+    fft_stages<T, L, R, S, NS * r>(v, lds, stride, t, tw);
   }
 }
 
@@ -129,14 +129,13 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[FftShape<L>::R],
 // thread still reads this line's LDS (callers place a barrier before).
 // Postcondition: natural-order result in LDS and in v (positions t+s*TPL).
 // Every thread of the block must call this (it contains barriers).
-template <typename T, int L, int S>
-__device__ __forceinline__ void fft_line(cx<T> (&v)[FftShape<L>::R],
-                                         cx<T>* lds, int stride, int t,
-                                         const cx<T>* tw) {
+template <typename T, int L, int S, int R>
+__device__ __forceinline__ void fft_line(cx<T> (&v)[R], cx<T>* lds,
+                                         int stride, int t, const cx<T>* tw) {
   if constexpr (L == 1) {
     return;
   } else {
-    fft_stages<T, L, S, 1>(v, lds, stride, t, tw);
+    fft_stages<T, L, R, S, 1>(v, lds, stride, t, tw);
   }
 }
 

@@ -44,7 +44,10 @@ __device__ __forceinline__ bool job_live(const Ctl* c, int phase_req) {
   return phase_req < 0 || c->phase == phase_req;
 }
 
-// Job index of this block: largest j with start[j] <= blockIdx.x.
+// Job index of this block: largest j with start[j] <= blockIdx.x.  The
+// result is the same for the whole block; readfirstlane makes that visible
+// to the compiler so the job descriptor is fetched with scalar loads into
+// scalar registers.
 __device__ __forceinline__ int find_job(const int* __restrict__ start,
                                         int njobs) {
   int lo = 0, hi = njobs - 1;
@@ -56,7 +59,7 @@ __device__ __forceinline__ int find_job(const int* __restrict__ start,
     else
       hi = mid - 1;
   }
-  return lo;
+  return __builtin_amdgcn_readfirstlane(lo);
 }
 
 enum RowMode : int {
@@ -233,13 +236,15 @@ __global__ void __launch_bounds__(RowShape<M>::THREADS)
   row_body<T, M, MODE, TI, TO>(jb, blockIdx.x, tw);
 }
 
+// C adjacent columns per workgroup; LDS of L*C complex (32 KiB in fp64 for
+// L <= 512), which lets five workgroups share a CU.
 template <int L>
 struct ColShape {
   static constexpr int R = FftShape<L>::R;
   static constexpr int TPL = FftShape<L>::TPL;
   static constexpr int C = (256 / TPL) >= 4 ? 256 / TPL : 4;
   static constexpr int THREADS = C * TPL;
-  static constexpr int LS = C + 1;  // padded LDS row (complex slots)
+  static constexpr int LS = C;  // LDS row (complex slots)
 };
 
 struct ColJob {
@@ -288,7 +293,7 @@ __device__ __forceinline__ void col_body(const ColJob& jb, long lb,
 }
 
 template <typename T, int L, int S, typename TI, typename TO>
-__global__ void __launch_bounds__(ColShape<L>::THREADS)
+__global__ void __launch_bounds__(ColShape<L>::THREADS, 5)
     col_kernel(const ColJob* __restrict__ jobs, const int* __restrict__ start,
                int njobs, const cx<T>* __restrict__ tw) {
   const int j = find_job(start, njobs);
@@ -298,7 +303,7 @@ __global__ void __launch_bounds__(ColShape<L>::THREADS)
 }
 
 template <typename T, int L, int S, typename TI, typename TO>
-__global__ void __launch_bounds__(ColShape<L>::THREADS)
+__global__ void __launch_bounds__(ColShape<L>::THREADS, 5)
     col_kernel1(ColJob jb, const cx<T>* __restrict__ tw) {
   if (!job_live(jb.ctl, jb.phase_req)) return;
   col_body<T, L, S, TI, TO>(jb, blockIdx.x, tw);

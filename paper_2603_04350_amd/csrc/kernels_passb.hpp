@@ -62,13 +62,20 @@ struct PassBArgs {
   double inv_ns;
 };
 
+// C kappa columns per workgroup; the LDS tile is NT*C complex (32 KiB for
+// NT <= 256), the block reduction reuses it, so five workgroups fit a CU.
+// Four time rows per thread (radix-4 stages) keep the registers within
+// that occupancy.
 template <int NT>
 struct PassBShape {
-  static constexpr int R = FftShape<NT>::R;
-  static constexpr int TPL = FftShape<NT>::TPL;
+  static constexpr int R = FftShape<NT, 4>::R;
+  static constexpr int TPL = FftShape<NT, 4>::TPL;
   static constexpr int C = (256 / TPL) >= 4 ? 256 / TPL : 4;
   static constexpr int THREADS = C * TPL;
-  static constexpr int LS = C + 1;
+  static constexpr int LS = C;
+  // waves per SIMD the register budget targets (longer time lines keep
+  // more twiddles live)
+  static constexpr int WAVES = NT <= 64 ? 5 : 4;
 };
 
 // Sum NV doubles over the block; thread 0 writes them to out[0..NV).
@@ -172,41 +179,44 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
       v[s] = r * a.gam[l];
     }
   } else {
-    // rows of U (or of the Krylov vector v for PB_OPAPPLY)
+    // rows of U (or of the Krylov vector v for PB_OPAPPLY) and, issued
+    // before the first barrier, the N^ (or J) rows and per-kappa tables
+    const bool nl_on = valid && a.nonlinear;
+    const cx<TN>* Nc = reinterpret_cast<const cx<TN>*>(Nh);
+    cx<double> n_cur[R];
 #pragma unroll
     for (int s = 0; s < R; ++s) {
       const int l = t + s * TPL;
       u[s] = valid ? a.U[l * Nk + kap] : mk(0.0, 0.0);
-      lds[l * LS + c] = u[s];
+      n_cur[s] = mk(0.0, 0.0);
+      if (nl_on && (MODE != PB_OPAPPLY || l >= 1))
+        n_cur[s] = cvt<double>(Nc[l * Nk + kap]);
     }
-    __syncthreads();
     const cx<double> first =
         (MODE == PB_OPAPPLY || !valid) ? mk(0.0, 0.0) : a.u0h[kap];
-    const bool nl_on = valid && a.nonlinear;
     const double c1 = nl_on ? a.c1[kap] : 0.0;
     const double c2 = (nl_on && a.etd2) ? a.c2[kap] : 0.0;
-    const cx<TN>* Nc = reinterpret_cast<const cx<TN>*>(Nh);
+#pragma unroll
+    for (int s = 0; s < R; ++s) lds[(t + s * TPL) * LS + c] = u[s];
+    __syncthreads();
 #pragma unroll
     for (int s = 0; s < R; ++s) {
       const int l = t + s * TPL;
       const cx<double> prev = (l == 0) ? first : lds[(l - 1) * LS + c];
+      // ETD2's second term reads the previous row (just loaded by a
+      // neighbouring thread, so an L2 hit)
+      cx<double> n_prev = mk(0.0, 0.0);
       cx<double> r;
       if constexpr (MODE == PB_OPAPPLY) {
         // (Q - G'(U)) v : v_l - E v_{l-1} - (c1 J_l + c2 J_{l-1}), where
         // J_l = FFT[N'(u_{l-1}) v_{l-1}] (J_0 = J_{-1} = 0: u_0 is fixed)
-        r = u[s] - prev * E;
-        if (nl_on) {
-          if (l >= 1) r = r - cvt<double>(Nc[l * Nk + kap]) * c1;
-          if (a.etd2 && l >= 2)
-            r = r - cvt<double>(Nc[(l - 1) * Nk + kap]) * c2;
-        }
+        if (nl_on && a.etd2 && l >= 2)
+          n_prev = cvt<double>(Nc[(l - 1) * Nk + kap]);
+        r = u[s] - prev * E - n_cur[s] * c1 - n_prev * c2;
       } else {
-        r = prev * E - u[s];
-        if (nl_on) {
-          r = r + cvt<double>(Nc[l * Nk + kap]) * c1;
-          if (a.etd2)
-            r = r + cvt<double>(Nc[(l == 0 ? 0 : l - 1) * Nk + kap]) * c2;
-        }
+        if (nl_on && a.etd2)
+          n_prev = cvt<double>(Nc[(l == 0 ? 0 : l - 1) * Nk + kap]);
+        r = prev * E - u[s] + n_cur[s] * c1 + n_prev * c2;
       }
       nrm_r += pw * norm2(r);
       v[s] = r * a.gam[l];
@@ -269,13 +279,18 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
   }
 }
 
+// Cap the registers at the occupancy PassBShape targets so the compiler
+// does not trade waves for early loads.
 template <int NT, int MODE, typename TN>
-__global__ void __launch_bounds__(PassBShape<NT>::THREADS)
+__global__ void __launch_bounds__(PassBShape<NT>::THREADS,
+                                  PassBShape<NT>::WAVES)
     passb_kernel(const PassBArgs* __restrict__ jobs,
                  const int* __restrict__ start, int njobs) {
   using SH = PassBShape<NT>;
+  static_assert(NT * SH::LS * 2 >= ((SH::THREADS + 63) / 64) * 4,
+                "reduction scratch fits the tile");
   __shared__ cx<double> lds[NT * SH::LS];
-  __shared__ double red[((SH::THREADS + 63) / 64) * 4];
+  double* red = reinterpret_cast<double*>(lds);
   const int j = find_job(start, njobs);
   const PassBArgs a = jobs[j];  // by value: the kernel stores through a.U
   const long lb = blockIdx.x - start[j];
@@ -310,11 +325,12 @@ __global__ void __launch_bounds__(256)
 }
 
 template <int NT, int MODE, typename TN>
-__global__ void __launch_bounds__(PassBShape<NT>::THREADS)
+__global__ void __launch_bounds__(PassBShape<NT>::THREADS,
+                                  PassBShape<NT>::WAVES)
     passb_kernel1(PassBArgs a) {
   using SH = PassBShape<NT>;
   __shared__ cx<double> lds[NT * SH::LS];
-  __shared__ double red[((SH::THREADS + 63) / 64) * 4];
+  double* red = reinterpret_cast<double*>(lds);
   passb_body<NT, MODE, TN>(a, blockIdx.x, static_cast<const TN*>(a.Nh), lds,
                            red);
 }
