@@ -61,4 +61,30 @@ __device__ __forceinline__ T norm2(cx<T> a) {
   return a.x * a.x + a.y * a.y;
 }
 
+// Accesses through pointers read from job tables.  The compiler cannot see
+// where such a pointer points and would emit flat instructions (which also
+// count against the LDS wait counter); every such pointer is device global
+// memory, and these say so.
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+
+// (The host compilation pass only type-checks device bodies and has no
+// address space 1, so it sees the plain access.)
+template <typename T>
+__device__ __forceinline__ T gld(const T* p, long i) {
+#if __HIP_DEVICE_COMPILE__
+  return ((const gmem<T>*)p)[i];
+#else
+  return p[i];
+#endif
+}
+template <typename T>
+__device__ __forceinline__ void gst(T* p, long i, T v) {
+#if __HIP_DEVICE_COMPILE__
+  ((gmem<T>*)p)[i] = v;
+#else
+  p[i] = v;
+#endif
+}
+
 }  // namespace expdiag

@@ -64,9 +64,14 @@ struct Group {
   std::vector<ColJob> cj;
   std::vector<PassBArgs> pj;
   std::vector<int> start;  // njobs + 1
+  // instances whose convergence reduction this launch performs (the
+  // hosting column stage: before its transform blocks; pass B: as a
+  // ctl_reduce launch right after)
+  std::vector<PassBArgs> red;
   double bytes = 0;        // algorithmic bytes of one full launch
   void* djobs = nullptr;
   int* dstart = nullptr;
+  void* dred = nullptr;
   int grid() const { return start.empty() ? 0 : start.back(); }
   int njobs() const { return static_cast<int>(start.size()) - 1; }
   std::tuple<int, int, int, int, int, int, int> key() const {
@@ -108,6 +113,7 @@ struct expdiag_ctx {
   cx<double>* Nh = nullptr;   // [Nt][Nk] fp64; fp32 view in its 2nd half
   cx<double>* T = nullptr;    // [Nt][Nk] scratch
   cx<double>* T2 = nullptr;   // [Nt][Nk] scratch (GMRES / Newton)
+  cx<float>* T32 = nullptr;   // [Nt][Nk] fp32 pass-A scratch (mixed, d >= 2)
   double* Uphys = nullptr;    // [Nt][Ns] physical iterate (Newton)
   float* Uphys32 = nullptr;   // [Nt][Ns] its fp32 copy (mixed Newton)
   cx<double>* u0h = nullptr;  // [Nk]
@@ -539,9 +545,10 @@ void plan_col(Plan& P, int stage, int L, const ColJob& j) {
 }
 
 void plan_passb(Plan& P, int stage, int Nt, const PassBArgs& a, size_t nb,
-                int variant) {
+                int variant, bool reduce_after) {
   Group& g = plan_group(P, stage, K_PASSB, variant, Nt, PB_ITERATE, 0, 0);
   g.pj.push_back(a);
+  if (reduce_after) g.red.push_back(a);
   g.start.push_back(g.start.back() + a.nblocks);
   g.bytes += passb_bytes(a, Nt, PB_ITERATE, nb);
 }
@@ -576,21 +583,112 @@ void plan_pass_a(Plan& P, expdiag_ctx* h, const Ctl* ctl, int ph) {
   plan_col<T, -1, T, T>(P, 4, h->n[0], make_col(Tt, N1, ns, in2, 1.0, ctl, ph));
 }
 
+// Pass A of one instance in an iteration plan (tcode 2 groups hold the
+// instance's fp32 job for the mixed-precision bulk phase and its fp64 job
+// side by side, picked per block from the control block; ti names the fp32
+// job's input type).  For d >= 2 the first stage, the inverse transform of
+// Uh along axis 0, runs in fp64 in both phases (tcode 3) and performs the
+// instance's convergence reduction of the previous iteration (`red`); the
+// bulk phase then reads that fp64 intermediate in the next stage and
+// continues in fp32 through T32.  Returns whether the reduction is hosted
+// (1D pass A is one row stage that depends on the phase: not hosted).
+// Instances without a bulk phase carry their fp64 job in both slots.  A
+// group's byte count is that of the phase the instance spends most
+// iterations in (fp32 when mixed).
+bool plan_pass_a_mp(Plan& P, expdiag_ctx* h, const Ctl* ctl,
+                    const PassBArgs& red) {
+  const int d = h->dim;
+  const long ns = h->Nt - 1;
+  const long nh2 = 2L * h->nh;
+  const int nl = h->n[d - 1];
+  const int M = nl / 2;
+  const double sc = 1.0 / static_cast<double>(h->Ns);
+  const bool mx = h->mixed;
+  cx<double>* T64 = h->T;
+  cx<float>* T32 = h->T32;
+  cx<double>* N64 = nh_view<double>(h) + h->Nk;  // slot 1
+  cx<float>* N32 = nh_view<float>(h) + h->Nk;
+  auto row2 = [&](int stage, const RowJob& j32, const RowJob& j64,
+                  int ti32) {
+    Group& g = plan_group(P, stage, K_ROW, 2, M, ROW_FUSED, ti32, 1);
+    g.rj.push_back(mx ? j32 : j64);
+    g.rj.push_back(j64);
+    g.start.push_back(g.start.back() + row_blocks(M, j64.nrows));
+    g.bytes += mx ? row_bytes(M, ROW_FUSED, j32.nrows,
+                              ti32 == 0 ? sizeof(double) : sizeof(float),
+                              sizeof(float))
+                  : row_bytes(M, ROW_FUSED, j64.nrows, sizeof(double),
+                              sizeof(double));
+  };
+  auto col2 = [&](int stage, int L, int S, const ColJob& j32,
+                  const ColJob& j64, int ti32) {
+    Group& g = plan_group(P, stage, K_COL, 2, L, S, ti32, 1);
+    g.cj.push_back(mx ? j32 : j64);
+    g.cj.push_back(j64);
+    g.start.push_back(g.start.back() + col_blocks(L, j64.outer, j64.inner));
+    const double ent = static_cast<double>(j64.outer) * L * j64.inner * 2;
+    g.bytes += mx ? ent * ((ti32 == 0 ? sizeof(double) : sizeof(float)) +
+                           sizeof(float))
+                  : ent * 2 * sizeof(double);
+  };
+  if (d == 1) {
+    row2(2, make_row(h, h->Uh, N32, ns, nh2, nh2, sc, ctl, -1),
+         make_row(h, h->Uh, N64, ns, nh2, nh2, sc, ctl, -1), 0);
+    return false;
+  }
+  const int n0 = h->n[0];
+  const long in2 = d == 3 ? static_cast<long>(h->n[1]) * h->nh : h->nh;
+  {
+    const ColJob j = make_col(h->Uh, T64, ns, in2, 1.0, ctl, -1);
+    Group& g = plan_group(P, 0, K_COL, 3, n0, 1, 0, 0);
+    g.cj.push_back(j);
+    g.red.push_back(red);
+    g.start.push_back(g.start.back() + col_blocks(n0, ns, in2));
+    g.bytes += static_cast<double>(ns) * n0 * in2 * 2 * 2 * sizeof(double);
+  }
+  const long rows = ns * (h->Ns / nl);
+  if (d == 2) {
+    row2(2, make_row(h, T64, T32, rows, nh2, nh2, sc, ctl, -1),
+         make_row(h, T64, T64, rows, nh2, nh2, sc, ctl, -1), 0);
+  } else {
+    const int n1 = h->n[1];
+    col2(1, n1, 1, make_col(T64, T32, ns * n0, h->nh, 1.0, ctl, -1),
+         make_col(T64, T64, ns * n0, h->nh, 1.0, ctl, -1), 0);
+    row2(2, make_row(h, T32, T32, rows, nh2, nh2, sc, ctl, -1),
+         make_row(h, T64, T64, rows, nh2, nh2, sc, ctl, -1), 1);
+    col2(3, n1, -1, make_col(T32, T32, ns * n0, h->nh, 1.0, ctl, -1),
+         make_col(T64, T64, ns * n0, h->nh, 1.0, ctl, -1), 1);
+  }
+  col2(4, n0, -1, make_col(T32, N32, ns, in2, 1.0, ctl, -1),
+       make_col(T64, N64, ns, in2, 1.0, ctl, -1), 1);
+  return true;
+}
+
 // All launches of one fixed-point iteration of instance h, with control
 // block `ctl` (device) and host mirror `mirror` (device address).
 void plan_iteration(Plan& P, expdiag_ctx* h, Ctl* ctl, Ctl* mirror,
                     double* hist) {
-  if (h->nonlinear) {
-    plan_pass_a<double>(P, h, ctl, 1);
-    if (h->mixed) plan_pass_a<float>(P, h, ctl, 0);
-  }
   PassBArgs a = passb_args(h);
   a.ctl = ctl;
   a.hmirror = mirror;
   a.hist = hist;
   if (h->nonlinear && h->mixed) a.Nh32 = nh_view<float>(h);
-  plan_passb(P, 5, h->Nt, a, sizeof(cx<double>), h->tvariant);
+  const bool hosted = h->nonlinear && plan_pass_a_mp(P, h, ctl, a);
+  plan_passb(P, 5, h->Nt, a, sizeof(cx<double>), h->tvariant, !hosted);
 }
+
+// Algorithmic bytes of one iteration of a plan.
+double plan_bytes(const Plan& P) {
+  double b = 0;
+  for (const auto& g : P.groups) b += g.bytes;
+  return b;
+}
+
+// Replaying a captured iteration pays off while launches cost more than
+// the kernels (small iterates); for large ones the captured graph measured
+// slower than plain launches on this GPU (~5 us per iteration of five
+// launches), so it is used only below this size.
+constexpr double GRAPH_MAX_BYTES = 64e6;
 
 size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
@@ -607,7 +705,8 @@ int plan_upload(expdiag_ctx* h, Plan& P, hipStream_t st) {
     const size_t jb = g.kind == K_ROW   ? g.rj.size() * sizeof(RowJob)
                       : g.kind == K_COL ? g.cj.size() * sizeof(ColJob)
                                         : g.pj.size() * sizeof(PassBArgs);
-    need += align256(jb) + align256(g.start.size() * sizeof(int));
+    need += align256(jb) + align256(g.start.size() * sizeof(int)) +
+            align256(g.red.size() * sizeof(PassBArgs));
   }
   if (need > P.cap) {
     if (P.arena != nullptr) (void)hipFree(P.arena);
@@ -641,6 +740,13 @@ int plan_upload(expdiag_ctx* h, Plan& P, hipStream_t st) {
     std::memcpy(P.staging + off, g.start.data(), sb);
     g.dstart = reinterpret_cast<int*>(P.arena + off);
     off += align256(sb);
+    g.dred = nullptr;
+    if (!g.red.empty()) {
+      const size_t rb = g.red.size() * sizeof(PassBArgs);
+      std::memcpy(P.staging + off, g.red.data(), rb);
+      g.dred = P.arena + off;
+      off += align256(rb);
+    }
   }
   HIPCHK(h, hipMemcpyAsync(P.arena, P.staging, off, hipMemcpyHostToDevice, st));
   P.uploaded = true;
@@ -677,16 +783,29 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st, const cx<double>* tw64
       ok = dispatch_pow2<2, 512>(g.len, [&](auto Mc) {
         constexpr int MM = decltype(Mc)::value;
         const dim3 th(RowShape<MM>::THREADS);
-        if (g.tcode == 0) {
-          hipLaunchKernelGGL((row_kernel<double, MM, ROW_FUSED, double, double>),
-                             dim3(grid), th, 0, st, J, g.dstart, nj, tw64);
-        } else if (g.ti == 0) {
-          hipLaunchKernelGGL((row_kernel<float, MM, ROW_FUSED, double, float>),
-                             dim3(grid), th, 0, st, J, g.dstart, nj, tw32);
-        } else {
-          hipLaunchKernelGGL((row_kernel<float, MM, ROW_FUSED, float, float>),
-                             dim3(grid), th, 0, st, J, g.dstart, nj, tw32);
-        }
+        if (g.ti == 0)  // 1D: the fp32 job reads the fp64 spectrum
+          hipLaunchKernelGGL((row_kernel_mp<MM, ROW_FUSED, double>),
+                             dim3(grid), th, 0, st, J, g.dstart, nj, tw32,
+                             tw64);
+        else
+          hipLaunchKernelGGL((row_kernel_mp<MM, ROW_FUSED, float>),
+                             dim3(grid), th, 0, st, J, g.dstart, nj, tw32,
+                             tw64);
+      });
+    } else if (g.kind == K_COL && g.tcode == 3) {
+      ProfScope ps(ph, P_COL, g.bytes);
+      const ColJob* J = static_cast<const ColJob*>(g.djobs);
+      const PassBArgs* RJ = static_cast<const PassBArgs*>(g.dred);
+      const int nred = static_cast<int>(g.red.size());
+      ok = dispatch_pow2<4, 1024>(g.len, [&](auto Lc) {
+        constexpr int LL = decltype(Lc)::value;
+        const dim3 th(ColShape<LL>::THREADS);
+        if (g.mode == 1)
+          hipLaunchKernelGGL((col_kernel_host<LL, 1>), dim3(grid + nred), th,
+                             0, st, J, g.dstart, nj, RJ, nred, tw64);
+        else
+          hipLaunchKernelGGL((col_kernel_host<LL, -1>), dim3(grid + nred),
+                             th, 0, st, J, g.dstart, nj, RJ, nred, tw64);
       });
     } else if (g.kind == K_COL) {
       ProfScope ps(ph, P_COL, g.bytes);
@@ -694,23 +813,17 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st, const cx<double>* tw64
       ok = dispatch_pow2<4, 1024>(g.len, [&](auto Lc) {
         constexpr int LL = decltype(Lc)::value;
         const dim3 th(ColShape<LL>::THREADS);
-        if (g.tcode == 0) {
-          if (g.mode == 1)
-            hipLaunchKernelGGL((col_kernel<double, LL, 1, double, double>),
-                               dim3(grid), th, 0, st, J, g.dstart, nj, tw64);
-          else
-            hipLaunchKernelGGL((col_kernel<double, LL, -1, double, double>),
-                               dim3(grid), th, 0, st, J, g.dstart, nj, tw64);
-        } else if (g.ti == 0) {
-          hipLaunchKernelGGL((col_kernel<float, LL, 1, double, float>),
-                             dim3(grid), th, 0, st, J, g.dstart, nj, tw32);
-        } else if (g.mode == 1) {
-          hipLaunchKernelGGL((col_kernel<float, LL, 1, float, float>),
-                             dim3(grid), th, 0, st, J, g.dstart, nj, tw32);
-        } else {
-          hipLaunchKernelGGL((col_kernel<float, LL, -1, float, float>),
-                             dim3(grid), th, 0, st, J, g.dstart, nj, tw32);
-        }
+        // first inverse stage reads the fp64 spectrum; the others read the
+        // stage before in the job's own precision
+        if (g.mode == 1 && g.ti == 0)
+          hipLaunchKernelGGL((col_kernel_mp<LL, 1, double>), dim3(grid), th,
+                             0, st, J, g.dstart, nj, tw32, tw64);
+        else if (g.mode == 1)
+          hipLaunchKernelGGL((col_kernel_mp<LL, 1, float>), dim3(grid), th, 0,
+                             st, J, g.dstart, nj, tw32, tw64);
+        else
+          hipLaunchKernelGGL((col_kernel_mp<LL, -1, float>), dim3(grid), th,
+                             0, st, J, g.dstart, nj, tw32, tw64);
       });
     } else {
       const PassBArgs* J = static_cast<const PassBArgs*>(g.djobs);
@@ -732,20 +845,41 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st, const cx<double>* tw64
           });
         }
       }
-      if (ok) {
+      if (ok && !g.red.empty()) {
         hipError_t e0 = hipGetLastError();
         if (e0 != hipSuccess)
           return fail(ph, EXPDIAG_EHIP, "plan launch: %s",
                       hipGetErrorString(e0));
+        const int nred = static_cast<int>(g.red.size());
         ProfScope pr(ph, P_RED, static_cast<double>(grid) * 32);
-        hipLaunchKernelGGL(ctl_reduce_kernel, dim3(nj), dim3(256), 0, st, J,
-                           nj);
+        hipLaunchKernelGGL(ctl_reduce_kernel, dim3(nred), dim3(CTL_THREADS),
+                           0, st, static_cast<const PassBArgs*>(g.dred),
+                           nred);
       }
     }
     if (!ok) return fail(ph, EXPDIAG_EUNSUPPORTED, "plan length %d", g.len);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
       return fail(ph, EXPDIAG_EHIP, "plan launch: %s", hipGetErrorString(e));
+  }
+  return 0;
+}
+
+// After the last iteration of a chunk: the convergence reduction of every
+// instance whose pass B has not been reduced yet (those hosted by the next
+// iteration's first stage), so the control blocks are current when the
+// host looks.
+int plan_finish(expdiag_ctx* ph, Plan& P, hipStream_t st) {
+  for (auto& g : P.groups) {
+    if (g.kind != K_PASSB || g.njobs() == 0) continue;
+    ProfScope pr(ph, P_RED, static_cast<double>(g.grid()) * 32);
+    hipLaunchKernelGGL(ctl_reduce_kernel, dim3(g.njobs()), dim3(CTL_THREADS),
+                       0, st, static_cast<const PassBArgs*>(g.djobs),
+                       g.njobs());
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+      return fail(ph, EXPDIAG_EHIP, "reduce launch: %s",
+                  hipGetErrorString(e));
   }
   return 0;
 }
@@ -909,10 +1043,12 @@ int check_grid(const expdiag_grid* g, Sizes* sz) {
   return 0;
 }
 
-size_t footprint(const Sizes& s, int Nt, bool nonlinear, int restart) {
+size_t footprint(const Sizes& s, int dim, int Nt, bool nonlinear,
+                 bool mixed, int restart) {
   const size_t st = static_cast<size_t>(Nt) * s.Nk * sizeof(cx<double>);
   size_t b = 2 * st;                   // Uh, T
   if (nonlinear) b += st;              // Nh
+  if (nonlinear && mixed && dim >= 2) b += st / 2;  // T32
   if (restart > 0) {
     b += st;                                          // T2
     b += static_cast<size_t>(restart + 1) * st;       // Krylov basis
@@ -953,6 +1089,7 @@ void release(expdiag_ctx* h) {
   fr(h->Nh);
   fr(h->T);
   fr(h->T2);
+  fr(h->T32);
   fr(h->Uphys);
   fr(h->Uphys32);
   fr(h->u0h);
@@ -1045,7 +1182,8 @@ size_t expdiag_footprint_bytes(const expdiag_grid* g, int Nt, int scheme,
   if (precision != EXPDIAG_FP64 && precision != EXPDIAG_MIXED) return 0;
   if (gmres_restart < 0 || gmres_restart > 64) return 0;
   // the nonlinearity is not known here: report the nonlinear footprint
-  return footprint(s, Nt, true, gmres_restart);
+  return footprint(s, g->dim, Nt, true, precision == EXPDIAG_MIXED,
+                   gmres_restart);
 }
 
 }  // extern "C"
@@ -1129,6 +1267,8 @@ int create_impl(const expdiag_grid* g, int Nt, double dt, double alpha,
   A(&h->Uh, st);
   A(&h->T, st);
   if (h->nonlinear) A(&h->Nh, st);
+  if (h->nonlinear && h->mixed && h->dim >= 2)
+    A(&h->T32, static_cast<size_t>(Nt) * h->Nk * sizeof(cx<float>));
   A(&h->u0h, h->Nk * sizeof(cx<double>));
   A(&h->E, h->Nk * sizeof(double));
   A(&h->c1, h->Nk * sizeof(double));
@@ -1194,6 +1334,8 @@ int create_impl(const expdiag_grid* g, int Nt, double dt, double alpha,
       h->use_graph = false;
       h->err.clear();
       (void)hipGetLastError();
+    } else {
+      h->use_graph = plan_bytes(h->plan) < GRAPH_MAX_BYTES;
     }
   }
   if (rc != 0) {
@@ -1273,7 +1415,7 @@ int run_iterations(expdiag_ctx* h, int chunk) {
       RCHK(plan_launch(h, h->plan, h->stream, h->tw64, h->tw32));
     }
   }
-  return 0;
+  return plan_finish(h, h->plan, h->stream);
 }
 
 // Iterations to request next: what the observed contraction predicts to

@@ -6,8 +6,26 @@
 // twiddles, does a radix-r DFT in registers and scatters the outputs to LDS
 // in Stockham order; after a barrier every thread re-reads positions
 // t + s*TPL, which are exactly the inputs of its next-stage butterflies (r
-// always divides R).  After the last stage the line sits in LDS in natural
-// order and the registers again hold positions t + s*TPL.
+// always divides R).
+//
+// Stage order: the one stage whose radix is smaller than R (when log2 L is
+// not a multiple of log2 R) comes first, every later stage has radix R.  The
+// last stage then has one butterfly per thread whose outputs are positions
+// t + s*TPL of the natural-order result, so it stays in registers and the
+// transform makes (stages - 1) trips through LDS.
+//
+// Lines of stride 1 (one line per thread group, as in the row transform)
+// pad their LDS image by one slot every 8 elements: element p sits at slot
+// p + p/8.  Without the pad the radix-r scatter of the first stage puts the
+// lanes of a wave r elements apart, which maps them to the same banks.
+// Strided lines (several adjacent columns per workgroup) already give each
+// 8-lane group a contiguous run and are not padded.
+//
+// Twiddles: each stage after the first needs w^s, s = 1..R-1, with
+// w = e^{-+2 pi i k/(NS R)} for its butterfly index k.  Only w is read from
+// the table, before the barrier that precedes the stage, so the load
+// overlaps the wait; the powers are formed by products (a few ulp, within
+// the transform's own O(log L) rounding).
 //
 // Sign convention: SIGN = -1 computes X_k = sum_j x_j e^{-2 pi i jk/L}
 // (forward), SIGN = +1 the same sum with e^{+...} (unnormalised inverse).
@@ -73,7 +91,7 @@ __device__ __forceinline__ void butterfly(cx<T>* a) {
 
 template <int S, typename T>
 __device__ __forceinline__ cx<T> twid(const cx<T>* tw, int j) {
-  cx<T> w = tw[j];
+  cx<T> w = gld(tw, j);
   if constexpr (S > 0) w.y = -w.y;
   return w;
 }
@@ -87,19 +105,88 @@ struct FftShape {
   static constexpr int TPL = L / R;
 };
 
+// Barrier among the threads that share a line's LDS data: the whole block,
+// or, when every line lives inside one wavefront (WAVE), just that
+// wavefront.  A wavefront's lanes execute together and its LDS operations
+// complete in issue order, so there a compiler-level fence is all that is
+// needed and the block's other wavefronts run on independently.
+template <bool WAVE>
+__device__ __forceinline__ void line_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// LDS slot of element p of a line (padded for stride-1 lines).
+template <bool PAD>
+__device__ __forceinline__ int slot(int p) {
+  return PAD ? p + (p >> 3) : p;
+}
+// Slots one line of n elements occupies.
+constexpr int line_slots(int n, bool pad) {
+  return pad ? n + ((n - 1) >> 3) : n;
+}
+
+// Radix of the stage with span NS: the remainder radix first, then R.
+template <int L, int R, int NS>
+constexpr int stage_radix() {
+  constexpr int rb = R > 1 ? ilog2c(L / NS) % ilog2c(R) : 0;
+  return rb == 0 ? R : (1 << rb);
+}
+
+// a[s] *= w^s, s = 1..r-1
+template <int r, typename T>
+__device__ __forceinline__ void apply_twiddles(cx<T>* a, cx<T> w1) {
+  if constexpr (r >= 2) a[1] = cmul(a[1], w1);
+  if constexpr (r >= 4) {
+    const cx<T> w2 = cmul(w1, w1);
+    const cx<T> w3 = cmul(w2, w1);
+    a[2] = cmul(a[2], w2);
+    a[3] = cmul(a[3], w3);
+    if constexpr (r == 8) {
+      const cx<T> w4 = cmul(w2, w2);
+      a[4] = cmul(a[4], w4);
+      a[5] = cmul(a[5], cmul(w4, w1));
+      a[6] = cmul(a[6], cmul(w4, w2));
+      a[7] = cmul(a[7], cmul(w4, w3));
+    }
+  }
+}
+
 // One Stockham stage with span NS, then recurse.  `lds` points at element 0
-// of this thread's line; element p lives at lds[p * stride].  R elements
-// per thread (a power of two, 2..8).
-template <typename T, int L, int R, int S, int NS>
-__device__ __forceinline__ void fft_stages(cx<T> (&v)[R], cx<T>* lds,
-                                           int stride, int t,
+// of this thread's line; element p lives at lds[slot<PAD>(p) * stride].
+// w1 is this stage's base twiddle (unused when NS == 1).  OUT_LDS: also
+// leave the natural-order result in LDS (a barrier follows before anyone
+// reads it).
+template <typename T, int L, int R, int S, int NS, bool PAD, bool OUT_LDS,
+          bool WAVE>
+__device__ __forceinline__ void fft_stages(cx<T> (&v)[R], cx<T> w1,
+                                           cx<T>* lds, int stride, int t,
                                            const cx<T>* tw) {
-  if constexpr (NS < L) {
-    constexpr int TPL = L / R;
-    constexpr int rem = L / NS;
-    constexpr int r = (rem % R == 0) ? R : rem;
-    constexpr int NB = R / r;
-    constexpr int twshift = TW_LOG - ilog2c(NS * r);
+  constexpr int TPL = L / R;
+  constexpr int r = stage_radix<L, R, NS>();
+  constexpr int NB = R / r;
+  static_assert(NS == 1 || NB == 1, "only the first stage has a small radix");
+  if constexpr (NS * r == L) {
+    // last stage: one butterfly per thread, outputs t + s*TPL
+    static_assert(NB == 1, "last stage has radix R");
+    cx<T> a[R];
+#pragma unroll
+    for (int s = 0; s < R; ++s) a[s] = v[s];
+    if constexpr (NS > 1) apply_twiddles<R>(a, w1);
+    butterfly<R, S>(a);
+#pragma unroll
+    for (int s = 0; s < R; ++s) v[s] = a[s];
+    if constexpr (OUT_LDS) {
+#pragma unroll
+      for (int s = 0; s < R; ++s)
+        lds[slot<PAD>(t + s * TPL) * stride] = v[s];
+    }
+  } else {
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       const int b = t + q * TPL;
@@ -107,35 +194,42 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[R], cx<T>* lds,
       cx<T> a[r];
 #pragma unroll
       for (int s = 0; s < r; ++s) a[s] = v[q + s * NB];
-      if constexpr (NS > 1) {
-#pragma unroll
-        for (int s = 1; s < r; ++s)
-          a[s] = cmul(a[s], twid<S>(tw, (s * k) << twshift));
-      }
+      if constexpr (NS > 1) apply_twiddles<r>(a, w1);
       butterfly<r, S>(a);
       const int base = (b / NS) * NS * r + k;
 #pragma unroll
-      for (int s = 0; s < r; ++s) lds[(base + s * NS) * stride] = a[s];
+      for (int s = 0; s < r; ++s)
+        lds[slot<PAD>(base + s * NS) * stride] = a[s];
     }
-    __syncthreads();
+    // next stage: span NS*r, radix R, one butterfly (index t) per thread
+    constexpr int NS2 = NS * r;
+    constexpr int sh2 = TW_LOG - ilog2c(NS2 * R);
+    const cx<T> w2 = twid<S>(tw, (t & (NS2 - 1)) << sh2);
+    line_sync<WAVE>();
 #pragma unroll
-    for (int s = 0; s < R; ++s) v[s] = lds[(t + s * TPL) * stride];
-    if constexpr (NS * r < L) __syncthreads();
-    fft_stages<T, L, R, S, NS * r>(v, lds, stride, t, tw);
+    for (int s = 0; s < R; ++s) v[s] = lds[slot<PAD>(t + s * TPL) * stride];
+    if constexpr (NS2 * R < L || OUT_LDS) line_sync<WAVE>();
+    fft_stages<T, L, R, S, NS2, PAD, OUT_LDS, WAVE>(v, w2, lds, stride, t,
+                                                    tw);
   }
 }
 
 // Full FFT of one line.  Precondition: v[s] holds element t + s*TPL and no
 // thread still reads this line's LDS (callers place a barrier before).
-// Postcondition: natural-order result in LDS and in v (positions t+s*TPL).
-// Every thread of the block must call this (it contains barriers).
-template <typename T, int L, int S, int R>
+// Postcondition: natural-order result in v (positions t + s*TPL) and, with
+// OUT_LDS, in LDS as well (visible after the caller's next barrier).
+// Every thread of the block (WAVE: of the wavefront) must call this (it
+// contains barriers).
+template <typename T, int L, int S, bool PAD = false, bool OUT_LDS = false,
+          bool WAVE = false, int R>
 __device__ __forceinline__ void fft_line(cx<T> (&v)[R], cx<T>* lds,
                                          int stride, int t, const cx<T>* tw) {
   if constexpr (L == 1) {
+    if constexpr (OUT_LDS) lds[0] = v[0];
     return;
   } else {
-    fft_stages<T, L, R, S, 1>(v, lds, stride, t, tw);
+    fft_stages<T, L, R, S, 1, PAD, OUT_LDS, WAVE>(v, mk<T>(1, 0), lds, stride,
+                                                  t, tw);
   }
 }
 

@@ -169,6 +169,7 @@ __global__ void __launch_bounds__(DENSE_THREADS)
   const long lb = blockIdx.x - start[j];
   if constexpr (MODE == PB_ITERATE) {
     if (a.ctl->done) return;
+    if (lb == 0 && threadIdx.x == 0) a.ctl->pending = 1;
     if (a.Nh32 != nullptr && a.ctl->phase == 0)
       passb_dense_body<NT, MODE, float>(
           a, lb, static_cast<const float*>(a.Nh32), lds, red);

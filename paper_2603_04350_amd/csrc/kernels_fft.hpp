@@ -29,6 +29,8 @@ struct Ctl {
   int iters;     // iterations completed
   int max_iter;
   int phase;     // 0: fp32 bulk residual (mixed precision), 1: fp64
+  int pending;   // 1: pass B wrote block partials not yet reduced
+  int spare;
   double tol;       // ||S|| / ||U|| target
   double bulk_tol;  // switch from phase 0 to 1 below this
   double last_rel;
@@ -36,22 +38,29 @@ struct Ctl {
   double last_unorm;
 };
 
+// Phase of the job's instance (1 without a control block), or -1 when it
+// has finished.
+__device__ __forceinline__ int job_phase(const Ctl* c) {
+  if (c == nullptr) return 1;
+  if (gld(&c->done, 0)) return -1;
+  return gld(&c->phase, 0);
+}
+
 // True when the job's instance still needs this work.  phase_req < 0: any
 // phase.
 __device__ __forceinline__ bool job_live(const Ctl* c, int phase_req) {
   if (c == nullptr) return true;
-  if (c->done) return false;
-  return phase_req < 0 || c->phase == phase_req;
+  if (gld(&c->done, 0)) return false;
+  return phase_req < 0 || gld(&c->phase, 0) == phase_req;
 }
 
-// Job index of this block: largest j with start[j] <= blockIdx.x.  The
-// result is the same for the whole block; readfirstlane makes that visible
-// to the compiler so the job descriptor is fetched with scalar loads into
-// scalar registers.
+// Job index of logical block b: largest j with start[j] <= b.  The result
+// is the same for the whole block; readfirstlane makes that visible to the
+// compiler so the job descriptor is fetched with scalar loads into scalar
+// registers.
 __device__ __forceinline__ int find_job(const int* __restrict__ start,
-                                        int njobs) {
+                                        int njobs, int b) {
   int lo = 0, hi = njobs - 1;
-  const int b = blockIdx.x;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (start[mid] <= b)
@@ -60,6 +69,20 @@ __device__ __forceinline__ int find_job(const int* __restrict__ start,
       hi = mid - 1;
   }
   return __builtin_amdgcn_readfirstlane(lo);
+}
+__device__ __forceinline__ int find_job(const int* __restrict__ start,
+                                        int njobs) {
+  return find_job(start, njobs, blockIdx.x);
+}
+
+// Workgroups of a launch are dealt to the eight XCDs in turn (block b runs
+// on XCD b % 8, each with its own L2).  This renumbering gives each XCD a
+// contiguous range of logical blocks, so neighbouring tiles, which share
+// the 128-byte lines at their edges, meet in the same L2.  A bijection of
+// [0, G) for any G.
+__device__ __forceinline__ int xcd_block(int b, int G) {
+  const int q = G >> 3, rem = G & 7, x = b & 7;
+  return x * q + (x < rem ? x : rem) + (b >> 3);
 }
 
 enum RowMode : int {
@@ -85,7 +108,10 @@ struct RowShape {
   static constexpr int TPR = FftShape<M>::TPL;
   static constexpr int RPB = TPR >= 256 ? 1 : 256 / TPR;
   static constexpr int THREADS = RPB * TPR;
-  static constexpr int LS = M + 1;  // LDS complex slots per row
+  // a row inside one wavefront synchronises only that wavefront
+  static constexpr bool WAVE = TPR <= 64;
+  // LDS slots per row: elements 0..M, padded one slot in nine
+  static constexpr int LS = line_slots(M + 1, true);
 };
 
 struct RowJob {
@@ -100,33 +126,34 @@ struct RowJob {
 };
 
 // One block of the row transform: rows [lb*RPB, lb*RPB + RPB) of job `jb`.
+// Row element k sits in LDS slot slot<true>(k) of its row.
+// `lds` holds RPB * LS elements.
 template <typename T, int M, int MODE, typename TI, typename TO>
 __device__ __forceinline__ void row_body(const RowJob& jb, long lb,
-                                         const cx<T>* __restrict__ tw) {
+                                         const cx<T>* __restrict__ tw,
+                                         cx<T>* lds) {
   using S = RowShape<M>;
   constexpr int R = S::R;
   constexpr int TPR = S::TPR;
   constexpr int wshift = TW_LOG - ilog2c(2 * M);
-  __shared__ cx<T> lds[S::RPB * S::LS];
   const int rl = threadIdx.x / TPR;
   const int t = threadIdx.x % TPR;
   const long row = lb * S::RPB + rl;
   const bool valid = row < jb.nrows;
+  // rows past the end read the last row (in bounds) and store nothing
+  const long rowc = valid ? row : jb.nrows - 1;
   cx<T>* lrow = lds + rl * S::LS;
-  const TI* in = static_cast<const TI*>(jb.in);
-  TO* out = static_cast<TO*>(jb.out);
+  const cx<TI>* src =
+      static_cast<const cx<TI>*>(jb.in) + rowc * (jb.in_pitch >> 1);
   const T n1 = static_cast<T>(jb.n1), n2 = static_cast<T>(jb.n2),
           n3 = static_cast<T>(jb.n3);
   const T scale = static_cast<T>(jb.scale);
   cx<T> v[R];
 
   if constexpr (MODE == ROW_R2C || MODE == ROW_NR2C) {
-    const TI* src = in + row * jb.in_pitch;
 #pragma unroll
     for (int s = 0; s < R; ++s) {
-      const int j = t + s * TPR;
-      cx<T> z = mk<T>(0, 0);
-      if (valid) z = cvt<T>(*reinterpret_cast<const cx<TI>*>(src + 2 * j));
+      cx<T> z = cvt<T>(gld(src, t + s * TPR));
       if constexpr (MODE == ROW_NR2C) {
         z.x = nonlin(z.x, n1, n2, n3);
         z.y = nonlin(z.y, n1, n2, n3);
@@ -135,26 +162,19 @@ __device__ __forceinline__ void row_body(const RowJob& jb, long lb,
     }
   } else {
     // load X_0..X_M of the half-spectrum row into LDS
-    const TI* src = in + row * jb.in_pitch;
 #pragma unroll
     for (int s = 0; s < R; ++s) {
       const int k = t + s * TPR;
-      cx<T> x = mk<T>(0, 0);
-      if (valid) x = cvt<T>(*reinterpret_cast<const cx<TI>*>(src + 2 * k));
-      lrow[k] = x;
+      lrow[slot<true>(k)] = cvt<T>(gld(src, k));
     }
-    if (t == 0) {
-      cx<T> x = mk<T>(0, 0);
-      if (valid) x = cvt<T>(*reinterpret_cast<const cx<TI>*>(src + 2 * M));
-      lrow[M] = x;
-    }
-    __syncthreads();
+    if (t == 0) lrow[slot<true>(M)] = cvt<T>(gld(src, M));
+    line_sync<S::WAVE>();
     // Z_k = [(X_k + conj X_{M-k}) + i (X_k - conj X_{M-k}) W^{-k}] * scale
 #pragma unroll
     for (int s = 0; s < R; ++s) {
       const int k = t + s * TPR;
-      cx<T> xk = lrow[k];
-      cx<T> xm = lrow[M - k];
+      cx<T> xk = lrow[slot<true>(k)];
+      cx<T> xm = lrow[slot<true>(M - k)];
       if (k == 0) {  // the k = 0 and Nyquist bins of a real row are real
         xk.y = 0;
         xm.y = 0;
@@ -163,17 +183,14 @@ __device__ __forceinline__ void row_body(const RowJob& jb, long lb,
       const cx<T> o2 = cmulc(xk - conj(xm), tw[k << wshift]);
       v[s] = (e2 + mul_si<1>(o2)) * scale;
     }
-    __syncthreads();
-    fft_line<T, M, 1>(v, lrow, 1, t, tw);
+    line_sync<S::WAVE>();
+    fft_line<T, M, 1, true, false, S::WAVE>(v, lrow, 1, t, tw);
     // v[s] = z_j = x_{2j} + i x_{2j+1},  j = t + s*TPR
     if constexpr (MODE == ROW_C2R) {
       if (valid) {
-        TO* dst = out + row * jb.out_pitch;
+        cx<TO>* dst = static_cast<cx<TO>*>(jb.out) + row * (jb.out_pitch >> 1);
 #pragma unroll
-        for (int s = 0; s < R; ++s) {
-          const int j = t + s * TPR;
-          *reinterpret_cast<cx<TO>*>(dst + 2 * j) = cvt<TO>(v[s]);
-        }
+        for (int s = 0; s < R; ++s) gst(dst, t + s * TPR, cvt<TO>(v[s]));
       }
       return;
     } else if constexpr (MODE == ROW_FUSED) {
@@ -183,29 +200,29 @@ __device__ __forceinline__ void row_body(const RowJob& jb, long lb,
         v[s].y = nonlin(v[s].y, n1, n2, n3);
       }
     } else {  // ROW_JVP
-      const TI* ua = static_cast<const TI*>(jb.aux) + row * jb.aux_pitch;
+      const cx<TI>* ua =
+          static_cast<const cx<TI>*>(jb.aux) + rowc * (jb.aux_pitch >> 1);
 #pragma unroll
       for (int s = 0; s < R; ++s) {
-        const int j = t + s * TPR;
-        cx<T> u = mk<T>(0, 0);
-        if (valid) u = cvt<T>(*reinterpret_cast<const cx<TI>*>(ua + 2 * j));
+        const cx<T> u = cvt<T>(gld(ua, t + s * TPR));
         v[s].x *= dnonlin(u.x, n1, n2, n3);
         v[s].y *= dnonlin(u.y, n1, n2, n3);
       }
     }
-    __syncthreads();
+    line_sync<S::WAVE>();
   }
 
   // forward: Z = FFT_M(z), then X_k = E_k + W^k O_k
-  fft_line<T, M, -1>(v, lrow, 1, t, tw);
+  fft_line<T, M, -1, true, true, S::WAVE>(v, lrow, 1, t, tw);
+  line_sync<S::WAVE>();
   if (!valid) return;
-  TO* dst = out + row * jb.out_pitch;
+  cx<TO>* dst = static_cast<cx<TO>*>(jb.out) + row * (jb.out_pitch >> 1);
   cx<T> x0e, x0o;
 #pragma unroll
   for (int s = 0; s < R; ++s) {
     const int k = t + s * TPR;
     const cx<T> zk = v[s];
-    const cx<T> zm = conj(lrow[(M - k) & (M - 1)]);
+    const cx<T> zm = conj(lrow[slot<true>((M - k) & (M - 1))]);
     const cx<T> e = (zk + zm) * static_cast<T>(0.5);
     const cx<T> o = mul_si<-1>(zk - zm) * static_cast<T>(0.5);
     if (s == 0) {
@@ -213,27 +230,44 @@ __device__ __forceinline__ void row_body(const RowJob& jb, long lb,
       x0o = o;
     }
     const cx<T> x = e + cmul(tw[k << wshift], o);
-    *reinterpret_cast<cx<TO>*>(dst + 2 * k) = cvt<TO>(x);
+    gst(dst, k, cvt<TO>(x));
   }
-  if (t == 0) *reinterpret_cast<cx<TO>*>(dst + 2 * M) = cvt<TO>(x0e - x0o);
+  if (t == 0) gst(dst, M, cvt<TO>(x0e - x0o));
 }
 
-template <typename T, int M, int MODE, typename TI, typename TO>
+// Job-table launch of one pass-A stage for instances in either precision
+// phase: jobs[2i] is instance i's fp32 job (mixed-precision bulk phase),
+// jobs[2i + 1] its fp64 job, and the instance's control block picks one, so
+// an iteration costs one launch per stage in either phase.  Both bodies
+// share one LDS tile (the fp32 one uses half of it).
+template <int M, int MODE, typename TI0>
 __global__ void __launch_bounds__(RowShape<M>::THREADS)
-    row_kernel(const RowJob* __restrict__ jobs, const int* __restrict__ start,
-               int njobs, const cx<T>* __restrict__ tw) {
-  const int j = find_job(start, njobs);
-  const RowJob jb = jobs[j];
-  if (!job_live(jb.ctl, jb.phase_req)) return;
-  row_body<T, M, MODE, TI, TO>(jb, blockIdx.x - start[j], tw);
+    row_kernel_mp(const RowJob* __restrict__ jobs,
+                  const int* __restrict__ start, int njobs,
+                  const cx<float>* __restrict__ tw32,
+                  const cx<double>* __restrict__ tw64) {
+  __shared__ cx<double> lds[RowShape<M>::RPB * RowShape<M>::LS];
+  const int i = find_job(start, njobs);
+  const long lb = blockIdx.x - start[i];
+  const int ph = job_phase(jobs[2 * i + 1].ctl);
+  if (ph < 0) return;
+  if (ph == 0) {
+    const RowJob jb = jobs[2 * i];
+    row_body<float, M, MODE, TI0, float>(jb, lb, tw32,
+                                         reinterpret_cast<cx<float>*>(lds));
+  } else {
+    const RowJob jb = jobs[2 * i + 1];
+    row_body<double, M, MODE, double, double>(jb, lb, tw64, lds);
+  }
 }
 
 // single job passed by value (per-call boundary transforms)
 template <typename T, int M, int MODE, typename TI, typename TO>
 __global__ void __launch_bounds__(RowShape<M>::THREADS)
     row_kernel1(RowJob jb, const cx<T>* __restrict__ tw) {
+  __shared__ cx<T> lds[RowShape<M>::RPB * RowShape<M>::LS];
   if (!job_live(jb.ctl, jb.phase_req)) return;
-  row_body<T, M, MODE, TI, TO>(jb, blockIdx.x, tw);
+  row_body<T, M, MODE, TI, TO>(jb, blockIdx.x, tw, lds);
 }
 
 // C adjacent columns per workgroup; LDS of L*C complex (32 KiB in fp64 for
@@ -258,55 +292,70 @@ struct ColJob {
 
 // Length-L transform along the middle axis of [outer][L][inner]; element
 // (o, p, c) at (o*L + p)*inner + c.  out = scale * FFT_S(in); in-place safe.
+// A job has outer * ceil(inner / C) blocks; lb < that count.
+// `lds` holds L * LS elements.
 template <typename T, int L, int S, typename TI, typename TO>
-__device__ __forceinline__ void col_body(const ColJob& jb, long lb,
-                                         const cx<T>* __restrict__ tw) {
+__device__ __forceinline__ void col_body(const ColJob& jb, int lb,
+                                         const cx<T>* __restrict__ tw,
+                                         cx<T>* lds) {
   using SH = ColShape<L>;
   constexpr int R = SH::R;
   constexpr int TPL = SH::TPL;
   constexpr int C = SH::C;
-  __shared__ cx<T> lds[L * SH::LS];
-  const long inner = jb.inner;
-  const long tiles = (inner + C - 1) / C;
-  const long o = lb / tiles;
-  const long tile = lb % tiles;
+  const int inner = static_cast<int>(jb.inner);
+  const int tiles = (inner + C - 1) / C;
+  const int o = lb / tiles;
+  const int tile = lb - o * tiles;
   const int c = threadIdx.x % C;
   const int t = threadIdx.x / C;
-  const long col = tile * C + c;
-  const bool valid = (col < inner) && (o < jb.outer);
-  const cx<TI>* src = static_cast<const cx<TI>*>(jb.in) + o * L * inner + col;
+  const int col = tile * C + c;
+  const bool valid = col < inner;
+  // columns past the edge read the last column (in bounds), store nothing
+  const long base = static_cast<long>(o) * L * inner + (valid ? col : inner - 1);
+  const cx<TI>* src = static_cast<const cx<TI>*>(jb.in) + base;
   cx<T> v[R];
 #pragma unroll
-  for (int s = 0; s < R; ++s) {
-    const long p = t + s * TPL;
-    v[s] = valid ? cvt<T>(src[p * inner]) : mk<T>(0, 0);
-  }
+  for (int s = 0; s < R; ++s) v[s] = cvt<T>(gld(src, (t + s * TPL) * inner));
   fft_line<T, L, S>(v, lds + c, SH::LS, t, tw);
   if (!valid) return;
-  cx<TO>* dst = static_cast<cx<TO>*>(jb.out) + o * L * inner + col;
+  cx<TO>* dst = static_cast<cx<TO>*>(jb.out) + base;
   const T scale = static_cast<T>(jb.scale);
 #pragma unroll
-  for (int s = 0; s < R; ++s) {
-    const long p = t + s * TPL;
-    dst[p * inner] = cvt<TO>(v[s] * scale);
-  }
+  for (int s = 0; s < R; ++s)
+    gst(dst, (t + s * TPL) * inner, cvt<TO>(v[s] * scale));
 }
 
-template <typename T, int L, int S, typename TI, typename TO>
+// Job-table launch for instances in either precision phase (see
+// row_kernel_mp): jobs[2i] fp32 (input type TI0, fp32 output), jobs[2i + 1]
+// fp64.
+template <int L, int S, typename TI0>
 __global__ void __launch_bounds__(ColShape<L>::THREADS, 5)
-    col_kernel(const ColJob* __restrict__ jobs, const int* __restrict__ start,
-               int njobs, const cx<T>* __restrict__ tw) {
-  const int j = find_job(start, njobs);
-  const ColJob jb = jobs[j];
-  if (!job_live(jb.ctl, jb.phase_req)) return;
-  col_body<T, L, S, TI, TO>(jb, blockIdx.x - start[j], tw);
+    col_kernel_mp(const ColJob* __restrict__ jobs,
+                  const int* __restrict__ start, int njobs,
+                  const cx<float>* __restrict__ tw32,
+                  const cx<double>* __restrict__ tw64) {
+  __shared__ cx<double> lds[L * ColShape<L>::LS];
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int i = find_job(start, njobs, b);
+  const int lb = b - start[i];
+  const int ph = job_phase(jobs[2 * i + 1].ctl);
+  if (ph < 0) return;
+  if (ph == 0) {
+    const ColJob jb = jobs[2 * i];
+    col_body<float, L, S, TI0, float>(jb, lb, tw32,
+                                      reinterpret_cast<cx<float>*>(lds));
+  } else {
+    const ColJob jb = jobs[2 * i + 1];
+    col_body<double, L, S, double, double>(jb, lb, tw64, lds);
+  }
 }
 
 template <typename T, int L, int S, typename TI, typename TO>
 __global__ void __launch_bounds__(ColShape<L>::THREADS, 5)
     col_kernel1(ColJob jb, const cx<T>* __restrict__ tw) {
+  __shared__ cx<T> lds[L * ColShape<L>::LS];
   if (!job_live(jb.ctl, jb.phase_req)) return;
-  col_body<T, L, S, TI, TO>(jb, blockIdx.x, tw);
+  col_body<T, L, S, TI, TO>(jb, xcd_block(blockIdx.x, gridDim.x), tw, lds);
 }
 
 }  // namespace expdiag

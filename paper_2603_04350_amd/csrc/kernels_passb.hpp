@@ -27,6 +27,8 @@
 
 namespace expdiag {
 
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
 enum PassBMode : int {
   PB_ITERATE = 0,   // residual + precond + update of U
   PB_PRECOND = 1,   // Sout = Q_alpha^{-1} Rin
@@ -62,17 +64,21 @@ struct PassBArgs {
   double inv_ns;
 };
 
-// C kappa columns per workgroup; the LDS tile is NT*C complex (32 KiB for
-// NT <= 256), the block reduction reuses it, so five workgroups fit a CU.
-// Four time rows per thread (radix-4 stages) keep the registers within
-// that occupancy.
+// C kappa columns per workgroup, TPL threads per column, four time rows per
+// thread (radix-4 stages keep the registers within the occupancy below).
+// Thread (c, t) = (tid % C, tid / C) and tile element (l, c) at LDS l*C + c,
+// so every global access of a wavefront is a run of C adjacent kappa (256
+// bytes).  (A layout with whole columns inside one wavefront needs only
+// wavefront-level synchronisation, but splits each wavefront's global
+// accesses into 64-byte runs and costs registers; it measured slower.)
 template <int NT>
 struct PassBShape {
   static constexpr int R = FftShape<NT, 4>::R;
   static constexpr int TPL = FftShape<NT, 4>::TPL;
   static constexpr int C = (256 / TPL) >= 4 ? 256 / TPL : 4;
   static constexpr int THREADS = C * TPL;
-  static constexpr int LS = C;
+  static constexpr int LS = C;        // LDS row (complex slots)
+  static constexpr int LDS = NT * C;  // complex elements of the tile
   // waves per SIMD the register budget targets (longer time lines keep
   // more twiddles live)
   static constexpr int WAVES = NT <= 64 ? 5 : 4;
@@ -135,7 +141,9 @@ __device__ inline void advance_ctl(const PassBArgs& a, const double* tot) {
     done = 1;
   }
   const bool publish = done != 0 || (it & 3) == 0 || c->phase != phase0;
-  c->done = done;
+  // read concurrently by the column blocks of the launch this may run in
+  __hip_atomic_store(&c->done, done, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
   if (a.hmirror != nullptr && publish) {
     volatile Ctl* m = a.hmirror;
     m->iters = it;
@@ -162,7 +170,7 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
   const long kap = lb * C + c;
   const bool valid = kap < a.Nk;
   const long Nk = a.Nk;
-  const double E = valid ? a.E[kap] : 0.0;
+  const double E = valid ? gld(a.E, kap) : 0.0;
   const int kl = static_cast<int>(kap % a.nh);
   const double pw = (!valid) ? 0.0 : ((kl == 0 || kl == a.nh - 1) ? 1.0 : 2.0);
 
@@ -174,9 +182,9 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
 #pragma unroll
     for (int s = 0; s < R; ++s) {
       const int l = t + s * TPL;
-      const cx<double> r = valid ? a.Rin[l * Nk + kap] : mk(0.0, 0.0);
+      const cx<double> r = valid ? gld(a.Rin, l * Nk + kap) : mk(0.0, 0.0);
       nrm_r += pw * norm2(r);
-      v[s] = r * a.gam[l];
+      v[s] = r * gld(a.gam, l);
     }
   } else {
     // rows of U (or of the Krylov vector v for PB_OPAPPLY) and, issued
@@ -187,15 +195,15 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
 #pragma unroll
     for (int s = 0; s < R; ++s) {
       const int l = t + s * TPL;
-      u[s] = valid ? a.U[l * Nk + kap] : mk(0.0, 0.0);
+      u[s] = valid ? gld(a.U, l * Nk + kap) : mk(0.0, 0.0);
       n_cur[s] = mk(0.0, 0.0);
       if (nl_on && (MODE != PB_OPAPPLY || l >= 1))
-        n_cur[s] = cvt<double>(Nc[l * Nk + kap]);
+        n_cur[s] = cvt<double>(gld(Nc, l * Nk + kap));
     }
     const cx<double> first =
-        (MODE == PB_OPAPPLY || !valid) ? mk(0.0, 0.0) : a.u0h[kap];
-    const double c1 = nl_on ? a.c1[kap] : 0.0;
-    const double c2 = (nl_on && a.etd2) ? a.c2[kap] : 0.0;
+        (MODE == PB_OPAPPLY || !valid) ? mk(0.0, 0.0) : gld(a.u0h, kap);
+    const double c1 = nl_on ? gld(a.c1, kap) : 0.0;
+    const double c2 = (nl_on && a.etd2) ? gld(a.c2, kap) : 0.0;
 #pragma unroll
     for (int s = 0; s < R; ++s) lds[(t + s * TPL) * LS + c] = u[s];
     __syncthreads();
@@ -211,22 +219,22 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
         // (Q - G'(U)) v : v_l - E v_{l-1} - (c1 J_l + c2 J_{l-1}), where
         // J_l = FFT[N'(u_{l-1}) v_{l-1}] (J_0 = J_{-1} = 0: u_0 is fixed)
         if (nl_on && a.etd2 && l >= 2)
-          n_prev = cvt<double>(Nc[(l - 1) * Nk + kap]);
+          n_prev = cvt<double>(gld(Nc, (l - 1) * Nk + kap));
         r = u[s] - prev * E - n_cur[s] * c1 - n_prev * c2;
       } else {
         if (nl_on && a.etd2)
-          n_prev = cvt<double>(Nc[(l == 0 ? 0 : l - 1) * Nk + kap]);
+          n_prev = cvt<double>(gld(Nc, (l == 0 ? 0 : l - 1) * Nk + kap));
         r = prev * E - u[s] + n_cur[s] * c1 + n_prev * c2;
       }
       nrm_r += pw * norm2(r);
-      v[s] = r * a.gam[l];
+      v[s] = r * gld(a.gam, l);
     }
     if constexpr (MODE == PB_RESIDUAL) {
       if (valid) {
 #pragma unroll
         for (int s = 0; s < R; ++s) {
           const int l = t + s * TPL;
-          a.Sout[l * Nk + kap] = v[s] * a.igam[l];
+          gst(a.Sout, l * Nk + kap, v[s] * gld(a.igam, l));
         }
       }
       double acc[4] = {nrm_r, 0.0, 0.0, 0.0};
@@ -242,7 +250,7 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
 #pragma unroll
   for (int s = 0; s < R; ++s) {
     const int m = t + s * TPL;
-    const cx<double> lam = a.lam[m];
+    const cx<double> lam = gld(a.lam, m);
     const double dr = 1.0 - lam.x * E, di = -lam.y * E;
     const double inv = 1.0 / (NT * (dr * dr + di * di));
     v[s] = cmul(v[s], mk(dr * inv, -di * inv));
@@ -255,19 +263,19 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
 #pragma unroll
     for (int s = 0; s < R; ++s) {
       const int l = t + s * TPL;
-      const cx<double> sv = v[s] * a.igam[l];
+      const cx<double> sv = v[s] * gld(a.igam, l);
       const cx<double> un = u[s] + sv;
       nrm_s += pw * norm2(sv);
       nrm_u += pw * norm2(un);
-      if (valid) a.U[l * Nk + kap] = un;
+      if (valid) gst(a.U, l * Nk + kap, un);
     }
   } else {
 #pragma unroll
     for (int s = 0; s < R; ++s) {
       const int l = t + s * TPL;
-      const cx<double> sv = v[s] * a.igam[l];
+      const cx<double> sv = v[s] * gld(a.igam, l);
       nrm_s += pw * norm2(sv);
-      if (valid) a.Sout[l * Nk + kap] = sv;
+      if (valid) gst(a.Sout, l * Nk + kap, sv);
     }
   }
   double acc[4] = {nrm_r, nrm_s, nrm_u, 0.0};
@@ -287,15 +295,16 @@ __global__ void __launch_bounds__(PassBShape<NT>::THREADS,
     passb_kernel(const PassBArgs* __restrict__ jobs,
                  const int* __restrict__ start, int njobs) {
   using SH = PassBShape<NT>;
-  static_assert(NT * SH::LS * 2 >= ((SH::THREADS + 63) / 64) * 4,
+  static_assert(SH::LDS * 2 >= ((SH::THREADS + 63) / 64) * 4,
                 "reduction scratch fits the tile");
-  __shared__ cx<double> lds[NT * SH::LS];
+  __shared__ cx<double> lds[SH::LDS];
   double* red = reinterpret_cast<double*>(lds);
   const int j = find_job(start, njobs);
   const PassBArgs a = jobs[j];  // by value: the kernel stores through a.U
   const long lb = blockIdx.x - start[j];
   if constexpr (MODE == PB_ITERATE) {
     if (a.ctl->done) return;
+    if (lb == 0 && threadIdx.x == 0) a.ctl->pending = 1;
     if (a.Nh32 != nullptr && a.ctl->phase == 0)
       passb_body<NT, MODE, float>(a, lb, static_cast<const float*>(a.Nh32),
                                   lds, red);
@@ -307,21 +316,83 @@ __global__ void __launch_bounds__(PassBShape<NT>::THREADS,
   }
 }
 
-// One block per job of a pass B job table: fixed-order sum of that
-// instance's block partials, then its convergence bookkeeping.
-__global__ void __launch_bounds__(256)
-    ctl_reduce_kernel(const PassBArgs* __restrict__ jobs, int njobs) {
-  __shared__ double red[4 * 4];
-  const PassBArgs a = jobs[blockIdx.x];
-  if (a.ctl->done) return;
+// Convergence bookkeeping of one instance after a pass B: the fixed-order
+// sum of its block partials, then advance_ctl.  Runs in one block of THREADS
+// threads; does nothing unless a pass B has written partials since the
+// last reduction (Ctl::pending), so it may be issued more often than
+// needed.  Thread i adds partials i, i + THREADS, ... in that order (all of
+// its loads issued before the first add), then the block sums the threads
+// in a fixed tree.
+template <int THREADS>
+__device__ __forceinline__ void reduce_instance(const PassBArgs& a,
+                                                double* red) {
+  constexpr int UNROLL = 4;
+  Ctl* ctl = a.ctl;
+  if (gld(&ctl->done, 0) || !gld(&ctl->pending, 0)) return;
+  const int nb = a.nblocks;
+  const dbl2* pp = reinterpret_cast<const dbl2*>(a.partials);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int b = threadIdx.x; b < a.nblocks; b += 256) {
+  for (int b0 = threadIdx.x; b0 < nb; b0 += THREADS * UNROLL) {
+    dbl2 lo[UNROLL], hi[UNROLL];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) acc[j] += a.partials[b * 4 + j];
+    for (int i = 0; i < UNROLL; ++i) {
+      const int b = b0 + i * THREADS;
+      lo[i] = b < nb ? gld(pp, 2 * b) : dbl2{0.0, 0.0};
+      hi[i] = b < nb ? gld(pp, 2 * b + 1) : dbl2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int i = 0; i < UNROLL; ++i) {
+      acc[0] += lo[i].x;
+      acc[1] += lo[i].y;
+      acc[2] += hi[i].x;
+    }
   }
   double tot[4];
-  block_sum<4, 256>(acc, red, tot);
-  if (threadIdx.x == 0) advance_ctl(a, tot);
+  block_sum<4, THREADS>(acc, red, tot);
+  if (threadIdx.x == 0) {
+    ctl->pending = 0;
+    advance_ctl(a, tot);
+  }
+}
+
+// One block per job of a pass B job table.
+constexpr int CTL_THREADS = 1024;
+
+__global__ void __launch_bounds__(CTL_THREADS)
+    ctl_reduce_kernel(const PassBArgs* __restrict__ jobs, int njobs) {
+  __shared__ double red[(CTL_THREADS / 64) * 4];
+  reduce_instance<CTL_THREADS>(jobs[blockIdx.x], red);
+}
+
+// The first inverse column stage of pass A (fp64, Uh -> T) with the
+// previous iteration's convergence bookkeeping folded in: logical blocks
+// [0, nred) each reduce one instance (red_jobs), the rest transform.  The
+// transform does not depend on the convergence state (only pass B changes
+// U), so it runs alongside the reduction; the later stages of the
+// iteration, launched after this one, see the updated state.  A block may
+// still transform an instance whose reduction in this launch finds it done:
+// the result is never read.
+template <int L, int S>
+__global__ void __launch_bounds__(ColShape<L>::THREADS, 5)
+    col_kernel_host(const ColJob* __restrict__ jobs,
+                    const int* __restrict__ start, int njobs,
+                    const PassBArgs* __restrict__ red_jobs, int nred,
+                    const cx<double>* __restrict__ tw64) {
+  __shared__ cx<double> lds[L * ColShape<L>::LS];
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  if (b < nred) {
+    reduce_instance<ColShape<L>::THREADS>(red_jobs[b],
+                                          reinterpret_cast<double*>(lds));
+    return;
+  }
+  const int cb = b - nred;
+  const int i = find_job(start, njobs, cb);
+  const ColJob jb = jobs[i];
+  if (jb.ctl != nullptr &&
+      __hip_atomic_load(&jb.ctl->done, __ATOMIC_RELAXED,
+                        __HIP_MEMORY_SCOPE_AGENT))
+    return;
+  col_body<double, L, S, double, double>(jb, cb - start[i], tw64, lds);
 }
 
 template <int NT, int MODE, typename TN>
@@ -329,7 +400,7 @@ __global__ void __launch_bounds__(PassBShape<NT>::THREADS,
                                   PassBShape<NT>::WAVES)
     passb_kernel1(PassBArgs a) {
   using SH = PassBShape<NT>;
-  __shared__ cx<double> lds[NT * SH::LS];
+  __shared__ cx<double> lds[SH::LDS];
   double* red = reinterpret_cast<double*>(lds);
   passb_body<NT, MODE, TN>(a, blockIdx.x, static_cast<const TN*>(a.Nh), lds,
                            red);
