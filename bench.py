@@ -10,16 +10,17 @@ tolerance ||S||/||U|| <= 1e-11 (which lands within 1e-10 of sequential
 stepping), inputs already resident in HBM: boundary FFTs and every
 fixed-point iteration (pass A: spatial FFTs + nonlinearity; pass B:
 residual, alpha-scaled time transform, shifted solves, inverse transform,
-update, norms), replayed as a captured hipGraph.
+update, norms), launched as the library chooses for this size (plain
+launches; a captured hipGraph only for small iterates).
 
 value = space-time DOF-iterations per second of the plain FP64 solve
 (S = 256^2 * 64 DOF times iterations, over wall time).  Beside it:
   * the mixed-precision solve (fp32 bulk residual, fp64 refinement) timed
     the same way, with its time-to-tolerance against the FP64 path;
-  * per-kernel durations from HIP events recorded on the library's stream
-    around every launch during a second timed region of the same solves
-    (plain launches, so each kernel can be bracketed), and the roofline of
-    the dominant kernel from its algorithmic bytes per launch;
+  * per-kernel durations from HIP events attached to the launches of the
+    dominant kernel class (hipExtLaunchKernel start/stop events, on the
+    library's stream) during a second timed region of the same solves, and
+    the roofline of that class from its algorithmic bytes per launch;
   * batched: 256 heterogeneous Allen-Cahn instances (n in {64,128,256},
     Nt in {16..128}, eps ~ U[0.02,0.1], alpha in {1e-2,1e-3}) solved in one
     batched plan in mixed precision, against the same instances solved one

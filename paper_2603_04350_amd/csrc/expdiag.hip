@@ -16,6 +16,7 @@
 // batch of instances of any shapes costs one launch per group.  The plan is
 // captured once into a hipGraph and replayed; finished instances and
 // off-phase jobs exit at their first instruction.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -214,24 +215,42 @@ constexpr int tcode_of() {
 // ---------------------------------------------------------------- profiling
 // Brackets one launch with events when profiling is on and accounts the
 // launch's algorithmic bytes (what the kernel must read and write once).
+// With `ext` the launch itself carries the events (klaunch) and they time
+// the kernel's execution; otherwise they are recorded on the stream around
+// it (which adds the dispatch latency).
 struct ProfScope {
   expdiag_ctx* h;
   int cls;
+  bool ext;
   EventPair* ep = nullptr;
-  ProfScope(expdiag_ctx* h_, int c, double bytes) : h(h_), cls(c) {
+  ProfScope(expdiag_ctx* h_, int c, double bytes, bool ext_ = false)
+      : h(h_), cls(c), ext(ext_) {
     if (h == nullptr || !h->prof) return;
     h->prof_bytes[c] += bytes;
     h->prof_all[c] += 1;
     if (((h->prof_mask >> c) & 1) && h->ev_used < h->events.size()) {
       ep = &h->events[h->ev_used++];
       ep->cls = cls;
-      (void)hipEventRecord(ep->a, h->stream);
+      if (!ext) (void)hipEventRecord(ep->a, h->stream);
     }
   }
   ~ProfScope() {
-    if (ep != nullptr) (void)hipEventRecord(ep->b, h->stream);
+    if (ep != nullptr && !ext) (void)hipEventRecord(ep->b, h->stream);
   }
 };
+
+// Launch `kernel` on `st`.  When `ps` (made with ext) brackets this launch,
+// its start and stop events are attached to the dispatch itself, so they
+// record when the kernel starts and ends on the GPU.
+template <typename... KArgs, typename... Args>
+void klaunch(const ProfScope& ps, void (*kernel)(KArgs...), dim3 grid,
+             dim3 block, hipStream_t st, Args... args) {
+  if (ps.ep != nullptr)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, st, ps.ep->a, ps.ep->b, 0,
+                          args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+}
 
 template <typename T>
 const cx<T>* twid_table(expdiag_ctx* h) {
@@ -770,30 +789,28 @@ void plan_free(Plan& P) { plan_clear(P, false); }
 
 // Launch every group of the plan on `st` in stage order.  `ph` is the handle
 // used for profiling and error text (nullable).
-int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st, const cx<double>* tw64,
-                const cx<float>* tw32) {
+int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st,
+                const cx<double>* tw64, const cx<float>* tw32) {
   for (auto& g : P.groups) {
     const int grid = g.grid();
     if (grid == 0) continue;
     const int nj = g.njobs();
     bool ok = false;
     if (g.kind == K_ROW) {
-      ProfScope ps(ph, P_ROW, g.bytes);
+      ProfScope ps(ph, P_ROW, g.bytes, true);
       const RowJob* J = static_cast<const RowJob*>(g.djobs);
       ok = dispatch_pow2<2, 512>(g.len, [&](auto Mc) {
         constexpr int MM = decltype(Mc)::value;
         const dim3 th(RowShape<MM>::THREADS);
         if (g.ti == 0)  // 1D: the fp32 job reads the fp64 spectrum
-          hipLaunchKernelGGL((row_kernel_mp<MM, ROW_FUSED, double>),
-                             dim3(grid), th, 0, st, J, g.dstart, nj, tw32,
-                             tw64);
+          klaunch(ps, row_kernel_mp<MM, ROW_FUSED, double>, dim3(grid), th, st,
+                  J, g.dstart, nj, tw32, tw64);
         else
-          hipLaunchKernelGGL((row_kernel_mp<MM, ROW_FUSED, float>),
-                             dim3(grid), th, 0, st, J, g.dstart, nj, tw32,
-                             tw64);
+          klaunch(ps, row_kernel_mp<MM, ROW_FUSED, float>, dim3(grid), th, st,
+                  J, g.dstart, nj, tw32, tw64);
       });
     } else if (g.kind == K_COL && g.tcode == 3) {
-      ProfScope ps(ph, P_COL, g.bytes);
+      ProfScope ps(ph, P_COL, g.bytes, true);
       const ColJob* J = static_cast<const ColJob*>(g.djobs);
       const PassBArgs* RJ = static_cast<const PassBArgs*>(g.dred);
       const int nred = static_cast<int>(g.red.size());
@@ -801,14 +818,14 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st, const cx<double>* tw64
         constexpr int LL = decltype(Lc)::value;
         const dim3 th(ColShape<LL>::THREADS);
         if (g.mode == 1)
-          hipLaunchKernelGGL((col_kernel_host<LL, 1>), dim3(grid + nred), th,
-                             0, st, J, g.dstart, nj, RJ, nred, tw64);
+          klaunch(ps, col_kernel_host<LL, 1>, dim3(grid + nred), th, st, J,
+                  g.dstart, nj, RJ, nred, tw64);
         else
-          hipLaunchKernelGGL((col_kernel_host<LL, -1>), dim3(grid + nred),
-                             th, 0, st, J, g.dstart, nj, RJ, nred, tw64);
+          klaunch(ps, col_kernel_host<LL, -1>, dim3(grid + nred), th, st, J,
+                  g.dstart, nj, RJ, nred, tw64);
       });
     } else if (g.kind == K_COL) {
-      ProfScope ps(ph, P_COL, g.bytes);
+      ProfScope ps(ph, P_COL, g.bytes, true);
       const ColJob* J = static_cast<const ColJob*>(g.djobs);
       ok = dispatch_pow2<4, 1024>(g.len, [&](auto Lc) {
         constexpr int LL = decltype(Lc)::value;
@@ -816,32 +833,30 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st, const cx<double>* tw64
         // first inverse stage reads the fp64 spectrum; the others read the
         // stage before in the job's own precision
         if (g.mode == 1 && g.ti == 0)
-          hipLaunchKernelGGL((col_kernel_mp<LL, 1, double>), dim3(grid), th,
-                             0, st, J, g.dstart, nj, tw32, tw64);
+          klaunch(ps, col_kernel_mp<LL, 1, double>, dim3(grid), th, st, J,
+                  g.dstart, nj, tw32, tw64);
         else if (g.mode == 1)
-          hipLaunchKernelGGL((col_kernel_mp<LL, 1, float>), dim3(grid), th, 0,
-                             st, J, g.dstart, nj, tw32, tw64);
+          klaunch(ps, col_kernel_mp<LL, 1, float>, dim3(grid), th, st, J,
+                  g.dstart, nj, tw32, tw64);
         else
-          hipLaunchKernelGGL((col_kernel_mp<LL, -1, float>), dim3(grid), th,
-                             0, st, J, g.dstart, nj, tw32, tw64);
+          klaunch(ps, col_kernel_mp<LL, -1, float>, dim3(grid), th, st, J,
+                  g.dstart, nj, tw32, tw64);
       });
     } else {
       const PassBArgs* J = static_cast<const PassBArgs*>(g.djobs);
       {
-        ProfScope ps(ph, P_PASSB, g.bytes);
+        ProfScope ps(ph, P_PASSB, g.bytes, true);
         if (g.tcode == 1) {
           ok = dispatch_pow2<DENSE_NT_MIN, DENSE_NT_MAX>(g.len, [&](auto Nc) {
             constexpr int NN = decltype(Nc)::value;
-            hipLaunchKernelGGL((passb_dense_kernel<NN, PB_ITERATE, double>),
-                               dim3(grid), dim3(DENSE_THREADS), 0, st, J,
-                               g.dstart, nj);
+            klaunch(ps, passb_dense_kernel<NN, PB_ITERATE, double>, dim3(grid),
+                    dim3(DENSE_THREADS), st, J, g.dstart, nj);
           });
         } else {
           ok = dispatch_pow2<2, 512>(g.len, [&](auto Nc) {
             constexpr int NN = decltype(Nc)::value;
-            hipLaunchKernelGGL((passb_kernel<NN, PB_ITERATE, double>),
-                               dim3(grid), dim3(PassBShape<NN>::THREADS), 0,
-                               st, J, g.dstart, nj);
+            klaunch(ps, passb_kernel<NN, PB_ITERATE, double>, dim3(grid),
+                    dim3(PassBShape<NN>::THREADS), st, J, g.dstart, nj);
           });
         }
       }
@@ -851,10 +866,9 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st, const cx<double>* tw64
           return fail(ph, EXPDIAG_EHIP, "plan launch: %s",
                       hipGetErrorString(e0));
         const int nred = static_cast<int>(g.red.size());
-        ProfScope pr(ph, P_RED, static_cast<double>(grid) * 32);
-        hipLaunchKernelGGL(ctl_reduce_kernel, dim3(nred), dim3(CTL_THREADS),
-                           0, st, static_cast<const PassBArgs*>(g.dred),
-                           nred);
+        ProfScope pr(ph, P_RED, static_cast<double>(grid) * 32, true);
+        klaunch(pr, ctl_reduce_kernel, dim3(nred), dim3(CTL_THREADS), st,
+                static_cast<const PassBArgs*>(g.dred), nred);
       }
     }
     if (!ok) return fail(ph, EXPDIAG_EUNSUPPORTED, "plan length %d", g.len);
@@ -872,10 +886,9 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st, const cx<double>* tw64
 int plan_finish(expdiag_ctx* ph, Plan& P, hipStream_t st) {
   for (auto& g : P.groups) {
     if (g.kind != K_PASSB || g.njobs() == 0) continue;
-    ProfScope pr(ph, P_RED, static_cast<double>(g.grid()) * 32);
-    hipLaunchKernelGGL(ctl_reduce_kernel, dim3(g.njobs()), dim3(CTL_THREADS),
-                       0, st, static_cast<const PassBArgs*>(g.djobs),
-                       g.njobs());
+    ProfScope pr(ph, P_RED, static_cast<double>(g.grid()) * 32, true);
+    klaunch(pr, ctl_reduce_kernel, dim3(g.njobs()), dim3(CTL_THREADS), st,
+            static_cast<const PassBArgs*>(g.djobs), g.njobs());
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
       return fail(ph, EXPDIAG_EHIP, "reduce launch: %s",

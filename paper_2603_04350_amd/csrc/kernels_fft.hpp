@@ -125,9 +125,43 @@ struct RowJob {
   int phase_req;
 };
 
+// Forward half of a row: Z = FFT_M(z) of v (z_j = x_{2j} + i x_{2j+1}),
+// then X_k = E_k + W^k O_k stored for k = 0..M (valid rows only).  The
+// caller has synchronised so that nobody still reads this row's LDS.
+template <typename T, int M, typename TO, int R>
+__device__ __forceinline__ void row_forward(const RowJob& jb, long row,
+                                            bool valid, int t, cx<T> (&v)[R],
+                                            cx<T>* lrow,
+                                            const cx<T>* __restrict__ tw) {
+  using S = RowShape<M>;
+  constexpr int TPR = S::TPR;
+  constexpr int wshift = TW_LOG - ilog2c(2 * M);
+  fft_line<T, M, -1, true, true, S::WAVE>(v, lrow, 1, t, tw);
+  line_sync<S::WAVE>();
+  if (!valid) return;
+  cx<TO>* dst = static_cast<cx<TO>*>(jb.out) + row * (jb.out_pitch >> 1);
+  cx<T> x0e, x0o;
+#pragma unroll
+  for (int s = 0; s < R; ++s) {
+    const int k = t + s * TPR;
+    const cx<T> zk = v[s];
+    const cx<T> zm = conj(lrow[slot<true>((M - k) & (M - 1))]);
+    const cx<T> e = (zk + zm) * static_cast<T>(0.5);
+    const cx<T> o = mul_si<-1>(zk - zm) * static_cast<T>(0.5);
+    if (s == 0) {
+      x0e = e;
+      x0o = o;
+    }
+    const cx<T> x = e + cmul(tw[k << wshift], o);
+    gst(dst, k, cvt<TO>(x));
+  }
+  if (t == 0) gst(dst, M, cvt<TO>(x0e - x0o));
+}
+
 // One block of the row transform: rows [lb*RPB, lb*RPB + RPB) of job `jb`.
-// Row element k sits in LDS slot slot<true>(k) of its row.
-// `lds` holds RPB * LS elements.
+// Row element k sits in LDS slot slot<true>(k) of its row; `lds` holds
+// RPB * LS elements.  (Loading a second group of rows while the first is
+// transformed, at the cost of the registers that holds, measured slower.)
 template <typename T, int M, int MODE, typename TI, typename TO>
 __device__ __forceinline__ void row_body(const RowJob& jb, long lb,
                                          const cx<T>* __restrict__ tw,
@@ -161,7 +195,7 @@ __device__ __forceinline__ void row_body(const RowJob& jb, long lb,
       v[s] = z;
     }
   } else {
-    // load X_0..X_M of the half-spectrum row into LDS
+    // X_0..X_M of the half-spectrum row into LDS
 #pragma unroll
     for (int s = 0; s < R; ++s) {
       const int k = t + s * TPR;
@@ -211,28 +245,7 @@ __device__ __forceinline__ void row_body(const RowJob& jb, long lb,
     }
     line_sync<S::WAVE>();
   }
-
-  // forward: Z = FFT_M(z), then X_k = E_k + W^k O_k
-  fft_line<T, M, -1, true, true, S::WAVE>(v, lrow, 1, t, tw);
-  line_sync<S::WAVE>();
-  if (!valid) return;
-  cx<TO>* dst = static_cast<cx<TO>*>(jb.out) + row * (jb.out_pitch >> 1);
-  cx<T> x0e, x0o;
-#pragma unroll
-  for (int s = 0; s < R; ++s) {
-    const int k = t + s * TPR;
-    const cx<T> zk = v[s];
-    const cx<T> zm = conj(lrow[slot<true>((M - k) & (M - 1))]);
-    const cx<T> e = (zk + zm) * static_cast<T>(0.5);
-    const cx<T> o = mul_si<-1>(zk - zm) * static_cast<T>(0.5);
-    if (s == 0) {
-      x0e = e;
-      x0o = o;
-    }
-    const cx<T> x = e + cmul(tw[k << wshift], o);
-    gst(dst, k, cvt<TO>(x));
-  }
-  if (t == 0) gst(dst, M, cvt<TO>(x0e - x0o));
+  row_forward<T, M, TO>(jb, row, valid, t, v, lrow, tw);
 }
 
 // Job-table launch of one pass-A stage for instances in either precision

@@ -326,7 +326,7 @@ __global__ void __launch_bounds__(PassBShape<NT>::THREADS,
 template <int THREADS>
 __device__ __forceinline__ void reduce_instance(const PassBArgs& a,
                                                 double* red) {
-  constexpr int UNROLL = 4;
+  constexpr int UNROLL = 8;
   Ctl* ctl = a.ctl;
   if (gld(&ctl->done, 0) || !gld(&ctl->pending, 0)) return;
   const int nb = a.nblocks;
