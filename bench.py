@@ -44,7 +44,8 @@ TOL = 1e-11
 
 
 DEVICE_SOURCES = ("cx.hpp", "fft_core.hpp", "kernels_fft.hpp",
-                  "kernels_passb.hpp", "kernels_krylov.hpp")
+                  "kernels_passb.hpp", "kernels_krylov.hpp",
+                  "kernels_dense.hpp")
 
 
 def _src_hash():
