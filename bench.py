@@ -25,9 +25,10 @@ value = space-time DOF-iterations per second of the plain FP64 solve
     Nt in {16..128}, eps ~ U[0.02,0.1], alpha in {1e-2,1e-3}) solved in one
     batched plan in mixed precision, against the same instances solved one
     after another by the plain FP64 single-instance path;
-  * served: Poisson arrivals of batch-shaped 2D requests mixed with 3D
-    128^3 x 32 heat / Allen-Cahn requests into the continuous-batching
-    server; p50/p99 latency and solves/s per arrival rate.
+  * served: batch-shaped 2D requests mixed with 3D 128^3 x 32 heat /
+    Allen-Cahn requests into the continuous-batching server: all at once
+    (its capacity), then Poisson arrivals at 0.5 and 0.9 of that capacity;
+    p50/p99 latency and solves/s per arrival rate.
 """
 import argparse
 import hashlib
@@ -201,55 +202,71 @@ def bench_batched(count):
     }
 
 
-def bench_served(rates_frac, n_req, sat_solves_per_s):
-    import numpy as np
+def _serve_run(times, insts, dev):
+    """Submit instance k at time times[k] (seconds from the start) into a
+    fresh server; returns (results, wall seconds)."""
     import torch
-    import workloads as W
     from paper_2603_04350_amd import expdiag as X
-    dev = "cuda:0"
-    out = []
-    for frac in rates_frac:
-        rate = frac * sat_solves_per_s
-        times, insts = W.served_stream(n_req, rate, seed=1)
-        u0s = [torch.from_numpy(i.u0).to(dev) for i in insts]
-        Us = [torch.zeros((i.Nt,) + i.shape, dtype=torch.float64,
-                          device=dev) for i in insts]
-        torch.cuda.synchronize()
-        srv = X.expdiag_server_create(64 << 30, 128)
-        ids = {}
-        t0 = time.perf_counter()
-        done = []
-        for k, (ta, inst) in enumerate(zip(times, insts)):
-            while time.perf_counter() - t0 < ta:
-                res, _ = X.expdiag_server_poll(srv)
-                done.extend(res)
-                time.sleep(0.0005)
-            prob = X.make_problem(inst.a, inst.c, inst.n1, inst.n2, inst.n3,
-                                  inst.precision)
-            rid = X.expdiag_server_submit(srv, inst.shape, inst.Nt, inst.dt,
-                                          inst.alpha, inst.scheme, prob,
-                                          u0s[k], Us[k], 400, TOL)
-            ids[rid] = k
-        while len(done) < n_req:
+    u0s = [torch.from_numpy(i.u0).to(dev) for i in insts]
+    Us = [torch.zeros((i.Nt,) + i.shape, dtype=torch.float64, device=dev)
+          for i in insts]
+    torch.cuda.synchronize()
+    srv = X.expdiag_server_create(64 << 30, 128)
+    t0 = time.perf_counter()
+    done = []
+    for k, (ta, inst) in enumerate(zip(times, insts)):
+        while time.perf_counter() - t0 < ta:
             res, _ = X.expdiag_server_poll(srv)
             done.extend(res)
             time.sleep(0.0005)
-        wall = time.perf_counter() - t0
-        X.expdiag_server_destroy(srv)
+        prob = X.make_problem(inst.a, inst.c, inst.n1, inst.n2, inst.n3,
+                              inst.precision)
+        X.expdiag_server_submit(srv, inst.shape, inst.Nt, inst.dt,
+                                inst.alpha, inst.scheme, prob, u0s[k], Us[k],
+                                400, TOL)
+    while len(done) < len(insts):
+        res, _ = X.expdiag_server_poll(srv)
+        done.extend(res)
+        time.sleep(0.0005)
+    wall = time.perf_counter() - t0
+    X.expdiag_server_destroy(srv)
+    del Us, u0s
+    torch.cuda.empty_cache()
+    return done, wall
+
+
+def bench_served(rates_frac, n_req):
+    """Continuous batching: first every request at once (the server's
+    capacity in solves/s), then Poisson arrivals at fractions of that
+    capacity; p50/p99 of submit-to-result latency per arrival rate."""
+    import numpy as np
+    import workloads as W
+    dev = "cuda:0"
+
+    def summary(done, wall, rate, frac, insts):
         lat = np.array([r["t_done"] - r["t_submit"] for r in done])
-        ok = sum(1 for r in done if r["status"] == 0)
-        out.append({
+        return {
             "rate_solves_per_s": rate,
-            "rate_frac_of_batched_throughput": frac,
-            "requests": n_req,
+            "rate_frac_of_capacity": frac,
+            "requests": len(insts),
             "requests_3d": sum(1 for i in insts if i.dim == 3),
-            "converged": ok,
+            "converged": sum(1 for r in done if r["status"] == 0),
             "p50_latency_ms": 1e3 * float(np.percentile(lat, 50)),
             "p99_latency_ms": 1e3 * float(np.percentile(lat, 99)),
-            "throughput_solves_per_s": n_req / wall,
-        })
-        del Us, u0s
-        torch.cuda.empty_cache()
+            "throughput_solves_per_s": len(insts) / wall,
+        }
+
+    _, insts = W.served_stream(n_req, 1.0, seed=1)
+    done, wall = _serve_run([0.0] * n_req, insts, dev)
+    cap = n_req / wall
+    out = {"capacity_solves_per_s": cap,
+           "burst": summary(done, wall, None, None, insts),
+           "poisson": []}
+    for frac in rates_frac:
+        rate = frac * cap
+        times, insts = W.served_stream(n_req, rate, seed=1)
+        done, wall = _serve_run(times, insts, dev)
+        out["poisson"].append(summary(done, wall, rate, frac, insts))
     return out
 
 
@@ -361,10 +378,8 @@ def main():
         _log(f"batched: {args.batch} instances")
         line["batched"] = bench_batched(args.batch)
         if not args.no_serve:
-            sat = args.batch / line["batched"]["time_to_tol_s_batched_mixed"]
             _log("served")
-            line["served"] = bench_served((0.5, 0.9), args.serve_requests,
-                                          sat)
+            line["served"] = bench_served((0.5, 0.9), args.serve_requests)
     if not args.no_cpu_baseline and rank == 0:
         _log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(inst, fp["U"], mx["U"],

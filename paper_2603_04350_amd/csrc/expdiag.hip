@@ -926,70 +926,148 @@ long double phi1l(long double z) {
   if (z == 0.0L) return 1.0L;
   return expm1l(z) / z;
 }
+
+// 1/n!, n = 0..39 (once per process)
+const long double* inv_factorials() {
+  static const std::vector<long double> f = [] {
+    std::vector<long double> v(40);
+    long double fact = 1.0L;
+    for (int i = 0; i < 40; ++i) {
+      if (i > 0) fact *= i;
+      v[i] = 1.0L / fact;
+    }
+    return v;
+  }();
+  return f.data();
+}
+
 long double phi2l(long double z) {
   if (fabsl(z) < 1.0L) {
     // sum_{j>=0} z^j / (j+2)!, Horner from the tail
-    long double fact[40];
-    fact[0] = 1.0L;
-    for (int i = 1; i < 40; ++i) fact[i] = fact[i - 1] * i;
+    const long double* inv = inv_factorials();
     long double acc = 0.0L;
-    for (int j = 35; j >= 0; --j) acc = acc * z + 1.0L / fact[j + 2];
+    for (int j = 35; j >= 0; --j) acc = acc * z + inv[j + 2];
     return acc;
   }
   return (expm1l(z) - z) / (z * z);
 }
 
-int build_tables(expdiag_ctx* h) {
+// exp(-2 pi i j / TW_N), j < TW_N, in fp64 and fp32 (once per process)
+struct TwiddleTables {
+  std::vector<cx<double>> d;
+  std::vector<cx<float>> f;
+};
+const TwiddleTables& twiddle_tables() {
+  static const TwiddleTables t = [] {
+    TwiddleTables r;
+    r.d.resize(TW_N);
+    r.f.resize(TW_N);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int j = 0; j < TW_N; ++j) {
+      const long double th = -2.0L * pi * j / TW_N;
+      const long double cr = cosl(th), si = sinl(th);
+      r.d[j] = mk<double>(static_cast<double>(cr), static_cast<double>(si));
+      r.f[j] = mk<float>(static_cast<float>(cr), static_cast<float>(si));
+    }
+    return r;
+  }();
+  return t;
+}
+
+// Per-kappa tables E = e^{dt mu}, c1, c2 (eq. etd1_update / etd2_update
+// weights), mu = -a |k|^2 - c.  They depend on kappa only through the
+// integer |k|^2, so each value of |k|^2 that occurs is evaluated once (in
+// long double, on up to eight host threads) and then gathered.
+void symbol_tables(expdiag_ctx* h, std::vector<double>& E,
+                   std::vector<double>& c1, std::vector<double>& c2) {
   const int d = h->dim;
   const long Nk = h->Nk;
-  std::vector<double> E(Nk), c1(Nk), c2(Nk);
-  const long double a = h->p.a, c = h->p.c, dt = h->dt;
-  long idx = 0;
   const int n0 = h->n[0], n1 = d >= 2 ? h->n[1] : 1;
-  auto wn = [](int j, int n) { return j <= n / 2 ? j : j - n; };
   const int outer0 = d >= 2 ? n0 : 1;
   const int outer1 = d >= 3 ? n1 : 1;
+  auto wn = [](int j, int n) { return j <= n / 2 ? j : j - n; };
+  std::vector<int> k2(Nk);
+  long idx = 0, k2max = 0;
   for (int i0 = 0; i0 < outer0; ++i0) {
+    const long a0 = d >= 2 ? static_cast<long>(wn(i0, n0)) * wn(i0, n0) : 0;
     for (int i1 = 0; i1 < outer1; ++i1) {
+      const long a1 = d >= 3 ? static_cast<long>(wn(i1, n1)) * wn(i1, n1) : 0;
       for (int kl = 0; kl < h->nh; ++kl) {
-        long double k2 = static_cast<long double>(kl) * kl;
-        if (d >= 2) {
-          const long double k0 = wn(i0, n0);
-          k2 += k0 * k0;
-        }
-        if (d >= 3) {
-          const long double k1 = wn(i1, n1);
-          k2 += k1 * k1;
-        }
-        const long double mu = -a * k2 - c;
-        const long double z = dt * mu;
-        const long double w1 = dt * phi1l(z);
-        const long double w2 = dt * phi2l(z);
-        E[idx] = static_cast<double>(expl(z));
-        if (h->scheme == EXPDIAG_ETD1) {
-          c1[idx] = static_cast<double>(w1);
-          c2[idx] = 0.0;
-        } else {
-          c1[idx] = static_cast<double>(w1 + w2);
-          c2[idx] = static_cast<double>(-w2);
-        }
-        ++idx;
+        const long v = a0 + a1 + static_cast<long>(kl) * kl;
+        k2[idx++] = static_cast<int>(v);
+        k2max = std::max(k2max, v);
       }
     }
   }
+  std::vector<int> slot(k2max + 1, -1);
+  std::vector<int> vals;
+  for (long i = 0; i < Nk; ++i) {
+    if (slot[k2[i]] < 0) {
+      slot[k2[i]] = static_cast<int>(vals.size());
+      vals.push_back(k2[i]);
+    }
+  }
+  const long nv = static_cast<long>(vals.size());
+  std::vector<double> tE(nv), t1(nv), t2(nv);
+  const long double a = h->p.a, c = h->p.c, dt = h->dt;
+  const bool etd2 = h->scheme == EXPDIAG_ETD2;
+  auto eval = [&](long lo, long hi) {
+    for (long i = lo; i < hi; ++i) {
+      const long double z = dt * (-a * static_cast<long double>(vals[i]) - c);
+      const long double w1 = dt * phi1l(z);
+      tE[i] = static_cast<double>(expl(z));
+      if (etd2) {
+        const long double w2 = dt * phi2l(z);
+        t1[i] = static_cast<double>(w1 + w2);
+        t2[i] = static_cast<double>(-w2);
+      } else {
+        t1[i] = static_cast<double>(w1);
+        t2[i] = 0.0;
+      }
+    }
+  };
+  const int nthr = nv < 4096 ? 1 : 8;
+  if (nthr == 1) {
+    eval(0, nv);
+  } else {
+    std::vector<std::thread> th;
+    for (int k = 0; k < nthr; ++k)
+      th.emplace_back(eval, nv * k / nthr, nv * (k + 1) / nthr);
+    for (auto& t : th) t.join();
+  }
+  E.resize(Nk);
+  c1.resize(Nk);
+  c2.resize(Nk);
+  for (long i = 0; i < Nk; ++i) {
+    const int j = slot[k2[i]];
+    E[i] = tE[j];
+    c1[i] = t1[j];
+    c2[i] = t2[j];
+  }
+}
+
+int build_tables(expdiag_ctx* h) {
+  const long Nk = h->Nk;
+  std::vector<double> E, c1, c2;
+  symbol_tables(h, E, c1, c2);
   const int Nt = h->Nt;
   std::vector<double> gam(Nt), igam(Nt);
   std::vector<cx<double>> lam(Nt);
+  // e^{2 pi i j/Nt}, j < Nt: every angle the time tables use
+  std::vector<long double> cs(Nt), sn(Nt);
   const long double la = logl(static_cast<long double>(h->alpha));
   const long double pi = 3.141592653589793238462643383279502884L;
   const long double root = expl(la / Nt);
+  std::vector<long double> gl(Nt);
   for (int l = 0; l < Nt; ++l) {
-    const long double g = expl(la * l / Nt);
-    gam[l] = static_cast<double>(g);
-    igam[l] = static_cast<double>(1.0L / g);
     const long double th = 2.0L * pi * l / Nt;
-    lam[l] = mk<double>(static_cast<double>(root * cosl(th)),
-                        static_cast<double>(root * sinl(th)));
+    cs[l] = cosl(th);
+    sn[l] = sinl(th);
+    gl[l] = expl(la * l / Nt);
+    gam[l] = static_cast<double>(gl[l]);
+    igam[l] = static_cast<double>(1.0L / gl[l]);
+    lam[l] = mk<double>(static_cast<double>(root * cs[l]),
+                        static_cast<double>(root * sn[l]));
   }
   if (h->Wf != nullptr) {
     // [[Re, -Im], [Im, Re]] of Wf[m][l] = gamma_l e^{+2 pi i ml/Nt} / Nt and
@@ -998,15 +1076,15 @@ int build_tables(expdiag_ctx* h) {
     std::vector<double> wf(static_cast<size_t>(K) * K), wi(wf.size());
     for (int m = 0; m < Nt; ++m) {
       for (int l = 0; l < Nt; ++l) {
-        const long double th = 2.0L * pi * ((static_cast<long>(m) * l) % Nt) / Nt;
-        const long double g = expl(la * l / Nt);
-        const long double fr = g * cosl(th) / Nt, fi = g * sinl(th) / Nt;
+        const int j = static_cast<int>((static_cast<long>(m) * l) % Nt);
+        const long double g = gl[l];
+        const long double fr = g * cs[j] / Nt, fi = g * sn[j] / Nt;
         wf[m * K + l] = static_cast<double>(fr);
         wf[m * K + Nt + l] = static_cast<double>(-fi);
         wf[(Nt + m) * K + l] = static_cast<double>(fi);
         wf[(Nt + m) * K + Nt + l] = static_cast<double>(fr);
         // Wi row l, column m
-        const long double ir = cosl(th) / g, ii = -sinl(th) / g;
+        const long double ir = cs[j] / g, ii = -sn[j] / g;
         wi[l * K + m] = static_cast<double>(ir);
         wi[l * K + Nt + m] = static_cast<double>(-ii);
         wi[(Nt + l) * K + m] = static_cast<double>(ii);
@@ -1018,22 +1096,15 @@ int build_tables(expdiag_ctx* h) {
     HIPCHK(h, hipMemcpy(h->Wi, wi.data(), wi.size() * sizeof(double),
                         hipMemcpyHostToDevice));
   }
-  std::vector<cx<double>> tw(TW_N);
-  std::vector<cx<float>> tw32(TW_N);
-  for (int j = 0; j < TW_N; ++j) {
-    const long double th = -2.0L * pi * j / TW_N;
-    const long double cr = cosl(th), si = sinl(th);
-    tw[j] = mk<double>(static_cast<double>(cr), static_cast<double>(si));
-    tw32[j] = mk<float>(static_cast<float>(cr), static_cast<float>(si));
-  }
+  const TwiddleTables& tw = twiddle_tables();
   HIPCHK(h, hipMemcpy(h->E, E.data(), Nk * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->c1, c1.data(), Nk * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->c2, c2.data(), Nk * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->gam, gam.data(), Nt * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->igam, igam.data(), Nt * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->lam, lam.data(), Nt * sizeof(cx<double>), hipMemcpyHostToDevice));
-  HIPCHK(h, hipMemcpy(h->tw64, tw.data(), TW_N * sizeof(cx<double>), hipMemcpyHostToDevice));
-  HIPCHK(h, hipMemcpy(h->tw32, tw32.data(), TW_N * sizeof(cx<float>), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->tw64, tw.d.data(), TW_N * sizeof(cx<double>), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->tw32, tw.f.data(), TW_N * sizeof(cx<float>), hipMemcpyHostToDevice));
   return 0;
 }
 
