@@ -360,6 +360,14 @@ PassBArgs passb_args(expdiag_ctx* h) {
   a.etd2 = h->scheme == EXPDIAG_ETD2 ? 1 : 0;
   a.nblocks = passb_blocks(h);
   a.inv_ns = 1.0 / static_cast<double>(h->Ns);
+  // the same long-double values as the gamma table
+  const int R = std::min(h->Nt, 4), tpl = h->Nt / R;
+  const long double la = logl(static_cast<long double>(h->alpha));
+  for (int s = 0; s < 4; ++s) {
+    const long double g = s < R ? expl(la * (s * tpl) / h->Nt) : 1.0L;
+    a.gstep[s] = static_cast<double>(g);
+    a.igstep[s] = static_cast<double>(1.0L / g);
+  }
   return a;
 }
 

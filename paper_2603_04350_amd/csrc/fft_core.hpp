@@ -163,7 +163,7 @@ __device__ __forceinline__ void apply_twiddles(cx<T>* a, cx<T> w1) {
 // leave the natural-order result in LDS (a barrier follows before anyone
 // reads it).
 template <typename T, int L, int R, int S, int NS, bool PAD, bool OUT_LDS,
-          bool WAVE>
+          bool WAVE, int ST = 0, bool PRE = false>
 __device__ __forceinline__ void fft_stages(cx<T> (&v)[R], cx<T> w1,
                                            cx<T>* lds, int stride, int t,
                                            const cx<T>* tw) {
@@ -201,16 +201,57 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[R], cx<T> w1,
       for (int s = 0; s < r; ++s)
         lds[slot<PAD>(base + s * NS) * stride] = a[s];
     }
-    // next stage: span NS*r, radix R, one butterfly (index t) per thread
+    // next stage: span NS*r, radix R, one butterfly (index t) per thread;
+    // PRE: `tw` holds the stages' base twiddles (forward sign), already in
+    // registers (fft_stage_twiddles)
     constexpr int NS2 = NS * r;
     constexpr int sh2 = TW_LOG - ilog2c(NS2 * R);
-    const cx<T> w2 = twid<S>(tw, (t & (NS2 - 1)) << sh2);
+    cx<T> w2;
+    if constexpr (PRE)
+      w2 = S > 0 ? conj(tw[ST + 1]) : tw[ST + 1];
+    else
+      w2 = twid<S>(tw, (t & (NS2 - 1)) << sh2);
     line_sync<WAVE>();
 #pragma unroll
     for (int s = 0; s < R; ++s) v[s] = lds[slot<PAD>(t + s * TPL) * stride];
     if constexpr (NS2 * R < L || OUT_LDS) line_sync<WAVE>();
-    fft_stages<T, L, R, S, NS2, PAD, OUT_LDS, WAVE>(v, w2, lds, stride, t,
-                                                    tw);
+    fft_stages<T, L, R, S, NS2, PAD, OUT_LDS, WAVE, ST + 1, PRE>(
+        v, w2, lds, stride, t, tw);
+  }
+}
+
+// e^{-i pi j / 8}, j = 0..7 (exact to the last bit in fp64)
+template <typename T>
+__device__ __forceinline__ cx<T> eighth_root(int j) {
+  constexpr long double C1 = 0.92387953251128675612818318939678829L;
+  constexpr long double S1 = 0.38268343236508977172845998403039887L;
+  constexpr long double H = 0.70710678118654752440084436210484904L;
+  const long double re[8] = {1.0L, C1, H, S1, 0.0L, -S1, -H, -C1};
+  const long double im[8] = {0.0L, -S1, -H, -C1, -1.0L, -C1, -H, -S1};
+  return mk<T>(static_cast<T>(re[j]), static_cast<T>(im[j]));
+}
+
+// Number of stages of a length-L transform with R elements per thread.
+template <int L, int R, int NS = 1>
+constexpr int fft_stage_count() {
+  if constexpr (NS >= L) {
+    return 0;
+  } else {
+    return 1 + fft_stage_count<L, R, NS * stage_radix<L, R, NS>()>();
+  }
+}
+
+// Base twiddle (forward sign) of every stage after the first for thread t:
+// w[st] for stage st = 1 .. stages-1 (w[0] unused).  Lets a caller issue
+// these loads together with its data loads (fft_line_pre).
+template <typename T, int L, int R, int NS = 1, int ST = 0>
+__device__ __forceinline__ void fft_stage_twiddles(cx<T>* w, int t,
+                                                   const cx<T>* tw) {
+  if constexpr (NS * stage_radix<L, R, NS>() < L) {
+    constexpr int NS2 = NS * stage_radix<L, R, NS>();
+    constexpr int sh2 = TW_LOG - ilog2c(NS2 * R);
+    w[ST + 1] = gld(tw, (t & (NS2 - 1)) << sh2);
+    fft_stage_twiddles<T, L, R, NS2, ST + 1>(w, t, tw);
   }
 }
 
@@ -231,6 +272,16 @@ __device__ __forceinline__ void fft_line(cx<T> (&v)[R], cx<T>* lds,
     fft_stages<T, L, R, S, 1, PAD, OUT_LDS, WAVE>(v, mk<T>(1, 0), lds, stride,
                                                   t, tw);
   }
+}
+
+// fft_line with the stage twiddles already loaded (fft_stage_twiddles).
+template <typename T, int L, int S, int R>
+__device__ __forceinline__ void fft_line_pre(cx<T> (&v)[R], cx<T>* lds,
+                                             int stride, int t,
+                                             const cx<T>* wst) {
+  if constexpr (L > 1)
+    fft_stages<T, L, R, S, 1, false, false, false, 0, true>(
+        v, mk<T>(1, 0), lds, stride, t, wst);
 }
 
 }  // namespace expdiag

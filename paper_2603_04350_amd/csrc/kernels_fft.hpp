@@ -128,15 +128,16 @@ struct RowJob {
 // Forward half of a row: Z = FFT_M(z) of v (z_j = x_{2j} + i x_{2j+1}),
 // then X_k = E_k + W^k O_k stored for k = 0..M (valid rows only).  The
 // caller has synchronised so that nobody still reads this row's LDS.
+// wst: stage twiddles (fft_stage_twiddles); wk[s] = W^{t + s*TPR}.
 template <typename T, int M, typename TO, int R>
 __device__ __forceinline__ void row_forward(const RowJob& jb, long row,
                                             bool valid, int t, cx<T> (&v)[R],
-                                            cx<T>* lrow,
-                                            const cx<T>* __restrict__ tw) {
+                                            cx<T>* lrow, const cx<T>* wst,
+                                            const cx<T> (&wk)[R]) {
   using S = RowShape<M>;
   constexpr int TPR = S::TPR;
-  constexpr int wshift = TW_LOG - ilog2c(2 * M);
-  fft_line<T, M, -1, true, true, S::WAVE>(v, lrow, 1, t, tw);
+  fft_stages<T, M, R, -1, 1, true, true, S::WAVE, 0, true>(
+      v, mk<T>(1, 0), lrow, 1, t, wst);
   line_sync<S::WAVE>();
   if (!valid) return;
   cx<TO>* dst = static_cast<cx<TO>*>(jb.out) + row * (jb.out_pitch >> 1);
@@ -152,7 +153,7 @@ __device__ __forceinline__ void row_forward(const RowJob& jb, long row,
       x0e = e;
       x0o = o;
     }
-    const cx<T> x = e + cmul(tw[k << wshift], o);
+    const cx<T> x = e + cmul(wk[s], o);
     gst(dst, k, cvt<TO>(x));
   }
   if (t == 0) gst(dst, M, cvt<TO>(x0e - x0o));
@@ -184,10 +185,28 @@ __device__ __forceinline__ void row_body(const RowJob& jb, long lb,
   const T scale = static_cast<T>(jb.scale);
   cx<T> v[R];
 
+  // every global load up front (loads complete in issue order, so a later
+  // one would cost another memory latency): the row, then the twiddles.
+  // W^k, k = t + s*TPR, is W^t e^{-i pi s/R}; the stage twiddles of both
+  // transforms are the same (conjugated for the inverse).
+  cx<TI> xin[R];
+  cx<TI> xm_in = mk<TI>(0, 0);
+#pragma unroll
+  for (int s = 0; s < R; ++s) xin[s] = gld(src, t + s * TPR);
+  if constexpr (MODE != ROW_R2C && MODE != ROW_NR2C) xm_in = gld(src, M);
+  const cx<T> wt = gld(tw, t << wshift);
+  constexpr int NST = fft_stage_count<M, R>();
+  cx<T> wst[NST > 1 ? NST : 2];
+  fft_stage_twiddles<T, M, R>(wst, t, tw);
+  cx<T> wk[R];
+#pragma unroll
+  for (int s = 0; s < R; ++s)
+    wk[s] = s == 0 ? wt : cmul(wt, eighth_root<T>(s * (8 / R)));
+
   if constexpr (MODE == ROW_R2C || MODE == ROW_NR2C) {
 #pragma unroll
     for (int s = 0; s < R; ++s) {
-      cx<T> z = cvt<T>(gld(src, t + s * TPR));
+      cx<T> z = cvt<T>(xin[s]);
       if constexpr (MODE == ROW_NR2C) {
         z.x = nonlin(z.x, n1, n2, n3);
         z.y = nonlin(z.y, n1, n2, n3);
@@ -197,11 +216,11 @@ __device__ __forceinline__ void row_body(const RowJob& jb, long lb,
   } else {
     // X_0..X_M of the half-spectrum row into LDS
 #pragma unroll
-    for (int s = 0; s < R; ++s) {
-      const int k = t + s * TPR;
-      lrow[slot<true>(k)] = cvt<T>(gld(src, k));
-    }
-    if (t == 0) lrow[slot<true>(M)] = cvt<T>(gld(src, M));
+    for (int s = 0; s < R; ++s)
+      lrow[slot<true>(t + s * TPR)] = cvt<T>(xin[s]);
+    // every lane of the row stores the same X_M: a store under t == 0
+    // would let the compiler move the load behind the first wait
+    lrow[slot<true>(M)] = cvt<T>(xm_in);
     line_sync<S::WAVE>();
     // Z_k = [(X_k + conj X_{M-k}) + i (X_k - conj X_{M-k}) W^{-k}] * scale
 #pragma unroll
@@ -214,11 +233,12 @@ __device__ __forceinline__ void row_body(const RowJob& jb, long lb,
         xm.y = 0;
       }
       const cx<T> e2 = xk + conj(xm);
-      const cx<T> o2 = cmulc(xk - conj(xm), tw[k << wshift]);
+      const cx<T> o2 = cmulc(xk - conj(xm), wk[s]);
       v[s] = (e2 + mul_si<1>(o2)) * scale;
     }
     line_sync<S::WAVE>();
-    fft_line<T, M, 1, true, false, S::WAVE>(v, lrow, 1, t, tw);
+    fft_stages<T, M, R, 1, 1, true, false, S::WAVE, 0, true>(
+        v, mk<T>(1, 0), lrow, 1, t, wst);
     // v[s] = z_j = x_{2j} + i x_{2j+1},  j = t + s*TPR
     if constexpr (MODE == ROW_C2R) {
       if (valid) {
@@ -245,7 +265,7 @@ __device__ __forceinline__ void row_body(const RowJob& jb, long lb,
     }
     line_sync<S::WAVE>();
   }
-  row_forward<T, M, TO>(jb, row, valid, t, v, lrow, tw);
+  row_forward<T, M, TO>(jb, row, valid, t, v, lrow, wst, wk);
 }
 
 // Job-table launch of one pass-A stage for instances in either precision
@@ -326,10 +346,18 @@ __device__ __forceinline__ void col_body(const ColJob& jb, int lb,
   // columns past the edge read the last column (in bounds), store nothing
   const long base = static_cast<long>(o) * L * inner + (valid ? col : inner - 1);
   const cx<TI>* src = static_cast<const cx<TI>*>(jb.in) + base;
+  cx<TI> xin[R];
+#pragma unroll
+  for (int s = 0; s < R; ++s) xin[s] = gld(src, (t + s * TPL) * inner);
+  // stage twiddles issued with the data (loads complete in issue order)
+  constexpr int NST = fft_stage_count<L, R>();
+  cx<T> wst[NST > 1 ? NST : 2];
+  fft_stage_twiddles<T, L, R>(wst, t, tw);
   cx<T> v[R];
 #pragma unroll
-  for (int s = 0; s < R; ++s) v[s] = cvt<T>(gld(src, (t + s * TPL) * inner));
-  fft_line<T, L, S>(v, lds + c, SH::LS, t, tw);
+  for (int s = 0; s < R; ++s) v[s] = cvt<T>(xin[s]);
+  fft_stages<T, L, R, S, 1, false, false, false, 0, true>(
+      v, mk<T>(1, 0), lds + c, SH::LS, t, wst);
   if (!valid) return;
   cx<TO>* dst = static_cast<cx<TO>*>(jb.out) + base;
   const T scale = static_cast<T>(jb.scale);

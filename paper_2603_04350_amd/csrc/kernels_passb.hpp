@@ -62,6 +62,11 @@ struct PassBArgs {
   int etd2;
   int nblocks;
   double inv_ns;
+  // gamma_{s TPL} and 1/gamma_{s TPL}, s < R, of the radix-FFT pass B
+  // (R = min(Nt, 4), TPL = Nt/R): row t + s TPL of a thread scales by
+  // gamma_t gamma_{s TPL}
+  double gstep[4];
+  double igstep[4];
 };
 
 // C kappa columns per workgroup, TPL threads per column, four time rows per
@@ -79,9 +84,10 @@ struct PassBShape {
   static constexpr int THREADS = C * TPL;
   static constexpr int LS = C;        // LDS row (complex slots)
   static constexpr int LDS = NT * C;  // complex elements of the tile
-  // waves per SIMD the register budget targets (longer time lines keep
-  // more twiddles live)
-  static constexpr int WAVES = NT <= 64 ? 5 : 4;
+  // waves per SIMD the register budget targets: every load of a thread is
+  // in flight at once, which needs 97-128 registers; at five waves the
+  // spills cost more than the extra wave gains
+  static constexpr int WAVES = 4;
 };
 
 // Sum NV doubles over the block; thread 0 writes them to out[0..NV).
@@ -155,6 +161,15 @@ __device__ inline void advance_ctl(const PassBArgs& a, const double* tot) {
   }
 }
 
+// Every global load a thread needs is issued before the first value is
+// used, and none sits behind a per-element branch (columns past Nk load
+// column Nk-1 and are masked afterwards): global loads complete in issue
+// order, so a load issued after the data loads, or a wait inside a loop,
+// would cost another full memory latency.  The per-row tables are read
+// once per thread: gamma_{t+s TPL} = gamma_t gamma_{s TPL} (the second
+// factor is uniform, a scalar load) and lambda_{t+s TPL} = lambda_t
+// e^{2 pi i s/R}.  Rows l-1 (of U, and of N^ for ETD2) come from the
+// neighbouring threads through the LDS tile.
 template <int NT, int MODE, typename TN>
 __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
                                            const TN* Nh, cx<double>* lds,
@@ -167,74 +182,106 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
 
   const int c = threadIdx.x % C;
   const int t = threadIdx.x / C;
-  const long kap = lb * C + c;
-  const bool valid = kap < a.Nk;
   const long Nk = a.Nk;
-  const double E = valid ? gld(a.E, kap) : 0.0;
-  const int kl = static_cast<int>(kap % a.nh);
+  const long kap = lb * C + c;
+  const bool valid = kap < Nk;
+  const long kc = valid ? kap : Nk - 1;  // in-bounds column for the loads
+  const int kl = static_cast<int>(kc) % a.nh;
   const double pw = (!valid) ? 0.0 : ((kl == 0 || kl == a.nh - 1) ? 1.0 : 2.0);
+  const cx<double> zero = mk(0.0, 0.0);
 
+  // loads: data rows first, then the per-kappa and per-row tables
   cx<double> u[R];
+  cx<TN> nr[R];
+  const cx<TN>* Nc = reinterpret_cast<const cx<TN>*>(Nh);
+  const bool nl = MODE != PB_PRECOND && a.nonlinear;
+  const bool two = nl && a.etd2;
+#pragma unroll
+  for (int s = 0; s < R; ++s) {
+    const int l = t + s * TPL;
+    u[s] = gld(MODE == PB_PRECOND ? a.Rin : a.U, l * Nk + kc);
+  }
+  if (nl) {
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      const int l = t + s * TPL;
+      nr[s] = gld(Nc, l * Nk + kc);
+    }
+  }
+  const double E = gld(a.E, kc);
+  cx<double> first = zero;
+  double c1 = 0.0, c2 = 0.0;
+  if constexpr (MODE != PB_PRECOND && MODE != PB_OPAPPLY)
+    first = gld(a.u0h, kc);
+  if (nl) c1 = gld(a.c1, kc);
+  if (two) c2 = gld(a.c2, kc);
+  const double gam_t = gld(a.gam, t), igam_t = gld(a.igam, t);
+  const cx<double> lam_t = gld(a.lam, t);
+  constexpr int NST = fft_stage_count<NT, R>();
+  cx<double> wst[NST > 1 ? NST : 2];
+  fft_stage_twiddles<double, NT, R>(wst, t, a.tw);
+  auto gam = [&](int s) { return s == 0 ? gam_t : gam_t * a.gstep[s]; };
+  auto igam = [&](int s) { return s == 0 ? igam_t : igam_t * a.igstep[s]; };
+
   cx<double> v[R];
   double nrm_r = 0.0, nrm_s = 0.0, nrm_u = 0.0;
 
   if constexpr (MODE == PB_PRECOND) {
 #pragma unroll
     for (int s = 0; s < R; ++s) {
-      const int l = t + s * TPL;
-      const cx<double> r = valid ? gld(a.Rin, l * Nk + kap) : mk(0.0, 0.0);
+      const cx<double> r = valid ? u[s] : zero;
       nrm_r += pw * norm2(r);
-      v[s] = r * gld(a.gam, l);
+      v[s] = r * gam(s);
     }
   } else {
-    // rows of U (or of the Krylov vector v for PB_OPAPPLY) and, issued
-    // before the first barrier, the N^ (or J) rows and per-kappa tables
-    const bool nl_on = valid && a.nonlinear;
-    const cx<TN>* Nc = reinterpret_cast<const cx<TN>*>(Nh);
-    cx<double> n_cur[R];
+    // residual, U part (rows of U, or of the Krylov vector v for PB_OPAPPLY)
 #pragma unroll
     for (int s = 0; s < R; ++s) {
-      const int l = t + s * TPL;
-      u[s] = valid ? gld(a.U, l * Nk + kap) : mk(0.0, 0.0);
-      n_cur[s] = mk(0.0, 0.0);
-      if (nl_on && (MODE != PB_OPAPPLY || l >= 1))
-        n_cur[s] = cvt<double>(gld(Nc, l * Nk + kap));
+      if (!valid) u[s] = zero;
+      lds[(t + s * TPL) * LS + c] = u[s];
     }
-    const cx<double> first =
-        (MODE == PB_OPAPPLY || !valid) ? mk(0.0, 0.0) : gld(a.u0h, kap);
-    const double c1 = nl_on ? gld(a.c1, kap) : 0.0;
-    const double c2 = (nl_on && a.etd2) ? gld(a.c2, kap) : 0.0;
-#pragma unroll
-    for (int s = 0; s < R; ++s) lds[(t + s * TPL) * LS + c] = u[s];
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < R; ++s) {
       const int l = t + s * TPL;
       const cx<double> prev = (l == 0) ? first : lds[(l - 1) * LS + c];
-      // ETD2's second term reads the previous row (just loaded by a
-      // neighbouring thread, so an L2 hit)
-      cx<double> n_prev = mk(0.0, 0.0);
-      cx<double> r;
-      if constexpr (MODE == PB_OPAPPLY) {
-        // (Q - G'(U)) v : v_l - E v_{l-1} - (c1 J_l + c2 J_{l-1}), where
-        // J_l = FFT[N'(u_{l-1}) v_{l-1}] (J_0 = J_{-1} = 0: u_0 is fixed)
-        if (nl_on && a.etd2 && l >= 2)
-          n_prev = cvt<double>(gld(Nc, (l - 1) * Nk + kap));
-        r = u[s] - prev * E - n_cur[s] * c1 - n_prev * c2;
-      } else {
-        if (nl_on && a.etd2)
-          n_prev = cvt<double>(gld(Nc, (l == 0 ? 0 : l - 1) * Nk + kap));
-        r = prev * E - u[s] + n_cur[s] * c1 + n_prev * c2;
+      cx<double> n_cur = zero;
+      if (nl && valid && (MODE != PB_OPAPPLY || l >= 1))
+        n_cur = cvt<double>(nr[s]);
+      // PB_OPAPPLY, (Q - G'(U)) v: v_l - E v_{l-1} - (c1 J_l + c2 J_{l-1})
+      // with J_l = FFT[N'(u_{l-1}) v_{l-1}] (J_0 = 0: u_0 is fixed); else
+      // R_l = E U_{l-1} - U_l + c1 N_l + c2 N_{l-1}
+      v[s] = (MODE == PB_OPAPPLY) ? u[s] - prev * E - n_cur * c1
+                                  : prev * E - u[s] + n_cur * c1;
+      nr[s] = cvt<TN>(n_cur);  // masked row for the N_{l-1} exchange
+    }
+    if (two) {
+      // ETD2: c2 N^_{l-1} with N^_{-1} := N^_0 (J_{-1} := 0 for PB_OPAPPLY)
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < R; ++s)
+        lds[(t + s * TPL) * LS + c] = cvt<double>(nr[s]);
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        const int l = t + s * TPL;
+        const int lp = (l == 0) ? (MODE == PB_OPAPPLY ? -1 : 0) : l - 1;
+        const cx<double> n_prev = lp < 0 ? zero : lds[lp * LS + c];
+        v[s] = (MODE == PB_OPAPPLY) ? v[s] - n_prev * c2 : v[s] + n_prev * c2;
       }
-      nrm_r += pw * norm2(r);
-      v[s] = r * gld(a.gam, l);
+    }
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      if (!valid) v[s] = zero;  // columns past Nk carry nothing
+      nrm_r += pw * norm2(v[s]);
+      v[s] = v[s] * gam(s);
     }
     if constexpr (MODE == PB_RESIDUAL) {
       if (valid) {
 #pragma unroll
         for (int s = 0; s < R; ++s) {
           const int l = t + s * TPL;
-          gst(a.Sout, l * Nk + kap, v[s] * gld(a.igam, l));
+          gst(a.Sout, l * Nk + kap, v[s] * igam(s));
         }
       }
       double acc[4] = {nrm_r, 0.0, 0.0, 0.0};
@@ -245,25 +292,33 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
   }
 
   // step (a): forward time transform with the + sign
-  fft_line<double, NT, 1>(v, lds + c, LS, t, a.tw);
-  // step (b): shifted solves, 1/(Nt (1 - lambda_m E))
+  fft_line_pre<double, NT, 1>(v, lds + c, LS, t, wst);
+  // step (b): shifted solves, 1/(Nt (1 - lambda_m E)), m = t + s TPL
 #pragma unroll
   for (int s = 0; s < R; ++s) {
-    const int m = t + s * TPL;
-    const cx<double> lam = gld(a.lam, m);
+    cx<double> lam = lam_t;  // times e^{2 pi i s/R}
+    if constexpr (R == 4) {
+      if (s == 1) lam = mul_si<1>(lam_t);
+      if (s == 2) lam = mk(-lam_t.x, -lam_t.y);
+      if (s == 3) lam = mul_si<-1>(lam_t);
+    } else if constexpr (R == 2) {
+      if (s == 1) lam = mk(-lam_t.x, -lam_t.y);
+    } else {
+      static_assert(R == 1 || R == 2 || R == 4, "rotations for R <= 4");
+    }
     const double dr = 1.0 - lam.x * E, di = -lam.y * E;
     const double inv = 1.0 / (NT * (dr * dr + di * di));
     v[s] = cmul(v[s], mk(dr * inv, -di * inv));
   }
   __syncthreads();
   // step (c): inverse time transform with the - sign, then Gamma^{-1}
-  fft_line<double, NT, -1>(v, lds + c, LS, t, a.tw);
+  fft_line_pre<double, NT, -1>(v, lds + c, LS, t, wst);
 
   if constexpr (MODE == PB_ITERATE) {
 #pragma unroll
     for (int s = 0; s < R; ++s) {
       const int l = t + s * TPL;
-      const cx<double> sv = v[s] * gld(a.igam, l);
+      const cx<double> sv = v[s] * igam(s);
       const cx<double> un = u[s] + sv;
       nrm_s += pw * norm2(sv);
       nrm_u += pw * norm2(un);
@@ -273,7 +328,7 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
 #pragma unroll
     for (int s = 0; s < R; ++s) {
       const int l = t + s * TPL;
-      const cx<double> sv = v[s] * gld(a.igam, l);
+      const cx<double> sv = v[s] * igam(s);
       nrm_s += pw * norm2(sv);
       if (valid) gst(a.Sout, l * Nk + kap, sv);
     }
@@ -287,8 +342,6 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
   }
 }
 
-// Cap the registers at the occupancy PassBShape targets so the compiler
-// does not trade waves for early loads.
 template <int NT, int MODE, typename TN>
 __global__ void __launch_bounds__(PassBShape<NT>::THREADS,
                                   PassBShape<NT>::WAVES)
