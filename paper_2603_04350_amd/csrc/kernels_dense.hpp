@@ -168,9 +168,10 @@ __global__ void __launch_bounds__(DENSE_THREADS)
   const PassBArgs a = jobs[j];
   const long lb = blockIdx.x - start[j];
   if constexpr (MODE == PB_ITERATE) {
-    if (a.ctl->done) return;
+    const int ph = job_phase(a.ctl);
+    if (ph < 0) return;
     if (lb == 0 && threadIdx.x == 0) a.ctl->pending = 1;
-    if (a.Nh32 != nullptr && a.ctl->phase == 0)
+    if (a.Nh32 != nullptr && ph == 0)
       passb_dense_body<NT, MODE, float>(
           a, lb, static_cast<const float*>(a.Nh32), lds, red);
     else

@@ -26,9 +26,9 @@ namespace expdiag {
 // Per-instance control block, device resident (kernels_passb.hpp updates it).
 struct Ctl {
   int done;      // 0 running, 1 finished (tolerance or max_iter), 2 diverged
+  int phase;     // 0: fp32 bulk residual (mixed precision), 1: fp64
   int iters;     // iterations completed
   int max_iter;
-  int phase;     // 0: fp32 bulk residual (mixed precision), 1: fp64
   int pending;   // 1: pass B wrote block partials not yet reduced
   int spare;
   double tol;       // ||S|| / ||U|| target
@@ -42,8 +42,19 @@ struct Ctl {
 // has finished.
 __device__ __forceinline__ int job_phase(const Ctl* c) {
   if (c == nullptr) return 1;
-  if (gld(&c->done, 0)) return -1;
-  return gld(&c->phase, 0);
+  typedef int i2 __attribute__((ext_vector_type(2)));
+  const i2 dp = gld(reinterpret_cast<const i2*>(c), 0);  // {done, phase}
+  return dp.x ? -1 : dp.y;
+}
+
+// Values a thread has just issued loads for, marked as modified by an
+// empty asm statement: the compiler then keeps them in registers instead of
+// moving their loads next to the first use, where (loads completing in
+// issue order) each would cost another memory latency.
+template <typename T, int N>
+__device__ __forceinline__ void pin_loaded(cx<T> (&w)[N]) {
+#pragma unroll
+  for (int i = 1; i < N; ++i) asm volatile("" : "+v"(w[i].x), "+v"(w[i].y));
 }
 
 // True when the job's instance still needs this work.  phase_req < 0: any
@@ -198,6 +209,7 @@ __device__ __forceinline__ void row_body(const RowJob& jb, long lb,
   constexpr int NST = fft_stage_count<M, R>();
   cx<T> wst[NST > 1 ? NST : 2];
   fft_stage_twiddles<T, M, R>(wst, t, tw);
+  pin_loaded(wst);
   cx<T> wk[R];
 #pragma unroll
   for (int s = 0; s < R; ++s)
@@ -282,15 +294,15 @@ __global__ void __launch_bounds__(RowShape<M>::THREADS)
   __shared__ cx<double> lds[RowShape<M>::RPB * RowShape<M>::LS];
   const int i = find_job(start, njobs);
   const long lb = blockIdx.x - start[i];
-  const int ph = job_phase(jobs[2 * i + 1].ctl);
+  const RowJob j1 = jobs[2 * i + 1];
+  const int ph = job_phase(j1.ctl);
   if (ph < 0) return;
   if (ph == 0) {
     const RowJob jb = jobs[2 * i];
     row_body<float, M, MODE, TI0, float>(jb, lb, tw32,
                                          reinterpret_cast<cx<float>*>(lds));
   } else {
-    const RowJob jb = jobs[2 * i + 1];
-    row_body<double, M, MODE, double, double>(jb, lb, tw64, lds);
+    row_body<double, M, MODE, double, double>(j1, lb, tw64, lds);
   }
 }
 
@@ -353,6 +365,7 @@ __device__ __forceinline__ void col_body(const ColJob& jb, int lb,
   constexpr int NST = fft_stage_count<L, R>();
   cx<T> wst[NST > 1 ? NST : 2];
   fft_stage_twiddles<T, L, R>(wst, t, tw);
+  pin_loaded(wst);
   cx<T> v[R];
 #pragma unroll
   for (int s = 0; s < R; ++s) v[s] = cvt<T>(xin[s]);
@@ -379,15 +392,15 @@ __global__ void __launch_bounds__(ColShape<L>::THREADS, 5)
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const int i = find_job(start, njobs, b);
   const int lb = b - start[i];
-  const int ph = job_phase(jobs[2 * i + 1].ctl);
+  const ColJob j1 = jobs[2 * i + 1];
+  const int ph = job_phase(j1.ctl);
   if (ph < 0) return;
   if (ph == 0) {
     const ColJob jb = jobs[2 * i];
     col_body<float, L, S, TI0, float>(jb, lb, tw32,
                                       reinterpret_cast<cx<float>*>(lds));
   } else {
-    const ColJob jb = jobs[2 * i + 1];
-    col_body<double, L, S, double, double>(jb, lb, tw64, lds);
+    col_body<double, L, S, double, double>(j1, lb, tw64, lds);
   }
 }
 

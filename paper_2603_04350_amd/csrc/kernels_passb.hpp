@@ -220,6 +220,7 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
   constexpr int NST = fft_stage_count<NT, R>();
   cx<double> wst[NST > 1 ? NST : 2];
   fft_stage_twiddles<double, NT, R>(wst, t, a.tw);
+  pin_loaded(wst);
   auto gam = [&](int s) { return s == 0 ? gam_t : gam_t * a.gstep[s]; };
   auto igam = [&](int s) { return s == 0 ? igam_t : igam_t * a.igstep[s]; };
 
@@ -356,9 +357,10 @@ __global__ void __launch_bounds__(PassBShape<NT>::THREADS,
   const PassBArgs a = jobs[j];  // by value: the kernel stores through a.U
   const long lb = blockIdx.x - start[j];
   if constexpr (MODE == PB_ITERATE) {
-    if (a.ctl->done) return;
+    const int ph = job_phase(a.ctl);
+    if (ph < 0) return;
     if (lb == 0 && threadIdx.x == 0) a.ctl->pending = 1;
-    if (a.Nh32 != nullptr && a.ctl->phase == 0)
+    if (a.Nh32 != nullptr && ph == 0)
       passb_body<NT, MODE, float>(a, lb, static_cast<const float*>(a.Nh32),
                                   lds, red);
     else
