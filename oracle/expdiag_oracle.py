@@ -30,9 +30,16 @@ Readings taken where the paper is silent (also listed in the design doc):
   * The fixed point is written in residual-correction form
     u^{k+1} = u^k + Q_alpha^{-1}(f + G(u^k) - Q u^k)  (eq. pcond-1st-order),
     which equals the paper's b^{k-1} form in exact arithmetic.
+  * EBDF2 (scheme 3, Sec. 4, linear problems only): the starting value is
+    u_1 = A u_0, the exact exponential step (the paper leaves u_1 open).
+    Space-time arrays still hold u_1..u_Nt; the unknown of the paper's
+    system is v = (u_2..u_Nt), and f_2 is built from u_0 and that u_1, so
+    the iteration on v does not depend on what slice 1 holds.  Slice 1's
+    own residual row is A u_0 - u_1 and its preconditioner is the identity.
 
-parity: every function here is pinned by tests/test_oracle_pins.py (closed
-forms, dense LU, mpmath, textbook GMRES, convergence order).
+parity: every function here is pinned by tests/test_oracle_pins.py and, for
+EBDF2, tests/test_oracle_ebdf2.py (closed forms, dense LU, mpmath, textbook
+GMRES, convergence order, the exact spectra of Sec. 4).
 """
 from __future__ import annotations
 
@@ -46,7 +53,12 @@ __all__ = [
     "fixed_point", "q_apply", "qalpha_apply", "gprime_apply", "gmres",
     "gmres_solve", "newton_gmres", "rel_err", "dense_operators",
     "dense_solve", "dense_newton", "time_dft", "time_idft",
+    "EBDF2", "ebdf2_tables", "sequential_ebdf2", "residual_ebdf2",
+    "r_apply_ebdf2", "ralpha_apply_ebdf2", "precond_apply_ebdf2",
+    "gmres_solve_ebdf2", "dense_operators_ebdf2",
 ]
+
+EBDF2 = 3  # scheme code of the second-order exponential BDF (Sec. 4)
 
 
 # ---------------------------------------------------------------------------
@@ -168,8 +180,11 @@ def sequential(st: Setup, u0):
 
     Linear part: u_n = A u_{n-1} (Sec. 2, eq. disc_wr).  The all-at-once
     system Q u = f of Sec. 3 (eq. all_at_once_1storder) has exactly this
-    block forward substitution as its solution.
+    block forward substitution as its solution.  Scheme EBDF2 steps by
+    sequential_ebdf2.
     """
+    if st.scheme == EBDF2:
+        return sequential_ebdf2(st, u0)
     U = np.empty((st.Nt,) + u0.shape)
     prev2, prev = u0, u0
     for j in range(st.Nt):
@@ -275,7 +290,9 @@ def fixed_point(st: Setup, u0, U0=None, max_iter=200, tol=1e-11, ref=None,
     """u^{k+1} = u^k + s^k,  Q_alpha s^k = f + G(u^k) - Q u^k.
 
     Eq. pcond-1st-order (linear) with the nonlinearity lagged one iteration
-    (Sec. 6.2).  U^0 = 0 unless given (Sec. 6 starts from zeros).
+    (Sec. 6.2); for EBDF2 the iteration of eq. pcond-2nd-order,
+    v^{k+1} = v^k + R_alpha^{-1}(f_2 - R v^k), on slices 2..Nt.
+    U^0 = 0 unless given (Sec. 6 starts from zeros).
     Stops when ||s^k|| <= tol ||u^{k+1}||, or, if `ref` is given and
     ref_tol is set, when rel_err(u^{k+1}, ref) <= ref_tol.
     Returns (U, iterations, history) where history holds
@@ -284,9 +301,10 @@ def fixed_point(st: Setup, u0, U0=None, max_iter=200, tol=1e-11, ref=None,
     """
     U = np.zeros((st.Nt,) + u0.shape) if U0 is None else U0.copy()
     hist, iterates = [], []
+    bdf2 = st.scheme == EBDF2
     for k in range(max_iter):
-        R = residual(st, u0, U)
-        S = precond_apply(st, R)
+        R = residual_ebdf2(st, u0, U) if bdf2 else residual(st, u0, U)
+        S = precond_apply_ebdf2(st, R) if bdf2 else precond_apply(st, R)
         U = U + S
         upd = np.linalg.norm(S) / max(np.linalg.norm(U), 1e-300)
         err = rel_err(U, ref) if ref is not None else float("nan")
@@ -507,3 +525,140 @@ def dense_newton(st: Setup, u0, tol=1e-14, max_iter=50, D=None):
             break
         U = U - np.linalg.solve(J_of(U), R)
     return U.reshape((Nt,) + u0.shape)
+
+
+# ---------------------------------------------------------------------------
+# EBDF2: the second-order exponential BDF of Sec. 4 (linear problems)
+# ---------------------------------------------------------------------------
+def ebdf2_tables(st: Setup):
+    """Time tables of the (Nt-1)-slice system (Sec. 4, with Nt replaced by
+    Nt-1 in the diagonalisation of Sec. 2): gamma_j = alpha^{j/(Nt-1)},
+    lambda_{0,j} = alpha^{1/(Nt-1)} e^{2 pi i j/(Nt-1)} and, as the paper
+    states them, lambda_{1,j} = alpha^{2/(Nt-1)} e^{4 pi i j/(Nt-1)},
+    j = 0..Nt-2."""
+    N = st.Nt - 1
+    j = np.arange(N, dtype=np.float64)
+    gamma = st.alpha ** (j / N)
+    lam0 = st.alpha ** (1.0 / N) * np.exp(2j * np.pi * j / N)
+    lam1 = st.alpha ** (2.0 / N) * np.exp(4j * np.pi * j / N)
+    return gamma, lam0, lam1
+
+
+def sequential_ebdf2(st: Setup, u0):
+    """u_1..u_Nt of eq. 2nd_order_scheme: u_n = 4/3 A u_{n-1} - 1/3 B u_{n-2}
+    with B = A^2, started from u_1 = A u_0."""
+    U = np.empty((st.Nt,) + u0.shape)
+    U[0] = st.A(u0)
+    prev2, prev = u0, U[0]
+    for j in range(1, st.Nt):
+        U[j] = 4.0 / 3.0 * st.A(prev) - 1.0 / 3.0 * st.A(st.A(prev2))
+        prev2, prev = prev, U[j]
+    return U
+
+
+def _B(st: Setup, v):
+    """B v with B = A^2 (eq. 2nd_order_scheme), applied through the symbol."""
+    return st.spectral_apply(v, st.E ** 2).real
+
+
+def r_apply_ebdf2(st: Setup, V):
+    """R v for v = (v_2..v_Nt) with R = I - 4/3 C_0 (x) A + 1/3 C_1 (x) B
+    (eq. all_at_once_2ndorder): row j is v_j - 4/3 A v_{j-1} + 1/3 B v_{j-2},
+    entries before v_2 being zero."""
+    out = V.copy()
+    out[1:] -= 4.0 / 3.0 * st.A(V[:-1])
+    out[2:] += 1.0 / 3.0 * _B(st, V[:-2])
+    return out
+
+
+def ralpha_apply_ebdf2(st: Setup, V):
+    """R_alpha v with C_0^alpha, C_1^alpha of eq. pcond-2nd-order: C_1^alpha
+    carries alpha at (1, Nt-2) and (2, Nt-1), C_0^alpha at (1, Nt-1)."""
+    out = r_apply_ebdf2(st, V)
+    a = st.alpha
+    out[0] += -4.0 / 3.0 * a * st.A(V[-1]) + 1.0 / 3.0 * a * _B(st, V[-2])
+    out[1] += 1.0 / 3.0 * a * _B(st, V[-1])
+    return out
+
+
+def residual_ebdf2(st: Setup, u0, U):
+    """Residual of the EBDF2 window on slices u_1..u_Nt.
+
+    Slice 1: A u_0 - u_1.  Slices 2..Nt: f_2 - R v (eq. all_at_once_2ndorder)
+    with v = (u_2..u_Nt) and f_2 = (4/3 A u_1 - 1/3 B u_0, -1/3 B u_1, 0..)
+    built from u_1 = A u_0, not from slice 1 of U.
+    """
+    u1 = st.A(u0)
+    R = np.empty_like(U)
+    R[0] = u1 - U[0]
+    f2 = np.zeros_like(U[1:])
+    f2[0] = 4.0 / 3.0 * st.A(u1) - 1.0 / 3.0 * _B(st, u0)
+    if st.Nt > 2:
+        f2[1] = -1.0 / 3.0 * _B(st, u1)
+    R[1:] = f2 - r_apply_ebdf2(st, U[1:])
+    return R
+
+
+def precond_apply_ebdf2(st: Setup, R):
+    """Slice 1 unchanged; slices 2..Nt: R_alpha^{-1} by the three steps of
+    eq. exp_ParaDiag_steps_2ndorder with Nt-1 time points:
+      (a) S_p = (F (x) I)(Gamma_alpha (x) I) r
+      (b) S_q,j = (I - 4/3 lambda_{0,j} A + 1/3 lambda_{1,j} B)^{-1} S_p,j
+      (c) s = (Gamma_alpha^{-1} (x) I)(F^* (x) I) S_q
+    """
+    gamma, lam0, lam1 = ebdf2_tables(st)
+    N = st.Nt - 1
+    g = gamma.reshape((N,) + (1,) * st.dim)
+    Sp = time_dft(g * R[1:])
+    Sq = np.empty_like(Sp)
+    E = st.E
+    for j in range(N):
+        sym = 1.0 - 4.0 / 3.0 * lam0[j] * E + 1.0 / 3.0 * lam1[j] * E * E
+        Sq[j] = st.spectral_apply(Sp[j], 1.0 / sym)
+    S = np.empty_like(R)
+    S[0] = R[0]
+    S[1:] = (time_idft(Sq) / g).real
+    return S
+
+
+def gmres_solve_ebdf2(st: Setup, u0, restart=20, tol=1e-10, max_iter=200):
+    """GMRES on R_alpha^{-1} R v = R_alpha^{-1} f_2 (Sec. 4.2), v^0 = 0;
+    returns the window u_1..u_Nt with u_1 = A u_0."""
+    zeros = np.zeros((st.Nt,) + u0.shape)
+    f2 = residual_ebdf2(st, u0, zeros)[1:]
+
+    def prec(v):
+        full = np.zeros((st.Nt,) + u0.shape)
+        full[1:] = v
+        return precond_apply_ebdf2(st, full)[1:]
+
+    b = prec(f2)
+    op = lambda v: prec(r_apply_ebdf2(st, v))
+    v, it, hist = gmres(op, b, np.zeros_like(f2), restart, tol, max_iter)
+    U = np.empty((st.Nt,) + u0.shape)
+    U[0] = st.A(u0)
+    U[1:] = v
+    return U, it, hist
+
+
+def dense_operators_ebdf2(st: Setup):
+    """Dense A, B, C_0, C_1, their alpha-circulant versions, R, R_alpha
+    (eqs. all_at_once_2ndorder, alpha_circ_c1, pcond-2nd-order), assembled
+    entry by entry for (Nt-1) time slices."""
+    D = dense_operators(st)
+    A = D["A"]
+    B = A @ A
+    N = st.Nt - 1
+    C0 = np.diag(np.ones(N - 1), -1)
+    C1 = np.diag(np.ones(N - 2), -2)
+    C0a = C0.copy()
+    C0a[0, N - 1] = st.alpha
+    C1a = C1.copy()
+    C1a[0, N - 2] = st.alpha
+    C1a[1, N - 1] = st.alpha
+    I = np.eye(N * A.shape[0])
+    return {
+        "A": A, "B": B, "C0": C0, "C1": C1, "C0a": C0a, "C1a": C1a,
+        "R": I - 4.0 / 3.0 * np.kron(C0, A) + 1.0 / 3.0 * np.kron(C1, B),
+        "Ra": I - 4.0 / 3.0 * np.kron(C0a, A) + 1.0 / 3.0 * np.kron(C1a, B),
+    }

@@ -95,3 +95,64 @@ def test_nonlinear_derivative_wrong(monkeypatch):
     # Newton-GMRES with a wrong Jacobian still converges (slower) to the
     # unique solution, so the pin is on the Newton step count
     assert _fails(P.test_newton_gmres_reaches_sequential, 1)
+
+
+# ---------------------------------------------------------------------------
+# EBDF2 (Sec. 4)
+# ---------------------------------------------------------------------------
+import tests.test_oracle_ebdf2 as P2  # noqa: E402
+
+
+def _patch_both(monkeypatch, name, fn):
+    """Replace an oracle function in its module and in the package
+    namespace the pins call it through."""
+    monkeypatch.setattr(OE, name, fn)
+    monkeypatch.setattr(P2.O, name, fn)
+
+
+def test_ebdf2_lambda1_replaced_by_lambda0(monkeypatch):
+    orig = OE.ebdf2_tables
+
+    def bad(st):
+        g, l0, l1 = orig(st)
+        return g, l0, l0
+    _patch_both(monkeypatch, "ebdf2_tables", bad)
+    assert _fails(P2.test_ebdf2_precond_equals_dense_inverse, 1, 12, 8, 1e-2)
+    assert _fails(P2.test_ebdf2_alpha_circulants_share_eigenvectors, 8, 1e-2)
+
+
+def test_ebdf2_B_is_A_not_A_squared(monkeypatch):
+    monkeypatch.setattr(OE, "_B", lambda st, v: st.A(v))
+    assert _fails(P2.test_ebdf2_single_mode_heat_exact)
+    assert _fails(P2.test_ebdf2_residual_and_operators_equal_dense)
+
+
+def test_ebdf2_f2_from_slice_one(monkeypatch):
+    def bad_residual(st, u0, U):
+        R = np.empty_like(U)
+        R[0] = st.A(u0) - U[0]
+        f2 = np.zeros_like(U[1:])
+        f2[0] = 4.0 / 3.0 * st.A(U[0]) - 1.0 / 3.0 * OE._B(st, u0)
+        f2[1] = -1.0 / 3.0 * OE._B(st, U[0])
+        R[1:] = f2 - OE.r_apply_ebdf2(st, U[1:])
+        return R
+    _patch_both(monkeypatch, "residual_ebdf2", bad_residual)
+    assert _fails(P2.test_ebdf2_residual_and_operators_equal_dense)
+
+
+def test_ebdf2_C1_alpha_misplaced(monkeypatch):
+    orig = OE.dense_operators_ebdf2
+
+    def bad(st):
+        D = orig(st)
+        N = st.Nt - 1
+        C1a = D["C1"].copy()
+        C1a[0, N - 1] = st.alpha        # one column off
+        C1a[1, N - 1] = st.alpha
+        D["C1a"] = C1a
+        I = np.eye(D["R"].shape[0])
+        D["Ra"] = I - 4.0 / 3.0 * np.kron(D["C0a"], D["A"]) + \
+            1.0 / 3.0 * np.kron(C1a, D["B"])
+        return D
+    _patch_both(monkeypatch, "dense_operators_ebdf2", bad)
+    assert _fails(P2.test_ebdf2_iteration_matrix_spectrum, 6, 0.05, 0.0)
