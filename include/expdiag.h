@@ -15,6 +15,14 @@
  *                 u_{-1} := u_0
  * For N == 0 both reduce to the paper's first-order scheme u_n = A u_{n-1}
  * (Sec. 2, eq. disc_wr).
+ *   EXPDIAG_EBDF2 (linear problems, N == 0): the second-order exponential
+ *                 BDF of Sec. 4 (eq. 2nd_order_scheme),
+ *                 u_n = 4/3 A u_{n-1} - 1/3 A^2 u_{n-2}, started from
+ *                 u_1 = A u_0.  Slice 1 of a window is that fixed start; the
+ *                 unknowns are u_2..u_Nt (eq. all_at_once_2ndorder), whose
+ *                 residual f_2 - R v takes u_1 = A u_0 whatever slice 1
+ *                 holds, and whose preconditioner is R_alpha of eq.
+ *                 pcond-2nd-order on Nt - 1 time points.
  *
  * Conventions for every entry point:
  *   - Array arguments are DEVICE pointers to float64 data owned by the caller
@@ -54,6 +62,7 @@ extern "C" {
 
 #define EXPDIAG_ETD1 1
 #define EXPDIAG_ETD2 2
+#define EXPDIAG_EBDF2 3
 
 #define EXPDIAG_FP64 0
 #define EXPDIAG_MIXED 1
@@ -87,9 +96,11 @@ typedef struct {
  * device workspace (size given by expdiag_footprint_bytes).
  *   g        grid (host pointer)
  *   Nt       number of time steps in the window, power of two, 2..512
+ *            (EBDF2: 8..128, its time transform being the dense one)
  *   dt       time step (> 0); the window is T = Nt dt
  *   alpha    circulant parameter, 0 < alpha < 1
- *   scheme   EXPDIAG_ETD1 or EXPDIAG_ETD2
+ *   scheme   EXPDIAG_ETD1, EXPDIAG_ETD2, or EXPDIAG_EBDF2 (linear problems
+ *            only; EUNSUPPORTED otherwise)
  *   p        PDE coefficients and options (host pointer)
  *   hip_stream  hipStream_t to enqueue on (NULL = default stream)
  *   out      receives the handle
@@ -113,6 +124,8 @@ size_t expdiag_footprint_bytes(const expdiag_grid* g, int Nt, int scheme,
 /* All-at-once residual R = f + G(U) - Q U (right-hand side of eq.
  * pcond-1st-order, with Q = I - C_0 (x) A and f = (A u0 + dt phi1 N(u0),
  * 0, .., 0)); slice n of R is A u_{n-1} + G_n - u_n with u_0 = u0.
+ * EBDF2: slice 1 is A u0 - u_1, slices 2..Nt are f_2 - R v (eq.
+ * all_at_once_2ndorder) with v = (u_2..u_Nt) and u_1 := A u0 in f_2.
  *   u0    Ns doubles (device)     U, R   Nt*Ns doubles (device, distinct)
  *   rnorm if non-NULL, host pointer receiving ||R||_2 (the call then
  *         synchronises); if NULL the call only enqueues. */
@@ -123,11 +136,16 @@ int expdiag_residual(expdiag_t h, const double* u0, const double* U,
  * (a) alpha-scaled forward time transform, (b) Nt independent shifted
  * solves (I - lambda_m A)^{-1}, pointwise in Fourier space, (c) inverse
  * time transform.  R and S are Nt*Ns doubles (device); S may equal R.
+ * EBDF2: slice 1 is copied, slices 2..Nt get R_alpha^{-1} by the steps of
+ * eq. exp_ParaDiag_steps_2ndorder (shifted solves
+ * (I - 4/3 lambda_0 A + 1/3 lambda_1 A^2)^{-1}) on Nt - 1 points.
  * Enqueue only. */
 int expdiag_precond_apply(expdiag_t h, const double* R, double* S);
 
 /* Preconditioned fixed point u^{k+1} = u^k + Q_alpha^{-1}(f + G(u^k) - Q u^k)
- * (eq. pcond-1st-order; nonlinear term lagged as in Sec. 6.2).
+ * (eq. pcond-1st-order; nonlinear term lagged as in Sec. 6.2); for EBDF2
+ * v^{k+1} = v^k + R_alpha^{-1}(f_2 - R v^k) (eq. pcond-2nd-order), slice 1
+ * being set to A u0.
  *   u0        initial condition, Ns doubles (device)
  *   U         in: initial iterate (zeros in the paper's experiments),
  *             out: final iterate; Nt*Ns doubles (device)
@@ -141,7 +159,9 @@ int expdiag_iterate(expdiag_t h, const double* u0, double* U, int max_iter,
                     double tol, int* iters, double* rel_update);
 
 /* Left-preconditioned GMRES(restart) (Sec. 3.2, Theorem thm_gmres1's
- * system Q_alpha^{-1} Q u = Q_alpha^{-1} f) for linear problems; for
+ * system Q_alpha^{-1} Q u = Q_alpha^{-1} f) for linear problems (EBDF2:
+ * R_alpha^{-1} R v = R_alpha^{-1} f_2 of Sec. 4.2, slice 1 set to A u0
+ * first); for
  * nonlinear problems, Newton's method on R(U) = 0 whose correction
  * equations (Q - G'(U)) d = R(U) are solved by the same preconditioned
  * GMRES with forcing term min(1e-3, ||R_j|| / ||R_0||).
@@ -178,7 +198,8 @@ int expdiag_set_graph(expdiag_t h, int on);
  * registers and LDS (any Nt), 1 = dense complex Nt x Nt GEMM on FP64 MFMA
  * (8 <= Nt <= 128).  Both compute the same operator; results agree to
  * rounding.  set() rebuilds the handle's plan (EUNSUPPORTED if the variant
- * does not cover Nt); get() returns the current one. */
+ * does not cover Nt, and for EBDF2, whose Nt - 1 points only the dense
+ * variant covers); get() returns the current one. */
 int expdiag_set_time_variant(expdiag_t h, int variant);
 int expdiag_get_time_variant(expdiag_t h);
 
@@ -187,7 +208,9 @@ int expdiag_get_time_variant(expdiag_t h);
  * records it in the JSON cache file `cache_path` (nullable) under the key
  * gfx950/d<d>/<n0>x<n1>x<n2>/Nt<Nt>/<fp64|mixed>; a cached entry is used
  * without measuring.  variant, us_fft, us_dense (host, nullable) receive
- * the choice and the per-launch times (us_dense = -1 when not applicable). */
+ * the choice and the per-launch times (us_dense = -1 when not applicable).
+ * EBDF2 handles have only the dense variant: it is timed and kept (us_fft =
+ * -1), and the cache is neither read nor written. */
 int expdiag_autotune(expdiag_t h, const char* cache_path, int* variant,
                      double* us_fft, double* us_dense);
 

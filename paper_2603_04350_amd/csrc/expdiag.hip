@@ -38,6 +38,7 @@
 
 #include "../../include/expdiag.h"
 #include "kernels_dense.hpp"
+#include "kernels_bdf2.hpp"
 #include "kernels_fft.hpp"
 #include "kernels_krylov.hpp"
 #include "kernels_passb.hpp"
@@ -416,6 +417,17 @@ double passb_bytes(const PassBArgs& a, int Nt, int mode, size_t nb) {
 template <int MODE, typename TN>
 int launch_passb1(expdiag_ctx* h, const PassBArgs& a) {
   ProfScope ps(h, P_PASSB, passb_bytes(a, h->Nt, MODE, sizeof(cx<TN>)));
+  if (h->scheme == EXPDIAG_EBDF2) {
+    const bool ok = dispatch_pow2<DENSE_NT_MIN, DENSE_NT_MAX>(h->Nt, [&](auto Nc) {
+      constexpr int NN = decltype(Nc)::value;
+      hipLaunchKernelGGL((passb_bdf2_kernel1<NN, MODE>),
+                         dim3(dense_blocks(h->Nk)), dim3(DENSE_THREADS), 0,
+                         h->stream, a);
+    });
+    if (!ok) return fail(h, EXPDIAG_EUNSUPPORTED, "EBDF2 Nt %d", h->Nt);
+    HIPCHK(h, hipGetLastError());
+    return 0;
+  }
   if (MODE == PB_PRECOND && h->tvariant == 1) {
     const bool ok = dispatch_pow2<DENSE_NT_MIN, DENSE_NT_MAX>(h->Nt, [&](auto Nc) {
       constexpr int NN = decltype(Nc)::value;
@@ -701,7 +713,9 @@ void plan_iteration(Plan& P, expdiag_ctx* h, Ctl* ctl, Ctl* mirror,
   a.hist = hist;
   if (h->nonlinear && h->mixed) a.Nh32 = nh_view<float>(h);
   const bool hosted = h->nonlinear && plan_pass_a_mp(P, h, ctl, a);
-  plan_passb(P, 5, h->Nt, a, sizeof(cx<double>), h->tvariant, !hosted);
+  // pass B variant: 0 radix FFT, 1 dense, 2 EBDF2 (dense, N = Nt - 1)
+  const int variant = h->scheme == EXPDIAG_EBDF2 ? 2 : h->tvariant;
+  plan_passb(P, 5, h->Nt, a, sizeof(cx<double>), variant, !hosted);
 }
 
 // Algorithmic bytes of one iteration of a plan.
@@ -858,6 +872,12 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st,
           ok = dispatch_pow2<DENSE_NT_MIN, DENSE_NT_MAX>(g.len, [&](auto Nc) {
             constexpr int NN = decltype(Nc)::value;
             klaunch(ps, passb_dense_kernel<NN, PB_ITERATE, double>, dim3(grid),
+                    dim3(DENSE_THREADS), st, J, g.dstart, nj);
+          });
+        } else if (g.tcode == 2) {
+          ok = dispatch_pow2<DENSE_NT_MIN, DENSE_NT_MAX>(g.len, [&](auto Nc) {
+            constexpr int NN = decltype(Nc)::value;
+            klaunch(ps, passb_bdf2_kernel<NN>, dim3(grid),
                     dim3(DENSE_THREADS), st, J, g.dstart, nj);
           });
         } else {
@@ -1059,44 +1079,51 @@ int build_tables(expdiag_ctx* h) {
   std::vector<double> E, c1, c2;
   symbol_tables(h, E, c1, c2);
   const int Nt = h->Nt;
-  std::vector<double> gam(Nt), igam(Nt);
-  std::vector<cx<double>> lam(Nt);
-  // e^{2 pi i j/Nt}, j < Nt: every angle the time tables use
-  std::vector<long double> cs(Nt), sn(Nt);
+  // The transform runs over N time points: Nt, or for EBDF2 the Nt - 1
+  // unknown slices 2..Nt, which sit at row offset o = 1 of a window.
+  const bool bdf2 = h->scheme == EXPDIAG_EBDF2;
+  const int N = bdf2 ? Nt - 1 : Nt;
+  const int o = bdf2 ? 1 : 0;
+  std::vector<double> gam(Nt, 1.0), igam(Nt, 1.0);
+  std::vector<cx<double>> lam(Nt, mk(0.0, 0.0));
+  // e^{2 pi i j/N}, j < N: every angle the time tables use
+  std::vector<long double> cs(N), sn(N);
   const long double la = logl(static_cast<long double>(h->alpha));
   const long double pi = 3.141592653589793238462643383279502884L;
-  const long double root = expl(la / Nt);
-  std::vector<long double> gl(Nt);
-  for (int l = 0; l < Nt; ++l) {
-    const long double th = 2.0L * pi * l / Nt;
+  const long double root = expl(la / N);
+  std::vector<long double> gl(N);
+  for (int l = 0; l < N; ++l) {
+    const long double th = 2.0L * pi * l / N;
     cs[l] = cosl(th);
     sn[l] = sinl(th);
-    gl[l] = expl(la * l / Nt);
+    gl[l] = expl(la * l / N);
     gam[l] = static_cast<double>(gl[l]);
     igam[l] = static_cast<double>(1.0L / gl[l]);
     lam[l] = mk<double>(static_cast<double>(root * cs[l]),
                         static_cast<double>(root * sn[l]));
   }
   if (h->Wf != nullptr) {
-    // [[Re, -Im], [Im, Re]] of Wf[m][l] = gamma_l e^{+2 pi i ml/Nt} / Nt and
-    // Wi[l][m] = gamma_l^{-1} e^{-2 pi i ml/Nt}
+    // [[Re, -Im], [Im, Re]] of Wf[m][l + o] = gamma_l e^{+2 pi i ml/N} / N
+    // and Wi[l + o][m] = gamma_l^{-1} e^{-2 pi i ml/N}, m, l < N; every
+    // other entry zero
     const int K = 2 * Nt;
-    std::vector<double> wf(static_cast<size_t>(K) * K), wi(wf.size());
-    for (int m = 0; m < Nt; ++m) {
-      for (int l = 0; l < Nt; ++l) {
-        const int j = static_cast<int>((static_cast<long>(m) * l) % Nt);
+    std::vector<double> wf(static_cast<size_t>(K) * K, 0.0), wi(wf.size(), 0.0);
+    for (int m = 0; m < N; ++m) {
+      for (int l = 0; l < N; ++l) {
+        const int j = static_cast<int>((static_cast<long>(m) * l) % N);
         const long double g = gl[l];
-        const long double fr = g * cs[j] / Nt, fi = g * sn[j] / Nt;
-        wf[m * K + l] = static_cast<double>(fr);
-        wf[m * K + Nt + l] = static_cast<double>(-fi);
-        wf[(Nt + m) * K + l] = static_cast<double>(fi);
-        wf[(Nt + m) * K + Nt + l] = static_cast<double>(fr);
-        // Wi row l, column m
+        const long double fr = g * cs[j] / N, fi = g * sn[j] / N;
+        const int c = l + o;
+        wf[m * K + c] = static_cast<double>(fr);
+        wf[m * K + Nt + c] = static_cast<double>(-fi);
+        wf[(Nt + m) * K + c] = static_cast<double>(fi);
+        wf[(Nt + m) * K + Nt + c] = static_cast<double>(fr);
+        // Wi row l + o, column m
         const long double ir = cs[j] / g, ii = -sn[j] / g;
-        wi[l * K + m] = static_cast<double>(ir);
-        wi[l * K + Nt + m] = static_cast<double>(-ii);
-        wi[(Nt + l) * K + m] = static_cast<double>(ii);
-        wi[(Nt + l) * K + Nt + m] = static_cast<double>(ir);
+        wi[c * K + m] = static_cast<double>(ir);
+        wi[c * K + Nt + m] = static_cast<double>(-ii);
+        wi[(Nt + c) * K + m] = static_cast<double>(ii);
+        wi[(Nt + c) * K + Nt + m] = static_cast<double>(ir);
       }
     }
     HIPCHK(h, hipMemcpy(h->Wf, wf.data(), wf.size() * sizeof(double),
@@ -1270,12 +1297,16 @@ size_t expdiag_footprint_bytes(const expdiag_grid* g, int Nt, int scheme,
   Sizes s{};
   if (check_grid(g, &s) != 0) return 0;
   if (!is_pow2(Nt) || Nt < 2 || Nt > 512) return 0;
-  if (scheme != EXPDIAG_ETD1 && scheme != EXPDIAG_ETD2) return 0;
+  if (scheme != EXPDIAG_ETD1 && scheme != EXPDIAG_ETD2 &&
+      scheme != EXPDIAG_EBDF2)
+    return 0;
+  if (scheme == EXPDIAG_EBDF2 && !dense_ok(Nt)) return 0;
   if (precision != EXPDIAG_FP64 && precision != EXPDIAG_MIXED) return 0;
   if (gmres_restart < 0 || gmres_restart > 64) return 0;
   // the nonlinearity is not known here: report the nonlinear footprint
-  return footprint(s, g->dim, Nt, true, precision == EXPDIAG_MIXED,
-                   gmres_restart);
+  // (EBDF2 is linear only)
+  return footprint(s, g->dim, Nt, scheme != EXPDIAG_EBDF2,
+                   precision == EXPDIAG_MIXED, gmres_restart);
 }
 
 }  // extern "C"
@@ -1292,8 +1323,16 @@ int validate_params(int Nt, double dt, double alpha, int scheme,
     return fail(nullptr, EXPDIAG_EINVAL, "dt must be > 0");
   if (!(alpha > 0.0 && alpha < 1.0))
     return fail(nullptr, EXPDIAG_EINVAL, "alpha must lie in (0, 1)");
-  if (scheme != EXPDIAG_ETD1 && scheme != EXPDIAG_ETD2)
+  if (scheme != EXPDIAG_ETD1 && scheme != EXPDIAG_ETD2 &&
+      scheme != EXPDIAG_EBDF2)
     return fail(nullptr, EXPDIAG_EINVAL, "unknown scheme %d", scheme);
+  if (scheme == EXPDIAG_EBDF2 &&
+      (p->n1 != 0.0 || p->n2 != 0.0 || p->n3 != 0.0))
+    return fail(nullptr, EXPDIAG_EUNSUPPORTED,
+                "EBDF2 is for linear problems (n1 = n2 = n3 = 0)");
+  if (scheme == EXPDIAG_EBDF2 && !dense_ok(Nt))
+    return fail(nullptr, EXPDIAG_EUNSUPPORTED,
+                "EBDF2 needs %d <= Nt <= %d", DENSE_NT_MIN, DENSE_NT_MAX);
   if (!(p->a >= 0.0) || !(p->c >= 0.0) || !std::isfinite(p->a) ||
       !std::isfinite(p->c) || !std::isfinite(p->n1) ||
       !std::isfinite(p->n2) || !std::isfinite(p->n3))
@@ -1313,6 +1352,10 @@ int reinit_params(expdiag_ctx* h, double dt, double alpha, int scheme,
   RCHK(validate_params(h->Nt, dt, alpha, scheme, p));
   h->dt = dt;
   h->alpha = alpha;
+  if (scheme == EXPDIAG_EBDF2)
+    h->tvariant = 1;  // N = Nt - 1 time points: dense transform only
+  else if (h->scheme == EXPDIAG_EBDF2)
+    h->tvariant = 0;
   h->scheme = scheme;
   h->p = *p;
   h->p.gmres_restart = h->restart_cap;
@@ -1350,6 +1393,7 @@ int create_impl(const expdiag_grid* g, int Nt, double dt, double alpha,
   h->nonlinear = (p->n1 != 0.0 || p->n2 != 0.0 || p->n3 != 0.0);
   h->mixed = p->precision == EXPDIAG_MIXED;
   h->restart_cap = p->gmres_restart;
+  if (scheme == EXPDIAG_EBDF2) h->tvariant = 1;
 
   const size_t st = static_cast<size_t>(Nt) * h->Nk * sizeof(cx<double>);
   int rc = 0;

@@ -23,6 +23,7 @@ EXPDIAG_EDIVERGED = -4
 EXPDIAG_EUNSUPPORTED = -5
 EXPDIAG_ETD1 = 1
 EXPDIAG_ETD2 = 2
+EXPDIAG_EBDF2 = 3
 EXPDIAG_FP64 = 0
 EXPDIAG_MIXED = 1
 

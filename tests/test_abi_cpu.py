@@ -55,7 +55,14 @@ def _create(lib, shape, Nt, dt, alpha, scheme, prob):
     ((64,), 8, 0.0, 1e-2, 1, X.make_problem(1.0), X.EXPDIAG_EINVAL),
     ((64,), 8, 0.1, 0.0, 1, X.make_problem(1.0), X.EXPDIAG_EINVAL),
     ((64,), 8, 0.1, 1.0, 1, X.make_problem(1.0), X.EXPDIAG_EINVAL),
-    ((64,), 8, 0.1, 1e-2, 3, X.make_problem(1.0), X.EXPDIAG_EINVAL),
+    ((64,), 8, 0.1, 1e-2, 4, X.make_problem(1.0), X.EXPDIAG_EINVAL),
+    # EBDF2: linear problems, 8 <= Nt <= 128
+    ((64,), 8, 0.1, 1e-2, X.EXPDIAG_EBDF2, X.make_problem(1.0, n1=1.0),
+     X.EXPDIAG_EUNSUPPORTED),
+    ((64,), 4, 0.1, 1e-2, X.EXPDIAG_EBDF2, X.make_problem(1.0),
+     X.EXPDIAG_EUNSUPPORTED),
+    ((64,), 256, 0.1, 1e-2, X.EXPDIAG_EBDF2, X.make_problem(1.0),
+     X.EXPDIAG_EUNSUPPORTED),
     ((64,), 8, 0.1, 1e-2, 1, X.make_problem(-1.0), X.EXPDIAG_EINVAL),
     ((64,), 8, 0.1, 1e-2, 1, X.make_problem(1.0, c=-0.1), X.EXPDIAG_EINVAL),
     ((64,), 8, 0.1, 1e-2, 1, X.make_problem(1.0, precision=7),
@@ -93,3 +100,7 @@ def test_footprint_bytes(lib):
     assert X.expdiag_footprint_bytes((63,), 8, 1) == 0
     assert X.expdiag_footprint_bytes((256, 256), 64, 1, gmres_restart=20) > \
         20 * state
+    # EBDF2 is linear: no nonlinear buffer; outside 8..128 it is unsupported
+    fb = X.expdiag_footprint_bytes((256, 256), 64, X.EXPDIAG_EBDF2)
+    assert 2 * state <= fb < 3 * state
+    assert X.expdiag_footprint_bytes((256, 256), 256, X.EXPDIAG_EBDF2) == 0

@@ -1,0 +1,223 @@
+"""GPU EBDF2 window (Sec. 4) vs the CPU oracle, element by element, through
+the C ABI.
+
+Tolerances as for the first-order path: the residual is a few FFT roundings
+(1e-13 relative); the preconditioner and the iterates carry the conditioning
+of the alpha-scaled time diagonalisation, roughly eps/alpha, so their bar is
+max(1e-12, 50 eps / alpha) relative; converged windows are held to 1e-12
+against sequential EBDF2 stepping.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+EPS = 2.220446049250313e-16
+
+# (dim, n, Nt, alpha, a, c): ragged kappa tiles, the smallest and largest Nt
+CASES = {
+    "heat1d_Nt16": (1, 64, 16, 1e-2, 1.0, 0.0),
+    "heat1d_Nt8_min": (1, 8, 8, 0.2, 0.5, 0.1),
+    "heat2d_Nt32": (2, 16, 32, 1e-3, 0.3, 0.2),
+    "heat2d_Nt128_max": (2, 8, 128, 1e-2, 0.05, 0.0),
+    "heat3d_Nt64": (3, 8, 64, 1e-3, 1.0, 0.0),
+}
+
+
+def _setup(case, T=1.0):
+    dim, n, Nt, alpha, a, c = CASES[case]
+    return O.Setup(dim, n, Nt, T / Nt, alpha, a, c, scheme=O.EBDF2)
+
+
+def _u0(st, seed=0):
+    rng = np.random.default_rng([seed, st.n, st.Nt, 3])
+    return rng.uniform(-0.9, 0.9, size=(st.n,) * st.dim)
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(
+        "cuda:0")
+
+
+def _zeros(st):
+    import torch
+    return torch.zeros((st.Nt,) + (st.n,) * st.dim, dtype=torch.float64,
+                       device="cuda:0")
+
+
+def _solver(st, restart=0):
+    from paper_2603_04350_amd import Solver
+    return Solver((st.n,) * st.dim, st.Nt, st.dt, st.alpha, st.scheme,
+                  st.a, st.c, 0.0, 0.0, 0.0, 0, restart)
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+def _bar(st):
+    return max(1e-12, 50 * EPS / st.alpha)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_ebdf2_residual_parity(case):
+    import torch
+    st = _setup(case)
+    u0 = _u0(st)
+    U = 0.5 * np.random.default_rng(1).standard_normal(
+        (st.Nt,) + (st.n,) * st.dim)
+    with _solver(st) as s:
+        R = torch.empty_like(_dev(U))
+        rn = s.residual(_dev(u0), _dev(U), R)
+        torch.cuda.synchronize()
+    Rr = O.residual_ebdf2(st, u0, U)
+    assert _rel(R.cpu().numpy(), Rr) < 1e-13
+    assert abs(rn - np.linalg.norm(Rr)) < 1e-12 * np.linalg.norm(Rr)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_ebdf2_precond_parity(case):
+    import torch
+    st = _setup(case)
+    Rv = np.random.default_rng(2).standard_normal((st.Nt,) + (st.n,) * st.dim)
+    with _solver(st) as s:
+        S = torch.empty_like(_dev(Rv))
+        s.precond_apply(_dev(Rv), S)
+        Rd = _dev(Rv)
+        s.precond_apply(Rd, Rd)          # in place
+        torch.cuda.synchronize()
+    Sr = O.precond_apply_ebdf2(st, Rv)
+    assert _rel(S.cpu().numpy(), Sr) < _bar(st)
+    assert np.array_equal(Rd.cpu().numpy(), S.cpu().numpy())
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_ebdf2_iterates_parity(case):
+    st = _setup(case)
+    u0 = _u0(st)
+    _, _, (_, its) = O.fixed_point(st, u0, max_iter=3, tol=0.0, record=True)
+    with _solver(st) as s:
+        for k in (1, 2, 3):
+            U = _zeros(st)
+            rc, it, rel = s.iterate(_dev(u0), U, max_iter=k, tol=0.0)
+            assert it == k
+            err = O.rel_err(U.cpu().numpy(), its[k - 1])
+            assert err < _bar(st), (k, err)
+
+
+def test_ebdf2_iterates_ignore_initial_slice_one():
+    """f_2 takes u_1 = A u_0, so a nonzero initial window gives the oracle's
+    iterates from that window (its slice 1 only affects slice 1's own row)."""
+    st = _setup("heat2d_Nt32")
+    u0 = _u0(st)
+    U0 = 0.3 * np.random.default_rng(5).standard_normal(
+        (st.Nt,) + (st.n,) * st.dim)
+    _, _, (_, its) = O.fixed_point(st, u0, U0=U0, max_iter=2, tol=0.0,
+                                   record=True)
+    with _solver(st) as s:
+        U = _dev(U0)
+        s.iterate(_dev(u0), U, max_iter=2, tol=0.0)
+    assert O.rel_err(U.cpu().numpy(), its[1]) < _bar(st)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_ebdf2_converged_equals_sequential(case):
+    st = _setup(case)
+    u0 = _u0(st)
+    ref = O.sequential_ebdf2(st, u0)
+    with _solver(st) as s:
+        U = _zeros(st)
+        rc, it, rel = s.iterate(_dev(u0), U, max_iter=200, tol=1e-14)
+    err = O.rel_err(U.cpu().numpy(), ref)
+    assert err < 1e-12, (it, rel, err)
+
+
+def test_ebdf2_full_size_heat2d_256_Nt64():
+    """The benchmark's EBDF2 shape: 256^2 grid, Nt = 64 (N = 63 unknown
+    slices), converged window against sequential stepping."""
+    st = O.Setup(2, 256, 64, 2.0 / 64, 1e-3, a=0.0025, scheme=O.EBDF2)
+    u0 = np.random.default_rng(0).uniform(-0.9, 0.9, size=(256, 256))
+    ref = O.sequential_ebdf2(st, u0)
+    with _solver(st) as s:
+        U = _zeros(st)
+        rc, it, rel = s.iterate(_dev(u0), U, max_iter=100, tol=1e-13)
+    assert rc == 0
+    assert O.rel_err(U.cpu().numpy(), ref) < 1e-12, (it, rel)
+
+
+@pytest.mark.parametrize("case", ["heat1d_Nt16", "heat2d_Nt32",
+                                  "heat3d_Nt64"])
+def test_ebdf2_gmres_solution(case):
+    st = _setup(case)
+    u0 = _u0(st)
+    ref = O.sequential_ebdf2(st, u0)
+    _, it_o, _ = O.gmres_solve_ebdf2(st, u0, restart=20, tol=1e-13)
+    with _solver(st, restart=20) as s:
+        U = _zeros(st)
+        rc, it, rel = s.gmres(_dev(u0), U, restart=20, max_iter=200,
+                              tol=1e-13)
+    assert rel <= 1e-13
+    assert O.rel_err(U.cpu().numpy(), ref) < 1e-12
+    assert abs(it - it_o) <= 1, (it, it_o)
+
+
+def test_ebdf2_gmres_single_mode_three_steps():
+    """u_0 = sin x: identity plus rank two on the one excited |k|, so GMRES
+    stops within three iterations (finite termination, Sec. 4.2)."""
+    st = O.Setup(1, 64, 16, 1.0 / 16, 0.1, a=1.0, scheme=O.EBDF2)
+    x = 2 * np.pi * np.arange(64) / 64
+    u0 = np.sin(x)
+    with _solver(st, restart=20) as s:
+        U = _zeros(st)
+        rc, it, rel = s.gmres(_dev(u0), U, restart=20, max_iter=20,
+                              tol=1e-12)
+    assert it <= 3
+    assert O.rel_err(U.cpu().numpy(), O.sequential_ebdf2(st, u0)) < 1e-12
+
+
+def test_ebdf2_variant_and_autotune():
+    from paper_2603_04350_amd import expdiag as X
+    st = _setup("heat2d_Nt32")
+    with _solver(st) as s:
+        assert X.expdiag_get_time_variant(s.h) == 1
+        with pytest.raises(RuntimeError):
+            X.expdiag_set_time_variant(s.h, 0)
+        v, tf, td = X.expdiag_autotune(s.h, None)
+        assert v == 1 and tf == -1 and td > 0
+
+
+def test_ebdf2_in_batch_with_etd_instances():
+    """A batch holding EBDF2 and ETD1 instances: each result is bitwise the
+    one its handle gives alone."""
+    import torch
+    from paper_2603_04350_amd import Batch, Solver
+    specs = [
+        ((32, 32), 32, 1.0 / 32, 1e-3, 3, 0.1, 0.0, 0.0, 0.0),
+        ((32, 32), 16, 1.0 / 16, 1e-2, 1, 0.01, 0.0, 1.0, -1.0),
+        ((64,), 64, 1.0 / 64, 1e-2, 3, 1.0, 0.1, 0.0, 0.0),
+        ((16, 16, 16), 8, 1.0 / 8, 1e-3, 3, 0.5, 0.0, 0.0, 0.0),
+    ]
+    rng = np.random.default_rng(9)
+    solvers, u0s = [], []
+    for shape, Nt, dt, alpha, scheme, a, c, n1, n3 in specs:
+        solvers.append(Solver(shape, Nt, dt, alpha, scheme, a, c, n1, 0.0,
+                              n3))
+        u0s.append(rng.uniform(-0.9, 0.9, size=shape))
+    solo = []
+    for s, sp, u0 in zip(solvers, specs, u0s):
+        U = torch.zeros((sp[1],) + sp[0], dtype=torch.float64,
+                        device="cuda:0")
+        s.iterate(_dev(u0), U, max_iter=200, tol=1e-12)
+        solo.append(U.cpu().numpy())
+    b = Batch(solvers)
+    Us = [torch.zeros((sp[1],) + sp[0], dtype=torch.float64,
+                      device="cuda:0") for sp in specs]
+    b.iterate([_dev(u) for u in u0s], Us, max_iter=200, tol=1e-12)
+    b.close()
+    for k in range(len(specs)):
+        assert np.array_equal(Us[k].cpu().numpy(), solo[k]), k
+    for s in solvers:
+        s.close()
