@@ -25,6 +25,10 @@ value = space-time DOF-iterations per second of the plain FP64 solve
     Nt in {16..128}, eps ~ U[0.02,0.1], alpha in {1e-2,1e-3}) solved in one
     batched plan in mixed precision, against the same instances solved one
     after another by the plain FP64 single-instance path;
+  * ebdf2: the same grid and window without the reaction term, solved by
+    the second-order exponential BDF window: Nt = 65 (64 unknown slices,
+    radix FFT time transform, pass B against HBM) and Nt = 64 (63, dense
+    time transform on FP64 MFMA, pass B against both peaks);
   * served: batch-shaped 2D requests mixed with 3D 128^3 x 32 heat /
     Allen-Cahn requests into the continuous-batching server: all at once
     (its capacity), then Poisson arrivals at 0.5 and 0.9 of that capacity;
@@ -41,12 +45,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_F64_PEAK_TFLOPS = 78.6
 TOL = 1e-11
 
 
 DEVICE_SOURCES = ("cx.hpp", "fft_core.hpp", "kernels_fft.hpp",
                   "kernels_passb.hpp", "kernels_krylov.hpp",
-                  "kernels_dense.hpp")
+                  "kernels_dense.hpp", "kernels_bdf2.hpp")
 
 
 def _src_hash():
@@ -110,10 +115,18 @@ def bench_single(inst, prec, steps, warmup):
         "us_per_iter": 1e6 * wall / iters,
         "U": U.cpu().numpy().copy(),
     }
+    # Kernel timing runs every solve for exactly its iteration count with
+    # tol = 0, so no launch is enqueued past convergence (such launches see
+    # the instance done and return at once; averaged in, they would flatter
+    # the per-launch time).
+    def step_fixed():
+        U.zero_()
+        return s.iterate(u0, U, max_iter=it, tol=0.0)
+
     # which kernel class dominates: one pass with events around every launch
     X.expdiag_profile_enable(s.h, 0x1F)
     for _ in range(2):
-        step()
+        step_fixed()
     ms, cnt, by, tm = X.expdiag_profile_read(s.h)
     dom = max(range(len(ms)), key=lambda i: ms[i])
     # timed region 2: the same solves with HIP events around every launch of
@@ -122,7 +135,7 @@ def bench_single(inst, prec, steps, warmup):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        step()
+        step_fixed()
     torch.cuda.synchronize()
     wall2 = time.perf_counter() - t0
     ms2, cnt2, by2, tm2 = X.expdiag_profile_read(s.h)
@@ -140,6 +153,53 @@ def bench_single(inst, prec, steps, warmup):
             d["GBps"] = d["bytes_per_launch"] / (d["avg_us"] * 1e-6) / 1e9
         out["kernels"][X.PROFILE_CLASSES[i]] = d
     s.close()
+    return out
+
+
+def bench_ebdf2(steps, warmup, Nt):
+    """Second-order exponential BDF window (Sec. 4) on the headline grid:
+    solves from zero to ||S||/||U|| <= TOL, then the pass B launches timed
+    with kernel-attached events.  Nt = 65 (64 unknown slices) takes the
+    radix FFT pass B, HBM-bound: algorithmic bytes 32 per window entry plus
+    the per-kappa tables.  Nt = 64 (63 unknown slices) takes the dense
+    pass B, one 2Nt x 2Nt real GEMM pair per 16 kappa columns on FP64
+    MFMA: executed flops 2 * 2 * (2Nt)^2 * 16 per block."""
+    import workloads as W
+    inst = W.diffusion2d_ebdf2(Nt=Nt, T=2.0)
+    fp = bench_single(inst, 0, steps, warmup)
+    kb = fp["kernels"]["passb"]
+    us = kb["avg_us"] if "avg_us" in kb else kb["avg_us_all_classes_timed"]
+    gbps = kb["bytes_per_launch"] / (us * 1e-6) / 1e9
+    dense = (Nt & (Nt - 1)) == 0
+    out = {
+        "workload": f"2D diffusion u_t = eps^2 Lap u, eps=0.05, periodic "
+                    f"256x256, Nt={Nt} ({Nt - 1} unknown slices), T=2, "
+                    f"EBDF2 Exp-ParaDiag fixed point, alpha=1e-3, "
+                    f"u0~U[-0.9,0.9] seed 0",
+        "time_transform": "dense MFMA" if dense else "radix FFT",
+        "ms_per_solve": fp["ms_per_solve"],
+        "iters_per_solve": fp["iters"],
+        "us_per_iter": fp["us_per_iter"],
+        "dof_iters_per_s": fp["dof_iters_per_s"],
+        "dominant": fp["dominant"],
+        "passb": {
+            "avg_us": us,
+            "bytes_per_launch": kb["bytes_per_launch"],
+            "roofline_hbm": {"bound": "hbm", "achieved": round(gbps, 1),
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(gbps / HBM_PEAK_GBS, 4)},
+        },
+        "U": fp["U"],
+    }
+    if dense:
+        Nk = inst.n * (inst.n // 2 + 1)
+        flops = 2 * 2 * (2 * Nt) ** 2 * 16 * ((Nk + 15) // 16)
+        tflops = flops / (us * 1e-6) / 1e12
+        out["passb"]["flops_per_launch"] = flops
+        out["passb"]["roofline_mfma"] = {
+            "bound": "mfma", "achieved": round(tflops, 2),
+            "peak": MFMA_F64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tflops / MFMA_F64_PEAK_TFLOPS, 4)}
     return out
 
 
@@ -293,6 +353,62 @@ def cpu_baseline(inst, U_fp64, U_mixed, sample_iters):
     }
 
 
+def cpu_baseline_ebdf2(U_gpu, sample_iters):
+    """The oracle's EBDF2 fixed point on the Nt = 65 window (a bounded sample
+    of iterations), and the GPU solution's error against sequential EBDF2."""
+    import oracle as O
+    import workloads as W
+    inst = W.diffusion2d_ebdf2(Nt=65, T=2.0)
+    st = O.Setup.from_instance(inst)
+    t0 = time.perf_counter()
+    O.fixed_point(st, inst.u0, max_iter=sample_iters, tol=0.0)
+    t1 = time.perf_counter()
+    ref = O.sequential(st, inst.u0)
+    return {
+        "value": inst.dof * sample_iters / (t1 - t0),
+        "unit": "DOF-iters/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{sample_iters} EBDF2 fixed-point iterations of the "
+                  f"256^2 x 65 diffusion window (numpy fp64), {t1 - t0:.1f} s",
+        "err_vs_oracle": float(O.rel_err(U_gpu, ref)),
+    }
+
+
+def profile_run(steps):
+    """Fixed-count solves only (tol = 0, so every launch does full work),
+    for a profiler wrapped around this process: the Allen-Cahn instance in
+    fp64 (22 iterations, its count to tolerance) and the EBDF2 windows with
+    Nt = 65 and 64 (5 iterations).  Prints the event-timed average launch
+    time of each kernel class for comparison with the profiler's."""
+    import torch
+    import workloads as W
+    from paper_2603_04350_amd import expdiag as X
+    out = {}
+    for name, inst, iters in (
+            ("allen_cahn2d_fp64", W.allen_cahn2d(), 22),
+            ("ebdf2_Nt65", W.diffusion2d_ebdf2(Nt=65, T=2.0), 5),
+            ("ebdf2_Nt64", W.diffusion2d_ebdf2(Nt=64, T=2.0), 5)):
+        u0 = torch.from_numpy(inst.u0).to("cuda:0")
+        U = torch.zeros((inst.Nt,) + inst.shape, dtype=torch.float64,
+                        device="cuda:0")
+        s = X.Solver.from_instance(inst, precision=0)
+        for _ in range(2):
+            U.zero_()
+            s.iterate(u0, U, max_iter=iters, tol=0.0)
+        X.expdiag_profile_enable(s.h, 0x1F)
+        for _ in range(steps):
+            U.zero_()
+            s.iterate(u0, U, max_iter=iters, tol=0.0)
+        ms, cnt, by, tm = X.expdiag_profile_read(s.h)
+        X.expdiag_profile_enable(s.h, 0)
+        out[name] = {X.PROFILE_CLASSES[i]: round(1e3 * ms[i] / tm[i], 3)
+                     for i in range(len(ms)) if tm[i]}
+        s.close()
+        _log(f"profile {name} done")
+    print(json.dumps({"event_avg_us": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -304,16 +420,23 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-ebdf2", action="store_true")
     ap.add_argument("--quick", action="store_true",
-                    help="fp64 single-instance solves only (profiler runs)")
+                    help="fp64 single-instance solves only")
+    ap.add_argument("--profile", action="store_true",
+                    help="fixed-count solves only, for profiler runs")
     args = ap.parse_args()
     if args.quick:
         args.no_batch = args.no_serve = args.no_cpu_baseline = True
+        args.no_ebdf2 = True
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
+    if args.profile:
+        profile_run(args.steps)
+        return
     import workloads as W
     inst = W.allen_cahn2d()
     _log("single-instance fp64")
@@ -374,6 +497,14 @@ def main():
         "roofline": roof,
         "src_hash": src_hash,
     }
+    if not args.no_ebdf2:
+        _log("ebdf2 single instance (radix FFT, Nt = 65; dense, Nt = 64)")
+        eb = bench_ebdf2(args.steps, args.warmup, 65)
+        U_eb = eb.pop("U")
+        ebd = bench_ebdf2(args.steps, args.warmup, 64)
+        ebd.pop("U")
+        eb["dense_variant_Nt64"] = ebd
+        line["ebdf2"] = eb
     if not args.no_batch:
         _log(f"batched: {args.batch} instances")
         line["batched"] = bench_batched(args.batch)
@@ -384,6 +515,9 @@ def main():
         _log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(inst, fp["U"], mx["U"],
                                             args.cpu_iters)
+        if not args.no_ebdf2:
+            line["ebdf2"]["cpu_baseline"] = cpu_baseline_ebdf2(
+                U_eb, args.cpu_iters)
     if rank == 0:
         print(json.dumps(line), flush=True)
 

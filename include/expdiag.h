@@ -95,8 +95,10 @@ typedef struct {
  * e^{2 pi i m/Nt} (eigenvalues of C_0^alpha, Sec. 2), twiddles, and all
  * device workspace (size given by expdiag_footprint_bytes).
  *   g        grid (host pointer)
- *   Nt       number of time steps in the window, power of two, 2..512
- *            (EBDF2: 8..128, its time transform being the dense one)
+ *   Nt       number of time steps in the window, power of two, 2..512.
+ *            EBDF2 transforms the Nt - 1 unknown slices: Nt - 1 a power of
+ *            two, 2..512, takes the radix FFT; otherwise Nt must be a power
+ *            of two in 8..128 and takes the dense transform
  *   dt       time step (> 0); the window is T = Nt dt
  *   alpha    circulant parameter, 0 < alpha < 1
  *   scheme   EXPDIAG_ETD1, EXPDIAG_ETD2, or EXPDIAG_EBDF2 (linear problems
@@ -198,8 +200,8 @@ int expdiag_set_graph(expdiag_t h, int on);
  * registers and LDS (any Nt), 1 = dense complex Nt x Nt GEMM on FP64 MFMA
  * (8 <= Nt <= 128).  Both compute the same operator; results agree to
  * rounding.  set() rebuilds the handle's plan (EUNSUPPORTED if the variant
- * does not cover Nt, and for EBDF2, whose Nt - 1 points only the dense
- * variant covers); get() returns the current one. */
+ * does not cover Nt; an EBDF2 handle has the one variant its Nt - 1 points
+ * allow); get() returns the current one. */
 int expdiag_set_time_variant(expdiag_t h, int variant);
 int expdiag_get_time_variant(expdiag_t h);
 
@@ -209,7 +211,7 @@ int expdiag_get_time_variant(expdiag_t h);
  * gfx950/d<d>/<n0>x<n1>x<n2>/Nt<Nt>/<fp64|mixed>; a cached entry is used
  * without measuring.  variant, us_fft, us_dense (host, nullable) receive
  * the choice and the per-launch times (us_dense = -1 when not applicable).
- * EBDF2 handles have only the dense variant: it is timed and kept (us_fft =
+ * EBDF2 handles have one variant: it is timed and kept (the other time is
  * -1), and the cache is neither read nor written. */
 int expdiag_autotune(expdiag_t h, const char* cache_path, int* variant,
                      double* us_fft, double* us_dense);

@@ -287,12 +287,23 @@ int passb_blocks_nt(int Nt, long Nk) {
   return static_cast<int>(b);
 }
 constexpr int DENSE_NT_MIN = 8, DENSE_NT_MAX = 128;
-bool dense_ok(int Nt) { return Nt >= DENSE_NT_MIN && Nt <= DENSE_NT_MAX; }
+bool dense_ok(int Nt) {
+  return is_pow2(Nt) && Nt >= DENSE_NT_MIN && Nt <= DENSE_NT_MAX;
+}
 int dense_blocks(long Nk) {
   return static_cast<int>((Nk + DENSE_C - 1) / DENSE_C);
 }
+// Time points of the transform in pass B: Nt, or Nt - 1 for EBDF2, whose
+// window row 0 is the fixed start u_1 = A u_0.
+int time_len(const expdiag_ctx* h) {
+  return h->scheme == EXPDIAG_EBDF2 ? h->Nt - 1 : h->Nt;
+}
+// EBDF2 windows take the radix FFT when Nt - 1 is a power of two (2..512)
+// and the dense transform when Nt is one (8..128).
+bool bdf2_fft_ok(int Nt) { return Nt >= 3 && Nt <= 513 && is_pow2(Nt - 1); }
 int passb_blocks(expdiag_ctx* h) {
-  return h->tvariant == 1 ? dense_blocks(h->Nk) : passb_blocks_nt(h->Nt, h->Nk);
+  return h->tvariant == 1 ? dense_blocks(h->Nk)
+                          : passb_blocks_nt(time_len(h), h->Nk);
 }
 
 double row_bytes(int M, int mode, long nrows, size_t si, size_t so) {
@@ -362,10 +373,11 @@ PassBArgs passb_args(expdiag_ctx* h) {
   a.nblocks = passb_blocks(h);
   a.inv_ns = 1.0 / static_cast<double>(h->Ns);
   // the same long-double values as the gamma table
-  const int R = std::min(h->Nt, 4), tpl = h->Nt / R;
+  const int N = time_len(h);
+  const int R = std::min(N, 4), tpl = N / R;
   const long double la = logl(static_cast<long double>(h->alpha));
   for (int s = 0; s < 4; ++s) {
-    const long double g = s < R ? expl(la * (s * tpl) / h->Nt) : 1.0L;
+    const long double g = s < R ? expl(la * (s * tpl) / N) : 1.0L;
     a.gstep[s] = static_cast<double>(g);
     a.igstep[s] = static_cast<double>(1.0L / g);
   }
@@ -418,12 +430,22 @@ template <int MODE, typename TN>
 int launch_passb1(expdiag_ctx* h, const PassBArgs& a) {
   ProfScope ps(h, P_PASSB, passb_bytes(a, h->Nt, MODE, sizeof(cx<TN>)));
   if (h->scheme == EXPDIAG_EBDF2) {
-    const bool ok = dispatch_pow2<DENSE_NT_MIN, DENSE_NT_MAX>(h->Nt, [&](auto Nc) {
-      constexpr int NN = decltype(Nc)::value;
-      hipLaunchKernelGGL((passb_bdf2_kernel1<NN, MODE>),
-                         dim3(dense_blocks(h->Nk)), dim3(DENSE_THREADS), 0,
-                         h->stream, a);
-    });
+    bool ok = false;
+    if (h->tvariant == 1) {
+      ok = dispatch_pow2<DENSE_NT_MIN, DENSE_NT_MAX>(h->Nt, [&](auto Nc) {
+        constexpr int NN = decltype(Nc)::value;
+        hipLaunchKernelGGL((passb_bdf2_kernel1<NN, MODE>),
+                           dim3(dense_blocks(h->Nk)), dim3(DENSE_THREADS), 0,
+                           h->stream, a);
+      });
+    } else {
+      ok = dispatch_pow2<2, 512>(h->Nt - 1, [&](auto Nc) {
+        constexpr int NN = decltype(Nc)::value;
+        hipLaunchKernelGGL((passb_bdf2_fft_kernel1<NN, MODE>),
+                           dim3(passb_blocks_nt(NN, h->Nk)),
+                           dim3(PassBShape<NN>::THREADS), 0, h->stream, a);
+      });
+    }
     if (!ok) return fail(h, EXPDIAG_EUNSUPPORTED, "EBDF2 Nt %d", h->Nt);
     HIPCHK(h, hipGetLastError());
     return 0;
@@ -713,9 +735,12 @@ void plan_iteration(Plan& P, expdiag_ctx* h, Ctl* ctl, Ctl* mirror,
   a.hist = hist;
   if (h->nonlinear && h->mixed) a.Nh32 = nh_view<float>(h);
   const bool hosted = h->nonlinear && plan_pass_a_mp(P, h, ctl, a);
-  // pass B variant: 0 radix FFT, 1 dense, 2 EBDF2 (dense, N = Nt - 1)
-  const int variant = h->scheme == EXPDIAG_EBDF2 ? 2 : h->tvariant;
-  plan_passb(P, 5, h->Nt, a, sizeof(cx<double>), variant, !hosted);
+  // pass B variant: 0 radix FFT, 1 dense, 2 EBDF2 dense, 3 EBDF2 radix FFT
+  // (the group length is the transform length for the radix kernels)
+  int variant = h->tvariant;
+  if (h->scheme == EXPDIAG_EBDF2) variant = h->tvariant == 1 ? 2 : 3;
+  const int len = variant == 3 ? time_len(h) : h->Nt;
+  plan_passb(P, 5, len, a, sizeof(cx<double>), variant, !hosted);
 }
 
 // Algorithmic bytes of one iteration of a plan.
@@ -879,6 +904,12 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st,
             constexpr int NN = decltype(Nc)::value;
             klaunch(ps, passb_bdf2_kernel<NN>, dim3(grid),
                     dim3(DENSE_THREADS), st, J, g.dstart, nj);
+          });
+        } else if (g.tcode == 3) {
+          ok = dispatch_pow2<2, 512>(g.len, [&](auto Nc) {
+            constexpr int NN = decltype(Nc)::value;
+            klaunch(ps, passb_bdf2_fft_kernel<NN>, dim3(grid),
+                    dim3(PassBShape<NN>::THREADS), st, J, g.dstart, nj);
           });
         } else {
           ok = dispatch_pow2<2, 512>(g.len, [&](auto Nc) {
@@ -1176,7 +1207,8 @@ size_t footprint(const Sizes& s, int dim, int Nt, bool nonlinear,
   }
   b += s.Nk * (sizeof(cx<double>) + 3 * sizeof(double));
   b += TW_N * (sizeof(cx<double>) + sizeof(cx<float>));
-  b += static_cast<size_t>(std::max(passb_blocks_nt(Nt, s.Nk),
+  b += static_cast<size_t>(std::max(std::max(passb_blocks_nt(Nt, s.Nk),
+                                             passb_blocks_nt(Nt - 1, s.Nk)),
                                     dense_blocks(s.Nk))) * 4 * sizeof(double);
   if (dense_ok(Nt)) b += 8 * static_cast<size_t>(Nt) * Nt * sizeof(double);
   return b;
@@ -1296,11 +1328,14 @@ size_t expdiag_footprint_bytes(const expdiag_grid* g, int Nt, int scheme,
                                int precision, int gmres_restart) {
   Sizes s{};
   if (check_grid(g, &s) != 0) return 0;
-  if (!is_pow2(Nt) || Nt < 2 || Nt > 512) return 0;
   if (scheme != EXPDIAG_ETD1 && scheme != EXPDIAG_ETD2 &&
       scheme != EXPDIAG_EBDF2)
     return 0;
-  if (scheme == EXPDIAG_EBDF2 && !dense_ok(Nt)) return 0;
+  if (scheme == EXPDIAG_EBDF2) {
+    if (!bdf2_fft_ok(Nt) && !dense_ok(Nt)) return 0;
+  } else if (!is_pow2(Nt) || Nt < 2 || Nt > 512) {
+    return 0;
+  }
   if (precision != EXPDIAG_FP64 && precision != EXPDIAG_MIXED) return 0;
   if (gmres_restart < 0 || gmres_restart > 64) return 0;
   // the nonlinearity is not known here: report the nonlinear footprint
@@ -1316,7 +1351,7 @@ namespace {
 int validate_params(int Nt, double dt, double alpha, int scheme,
                     const expdiag_problem* p) {
   if (Nt < 2) return fail(nullptr, EXPDIAG_EINVAL, "Nt must be >= 2");
-  if (!is_pow2(Nt) || Nt > 512)
+  if (scheme != EXPDIAG_EBDF2 && (!is_pow2(Nt) || Nt > 512))
     return fail(nullptr, EXPDIAG_EUNSUPPORTED,
                 "Nt must be a power of two <= 512");
   if (!(dt > 0.0) || !std::isfinite(dt))
@@ -1330,9 +1365,10 @@ int validate_params(int Nt, double dt, double alpha, int scheme,
       (p->n1 != 0.0 || p->n2 != 0.0 || p->n3 != 0.0))
     return fail(nullptr, EXPDIAG_EUNSUPPORTED,
                 "EBDF2 is for linear problems (n1 = n2 = n3 = 0)");
-  if (scheme == EXPDIAG_EBDF2 && !dense_ok(Nt))
+  if (scheme == EXPDIAG_EBDF2 && !bdf2_fft_ok(Nt) && !dense_ok(Nt))
     return fail(nullptr, EXPDIAG_EUNSUPPORTED,
-                "EBDF2 needs %d <= Nt <= %d", DENSE_NT_MIN, DENSE_NT_MAX);
+                "EBDF2 needs Nt - 1 a power of two <= 512, or Nt a power "
+                "of two in %d..%d", DENSE_NT_MIN, DENSE_NT_MAX);
   if (!(p->a >= 0.0) || !(p->c >= 0.0) || !std::isfinite(p->a) ||
       !std::isfinite(p->c) || !std::isfinite(p->n1) ||
       !std::isfinite(p->n2) || !std::isfinite(p->n3))
@@ -1353,7 +1389,7 @@ int reinit_params(expdiag_ctx* h, double dt, double alpha, int scheme,
   h->dt = dt;
   h->alpha = alpha;
   if (scheme == EXPDIAG_EBDF2)
-    h->tvariant = 1;  // N = Nt - 1 time points: dense transform only
+    h->tvariant = bdf2_fft_ok(h->Nt) ? 0 : 1;  // by N = Nt - 1
   else if (h->scheme == EXPDIAG_EBDF2)
     h->tvariant = 0;
   h->scheme = scheme;
@@ -1393,7 +1429,7 @@ int create_impl(const expdiag_grid* g, int Nt, double dt, double alpha,
   h->nonlinear = (p->n1 != 0.0 || p->n2 != 0.0 || p->n3 != 0.0);
   h->mixed = p->precision == EXPDIAG_MIXED;
   h->restart_cap = p->gmres_restart;
-  if (scheme == EXPDIAG_EBDF2) h->tvariant = 1;
+  if (scheme == EXPDIAG_EBDF2) h->tvariant = bdf2_fft_ok(Nt) ? 0 : 1;
 
   const size_t st = static_cast<size_t>(Nt) * h->Nk * sizeof(cx<double>);
   int rc = 0;
@@ -1418,7 +1454,7 @@ int create_impl(const expdiag_grid* g, int Nt, double dt, double alpha,
     A(&h->Wf, 4 * static_cast<size_t>(Nt) * Nt * sizeof(double));
     A(&h->Wi, 4 * static_cast<size_t>(Nt) * Nt * sizeof(double));
   }
-  h->max_partials = std::max(passb_blocks_nt(Nt, h->Nk), 1);
+  h->max_partials = std::max(passb_blocks_nt(time_len(h), h->Nk), 1);
   if (dense_ok(Nt)) h->max_partials = std::max(h->max_partials, dense_blocks(h->Nk));
   A(&h->partials, static_cast<size_t>(h->max_partials) * 4 * sizeof(double));
   A(&h->red_out, 8 * sizeof(double));
@@ -1557,16 +1593,20 @@ int run_iterations(expdiag_ctx* h, int chunk) {
 // Iterations to request next: what the observed contraction predicts to
 // reach the active target (flags make overshoot harmless), at least 1.
 int next_chunk(const Ctl& c, double rel_prev, int it_prev) {
+  constexpr int MAX_CHUNK = 64;
   const double goal = c.phase == 0 ? c.bulk_tol : c.tol;
+  if (!(goal > 0.0)) return MAX_CHUNK;  // tol = 0: run to max_iter
   int next = 8;
   if (rel_prev > 0.0 && c.last_rel > 0.0 && c.iters > it_prev &&
       c.last_rel < rel_prev) {
     const double rho =
         std::pow(c.last_rel / rel_prev, 1.0 / (c.iters - it_prev));
     const double need = std::log(goal / c.last_rel) / std::log(rho);
-    next = static_cast<int>(std::ceil(need > 0 ? need : 1.0));
+    // (need can be huge or not finite: compare before converting)
+    next = need < MAX_CHUNK ? static_cast<int>(std::ceil(need > 0 ? need : 1.0))
+                            : MAX_CHUNK;
   }
-  return std::max(1, std::min(next, 64));
+  return std::max(1, std::min(next, MAX_CHUNK));
 }
 
 }  // namespace
@@ -1635,7 +1675,8 @@ int expdiag_iterate(expdiag_t h, const double* u0, double* U, int max_iter,
     const Ctl c = read_mirror(h->h_mirror);
     if (c.done != 0 || c.iters >= max_iter) break;
     if (enqueued >= max_iter + 64) break;  // safety: device state stalled
-    chunk = next_chunk(c, rel_prev, it_prev);
+    // never more than the iterations still allowed (c.iters < max_iter)
+    chunk = std::min(next_chunk(c, rel_prev, it_prev), max_iter - c.iters);
     rel_prev = c.last_rel;
     it_prev = c.iters;
   }

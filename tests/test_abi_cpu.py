@@ -63,6 +63,12 @@ def _create(lib, shape, Nt, dt, alpha, scheme, prob):
      X.EXPDIAG_EUNSUPPORTED),
     ((64,), 256, 0.1, 1e-2, X.EXPDIAG_EBDF2, X.make_problem(1.0),
      X.EXPDIAG_EUNSUPPORTED),
+    ((64,), 66, 0.1, 1e-2, X.EXPDIAG_EBDF2, X.make_problem(1.0),
+     X.EXPDIAG_EUNSUPPORTED),
+    ((64,), 1025, 0.1, 1e-2, X.EXPDIAG_EBDF2, X.make_problem(1.0),
+     X.EXPDIAG_EUNSUPPORTED),
+    ((64,), 65, 0.1, 1e-2, X.EXPDIAG_ETD1, X.make_problem(1.0),
+     X.EXPDIAG_EUNSUPPORTED),
     ((64,), 8, 0.1, 1e-2, 1, X.make_problem(-1.0), X.EXPDIAG_EINVAL),
     ((64,), 8, 0.1, 1e-2, 1, X.make_problem(1.0, c=-0.1), X.EXPDIAG_EINVAL),
     ((64,), 8, 0.1, 1e-2, 1, X.make_problem(1.0, precision=7),
@@ -104,3 +110,6 @@ def test_footprint_bytes(lib):
     fb = X.expdiag_footprint_bytes((256, 256), 64, X.EXPDIAG_EBDF2)
     assert 2 * state <= fb < 3 * state
     assert X.expdiag_footprint_bytes((256, 256), 256, X.EXPDIAG_EBDF2) == 0
+    assert X.expdiag_footprint_bytes((256, 256), 65, X.EXPDIAG_EBDF2) > \
+        2 * state
+    assert X.expdiag_footprint_bytes((256, 256), 65, X.EXPDIAG_ETD1) == 0

@@ -17,12 +17,18 @@ pytestmark = pytest.mark.gpu
 EPS = 2.220446049250313e-16
 
 # (dim, n, Nt, alpha, a, c): ragged kappa tiles, the smallest and largest Nt
+# of both time transforms (dense: Nt a power of two; radix FFT: Nt - 1 one)
 CASES = {
     "heat1d_Nt16": (1, 64, 16, 1e-2, 1.0, 0.0),
     "heat1d_Nt8_min": (1, 8, 8, 0.2, 0.5, 0.1),
     "heat2d_Nt32": (2, 16, 32, 1e-3, 0.3, 0.2),
     "heat2d_Nt128_max": (2, 8, 128, 1e-2, 0.05, 0.0),
     "heat3d_Nt64": (3, 8, 64, 1e-3, 1.0, 0.0),
+    "fft_heat1d_Nt17": (1, 64, 17, 1e-2, 1.0, 0.0),
+    "fft_heat1d_Nt3_min": (1, 16, 3, 0.2, 0.5, 0.1),
+    "fft_heat2d_Nt65": (2, 16, 65, 1e-3, 0.3, 0.2),
+    "fft_heat2d_Nt513_max": (2, 8, 513, 1e-2, 0.01, 0.0),
+    "fft_heat3d_Nt9": (3, 8, 9, 1e-3, 1.0, 0.0),
 }
 
 
@@ -135,10 +141,12 @@ def test_ebdf2_converged_equals_sequential(case):
     assert err < 1e-12, (it, rel, err)
 
 
-def test_ebdf2_full_size_heat2d_256_Nt64():
-    """The benchmark's EBDF2 shape: 256^2 grid, Nt = 64 (N = 63 unknown
-    slices), converged window against sequential stepping."""
-    st = O.Setup(2, 256, 64, 2.0 / 64, 1e-3, a=0.0025, scheme=O.EBDF2)
+@pytest.mark.parametrize("Nt", [64, 65])
+def test_ebdf2_full_size_heat2d_256(Nt):
+    """The benchmark's EBDF2 shapes: 256^2 grid, Nt = 64 (63 unknown slices,
+    dense transform) and Nt = 65 (64, radix FFT), converged window against
+    sequential stepping."""
+    st = O.Setup(2, 256, Nt, 2.0 / Nt, 1e-3, a=0.0025, scheme=O.EBDF2)
     u0 = np.random.default_rng(0).uniform(-0.9, 0.9, size=(256, 256))
     ref = O.sequential_ebdf2(st, u0)
     with _solver(st) as s:
@@ -149,7 +157,8 @@ def test_ebdf2_full_size_heat2d_256_Nt64():
 
 
 @pytest.mark.parametrize("case", ["heat1d_Nt16", "heat2d_Nt32",
-                                  "heat3d_Nt64"])
+                                  "heat3d_Nt64", "fft_heat1d_Nt17",
+                                  "fft_heat2d_Nt65"])
 def test_ebdf2_gmres_solution(case):
     st = _setup(case)
     u0 = _u0(st)
@@ -178,15 +187,19 @@ def test_ebdf2_gmres_single_mode_three_steps():
     assert O.rel_err(U.cpu().numpy(), O.sequential_ebdf2(st, u0)) < 1e-12
 
 
-def test_ebdf2_variant_and_autotune():
+@pytest.mark.parametrize("case,variant", [("heat2d_Nt32", 1),
+                                          ("fft_heat2d_Nt65", 0)])
+def test_ebdf2_variant_and_autotune(case, variant):
     from paper_2603_04350_amd import expdiag as X
-    st = _setup("heat2d_Nt32")
+    st = _setup(case)
     with _solver(st) as s:
-        assert X.expdiag_get_time_variant(s.h) == 1
+        assert X.expdiag_get_time_variant(s.h) == variant
         with pytest.raises(RuntimeError):
-            X.expdiag_set_time_variant(s.h, 0)
+            X.expdiag_set_time_variant(s.h, 1 - variant)
         v, tf, td = X.expdiag_autotune(s.h, None)
-        assert v == 1 and tf == -1 and td > 0
+        assert v == variant
+        assert (tf > 0 and td == -1) if variant == 0 else \
+            (tf == -1 and td > 0)
 
 
 def test_ebdf2_in_batch_with_etd_instances():
@@ -199,6 +212,8 @@ def test_ebdf2_in_batch_with_etd_instances():
         ((32, 32), 16, 1.0 / 16, 1e-2, 1, 0.01, 0.0, 1.0, -1.0),
         ((64,), 64, 1.0 / 64, 1e-2, 3, 1.0, 0.1, 0.0, 0.0),
         ((16, 16, 16), 8, 1.0 / 8, 1e-3, 3, 0.5, 0.0, 0.0, 0.0),
+        ((32, 32), 33, 1.0 / 33, 1e-3, 3, 0.1, 0.0, 0.0, 0.0),
+        ((128,), 17, 1.0 / 17, 1e-2, 3, 1.0, 0.0, 0.0, 0.0),
     ]
     rng = np.random.default_rng(9)
     solvers, u0s = [], []

@@ -12,6 +12,8 @@ Workloads (all on periodic [0, 2*pi)^d):
                a_k, b_k ~ N(0, 0.1) (standard deviation 0.1).
   allen_cahn2d 2D Allen-Cahn u_t = eps^2 Lap u + u - u^3, eps=0.05, n=256,
                Nt=64, T=2, alpha=1e-3; u0 ~ U[-0.9, 0.9] i.i.d. per point.
+  diffusion2d_ebdf2  allen_cahn2d's grid, window and u0 without the
+               reaction (u_t = eps^2 Lap u), second-order exponential BDF.
   rd2d         2D reaction-diffusion u_t = 0.1 Lap u + u - u^3, n=512,
                Nt=128, T=1, ETD2; u0 = sum of 32 periodic Gaussians with
                amplitude U[-1,1], width U[0.1,0.5], centre U[0,2pi)^2.
@@ -31,6 +33,7 @@ import numpy as np
 
 __all__ = [
     "Instance", "grid_coords", "heat1d", "allen_cahn2d", "rd2d", "batch",
+    "diffusion2d_ebdf2",
     "served_stream", "uniform_field", "gaussians_field", "low_mode_field",
     "scaled",
 ]
@@ -129,6 +132,16 @@ def allen_cahn2d(seed: int = 0, n: int = 256, Nt: int = 64, T: float = 2.0,
     return Instance("allen_cahn2d", 2, n, Nt, T, alpha, a=eps * eps,
                     n1=1.0, n3=-1.0, scheme=scheme, precision=precision,
                     u0=uniform_field(rng, 2, n))
+
+
+def diffusion2d_ebdf2(seed: int = 0, n: int = 256, Nt: int = 64,
+                      T: float = 2.0, alpha: float = 1e-3,
+                      eps: float = 0.05) -> Instance:
+    """The Allen-Cahn grid and window without the reaction term, for the
+    second-order exponential BDF (scheme 3, linear problems)."""
+    rng = np.random.default_rng(seed)
+    return Instance("diffusion2d_ebdf2", 2, n, Nt, T, alpha, a=eps * eps,
+                    scheme=3, u0=uniform_field(rng, 2, n))
 
 
 def rd2d(seed: int = 0, n: int = 512, Nt: int = 128, T: float = 1.0,
