@@ -15,8 +15,11 @@ section / equation of that paper.
 
 Readings taken where the paper is silent (also listed in the design doc):
   * Spatial operator: Fourier collocation on periodic [0,2pi)^d, n even,
-    L = a*Lap - c with symbol mu_k = -a|k|^2 - c (the analysis of Sec. 2-3
-    only needs L_h diagonalisable with non-positive spectrum).
+    L = a*Lap - b.grad - c with symbol mu_k = -a|k|^2 - c - i b.k' (the
+    analysis of Sec. 2-3 only needs L_h diagonalisable with spectrum in the
+    closed left half plane; the advection term is the one of the remark
+    after Theorem thm_gmres22).  k' is the derivative wavenumber: k, except
+    0 at the Nyquist index, so that L maps real fields to real fields.
   * ETD1 = explicit exponential Euler,
         u_n = A u_{n-1} + dt*phi1(dt L) N(u_{n-1}),
     the ETD variant Sec. 5 allows; the all-at-once iteration lags the
@@ -64,9 +67,15 @@ EBDF2 = 3  # scheme code of the second-order exponential BDF (Sec. 4)
 # ---------------------------------------------------------------------------
 # phi functions (exponential-integrator weights)
 # ---------------------------------------------------------------------------
+def _as_float(z):
+    z = np.asarray(z)
+    return z if np.iscomplexobj(z) else z.astype(np.float64)
+
+
 def phi1(z):
-    """phi1(z) = (e^z - 1)/z, phi1(0) = 1 (exponential Euler weight)."""
-    z = np.asarray(z, dtype=np.float64)
+    """phi1(z) = (e^z - 1)/z, phi1(0) = 1 (exponential Euler weight); real
+    or complex z."""
+    z = _as_float(z)
     out = np.ones_like(z)
     nz = z != 0.0
     out[nz] = np.expm1(z[nz]) / z[nz]
@@ -77,9 +86,9 @@ def phi2(z):
     """phi2(z) = (e^z - 1 - z)/z^2, phi2(0) = 1/2.
 
     For |z| < 1 the direct formula cancels, so the Taylor series
-    sum_{j>=0} z^j/(j+2)! with 30 terms is used there.
+    sum_{j>=0} z^j/(j+2)! with 30 terms is used there.  Real or complex z.
     """
-    z = np.asarray(z, dtype=np.float64)
+    z = _as_float(z)
     out = np.empty_like(z)
     small = np.abs(z) < 1.0
     zs = z[small]
@@ -114,6 +123,7 @@ class Setup:
     n2: float = 0.0
     n3: float = 0.0
     scheme: int = 1
+    b: tuple = (0.0, 0.0, 0.0)
     mu: np.ndarray = field(init=False, repr=False)
     E: np.ndarray = field(init=False, repr=False)
     w1: np.ndarray = field(init=False, repr=False)
@@ -126,6 +136,12 @@ class Setup:
         grids = np.meshgrid(*([k] * self.dim), indexing="ij")
         k2 = sum(g * g for g in grids)
         self.mu = -self.a * k2 - self.c
+        if any(bj != 0.0 for bj in self.b[:self.dim]):
+            kd = k.copy()
+            kd[self.n // 2] = 0.0        # first derivative of the Nyquist mode
+            dgrids = np.meshgrid(*([kd] * self.dim), indexing="ij")
+            self.mu = self.mu - 1j * sum(
+                self.b[j] * dgrids[j] for j in range(self.dim))
         z = self.dt * self.mu
         self.E = np.exp(z)
         self.w1 = self.dt * phi1(z)
@@ -138,7 +154,8 @@ class Setup:
     @classmethod
     def from_instance(cls, inst):
         return cls(inst.dim, inst.n, inst.Nt, inst.dt, inst.alpha, inst.a,
-                   inst.c, inst.n1, inst.n2, inst.n3, inst.scheme)
+                   inst.c, inst.n1, inst.n2, inst.n3, inst.scheme,
+                   tuple(getattr(inst, "b", (0.0, 0.0, 0.0))))
 
     @property
     def axes(self):

@@ -156,3 +156,30 @@ def test_ebdf2_C1_alpha_misplaced(monkeypatch):
         return D
     _patch_both(monkeypatch, "dense_operators_ebdf2", bad)
     assert _fails(P2.test_ebdf2_iteration_matrix_spectrum, 6, 0.05, 0.0)
+
+
+# ---------------------------------------------------------------------------
+# complex symbols (advection)
+# ---------------------------------------------------------------------------
+import tests.test_oracle_complex as PC  # noqa: E402
+
+
+def test_advection_sign_flipped(monkeypatch):
+    def flip(s):
+        if any(s.b):
+            s.mu = s.mu.real - 1j * s.mu.imag
+            s.E = np.exp(s.dt * s.mu)
+    _patch_setup(monkeypatch, flip)
+    assert _fails(PC.test_advection_diffusion_exact_solution_1d)
+
+
+def test_advection_nyquist_derivative_kept(monkeypatch):
+    def keep(s):
+        if any(s.b):
+            k = np.fft.fftfreq(s.n, 1.0 / s.n)
+            grids = np.meshgrid(*([k] * s.dim), indexing="ij")
+            s.mu = -s.a * sum(g * g for g in grids) - s.c - 1j * sum(
+                s.b[j] * grids[j] for j in range(s.dim))
+            s.E = np.exp(s.dt * s.mu)
+    _patch_setup(monkeypatch, keep)
+    assert _fails(PC.test_complex_symbol_is_hermitian)
