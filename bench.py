@@ -29,6 +29,8 @@ value = space-time DOF-iterations per second of the plain FP64 solve
     the second-order exponential BDF window: Nt = 65 (64 unknown slices,
     radix FFT time transform, pass B against HBM) and Nt = 64 (63, dense
     time transform on FP64 MFMA, pass B against both peaks);
+  * advection: the headline instance with an advection term -b.grad u,
+    b = (2, 1), whose symbol is complex (complex E and phi tables);
   * served: batch-shaped 2D requests mixed with 3D 128^3 x 32 heat /
     Allen-Cahn requests into the continuous-batching server: all at once
     (its capacity), then Poisson arrivals at 0.5 and 0.9 of that capacity;
@@ -201,6 +203,32 @@ def bench_ebdf2(steps, warmup, Nt):
             "peak": MFMA_F64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(tflops / MFMA_F64_PEAK_TFLOPS, 4)}
     return out
+
+
+def bench_advection(steps, warmup):
+    """The headline instance with an advection term (complex symbol, real
+    state): the same kernels with complex E and phi tables."""
+    import workloads as W
+    inst = W.advection2d()
+    fp = bench_single(inst, 0, steps, warmup)
+    dom = fp["dominant"]
+    kb = fp["kernels"][dom]
+    return {
+        "workload": "2D Allen-Cahn eps=0.05 with advection b=(2,1), periodic "
+                    "256x256, Nt=64, T=2, ETD1, alpha=1e-3, u0~U[-0.9,0.9] "
+                    "seed 0",
+        "ms_per_solve": fp["ms_per_solve"],
+        "iters_per_solve": fp["iters"],
+        "us_per_iter": fp["us_per_iter"],
+        "dof_iters_per_s": fp["dof_iters_per_s"],
+        "dominant": dom,
+        "roofline": {"kernel": dom, "bound": "hbm",
+                     "achieved": round(kb["GBps"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s",
+                     "frac": round(kb["GBps"] / HBM_PEAK_GBS, 4),
+                     "avg_launch_us": kb["avg_us"]},
+        "U": fp["U"],
+    }
 
 
 def bench_batched(count):
@@ -420,7 +448,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--no-ebdf2", action="store_true")
+    ap.add_argument("--no-ebdf2", action="store_true",
+                    help="skip the EBDF2 and advection sections")
     ap.add_argument("--quick", action="store_true",
                     help="fp64 single-instance solves only")
     ap.add_argument("--profile", action="store_true",
@@ -505,6 +534,11 @@ def main():
         ebd.pop("U")
         eb["dense_variant_Nt64"] = ebd
         line["ebdf2"] = eb
+    if not args.no_ebdf2:
+        _log("advection (complex symbol)")
+        adv = bench_advection(args.steps, args.warmup)
+        U_adv = adv.pop("U")
+        line["advection"] = adv
     if not args.no_batch:
         _log(f"batched: {args.batch} instances")
         line["batched"] = bench_batched(args.batch)
@@ -518,6 +552,11 @@ def main():
         if not args.no_ebdf2:
             line["ebdf2"]["cpu_baseline"] = cpu_baseline_ebdf2(
                 U_eb, args.cpu_iters)
+            import oracle as O
+            import workloads as W
+            ia = W.advection2d()
+            line["advection"]["err_vs_oracle"] = float(O.rel_err(
+                U_adv, O.sequential(O.Setup.from_instance(ia), ia.u0)))
     if rank == 0:
         print(json.dumps(line), flush=True)
 

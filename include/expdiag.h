@@ -2,7 +2,7 @@
  * expdiag.h -- C ABI of the MI355X (gfx950) Exp-ParaDiag library.
  *
  * Solves the all-at-once space-time system of an exponential integrator for
- *     u_t = a Lap(u) - c u + N(u),   N(u) = n1 u + n2 u^2 + n3 u^3,
+ *     u_t = a Lap(u) - b.grad(u) - c u + N(u),   N(u) = n1 u + n2 u^2 + n3 u^3,
  * on the periodic box [0, 2pi)^dim with Fourier collocation, by the
  * alpha-circulant preconditioned fixed point (Garai & Chamakuri,
  * "Exp-ParaDiag", Sec. 3, eq. pcond-1st-order, steps (a)-(c) of eq.
@@ -76,8 +76,13 @@ typedef struct {
   int n[3];
 } expdiag_grid;
 
-/* u_t = a Lap(u) - c u + n1 u + n2 u^2 + n3 u^3.  The linear operator is
- * L = a Lap - c of Sec. 1 (eq. model_problem_linear); a >= 0, c >= 0.
+/* u_t = a Lap(u) - b.grad(u) - c u + n1 u + n2 u^2 + n3 u^3.  The linear
+ * operator is L = a Lap - c of Sec. 1 (eq. model_problem_linear) plus the
+ * advection term of the remark after Theorem thm_gmres22 (periodic, so
+ * diagonal in Fourier space with the complex symbol
+ * -a|k|^2 - c - i b.k'; k' is the wavenumber except 0 at an axis's Nyquist
+ * index, so real fields stay real); a >= 0, c >= 0, b finite (b[i] is the
+ * velocity along axis i; entries past dim are ignored).
  * precision: EXPDIAG_FP64, or EXPDIAG_MIXED (fp32 spatial FFTs and
  * nonlinearity in a bulk phase, fp64 residual and iterate afterwards; the
  * time transform is always fp64).
@@ -87,6 +92,7 @@ typedef struct {
   double a, c, n1, n2, n3;
   int precision;
   int gmres_restart;
+  double b[3];
 } expdiag_problem;
 
 /* Build a handle: spectral symbols E = exp(dt mu), dt phi1(dt mu),

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
@@ -108,6 +109,7 @@ struct expdiag_ctx {
   bool mixed = false;
   int restart_cap = 0;
   int tvariant = 0;  // time transform: 0 radix FFT, 1 dense MFMA GEMM
+  bool cplx = false;  // complex symbols (advection): E, c1, c2 not real
   bool light = false;  // no plan / graph of its own (batch, server)
 
   // device buffers
@@ -119,7 +121,7 @@ struct expdiag_ctx {
   double* Uphys = nullptr;    // [Nt][Ns] physical iterate (Newton)
   float* Uphys32 = nullptr;   // [Nt][Ns] its fp32 copy (mixed Newton)
   cx<double>* u0h = nullptr;  // [Nk]
-  double *E = nullptr, *c1 = nullptr, *c2 = nullptr;  // [Nk]
+  cx<double> *E = nullptr, *c1 = nullptr, *c2 = nullptr;  // [Nk]
   double *gam = nullptr, *igam = nullptr;             // [Nt]
   cx<double>* lam = nullptr;                          // [Nt]
   cx<double>* tw64 = nullptr;                         // [TW_N]
@@ -465,8 +467,12 @@ int launch_passb1(expdiag_ctx* h, const PassBArgs& a) {
     constexpr int NN = decltype(Nc)::value;
     using SH = PassBShape<NN>;
     const long blocks = (h->Nk + SH::C - 1) / SH::C;
-    hipLaunchKernelGGL((passb_kernel1<NN, MODE, TN>), dim3(blocks),
-                       dim3(SH::THREADS), 0, h->stream, a);
+    if (h->cplx)
+      hipLaunchKernelGGL((passb_kernel1<NN, MODE, TN, true>), dim3(blocks),
+                         dim3(SH::THREADS), 0, h->stream, a);
+    else
+      hipLaunchKernelGGL((passb_kernel1<NN, MODE, TN, false>), dim3(blocks),
+                         dim3(SH::THREADS), 0, h->stream, a);
   });
   if (!ok) return fail(h, EXPDIAG_EUNSUPPORTED, "Nt %d", h->Nt);
   HIPCHK(h, hipGetLastError());
@@ -735,10 +741,14 @@ void plan_iteration(Plan& P, expdiag_ctx* h, Ctl* ctl, Ctl* mirror,
   a.hist = hist;
   if (h->nonlinear && h->mixed) a.Nh32 = nh_view<float>(h);
   const bool hosted = h->nonlinear && plan_pass_a_mp(P, h, ctl, a);
-  // pass B variant: 0 radix FFT, 1 dense, 2 EBDF2 dense, 3 EBDF2 radix FFT
-  // (the group length is the transform length for the radix kernels)
+  // pass B variant: 0 radix FFT, 1 dense, 2 EBDF2 dense, 3 EBDF2 radix FFT,
+  // 4 radix FFT with complex symbols (the group length is the transform
+  // length for the radix kernels)
   int variant = h->tvariant;
-  if (h->scheme == EXPDIAG_EBDF2) variant = h->tvariant == 1 ? 2 : 3;
+  if (h->scheme == EXPDIAG_EBDF2)
+    variant = h->tvariant == 1 ? 2 : 3;
+  else if (variant == 0 && h->cplx)
+    variant = 4;
   const int len = variant == 3 ? time_len(h) : h->Nt;
   plan_passb(P, 5, len, a, sizeof(cx<double>), variant, !hosted);
 }
@@ -914,8 +924,14 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st,
         } else {
           ok = dispatch_pow2<2, 512>(g.len, [&](auto Nc) {
             constexpr int NN = decltype(Nc)::value;
-            klaunch(ps, passb_kernel<NN, PB_ITERATE, double>, dim3(grid),
-                    dim3(PassBShape<NN>::THREADS), st, J, g.dstart, nj);
+            if (g.tcode == 4)
+              klaunch(ps, passb_kernel<NN, PB_ITERATE, double, true>,
+                      dim3(grid), dim3(PassBShape<NN>::THREADS), st, J,
+                      g.dstart, nj);
+            else
+              klaunch(ps, passb_kernel<NN, PB_ITERATE, double, false>,
+                      dim3(grid), dim3(PassBShape<NN>::THREADS), st, J,
+                      g.dstart, nj);
           });
         }
       }
@@ -1033,18 +1049,107 @@ const TwiddleTables& twiddle_tables() {
   return t;
 }
 
+using cld = std::complex<long double>;
+
+// phi1, phi2 of a complex argument: power series for |z| < 1 (Horner from
+// the tail, 36 terms), the closed forms beyond.
+cld phi1c(cld z) {
+  const long double* inv = inv_factorials();
+  if (std::abs(z) < 1.0L) {
+    cld acc = 0.0L;
+    for (int j = 35; j >= 0; --j) acc = acc * z + inv[j + 1];
+    return acc;
+  }
+  return (std::exp(z) - 1.0L) / z;
+}
+cld phi2c(cld z) {
+  const long double* inv = inv_factorials();
+  if (std::abs(z) < 1.0L) {
+    cld acc = 0.0L;
+    for (int j = 35; j >= 0; --j) acc = acc * z + inv[j + 2];
+    return acc;
+  }
+  return (std::exp(z) - 1.0L - z) / (z * z);
+}
+
+cx<double> to_cx(cld v) {
+  return mk(static_cast<double>(v.real()), static_cast<double>(v.imag()));
+}
+
+// Runs f(lo, hi) over [0, n) on up to eight host threads.
+template <typename F>
+void parallel_ranges(long n, F&& f) {
+  const int nthr = n < 4096 ? 1 : 8;
+  if (nthr == 1) {
+    f(0L, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int k = 0; k < nthr; ++k)
+    th.emplace_back(f, n * k / nthr, n * (k + 1) / nthr);
+  for (auto& t : th) t.join();
+}
+
 // Per-kappa tables E = e^{dt mu}, c1, c2 (eq. etd1_update / etd2_update
-// weights), mu = -a |k|^2 - c.  They depend on kappa only through the
-// integer |k|^2, so each value of |k|^2 that occurs is evaluated once (in
-// long double, on up to eight host threads) and then gathered.
-void symbol_tables(expdiag_ctx* h, std::vector<double>& E,
-                   std::vector<double>& c1, std::vector<double>& c2) {
+// weights), mu = -a |k|^2 - c - i b.k'.  Without advection they depend on
+// kappa only through the integer |k|^2, so each value of |k|^2 that occurs
+// is evaluated once (real, long double) and then gathered; with advection
+// every kappa is evaluated (complex long double).  k' is the derivative
+// wavenumber: k, except 0 at the Nyquist index of its axis (so that
+// b.grad maps real fields to real fields).  Host threads: up to eight.
+void symbol_tables(expdiag_ctx* h, std::vector<cx<double>>& E,
+                   std::vector<cx<double>>& c1, std::vector<cx<double>>& c2) {
   const int d = h->dim;
   const long Nk = h->Nk;
   const int n0 = h->n[0], n1 = d >= 2 ? h->n[1] : 1;
   const int outer0 = d >= 2 ? n0 : 1;
   const int outer1 = d >= 3 ? n1 : 1;
   auto wn = [](int j, int n) { return j <= n / 2 ? j : j - n; };
+  // derivative wavenumber of index j on an axis of n points
+  auto wd = [](int j, int n) { return 2 * j == n ? 0 : (j < n / 2 ? j : j - n); };
+  const long double a = h->p.a, c = h->p.c, dt = h->dt;
+  const bool etd2 = h->scheme == EXPDIAG_ETD2;
+  E.resize(Nk);
+  c1.resize(Nk);
+  c2.resize(Nk);
+  const double* bv = h->p.b;
+  const bool adv = (bv[0] != 0.0) || (d >= 2 && bv[1] != 0.0) ||
+                   (d >= 3 && bv[2] != 0.0);
+  if (adv) {
+    // axis of each index: (i0, i1, kl) -> the dims present
+    const int nl = h->n[d - 1];
+    auto eval = [&](long lo, long hi) {
+      for (long i = lo; i < hi; ++i) {
+        const int kl = static_cast<int>(i % h->nh);
+        const long r = i / h->nh;
+        const int i1 = d >= 3 ? static_cast<int>(r % outer1) : 0;
+        const int i0 = d >= 2 ? static_cast<int>(d >= 3 ? r / outer1 : r) : 0;
+        long double k2 = static_cast<long double>(kl) * kl;
+        long double bk = bv[d - 1] * static_cast<long double>(wd(kl, nl));
+        if (d >= 2) {
+          k2 += static_cast<long double>(wn(i0, n0)) * wn(i0, n0);
+          bk += bv[0] * static_cast<long double>(wd(i0, n0));
+        }
+        if (d >= 3) {
+          k2 += static_cast<long double>(wn(i1, n1)) * wn(i1, n1);
+          bk += bv[1] * static_cast<long double>(wd(i1, n1));
+        }
+        const cld z = dt * cld(-a * k2 - c, -bk);
+        const cld w1 = dt * phi1c(z);
+        E[i] = to_cx(std::exp(z));
+        if (etd2) {
+          const cld w2 = dt * phi2c(z);
+          c1[i] = to_cx(w1 + w2);
+          c2[i] = to_cx(-w2);
+        } else {
+          c1[i] = to_cx(w1);
+          c2[i] = mk(0.0, 0.0);
+        }
+      }
+    };
+    parallel_ranges(Nk, eval);
+    return;
+  }
   std::vector<int> k2(Nk);
   long idx = 0, k2max = 0;
   for (int i0 = 0; i0 < outer0; ++i0) {
@@ -1068,8 +1173,6 @@ void symbol_tables(expdiag_ctx* h, std::vector<double>& E,
   }
   const long nv = static_cast<long>(vals.size());
   std::vector<double> tE(nv), t1(nv), t2(nv);
-  const long double a = h->p.a, c = h->p.c, dt = h->dt;
-  const bool etd2 = h->scheme == EXPDIAG_ETD2;
   auto eval = [&](long lo, long hi) {
     for (long i = lo; i < hi; ++i) {
       const long double z = dt * (-a * static_cast<long double>(vals[i]) - c);
@@ -1085,29 +1188,18 @@ void symbol_tables(expdiag_ctx* h, std::vector<double>& E,
       }
     }
   };
-  const int nthr = nv < 4096 ? 1 : 8;
-  if (nthr == 1) {
-    eval(0, nv);
-  } else {
-    std::vector<std::thread> th;
-    for (int k = 0; k < nthr; ++k)
-      th.emplace_back(eval, nv * k / nthr, nv * (k + 1) / nthr);
-    for (auto& t : th) t.join();
-  }
-  E.resize(Nk);
-  c1.resize(Nk);
-  c2.resize(Nk);
+  parallel_ranges(nv, eval);
   for (long i = 0; i < Nk; ++i) {
     const int j = slot[k2[i]];
-    E[i] = tE[j];
-    c1[i] = t1[j];
-    c2[i] = t2[j];
+    E[i] = mk(tE[j], 0.0);
+    c1[i] = mk(t1[j], 0.0);
+    c2[i] = mk(t2[j], 0.0);
   }
 }
 
 int build_tables(expdiag_ctx* h) {
   const long Nk = h->Nk;
-  std::vector<double> E, c1, c2;
+  std::vector<cx<double>> E, c1, c2;
   symbol_tables(h, E, c1, c2);
   const int Nt = h->Nt;
   // The transform runs over N time points: Nt, or for EBDF2 the Nt - 1
@@ -1162,10 +1254,13 @@ int build_tables(expdiag_ctx* h) {
     HIPCHK(h, hipMemcpy(h->Wi, wi.data(), wi.size() * sizeof(double),
                         hipMemcpyHostToDevice));
   }
+  h->cplx = false;
+  for (long i = 0; i < Nk && !h->cplx; ++i)
+    h->cplx = E[i].y != 0.0 || c1[i].y != 0.0 || c2[i].y != 0.0;
   const TwiddleTables& tw = twiddle_tables();
-  HIPCHK(h, hipMemcpy(h->E, E.data(), Nk * sizeof(double), hipMemcpyHostToDevice));
-  HIPCHK(h, hipMemcpy(h->c1, c1.data(), Nk * sizeof(double), hipMemcpyHostToDevice));
-  HIPCHK(h, hipMemcpy(h->c2, c2.data(), Nk * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->E, E.data(), Nk * sizeof(cx<double>), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->c1, c1.data(), Nk * sizeof(cx<double>), hipMemcpyHostToDevice));
+  HIPCHK(h, hipMemcpy(h->c2, c2.data(), Nk * sizeof(cx<double>), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->gam, gam.data(), Nt * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->igam, igam.data(), Nt * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->lam, lam.data(), Nt * sizeof(cx<double>), hipMemcpyHostToDevice));
@@ -1205,7 +1300,7 @@ size_t footprint(const Sizes& s, int dim, int Nt, bool nonlinear,
     if (nonlinear)
       b += static_cast<size_t>(Nt) * s.Ns * (sizeof(double) + sizeof(float));
   }
-  b += s.Nk * (sizeof(cx<double>) + 3 * sizeof(double));
+  b += s.Nk * 4 * sizeof(cx<double>);  // u0^, E, c1, c2
   b += TW_N * (sizeof(cx<double>) + sizeof(cx<float>));
   b += static_cast<size_t>(std::max(std::max(passb_blocks_nt(Nt, s.Nk),
                                              passb_blocks_nt(Nt - 1, s.Nk)),
@@ -1373,6 +1468,9 @@ int validate_params(int Nt, double dt, double alpha, int scheme,
       !std::isfinite(p->c) || !std::isfinite(p->n1) ||
       !std::isfinite(p->n2) || !std::isfinite(p->n3))
     return fail(nullptr, EXPDIAG_EINVAL, "a, c must be finite and >= 0");
+  if (!std::isfinite(p->b[0]) || !std::isfinite(p->b[1]) ||
+      !std::isfinite(p->b[2]))
+    return fail(nullptr, EXPDIAG_EINVAL, "advection velocity must be finite");
   if (p->precision != EXPDIAG_FP64 && p->precision != EXPDIAG_MIXED)
     return fail(nullptr, EXPDIAG_EINVAL, "unknown precision %d",
                 p->precision);
@@ -1442,9 +1540,9 @@ int create_impl(const expdiag_grid* g, int Nt, double dt, double alpha,
   if (h->nonlinear && h->mixed && h->dim >= 2)
     A(&h->T32, static_cast<size_t>(Nt) * h->Nk * sizeof(cx<float>));
   A(&h->u0h, h->Nk * sizeof(cx<double>));
-  A(&h->E, h->Nk * sizeof(double));
-  A(&h->c1, h->Nk * sizeof(double));
-  A(&h->c2, h->Nk * sizeof(double));
+  A(&h->E, h->Nk * sizeof(cx<double>));
+  A(&h->c1, h->Nk * sizeof(cx<double>));
+  A(&h->c2, h->Nk * sizeof(cx<double>));
   A(&h->gam, Nt * sizeof(double));
   A(&h->igam, Nt * sizeof(double));
   A(&h->lam, Nt * sizeof(cx<double>));

@@ -71,25 +71,25 @@ __device__ __forceinline__ void passb_bdf2_body(const PassBArgs& a, long lb,
       if constexpr (MODE == PB_PRECOND) {
         r = gld(a.Rin, l * Nk + kap);
       } else {
-        const double E = gld(a.E, kap);
-        const double E2 = E * E;
+        const cx<double> E = gld(a.E, kap);
+        const cx<double> E2 = cmul(E, E);
         const cx<double> u = Ut[e];
         // rows l-1 and l-2 (clamped; values, not addresses, are selected)
         const cx<double> q1 = Ut[(l >= 1 ? l - 1 : 0) * C + c];
         const cx<double> q2 = Ut[(l >= 2 ? l - 2 : 0) * C + c];
         if constexpr (MODE == PB_OPAPPLY) {
           r = u;
-          if (l >= 2) r = r - q1 * (c43 * E);
-          if (l >= 3) r = r + q2 * (c13 * E2);
+          if (l >= 2) r = r - cmul(q1, E * c43);
+          if (l >= 3) r = r + cmul(q2, E2 * c13);
         } else {
           const cx<double> h0 = gld(a.u0h, kap);
-          const cx<double> e1 = h0 * E;  // u_1 = A u_0
+          const cx<double> e1 = cmul(h0, E);  // u_1 = A u_0
           if (l == 0) {
             r = e1 - u;
           } else {
             const cx<double> p1 = l == 1 ? e1 : q1;
             const cx<double> p2 = l == 1 ? h0 : (l == 2 ? e1 : q2);
-            r = p1 * (c43 * E) - p2 * (c13 * E2) - u;
+            r = cmul(p1, E * c43) - cmul(p2, E2 * c13) - u;
           }
         }
       }
@@ -115,8 +115,8 @@ __device__ __forceinline__ void passb_bdf2_body(const PassBArgs& a, long lb,
       if (e >= NT * C) break;
       const int m = e / C, c = e % C;
       const long kap = k0 + c;
-      const double E = kap < Nk ? gld(a.E, kap) : 0.0;
-      const cx<double> z = gld(a.lam, m) * E;
+      const cx<double> E = kap < Nk ? gld(a.E, kap) : mk(0.0, 0.0);
+      const cx<double> z = cmul(gld(a.lam, m), E);
       const cx<double> d = cmul(mk(1.0 - z.x, -z.y),
                                 mk(1.0 - c13 * z.x, -c13 * z.y));
       const double inv = 1.0 / norm2(d);
@@ -146,7 +146,7 @@ __device__ __forceinline__ void passb_bdf2_body(const PassBArgs& a, long lb,
       if constexpr (MODE == PB_ITERATE) {
         // row 0 becomes E u0^ exactly rather than U_0 + (E u0^ - U_0)
         const cx<double> un =
-            l == 0 ? (valid ? gld(a.u0h, kap) * gld(a.E, kap) : zero)
+            l == 0 ? (valid ? cmul(gld(a.u0h, kap), gld(a.E, kap)) : zero)
                    : Ut[e] + sv;
         nrm_u += pw * norm2(un);
         if (valid) a.U[l * Nk + kap] = un;
@@ -221,7 +221,7 @@ __device__ __forceinline__ void passb_bdf2_fft_body(const PassBArgs& a,
 #pragma unroll
   for (int s = 0; s < R; ++s) u[s] = gld(in, (t + s * TPL + 1) * Nk + kc);
   const cx<double> w0 = gld(in, kc);
-  const double E = gld(a.E, kc);
+  const cx<double> E = gld(a.E, kc);
   cx<double> h0 = zero;
   if constexpr (MODE == PB_ITERATE || MODE == PB_RESIDUAL) h0 = gld(a.u0h, kc);
   const double gam_t = gld(a.gam, t), igam_t = gld(a.igam, t);
@@ -233,8 +233,8 @@ __device__ __forceinline__ void passb_bdf2_fft_body(const PassBArgs& a,
   auto gam = [&](int s) { return s == 0 ? gam_t : gam_t * a.gstep[s]; };
   auto igam = [&](int s) { return s == 0 ? igam_t : igam_t * a.igstep[s]; };
 
-  const double E2 = E * E;
-  const cx<double> e1 = h0 * E;  // u_1 = A u_0
+  const cx<double> E2 = cmul(E, E);
+  const cx<double> e1 = cmul(h0, E);  // u_1 = A u_0
   cx<double> v[R];
   cx<double> r0;  // window row 0: residual (or operator) row
   if constexpr (MODE == PB_PRECOND) {
@@ -255,12 +255,12 @@ __device__ __forceinline__ void passb_bdf2_fft_body(const PassBArgs& a,
         // (R v)_j with the entries before v_2 zero
         const cx<double> p1 = j >= 1 ? q1 : zero;
         const cx<double> p2 = j >= 2 ? q2 : zero;
-        v[s] = u[s] - p1 * (c43 * E) + p2 * (c13 * E2);
+        v[s] = u[s] - cmul(p1, E * c43) + cmul(p2, E2 * c13);
       } else {
         // f_2 - R v: row j needs u_{j+1} and u_j (u_1 = A u_0, u_0 given)
         const cx<double> p1 = j >= 1 ? q1 : e1;
         const cx<double> p2 = j >= 2 ? q2 : (j == 1 ? e1 : h0);
-        v[s] = p1 * (c43 * E) - p2 * (c13 * E2) - u[s];
+        v[s] = cmul(p1, E * c43) - cmul(p2, E2 * c13) - u[s];
       }
     }
     r0 = MODE == PB_OPAPPLY ? w0 : e1 - w0;
@@ -302,7 +302,7 @@ __device__ __forceinline__ void passb_bdf2_fft_body(const PassBArgs& a,
     } else {
       static_assert(R == 1 || R == 2 || R == 4, "rotations for R <= 4");
     }
-    const cx<double> z = lam * E;
+    const cx<double> z = cmul(lam, E);
     const cx<double> d = cmul(mk(1.0 - z.x, -z.y),
                               mk(1.0 - c13 * z.x, -c13 * z.y));
     v[s] = cmulc(v[s], d) * (1.0 / (N * norm2(d)));
@@ -373,9 +373,9 @@ __global__ void __launch_bounds__(PassBShape<N>::THREADS,
 // Slice u_1 = A u_0 of a spectral window (the fixed start of the scheme).
 __global__ void bdf2_start_kernel(cx<double>* __restrict__ U,
                                   const cx<double>* __restrict__ u0h,
-                                  const double* __restrict__ E, long Nk) {
+                                  const cx<double>* __restrict__ E, long Nk) {
   const long k = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k < Nk) U[k] = u0h[k] * E[k];
+  if (k < Nk) U[k] = cmul(u0h[k], E[k]);
 }
 
 }  // namespace expdiag

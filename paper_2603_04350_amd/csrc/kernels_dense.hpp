@@ -84,15 +84,15 @@ __device__ __forceinline__ void passb_dense_body(const PassBArgs& a, long lb,
       if (valid) r = a.Rin[l * Nk + kap];
     } else {
       if (valid) {
-        const double E = a.E[kap];
+        const cx<double> E = a.E[kap];
         const cx<double> prev = l == 0 ? a.u0h[kap] : Ut[(l - 1) * C + c];
-        r = prev * E - Ut[e];
+        r = cmul(prev, E) - Ut[e];
         if (a.nonlinear) {
           const cx<TN>* Nc = reinterpret_cast<const cx<TN>*>(Nh);
-          r = r + cvt<double>(Nc[l * Nk + kap]) * a.c1[kap];
+          r = r + cmul(cvt<double>(Nc[l * Nk + kap]), a.c1[kap]);
           if (a.etd2)
-            r = r + cvt<double>(Nc[(l == 0 ? 0 : l - 1) * Nk + kap]) *
-                        a.c2[kap];
+            r = r + cmul(cvt<double>(Nc[(l == 0 ? 0 : l - 1) * Nk + kap]),
+                         a.c2[kap]);
         }
       }
     }
@@ -111,9 +111,9 @@ __device__ __forceinline__ void passb_dense_body(const PassBArgs& a, long lb,
     if (e >= NT * C) break;
     const int m = e / C, c = e % C;
     const long kap = k0 + c;
-    const double E = kap < Nk ? a.E[kap] : 0.0;
-    const cx<double> lam = a.lam[m];
-    const double dr = 1.0 - lam.x * E, di = -lam.y * E;
+    const cx<double> E = kap < Nk ? a.E[kap] : mk(0.0, 0.0);
+    const cx<double> z = cmul(a.lam[m], E);
+    const double dr = 1.0 - z.x, di = -z.y;
     const double inv = 1.0 / (dr * dr + di * di);
     const cx<double> y = mk(Ym[m * C + c], Ym[(NT + m) * C + c]);
     const cx<double> x = cmul(y, mk(dr * inv, -di * inv));

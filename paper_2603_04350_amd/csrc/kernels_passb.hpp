@@ -41,9 +41,9 @@ struct PassBArgs {
   const void* Nh;         // [Nt][Nk] fp64 N^ (or J for PB_OPAPPLY), or null
   const void* Nh32;       // [Nt][Nk] fp32 N^ of the mixed bulk phase
   const cx<double>* u0h;  // [Nk]
-  const double* E;        // [Nk]
-  const double* c1;       // [Nk]
-  const double* c2;       // [Nk]
+  const cx<double>* E;    // [Nk] e^{dt mu} (complex when L has advection)
+  const cx<double>* c1;   // [Nk] nonlinear weights of the scheme
+  const cx<double>* c2;   // [Nk]
   const double* gam;      // [Nt]
   const double* igam;     // [Nt]
   const cx<double>* lam;  // [Nt]
@@ -170,10 +170,37 @@ __device__ inline void advance_ctl(const PassBArgs& a, const double* tot) {
 // factor is uniform, a scalar load) and lambda_{t+s TPL} = lambda_t
 // e^{2 pi i s/R}.  Rows l-1 (of U, and of N^ for ETD2) come from the
 // neighbouring threads through the LDS tile.
-template <int NT, int MODE, typename TN>
+// Per-kappa symbol values: complex (L with advection) or their real parts
+// (the tables' imaginary parts are zero), which keeps the registers of the
+// real case.
+template <bool CPLX>
+struct SymOf {
+  using T = cx<double>;
+  static __device__ __forceinline__ T load(const cx<double>* p, long k) {
+    return gld(p, k);
+  }
+  static __device__ __forceinline__ T zero() { return mk(0.0, 0.0); }
+};
+template <>
+struct SymOf<false> {
+  using T = double;
+  static __device__ __forceinline__ T load(const cx<double>* p, long k) {
+    return gld(reinterpret_cast<const double*>(p), 2 * k);
+  }
+  static __device__ __forceinline__ T zero() { return 0.0; }
+};
+__device__ __forceinline__ cx<double> smul(cx<double> a, double s) {
+  return a * s;
+}
+__device__ __forceinline__ cx<double> smul(cx<double> a, cx<double> s) {
+  return cmul(a, s);
+}
+
+template <int NT, int MODE, typename TN, bool CPLX>
 __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
                                            const TN* Nh, cx<double>* lds,
                                            double* red) {
+  using SY = SymOf<CPLX>;
   using SH = PassBShape<NT>;
   constexpr int R = SH::R;
   constexpr int TPL = SH::TPL;
@@ -208,13 +235,13 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
       nr[s] = gld(Nc, l * Nk + kc);
     }
   }
-  const double E = gld(a.E, kc);
+  const typename SY::T E = SY::load(a.E, kc);
   cx<double> first = zero;
-  double c1 = 0.0, c2 = 0.0;
+  typename SY::T c1 = SY::zero(), c2 = SY::zero();
   if constexpr (MODE != PB_PRECOND && MODE != PB_OPAPPLY)
     first = gld(a.u0h, kc);
-  if (nl) c1 = gld(a.c1, kc);
-  if (two) c2 = gld(a.c2, kc);
+  if (nl) c1 = SY::load(a.c1, kc);
+  if (two) c2 = SY::load(a.c2, kc);
   const double gam_t = gld(a.gam, t), igam_t = gld(a.igam, t);
   const cx<double> lam_t = gld(a.lam, t);
   constexpr int NST = fft_stage_count<NT, R>();
@@ -252,8 +279,8 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
       // PB_OPAPPLY, (Q - G'(U)) v: v_l - E v_{l-1} - (c1 J_l + c2 J_{l-1})
       // with J_l = FFT[N'(u_{l-1}) v_{l-1}] (J_0 = 0: u_0 is fixed); else
       // R_l = E U_{l-1} - U_l + c1 N_l + c2 N_{l-1}
-      v[s] = (MODE == PB_OPAPPLY) ? u[s] - prev * E - n_cur * c1
-                                  : prev * E - u[s] + n_cur * c1;
+      v[s] = (MODE == PB_OPAPPLY) ? u[s] - smul(prev, E) - smul(n_cur, c1)
+                                  : smul(prev, E) - u[s] + smul(n_cur, c1);
       nr[s] = cvt<TN>(n_cur);  // masked row for the N_{l-1} exchange
     }
     if (two) {
@@ -268,7 +295,8 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
         const int l = t + s * TPL;
         const int lp = (l == 0) ? (MODE == PB_OPAPPLY ? -1 : 0) : l - 1;
         const cx<double> n_prev = lp < 0 ? zero : lds[lp * LS + c];
-        v[s] = (MODE == PB_OPAPPLY) ? v[s] - n_prev * c2 : v[s] + n_prev * c2;
+        v[s] = (MODE == PB_OPAPPLY) ? v[s] - smul(n_prev, c2)
+                                    : v[s] + smul(n_prev, c2);
       }
     }
 #pragma unroll
@@ -307,7 +335,8 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
     } else {
       static_assert(R == 1 || R == 2 || R == 4, "rotations for R <= 4");
     }
-    const double dr = 1.0 - lam.x * E, di = -lam.y * E;
+    const cx<double> z = smul(lam, E);
+    const double dr = 1.0 - z.x, di = -z.y;
     const double inv = 1.0 / (NT * (dr * dr + di * di));
     v[s] = cmul(v[s], mk(dr * inv, -di * inv));
   }
@@ -343,7 +372,7 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
   }
 }
 
-template <int NT, int MODE, typename TN>
+template <int NT, int MODE, typename TN, bool CPLX>
 __global__ void __launch_bounds__(PassBShape<NT>::THREADS,
                                   PassBShape<NT>::WAVES)
     passb_kernel(const PassBArgs* __restrict__ jobs,
@@ -361,13 +390,16 @@ __global__ void __launch_bounds__(PassBShape<NT>::THREADS,
     if (ph < 0) return;
     if (lb == 0 && threadIdx.x == 0) a.ctl->pending = 1;
     if (a.Nh32 != nullptr && ph == 0)
-      passb_body<NT, MODE, float>(a, lb, static_cast<const float*>(a.Nh32),
+      passb_body<NT, MODE, float, CPLX>(a, lb,
+                                        static_cast<const float*>(a.Nh32),
                                   lds, red);
     else
-      passb_body<NT, MODE, double>(a, lb, static_cast<const double*>(a.Nh),
+      passb_body<NT, MODE, double, CPLX>(a, lb,
+                                         static_cast<const double*>(a.Nh),
                                    lds, red);
   } else {
-    passb_body<NT, MODE, TN>(a, lb, static_cast<const TN*>(a.Nh), lds, red);
+    passb_body<NT, MODE, TN, CPLX>(a, lb, static_cast<const TN*>(a.Nh), lds,
+                                   red);
   }
 }
 
@@ -450,15 +482,15 @@ __global__ void __launch_bounds__(ColShape<L>::THREADS, 5)
   col_body<double, L, S, double, double>(jb, cb - start[i], tw64, lds);
 }
 
-template <int NT, int MODE, typename TN>
+template <int NT, int MODE, typename TN, bool CPLX>
 __global__ void __launch_bounds__(PassBShape<NT>::THREADS,
                                   PassBShape<NT>::WAVES)
     passb_kernel1(PassBArgs a) {
   using SH = PassBShape<NT>;
   __shared__ cx<double> lds[SH::LDS];
   double* red = reinterpret_cast<double*>(lds);
-  passb_body<NT, MODE, TN>(a, blockIdx.x, static_cast<const TN*>(a.Nh), lds,
-                           red);
+  passb_body<NT, MODE, TN, CPLX>(a, blockIdx.x, static_cast<const TN*>(a.Nh),
+                                 lds, red);
 }
 
 // Fixed-order final reduction of per-block partials for the non-iterate

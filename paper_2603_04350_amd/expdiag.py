@@ -49,7 +49,8 @@ class Problem(ctypes.Structure):
     _fields_ = [("a", ctypes.c_double), ("c", ctypes.c_double),
                 ("n1", ctypes.c_double), ("n2", ctypes.c_double),
                 ("n3", ctypes.c_double), ("precision", ctypes.c_int),
-                ("gmres_restart", ctypes.c_int)]
+                ("gmres_restart", ctypes.c_int),
+                ("b", ctypes.c_double * 3)]
 
 
 class Result(ctypes.Structure):
@@ -145,9 +146,11 @@ def make_grid(shape: Sequence[int]) -> Grid:
 
 
 def make_problem(a, c=0.0, n1=0.0, n2=0.0, n3=0.0, precision=EXPDIAG_FP64,
-                 gmres_restart=0) -> Problem:
+                 gmres_restart=0, b=(0.0, 0.0, 0.0)) -> Problem:
+    bb = tuple(float(v) for v in b) + (0.0,) * (3 - len(b))
     return Problem(float(a), float(c), float(n1), float(n2), float(n3),
-                   int(precision), int(gmres_restart))
+                   int(precision), int(gmres_restart),
+                   (ctypes.c_double * 3)(*bb[:3]))
 
 
 def _ptr(t, numel=None, name="array"):
@@ -271,11 +274,11 @@ class Solver:
 
     def __init__(self, shape, Nt, dt, alpha, scheme=EXPDIAG_ETD1, a=1.0,
                  c=0.0, n1=0.0, n2=0.0, n3=0.0, precision=EXPDIAG_FP64,
-                 gmres_restart=0, stream=None):
+                 gmres_restart=0, stream=None, b=(0.0, 0.0, 0.0)):
         self.shape = tuple(int(v) for v in shape)
         self.Nt = int(Nt)
         self.problem = make_problem(a, c, n1, n2, n3, precision,
-                                    gmres_restart)
+                                    gmres_restart, b)
         self.h = expdiag_create(self.shape, Nt, dt, alpha, scheme,
                                 self.problem, stream)
 
@@ -285,7 +288,7 @@ class Solver:
         return cls(inst.shape, inst.Nt, inst.dt, inst.alpha, inst.scheme,
                    inst.a, inst.c, inst.n1, inst.n2, inst.n3,
                    inst.precision if precision is None else precision,
-                   gmres_restart, stream)
+                   gmres_restart, stream, getattr(inst, "b", (0.0, 0.0, 0.0)))
 
     def close(self):
         if self.h is not None:

@@ -14,6 +14,8 @@ Workloads (all on periodic [0, 2*pi)^d):
                Nt=64, T=2, alpha=1e-3; u0 ~ U[-0.9, 0.9] i.i.d. per point.
   diffusion2d_ebdf2  allen_cahn2d's grid, window and u0 without the
                reaction (u_t = eps^2 Lap u), second-order exponential BDF.
+  advection2d  allen_cahn2d with an advection term -b.grad u, b = (2, 1)
+               (complex symbol, real state).
   rd2d         2D reaction-diffusion u_t = 0.1 Lap u + u - u^3, n=512,
                Nt=128, T=1, ETD2; u0 = sum of 32 periodic Gaussians with
                amplitude U[-1,1], width U[0.1,0.5], centre U[0,2pi)^2.
@@ -33,7 +35,7 @@ import numpy as np
 
 __all__ = [
     "Instance", "grid_coords", "heat1d", "allen_cahn2d", "rd2d", "batch",
-    "diffusion2d_ebdf2",
+    "diffusion2d_ebdf2", "advection2d",
     "served_stream", "uniform_field", "gaussians_field", "low_mode_field",
     "scaled",
 ]
@@ -60,6 +62,7 @@ class Instance:
     scheme: int = 1
     precision: int = 0
     u0: Optional[np.ndarray] = None
+    b: tuple = (0.0, 0.0, 0.0)
 
     @property
     def dt(self) -> float:
@@ -142,6 +145,19 @@ def diffusion2d_ebdf2(seed: int = 0, n: int = 256, Nt: int = 64,
     rng = np.random.default_rng(seed)
     return Instance("diffusion2d_ebdf2", 2, n, Nt, T, alpha, a=eps * eps,
                     scheme=3, u0=uniform_field(rng, 2, n))
+
+
+def advection2d(seed: int = 0, n: int = 256, Nt: int = 64, T: float = 2.0,
+                alpha: float = 1e-3, eps: float = 0.05,
+                b: tuple = (2.0, 1.0), nonlinear: bool = True) -> Instance:
+    """allen_cahn2d's grid, window and u0 with an advection term
+    -b.grad(u) (complex symbol, real state); without the reaction term when
+    nonlinear is False."""
+    rng = np.random.default_rng(seed)
+    return Instance("advection2d", 2, n, Nt, T, alpha, a=eps * eps,
+                    n1=1.0 if nonlinear else 0.0,
+                    n3=-1.0 if nonlinear else 0.0,
+                    u0=uniform_field(rng, 2, n), b=tuple(b) + (0.0,))
 
 
 def rd2d(seed: int = 0, n: int = 512, Nt: int = 128, T: float = 1.0,
