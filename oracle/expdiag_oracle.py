@@ -33,6 +33,11 @@ Readings taken where the paper is silent (also listed in the design doc):
   * The fixed point is written in residual-correction form
     u^{k+1} = u^k + Q_alpha^{-1}(f + G(u^k) - Q u^k)  (eq. pcond-1st-order),
     which equals the paper's b^{k-1} form in exact arithmetic.
+  * Complex coefficients a + i a_im, c + i c_im (the Schroedinger equation
+    of Sec. 6 has a = i) make the state complex; such a Setup (or one with
+    cstate=True) keeps every field complex and takes no real part.  GMRES
+    then runs on the real and imaginary parts as one real vector (inner
+    product Re(x^H y)).
   * EBDF2 (scheme 3, Sec. 4, linear problems only): the starting value is
     u_1 = A u_0, the exact exponential step (the paper leaves u_1 open).
     Space-time arrays still hold u_1..u_Nt; the unknown of the paper's
@@ -124,6 +129,9 @@ class Setup:
     n3: float = 0.0
     scheme: int = 1
     b: tuple = (0.0, 0.0, 0.0)
+    a_im: float = 0.0
+    c_im: float = 0.0
+    cstate: bool = False
     mu: np.ndarray = field(init=False, repr=False)
     E: np.ndarray = field(init=False, repr=False)
     w1: np.ndarray = field(init=False, repr=False)
@@ -136,6 +144,10 @@ class Setup:
         grids = np.meshgrid(*([k] * self.dim), indexing="ij")
         k2 = sum(g * g for g in grids)
         self.mu = -self.a * k2 - self.c
+        if self.a_im != 0.0 or self.c_im != 0.0:
+            # complex coefficients (Schroedinger: a = i): complex state
+            self.cstate = True
+            self.mu = self.mu - 1j * (self.a_im * k2 + self.c_im)
         if any(bj != 0.0 for bj in self.b[:self.dim]):
             kd = k.copy()
             kd[self.n // 2] = 0.0        # first derivative of the Nyquist mode
@@ -155,7 +167,17 @@ class Setup:
     def from_instance(cls, inst):
         return cls(inst.dim, inst.n, inst.Nt, inst.dt, inst.alpha, inst.a,
                    inst.c, inst.n1, inst.n2, inst.n3, inst.scheme,
-                   tuple(getattr(inst, "b", (0.0, 0.0, 0.0))))
+                   tuple(getattr(inst, "b", (0.0, 0.0, 0.0))),
+                   getattr(inst, "a_im", 0.0), getattr(inst, "c_im", 0.0),
+                   bool(getattr(inst, "cstate", False)))
+
+    @property
+    def dtype(self):
+        """Complex state (complex coefficients, or a complex u_0) or real."""
+        return np.complex128 if self.cstate else np.float64
+
+    def _out(self, w):
+        return w if self.cstate else w.real
 
     @property
     def axes(self):
@@ -173,14 +195,14 @@ class Setup:
         return np.fft.ifftn(g * np.fft.fftn(v, axes=axes), axes=axes)
 
     def A(self, v):
-        """A v with A = exp(dt L_h); real in, real out."""
-        return self.spectral_apply(v, self.E).real
+        """A v with A = exp(dt L_h); real in, real out for a real state."""
+        return self._out(self.spectral_apply(v, self.E))
 
     def W1(self, v):
-        return self.spectral_apply(v, self.w1).real
+        return self._out(self.spectral_apply(v, self.w1))
 
     def W2(self, v):
-        return self.spectral_apply(v, self.w2).real
+        return self._out(self.spectral_apply(v, self.w2))
 
     def N(self, u):
         return self.n1 * u + self.n2 * u * u + self.n3 * u * u * u
@@ -202,7 +224,7 @@ def sequential(st: Setup, u0):
     """
     if st.scheme == EBDF2:
         return sequential_ebdf2(st, u0)
-    U = np.empty((st.Nt,) + u0.shape)
+    U = np.empty((st.Nt,) + u0.shape, dtype=st.dtype)
     prev2, prev = u0, u0
     for j in range(st.Nt):
         un = st.A(prev)
@@ -287,15 +309,15 @@ def precond_apply(st: Setup, R):
     for m in range(st.Nt):
         Sb[m] = st.spectral_apply(Sa[m], 1.0 / (1.0 - st.lam[m] * st.E))
     S = time_idft(Sb) / g
-    return S.real
+    return st._out(S)
 
 
 def rel_err(U, V):
     """max_n ||u_n - v_n||_2 / max_n ||v_n||_2: the L_inf(0,T; L2) error
     of Sec. 6, normalised by the reference's norm."""
     ax = tuple(range(1, U.ndim))
-    num = np.sqrt(np.sum((U - V) ** 2, axis=ax)).max()
-    den = np.sqrt(np.sum(V ** 2, axis=ax)).max()
+    num = np.sqrt(np.sum(np.abs(U - V) ** 2, axis=ax)).max()
+    den = np.sqrt(np.sum(np.abs(V) ** 2, axis=ax)).max()
     return num / den
 
 
@@ -316,7 +338,8 @@ def fixed_point(st: Setup, u0, U0=None, max_iter=200, tol=1e-11, ref=None,
     (||s||/||u||, rel_err vs ref or nan) per iteration and, if record,
     the iterates themselves.
     """
-    U = np.zeros((st.Nt,) + u0.shape) if U0 is None else U0.copy()
+    U = np.zeros((st.Nt,) + u0.shape, dtype=st.dtype) if U0 is None \
+        else U0.copy()
     hist, iterates = [], []
     bdf2 = st.scheme == EBDF2
     for k in range(max_iter):
@@ -400,14 +423,28 @@ def gmres(matvec, b, x0, restart=20, tol=1e-10, max_iter=200):
     return x, total, hist
 
 
+def _real_view(st: Setup, op, b, x0):
+    """A complex-state problem as a real one of twice the size (real and
+    imaginary parts), on which the real GMRES runs with the inner product
+    Re(x^H y)."""
+    if not st.cstate:
+        return op, b, x0, lambda x: x
+    shape = b.shape
+    to_r = lambda z: np.stack([z.real, z.imag])
+    to_c = lambda r: r[0] + 1j * r[1]
+    return (lambda r: to_r(op(to_c(r)))), to_r(b), to_r(x0), to_c
+
+
 def gmres_solve(st: Setup, u0, restart=20, tol=1e-10, max_iter=200):
     """Linear problems: GMRES on Q_alpha^{-1} Q u = Q_alpha^{-1} f
     (Sec. 3.2, Theorem thm_gmres1 system), u^0 = 0."""
-    zeros = np.zeros((st.Nt,) + u0.shape)
+    zeros = np.zeros((st.Nt,) + u0.shape, dtype=st.dtype)
     f = residual(st, u0, zeros)          # f - Q*0
     b = precond_apply(st, f)
     op = lambda v: precond_apply(st, q_apply(st, v))
-    return gmres(op, b, zeros, restart, tol, max_iter)
+    rop, rb, rx0, back = _real_view(st, op, b, zeros)
+    x, it, hist = gmres(rop, rb, rx0, restart, tol, max_iter)
+    return back(x), it, hist
 
 
 def gprime_apply(st: Setup, u0, U, V):
@@ -473,7 +510,8 @@ def dense_operators(st: Setup):
     Finv = F.conj().T / F.shape[0]
 
     def dense_of(sym):
-        return (Finv @ np.diag(sym.ravel()) @ F).real
+        M = Finv @ np.diag(sym.ravel()) @ F
+        return M if st.cstate else M.real
 
     A = dense_of(st.E)
     Ns = A.shape[0]
@@ -492,7 +530,7 @@ def dense_solve(st: Setup, u0, D=None):
     """Linear all-at-once solve Q u = f by LU (numpy.linalg.solve)."""
     D = D or dense_operators(st)
     Ns = u0.size
-    f = np.zeros(st.Nt * Ns)
+    f = np.zeros(st.Nt * Ns, dtype=st.dtype)
     f[:Ns] = D["A"] @ u0.ravel()
     return np.linalg.solve(D["Q"], f).reshape((st.Nt,) + u0.shape)
 
@@ -564,7 +602,7 @@ def ebdf2_tables(st: Setup):
 def sequential_ebdf2(st: Setup, u0):
     """u_1..u_Nt of eq. 2nd_order_scheme: u_n = 4/3 A u_{n-1} - 1/3 B u_{n-2}
     with B = A^2, started from u_1 = A u_0."""
-    U = np.empty((st.Nt,) + u0.shape)
+    U = np.empty((st.Nt,) + u0.shape, dtype=st.dtype)
     U[0] = st.A(u0)
     prev2, prev = u0, U[0]
     for j in range(1, st.Nt):
@@ -575,7 +613,7 @@ def sequential_ebdf2(st: Setup, u0):
 
 def _B(st: Setup, v):
     """B v with B = A^2 (eq. 2nd_order_scheme), applied through the symbol."""
-    return st.spectral_apply(v, st.E ** 2).real
+    return st._out(st.spectral_apply(v, st.E ** 2))
 
 
 def r_apply_ebdf2(st: Setup, V):
@@ -634,25 +672,27 @@ def precond_apply_ebdf2(st: Setup, R):
         Sq[j] = st.spectral_apply(Sp[j], 1.0 / sym)
     S = np.empty_like(R)
     S[0] = R[0]
-    S[1:] = (time_idft(Sq) / g).real
+    S[1:] = st._out(time_idft(Sq) / g)
     return S
 
 
 def gmres_solve_ebdf2(st: Setup, u0, restart=20, tol=1e-10, max_iter=200):
     """GMRES on R_alpha^{-1} R v = R_alpha^{-1} f_2 (Sec. 4.2), v^0 = 0;
     returns the window u_1..u_Nt with u_1 = A u_0."""
-    zeros = np.zeros((st.Nt,) + u0.shape)
+    zeros = np.zeros((st.Nt,) + u0.shape, dtype=st.dtype)
     f2 = residual_ebdf2(st, u0, zeros)[1:]
 
     def prec(v):
-        full = np.zeros((st.Nt,) + u0.shape)
+        full = np.zeros((st.Nt,) + u0.shape, dtype=st.dtype)
         full[1:] = v
         return precond_apply_ebdf2(st, full)[1:]
 
     b = prec(f2)
     op = lambda v: prec(r_apply_ebdf2(st, v))
-    v, it, hist = gmres(op, b, np.zeros_like(f2), restart, tol, max_iter)
-    U = np.empty((st.Nt,) + u0.shape)
+    rop, rb, rx0, back = _real_view(st, op, b, np.zeros_like(f2))
+    v, it, hist = gmres(rop, rb, rx0, restart, tol, max_iter)
+    v = back(v)
+    U = np.empty((st.Nt,) + u0.shape, dtype=st.dtype)
     U[0] = st.A(u0)
     U[1:] = v
     return U, it, hist

@@ -3,8 +3,12 @@ L = a Lap - b.grad - c (the remark after Theorem thm_gmres22), whose symbol
 mu_k = -a|k|^2 - c - i b.k' makes E_k = e^{dt mu_k} complex while the state
 stays real.
 
+The second half covers complex states: the Schroedinger equation of Sec. 6
+(a = i, c = 2i), whose symbol is purely imaginary.
+
 Independent references: the exact solution of the PDE for trigonometric
-data (advected, damped modes), the per-mode closed form of every iterate
+data (advected, damped or rotating modes), norm conservation, the per-mode
+closed form of every iterate
 with a complex e^{mu T} (derived from the iteration matrix of eq.
 pcond_system, as for real symbols), dense LU and dense eigenvalues on the
 assembled matrices, and GMRES's finite termination.
@@ -156,3 +160,91 @@ def test_complex_phi_against_series():
             s2 = (cmath.exp(z) - 1 - z) / (z * z)
         assert abs(a1 - s1) <= 1e-15 * abs(s1)
         assert abs(a2 - s2) <= 1e-15 * abs(s2)
+
+
+# ---------------------------------------------------------------------------
+# complex state: the Schroedinger equation of Sec. 6 (a = i, c = i c_im)
+# ---------------------------------------------------------------------------
+def _schroedinger(dim, n, Nt, T, alpha, c_im=2.0, scheme=1):
+    return O.Setup(dim, n, Nt, T / Nt, alpha, a=0.0, a_im=1.0, c_im=c_im,
+                   scheme=scheme)
+
+
+def _packet(dim, n, k0=5.0, w=0.4):
+    x = 2 * np.pi * np.arange(n) / n
+    g = np.meshgrid(*([x] * dim), indexing="ij")
+    r2 = sum((gi - np.pi) ** 2 for gi in g)
+    return np.exp(-r2 / (2 * w * w)) * np.exp(-1j * k0 * (g[0] - np.pi))
+
+
+@pytest.mark.parametrize("scheme", [1, O.EBDF2])
+def test_schroedinger_plane_waves_exact(scheme):
+    """u_t = i u_xx - 2i u from e^{i3x} + 0.5 e^{-2ix}: each plane wave
+    rotates by e^{-i(k^2 + 2)t}; ETD1 and EBDF2 (from u_1 = A u_0) are exact."""
+    n, Nt, T = 32, 16, 1.0
+    st = _schroedinger(1, n, Nt, T, 1e-2, scheme=scheme)
+    x = 2 * np.pi * np.arange(n) / n
+    u0 = np.exp(3j * x) + 0.5 * np.exp(-2j * x)
+    t = (np.arange(Nt) + 1) * T / Nt
+    ex = np.array([np.exp(-11j * tt) * np.exp(3j * x)
+                   + 0.5 * np.exp(-6j * tt) * np.exp(-2j * x) for tt in t])
+    assert np.max(np.abs(O.sequential(st, u0) - ex)) < 1e-14
+    U, _, _ = O.fixed_point(st, u0, tol=1e-15, max_iter=40)
+    assert np.max(np.abs(U - ex)) < 1e-13
+
+
+def test_schroedinger_conserves_norm():
+    """i Lap - 2i has a purely imaginary spectrum: A is unitary, so every
+    slice keeps the l2 norm of u_0."""
+    st = _schroedinger(2, 16, 8, 0.5, 1e-3)
+    u0 = _packet(2, 16)
+    U = O.sequential(st, u0)
+    n0 = np.linalg.norm(u0)
+    for m in range(st.Nt):
+        assert abs(np.linalg.norm(U[m]) - n0) < 1e-13 * n0
+
+
+def test_schroedinger_iterates_closed_form():
+    """Every iterate: (1 - psi_k^k) E_k^n u^_{0,k} with |e^{mu_k T}| = 1, so
+    |psi_k| = alpha/|1 - alpha e^{mu_k T}| for every mode."""
+    st = _schroedinger(1, 16, 8, 1.0, 0.05)
+    u0 = _packet(1, 16, k0=3.0, w=0.6)
+    _, _, (_, its) = O.fixed_point(st, u0, max_iter=4, tol=0.0, record=True)
+    u0h = np.fft.fft(u0)
+    ET = st.E ** st.Nt
+    assert np.allclose(np.abs(ET), 1.0, atol=1e-14)
+    psi = -st.alpha * ET / (1.0 - st.alpha * ET)
+    for k, Uk in enumerate(its, start=1):
+        for m in range(st.Nt):
+            pred = (1.0 - psi ** k) * st.E ** (m + 1) * u0h
+            assert np.max(np.abs(np.fft.fft(Uk[m]) - pred)) <= \
+                1e-13 * np.max(np.abs(u0h))
+
+
+def test_schroedinger_precond_and_solve_dense():
+    st = _schroedinger(1, 8, 5, 0.5, 0.1)
+    D = O.dense_operators(st)
+    rng = np.random.default_rng(12)
+    R = rng.standard_normal((5, 8)) + 1j * rng.standard_normal((5, 8))
+    S = O.precond_apply(st, R)
+    Sd = np.linalg.solve(D["Qa"], R.ravel()).reshape(R.shape)
+    assert np.max(np.abs(S - Sd)) < 1e-12 * np.max(np.abs(Sd))
+    u0 = _packet(1, 8, w=0.8)
+    assert O.rel_err(O.sequential(st, u0), O.dense_solve(st, u0, D)) < 1e-14
+    ev = np.linalg.eigvals(np.linalg.solve(D["Qa"], D["Q"]))
+    assert np.max(np.abs(ev - 1)) <= st.alpha / (1 - st.alpha) + 1e-12
+
+
+def test_schroedinger_gmres_finite_termination():
+    """Real GMRES on the real and imaginary parts: the preconditioned
+    operator is the identity plus a real rank of 2 per excited mode."""
+    n, Nt = 6, 5
+    st = _schroedinger(1, n, Nt, 0.5, 0.3)
+    u0 = _packet(1, n, w=0.9)
+    U, it, _ = O.gmres_solve(st, u0, restart=50, tol=1e-13, max_iter=50)
+    assert it <= 2 * n + 1
+    assert O.rel_err(U, O.sequential(st, u0)) < 1e-11
+    x = 2 * np.pi * np.arange(16) / 16
+    st1 = _schroedinger(1, 16, 8, 1.0, 0.1)
+    U1, it1, _ = O.gmres_solve(st1, np.exp(3j * x), restart=20, tol=1e-12)
+    assert it1 <= 3
