@@ -31,6 +31,8 @@ value = space-time DOF-iterations per second of the plain FP64 solve
     time transform on FP64 MFMA, pass B against both peaks);
   * advection: the headline instance with an advection term -b.grad u,
     b = (2, 1), whose symbol is complex (complex E and phi tables);
+  * schroedinger: u_t = i Lap u - 2i u on the same grid, a complex state
+    (full spectrum, C2C boundary transforms), from a wave packet;
   * served: batch-shaped 2D requests mixed with 3D 128^3 x 32 heat /
     Allen-Cahn requests into the continuous-batching server: all at once
     (its capacity), then Poisson arrivals at 0.5 and 0.9 of that capacity;
@@ -229,6 +231,64 @@ def bench_advection(steps, warmup):
                      "avg_launch_us": kb["avg_us"]},
         "U": fp["U"],
     }
+
+
+def bench_schroedinger(steps, warmup):
+    """Complex state: u_t = i Lap u - 2i u on 256^2 from a wave packet,
+    full-spectrum pass B (complex symbols), C2C boundary transforms."""
+    import torch
+    import workloads as W
+    from paper_2603_04350_amd import expdiag as X
+    inst = W.schroedinger2d()
+    dev = "cuda:0"
+    u0 = torch.from_numpy(inst.u0).to(dev)
+    U = torch.zeros((inst.Nt,) + inst.shape, dtype=torch.complex128,
+                    device=dev)
+    s = X.Solver.from_instance(inst)
+
+    def step():
+        U.zero_()
+        return s.iterate(u0, U, max_iter=400, tol=TOL)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    for _ in range(steps):
+        rc, it, rel = step()
+        iters += it
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # pass B launches, each solve run for its iteration count with tol = 0
+    X.expdiag_profile_enable(s.h, 1 << X.PROFILE_CLASSES.index("passb"))
+    for _ in range(steps):
+        U.zero_()
+        s.iterate(u0, U, max_iter=it, tol=0.0)
+    ms, cnt, by, tm = X.expdiag_profile_read(s.h)
+    X.expdiag_profile_enable(s.h, 0)
+    pb = X.PROFILE_CLASSES.index("passb")
+    us = 1e3 * ms[pb] / tm[pb]
+    bpl = by[pb] / cnt[pb]
+    out = {
+        "workload": "2D Schroedinger u_t = i Lap u - 2i u (complex state), "
+                    "periodic 256x256, Nt=64, T=1, ETD1, alpha=1e-3, "
+                    "u0 = Gaussian wave packet (width 0.4, wavenumber 5)",
+        "ms_per_solve": 1e3 * wall / steps,
+        "iters_per_solve": it,
+        "us_per_iter": 1e6 * wall / iters,
+        "dof_iters_per_s": inst.dof * iters / wall,
+        "passb": {"avg_us": us, "bytes_per_launch": bpl,
+                  "roofline_hbm": {"bound": "hbm",
+                                   "achieved": round(bpl / (us * 1e-6) / 1e9,
+                                                     1),
+                                   "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                   "frac": round(bpl / (us * 1e-6) / 1e9 /
+                                                 HBM_PEAK_GBS, 4)}},
+        "U": U.cpu().numpy().copy(),
+    }
+    s.close()
+    return out
 
 
 def bench_batched(count):
@@ -539,6 +599,10 @@ def main():
         adv = bench_advection(args.steps, args.warmup)
         U_adv = adv.pop("U")
         line["advection"] = adv
+        _log("schroedinger (complex state)")
+        se = bench_schroedinger(args.steps, args.warmup)
+        U_se = se.pop("U")
+        line["schroedinger"] = se
     if not args.no_batch:
         _log(f"batched: {args.batch} instances")
         line["batched"] = bench_batched(args.batch)
@@ -557,6 +621,9 @@ def main():
             ia = W.advection2d()
             line["advection"]["err_vs_oracle"] = float(O.rel_err(
                 U_adv, O.sequential(O.Setup.from_instance(ia), ia.u0)))
+            isc = W.schroedinger2d()
+            line["schroedinger"]["err_vs_oracle"] = float(O.rel_err(
+                U_se, O.sequential(O.Setup.from_instance(isc), isc.u0)))
     if rank == 0:
         print(json.dumps(line), flush=True)
 

@@ -83,6 +83,14 @@ typedef struct {
  * -a|k|^2 - c - i b.k'; k' is the wavenumber except 0 at an axis's Nyquist
  * index, so real fields stay real); a >= 0, c >= 0, b finite (b[i] is the
  * velocity along axis i; entries past dim are ignored).
+ * Complex state (complex_state = 1, linear problems only): the coefficients
+ * become a + i a_im and c + i c_im (the Schroedinger equation of Sec. 6 has
+ * a = i), and every physical array (u0, U, R, S) holds complex values,
+ * interleaved (re, im) doubles: a field is Ns complex numbers, a window
+ * Nt * Ns.  Nonzero a_im or c_im need complex_state = 1 (the operator no
+ * longer maps real fields to real fields).  GMRES then treats real and
+ * imaginary parts as one real vector (inner product Re(x^H y)).  The server
+ * does not take complex-state requests (EUNSUPPORTED).
  * precision: EXPDIAG_FP64, or EXPDIAG_MIXED (fp32 spatial FFTs and
  * nonlinearity in a bulk phase, fp64 residual and iterate afterwards; the
  * time transform is always fp64).
@@ -93,6 +101,8 @@ typedef struct {
   int precision;
   int gmres_restart;
   double b[3];
+  double a_im, c_im;
+  int complex_state;
 } expdiag_problem;
 
 /* Build a handle: spectral symbols E = exp(dt mu), dt phi1(dt mu),

@@ -110,6 +110,9 @@ struct expdiag_ctx {
   int restart_cap = 0;
   int tvariant = 0;  // time transform: 0 radix FFT, 1 dense MFMA GEMM
   bool cplx = false;  // complex symbols (advection): E, c1, c2 not real
+  // complex state (complex coefficients): physical arrays are complex, the
+  // spectral state is the full spectrum (Nk = Ns, nh = n_last)
+  bool cstate = false;
   bool light = false;  // no plan / graph of its own (batch, server)
 
   // device buffers
@@ -303,6 +306,11 @@ int time_len(const expdiag_ctx* h) {
 // EBDF2 windows take the radix FFT when Nt - 1 is a power of two (2..512)
 // and the dense transform when Nt is one (8..128).
 bool bdf2_fft_ok(int Nt) { return Nt >= 3 && Nt <= 513 && is_pow2(Nt - 1); }
+// Spectral index width the kernels weight inner products by: entries at
+// kl = kappa % nh in {0, nh - 1} count once, the others twice (Parseval on
+// a half spectrum).  A full spectrum (complex state) weights every entry
+// once, which nh = 1 gives (kl is then always 0).
+int parseval_nh(const expdiag_ctx* h) { return h->cstate ? 1 : h->nh; }
 int passb_blocks(expdiag_ctx* h) {
   return h->tvariant == 1 ? dense_blocks(h->Nk)
                           : passb_blocks_nt(time_len(h), h->Nk);
@@ -369,7 +377,7 @@ PassBArgs passb_args(expdiag_ctx* h) {
   a.Wf = h->Wf;
   a.Wi = h->Wi;
   a.Nk = h->Nk;
-  a.nh = h->nh;
+  a.nh = parseval_nh(h);
   a.nonlinear = h->nonlinear ? 1 : 0;
   a.etd2 = h->scheme == EXPDIAG_ETD2 ? 1 : 0;
   a.nblocks = passb_blocks(h);
@@ -490,8 +498,73 @@ int launch_reduce(expdiag_ctx* h, int nblocks) {
 
 // real physical slices [ns][Ns] -> half spectra [ns][Nk].  ROWMODE is
 // ROW_R2C or ROW_NR2C (apply N pointwise first).  Uses h->T as scratch.
+// Complex rows of the last axis, length n_last: dst = scale * FFT_S(src).
+template <int S>
+int launch_row_c2c(expdiag_ctx* h, const cx<double>* src, cx<double>* dst,
+                   long rows, double scale) {
+  const int M = h->n[h->dim - 1];
+  ProfScope ps(h, P_ROW, static_cast<double>(rows) * M * 32);
+  const bool ok = dispatch_pow2<4, 1024>(M, [&](auto Mc) {
+    constexpr int MM = decltype(Mc)::value;
+    using SH = RowShape<MM>;
+    const long blocks = (rows + SH::RPB - 1) / SH::RPB;
+    hipLaunchKernelGGL((row_c2c_kernel<MM, S>), dim3(blocks),
+                       dim3(SH::THREADS), 0, h->stream, src, dst, rows,
+                       scale, h->tw64);
+  });
+  if (!ok) return fail(h, EXPDIAG_EUNSUPPORTED, "row length %d", M);
+  HIPCHK(h, hipGetLastError());
+  return 0;
+}
+
+// Complex-state slices, physical [ns][Ns] complex <-> full spectra
+// [ns][Ns]: C2C transforms along every axis (forward: the last axis first;
+// inverse: the last axis last, scaled by 1/Ns).  Uses h->T as scratch.
+int fwd_slices_c2c(expdiag_ctx* h, const cx<double>* src, cx<double>* dst,
+                   long ns) {
+  const int d = h->dim;
+  const int nl = h->n[d - 1];
+  if (d == 1) return launch_row_c2c<-1>(h, src, dst, ns, 1.0);
+  RCHK(launch_row_c2c<-1>(h, src, h->T, ns * (h->Ns / nl), 1.0));
+  if (d == 2)
+    return launch_col1<double, -1, double, double>(
+        h, h->n[0], make_col(h->T, dst, ns, nl, 1.0, nullptr, -1));
+  RCHK((launch_col1<double, -1, double, double>(
+      h, h->n[1], make_col(h->T, h->T, ns * h->n[0], nl, 1.0, nullptr, -1))));
+  return launch_col1<double, -1, double, double>(
+      h, h->n[0],
+      make_col(h->T, dst, ns, static_cast<long>(h->n[1]) * nl, 1.0, nullptr,
+               -1));
+}
+
+int inv_slices_c2c(expdiag_ctx* h, const cx<double>* src, cx<double>* dst,
+                   long ns) {
+  const int d = h->dim;
+  const int nl = h->n[d - 1];
+  const double sc = 1.0 / static_cast<double>(h->Ns);
+  if (d == 1) return launch_row_c2c<1>(h, src, dst, ns, sc);
+  if (d == 2) {
+    RCHK((launch_col1<double, 1, double, double>(
+        h, h->n[0], make_col(src, h->T, ns, nl, 1.0, nullptr, -1))));
+  } else {
+    RCHK((launch_col1<double, 1, double, double>(
+        h, h->n[0],
+        make_col(src, h->T, ns, static_cast<long>(h->n[1]) * nl, 1.0,
+                 nullptr, -1))));
+    RCHK((launch_col1<double, 1, double, double>(
+        h, h->n[1], make_col(h->T, h->T, ns * h->n[0], nl, 1.0, nullptr,
+                             -1))));
+  }
+  return launch_row_c2c<1>(h, h->T, dst, ns * (h->Ns / nl), sc);
+}
+
 template <int ROWMODE>
 int fwd_slices(expdiag_ctx* h, const double* src, cx<double>* dst, long ns) {
+  if constexpr (ROWMODE == ROW_R2C) {
+    if (h->cstate)
+      return fwd_slices_c2c(h, reinterpret_cast<const cx<double>*>(src), dst,
+                            ns);
+  }
   const int d = h->dim;
   const long nh2 = 2L * h->nh;
   const int nl = h->n[d - 1];
@@ -515,6 +588,8 @@ int fwd_slices(expdiag_ctx* h, const double* src, cx<double>* dst, long ns) {
 // half spectra [ns][Nk] -> real physical slices [ns][Ns] (normalised).
 // `src` may be h->T.
 int inv_slices(expdiag_ctx* h, const cx<double>* src, double* dst, long ns) {
+  if (h->cstate)
+    return inv_slices_c2c(h, src, reinterpret_cast<cx<double>*>(dst), ns);
   const int d = h->dim;
   const long nh2 = 2L * h->nh;
   const int nl = h->n[d - 1];
@@ -1113,8 +1188,10 @@ void symbol_tables(expdiag_ctx* h, std::vector<cx<double>>& E,
   c1.resize(Nk);
   c2.resize(Nk);
   const double* bv = h->p.b;
+  const long double ai = h->p.a_im, ci = h->p.c_im;
   const bool adv = (bv[0] != 0.0) || (d >= 2 && bv[1] != 0.0) ||
-                   (d >= 3 && bv[2] != 0.0);
+                   (d >= 3 && bv[2] != 0.0) || ai != 0.0L || ci != 0.0L;
+  const int nlast = h->n[d - 1];
   if (adv) {
     // axis of each index: (i0, i1, kl) -> the dims present
     const int nl = h->n[d - 1];
@@ -1124,7 +1201,8 @@ void symbol_tables(expdiag_ctx* h, std::vector<cx<double>>& E,
         const long r = i / h->nh;
         const int i1 = d >= 3 ? static_cast<int>(r % outer1) : 0;
         const int i0 = d >= 2 ? static_cast<int>(d >= 3 ? r / outer1 : r) : 0;
-        long double k2 = static_cast<long double>(kl) * kl;
+        // (half spectrum: kl <= n/2, so wn(kl) = kl; full spectrum: all kl)
+        long double k2 = static_cast<long double>(wn(kl, nl)) * wn(kl, nl);
         long double bk = bv[d - 1] * static_cast<long double>(wd(kl, nl));
         if (d >= 2) {
           k2 += static_cast<long double>(wn(i0, n0)) * wn(i0, n0);
@@ -1134,7 +1212,7 @@ void symbol_tables(expdiag_ctx* h, std::vector<cx<double>>& E,
           k2 += static_cast<long double>(wn(i1, n1)) * wn(i1, n1);
           bk += bv[1] * static_cast<long double>(wd(i1, n1));
         }
-        const cld z = dt * cld(-a * k2 - c, -bk);
+        const cld z = dt * cld(-a * k2 - c, -bk - ai * k2 - ci);
         const cld w1 = dt * phi1c(z);
         E[i] = to_cx(std::exp(z));
         if (etd2) {
@@ -1157,7 +1235,8 @@ void symbol_tables(expdiag_ctx* h, std::vector<cx<double>>& E,
     for (int i1 = 0; i1 < outer1; ++i1) {
       const long a1 = d >= 3 ? static_cast<long>(wn(i1, n1)) * wn(i1, n1) : 0;
       for (int kl = 0; kl < h->nh; ++kl) {
-        const long v = a0 + a1 + static_cast<long>(kl) * kl;
+        const long wl = wn(kl, nlast);
+        const long v = a0 + a1 + wl * wl;
         k2[idx++] = static_cast<int>(v);
         k2max = std::max(k2max, v);
       }
@@ -1469,8 +1548,18 @@ int validate_params(int Nt, double dt, double alpha, int scheme,
       !std::isfinite(p->n2) || !std::isfinite(p->n3))
     return fail(nullptr, EXPDIAG_EINVAL, "a, c must be finite and >= 0");
   if (!std::isfinite(p->b[0]) || !std::isfinite(p->b[1]) ||
-      !std::isfinite(p->b[2]))
-    return fail(nullptr, EXPDIAG_EINVAL, "advection velocity must be finite");
+      !std::isfinite(p->b[2]) || !std::isfinite(p->a_im) ||
+      !std::isfinite(p->c_im))
+    return fail(nullptr, EXPDIAG_EINVAL,
+                "advection velocity and imaginary parts must be finite");
+  if (p->complex_state != 0 && p->complex_state != 1)
+    return fail(nullptr, EXPDIAG_EINVAL, "complex_state must be 0 or 1");
+  if ((p->a_im != 0.0 || p->c_im != 0.0) && p->complex_state == 0)
+    return fail(nullptr, EXPDIAG_EINVAL,
+                "complex coefficients need complex_state = 1");
+  if (p->complex_state == 1 && (p->n1 != 0.0 || p->n2 != 0.0 || p->n3 != 0.0))
+    return fail(nullptr, EXPDIAG_EUNSUPPORTED,
+                "a complex state is for linear problems");
   if (p->precision != EXPDIAG_FP64 && p->precision != EXPDIAG_MIXED)
     return fail(nullptr, EXPDIAG_EINVAL, "unknown precision %d",
                 p->precision);
@@ -1484,6 +1573,8 @@ int validate_params(int Nt, double dt, double alpha, int scheme,
 int reinit_params(expdiag_ctx* h, double dt, double alpha, int scheme,
                   const expdiag_problem* p) {
   RCHK(validate_params(h->Nt, dt, alpha, scheme, p));
+  if ((p->complex_state == 1) != h->cstate)
+    return fail(h, EXPDIAG_EINVAL, "complex_state differs from the handle's");
   h->dt = dt;
   h->alpha = alpha;
   if (scheme == EXPDIAG_EBDF2)
@@ -1510,6 +1601,11 @@ int create_impl(const expdiag_grid* g, int Nt, double dt, double alpha,
   if (gc != 0)
     return fail(nullptr, gc, "grid: dim 1..3, n even, power of two, 4..1024");
   RCHK(validate_params(Nt, dt, alpha, scheme, p));
+  if (p->complex_state == 1) {
+    // the full spectrum: every last-axis index
+    s.nh = g->n[g->dim - 1];
+    s.Nk = s.Ns;
+  }
 
   expdiag_ctx* h = new (std::nothrow) expdiag_ctx();
   if (h == nullptr) return fail(nullptr, EXPDIAG_ENOMEM, "host allocation");
@@ -1526,6 +1622,7 @@ int create_impl(const expdiag_grid* g, int Nt, double dt, double alpha,
   h->nh = static_cast<int>(s.nh);
   h->nonlinear = (p->n1 != 0.0 || p->n2 != 0.0 || p->n3 != 0.0);
   h->mixed = p->precision == EXPDIAG_MIXED;
+  h->cstate = p->complex_state == 1;
   h->restart_cap = p->gmres_restart;
   if (scheme == EXPDIAG_EBDF2) h->tvariant = bdf2_fft_ok(Nt) ? 0 : 1;
 

@@ -280,6 +280,39 @@ __device__ __forceinline__ void row_body(const RowJob& jb, long lb,
   row_forward<T, M, TO>(jb, row, valid, t, v, lrow, wst, wk);
 }
 
+// Complex rows of length M (the last axis of a complex state): row r of
+// `out` (r * M complex elements in) = scale * FFT_S(row r of `in`); in
+// place allowed (a block reads its rows before it writes).  Rows past
+// nrows read the last row and store nothing.
+template <int M, int S>
+__global__ void __launch_bounds__(RowShape<M>::THREADS)
+    row_c2c_kernel(const cx<double>* __restrict__ in, cx<double>* out,
+                   long nrows, double scale,
+                   const cx<double>* __restrict__ tw) {
+  using SH = RowShape<M>;
+  constexpr int R = SH::R;
+  constexpr int TPR = SH::TPR;
+  __shared__ cx<double> lds[SH::RPB * SH::LS];
+  const int rl = threadIdx.x / TPR;
+  const int t = threadIdx.x % TPR;
+  const long row = static_cast<long>(blockIdx.x) * SH::RPB + rl;
+  const bool valid = row < nrows;
+  const cx<double>* src = in + (valid ? row : nrows - 1) * M;
+  cx<double> v[R];
+#pragma unroll
+  for (int s = 0; s < R; ++s) v[s] = gld(src, t + s * TPR);
+  constexpr int NST = fft_stage_count<M, R>();
+  cx<double> wst[NST > 1 ? NST : 2];
+  fft_stage_twiddles<double, M, R>(wst, t, tw);
+  pin_loaded(wst);
+  fft_stages<double, M, R, S, 1, true, false, SH::WAVE, 0, true>(
+      v, mk(1.0, 0.0), lds + rl * SH::LS, 1, t, wst);
+  if (!valid) return;
+  cx<double>* dst = out + row * M;
+#pragma unroll
+  for (int s = 0; s < R; ++s) gst(dst, t + s * TPR, v[s] * scale);
+}
+
 // Job-table launch of one pass-A stage for instances in either precision
 // phase: jobs[2i] is instance i's fp32 job (mixed-precision bulk phase),
 // jobs[2i + 1] its fp64 job, and the instance's control block picks one, so

@@ -50,7 +50,9 @@ class Problem(ctypes.Structure):
                 ("n1", ctypes.c_double), ("n2", ctypes.c_double),
                 ("n3", ctypes.c_double), ("precision", ctypes.c_int),
                 ("gmres_restart", ctypes.c_int),
-                ("b", ctypes.c_double * 3)]
+                ("b", ctypes.c_double * 3),
+                ("a_im", ctypes.c_double), ("c_im", ctypes.c_double),
+                ("complex_state", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):
@@ -146,11 +148,16 @@ def make_grid(shape: Sequence[int]) -> Grid:
 
 
 def make_problem(a, c=0.0, n1=0.0, n2=0.0, n3=0.0, precision=EXPDIAG_FP64,
-                 gmres_restart=0, b=(0.0, 0.0, 0.0)) -> Problem:
+                 gmres_restart=0, b=(0.0, 0.0, 0.0), a_im=0.0, c_im=0.0,
+                 complex_state=None) -> Problem:
+    """complex_state defaults to 1 when a_im or c_im is nonzero."""
     bb = tuple(float(v) for v in b) + (0.0,) * (3 - len(b))
+    if complex_state is None:
+        complex_state = 1 if (a_im != 0.0 or c_im != 0.0) else 0
     return Problem(float(a), float(c), float(n1), float(n2), float(n3),
                    int(precision), int(gmres_restart),
-                   (ctypes.c_double * 3)(*bb[:3]))
+                   (ctypes.c_double * 3)(*bb[:3]), float(a_im), float(c_im),
+                   int(complex_state))
 
 
 def _ptr(t, numel=None, name="array"):
@@ -159,8 +166,10 @@ def _ptr(t, numel=None, name="array"):
     import torch
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch tensor")
-    if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
-        raise ValueError(f"{name} must be a contiguous float64 GPU tensor")
+    if t.dtype not in (torch.float64, torch.complex128) or \
+            not t.is_contiguous() or not t.is_cuda:
+        raise ValueError(f"{name} must be a contiguous float64 or "
+                         "complex128 GPU tensor")
     if numel is not None and t.numel() != numel:
         raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
     return ctypes.c_void_p(t.data_ptr())
@@ -274,11 +283,13 @@ class Solver:
 
     def __init__(self, shape, Nt, dt, alpha, scheme=EXPDIAG_ETD1, a=1.0,
                  c=0.0, n1=0.0, n2=0.0, n3=0.0, precision=EXPDIAG_FP64,
-                 gmres_restart=0, stream=None, b=(0.0, 0.0, 0.0)):
+                 gmres_restart=0, stream=None, b=(0.0, 0.0, 0.0), a_im=0.0,
+                 c_im=0.0, complex_state=None):
         self.shape = tuple(int(v) for v in shape)
         self.Nt = int(Nt)
         self.problem = make_problem(a, c, n1, n2, n3, precision,
-                                    gmres_restart, b)
+                                    gmres_restart, b, a_im, c_im,
+                                    complex_state)
         self.h = expdiag_create(self.shape, Nt, dt, alpha, scheme,
                                 self.problem, stream)
 
@@ -288,7 +299,9 @@ class Solver:
         return cls(inst.shape, inst.Nt, inst.dt, inst.alpha, inst.scheme,
                    inst.a, inst.c, inst.n1, inst.n2, inst.n3,
                    inst.precision if precision is None else precision,
-                   gmres_restart, stream, getattr(inst, "b", (0.0, 0.0, 0.0)))
+                   gmres_restart, stream, getattr(inst, "b", (0.0, 0.0, 0.0)),
+                   getattr(inst, "a_im", 0.0), getattr(inst, "c_im", 0.0),
+                   1 if getattr(inst, "cstate", False) else None)
 
     def close(self):
         if self.h is not None:

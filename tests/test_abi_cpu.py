@@ -69,6 +69,15 @@ def _create(lib, shape, Nt, dt, alpha, scheme, prob):
      X.EXPDIAG_EUNSUPPORTED),
     ((64,), 65, 0.1, 1e-2, X.EXPDIAG_ETD1, X.make_problem(1.0),
      X.EXPDIAG_EUNSUPPORTED),
+    # complex coefficients need a complex state; a complex state is linear
+    ((64,), 8, 0.1, 1e-2, 1, X.make_problem(0.0, a_im=1.0, complex_state=0),
+     X.EXPDIAG_EINVAL),
+    ((64,), 8, 0.1, 1e-2, 1, X.make_problem(1.0, complex_state=2),
+     X.EXPDIAG_EINVAL),
+    ((64,), 8, 0.1, 1e-2, 1, X.make_problem(1.0, n1=1.0, complex_state=1),
+     X.EXPDIAG_EUNSUPPORTED),
+    ((64,), 8, 0.1, 1e-2, 1, X.make_problem(1.0, b=(float("nan"),)),
+     X.EXPDIAG_EINVAL),
     ((64,), 8, 0.1, 1e-2, 1, X.make_problem(-1.0), X.EXPDIAG_EINVAL),
     ((64,), 8, 0.1, 1e-2, 1, X.make_problem(1.0, c=-0.1), X.EXPDIAG_EINVAL),
     ((64,), 8, 0.1, 1e-2, 1, X.make_problem(1.0, precision=7),

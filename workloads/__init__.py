@@ -16,6 +16,9 @@ Workloads (all on periodic [0, 2*pi)^d):
                reaction (u_t = eps^2 Lap u), second-order exponential BDF.
   advection2d  allen_cahn2d with an advection term -b.grad u, b = (2, 1)
                (complex symbol, real state).
+  schroedinger2d  u_t = i Lap u - 2i u (complex state), n=256, Nt=64, T=1,
+               alpha=1e-3, u0 = Gaussian wave packet (width 0.4,
+               wavenumber 5) centred in the box.
   rd2d         2D reaction-diffusion u_t = 0.1 Lap u + u - u^3, n=512,
                Nt=128, T=1, ETD2; u0 = sum of 32 periodic Gaussians with
                amplitude U[-1,1], width U[0.1,0.5], centre U[0,2pi)^2.
@@ -35,7 +38,7 @@ import numpy as np
 
 __all__ = [
     "Instance", "grid_coords", "heat1d", "allen_cahn2d", "rd2d", "batch",
-    "diffusion2d_ebdf2", "advection2d",
+    "diffusion2d_ebdf2", "advection2d", "schroedinger2d", "wave_packet",
     "served_stream", "uniform_field", "gaussians_field", "low_mode_field",
     "scaled",
 ]
@@ -63,6 +66,9 @@ class Instance:
     precision: int = 0
     u0: Optional[np.ndarray] = None
     b: tuple = (0.0, 0.0, 0.0)
+    a_im: float = 0.0
+    c_im: float = 0.0
+    cstate: bool = False
 
     @property
     def dt(self) -> float:
@@ -158,6 +164,27 @@ def advection2d(seed: int = 0, n: int = 256, Nt: int = 64, T: float = 2.0,
                     n1=1.0 if nonlinear else 0.0,
                     n3=-1.0 if nonlinear else 0.0,
                     u0=uniform_field(rng, 2, n), b=tuple(b) + (0.0,))
+
+
+def wave_packet(dim: int, n: int, k0: float = 5.0, width: float = 0.4,
+                centre: float = math.pi) -> np.ndarray:
+    """Gaussian packet exp(-|x - centre|^2 / (2 width^2)) e^{-i k0 (x_0 -
+    centre)} (complex128), periodic box, no randomness."""
+    g = grid_coords(dim, n)
+    r2 = sum((gi - centre) ** 2 for gi in g)
+    return (np.exp(-r2 / (2.0 * width * width))
+            * np.exp(-1j * k0 * (g[0] - centre))).astype(np.complex128)
+
+
+def schroedinger2d(n: int = 256, Nt: int = 64, T: float = 1.0,
+                   alpha: float = 1e-3, c_im: float = 2.0,
+                   scheme: int = 1) -> Instance:
+    """u_t = i Lap u - i c_im u (a = i, the Schroedinger equation of the
+    paper's Sec. 6) on the periodic box, complex state, from a Gaussian wave
+    packet (width 0.4, wavenumber 5)."""
+    return Instance("schroedinger2d", 2, n, Nt, T, alpha, a=0.0,
+                    scheme=scheme, u0=wave_packet(2, n), a_im=1.0,
+                    c_im=c_im, cstate=True)
 
 
 def rd2d(seed: int = 0, n: int = 512, Nt: int = 128, T: float = 1.0,
