@@ -131,7 +131,8 @@ int expdiag_create(const expdiag_grid* g, int Nt, double dt, double alpha,
 /* Release a handle and its workspace (NULL is accepted). */
 int expdiag_destroy(expdiag_t h);
 
-/* Replace the stream the handle enqueues on. */
+/* Replace the stream the handle enqueues on (waits for the work already
+ * enqueued on the old one). */
 int expdiag_set_stream(expdiag_t h, void* hip_stream);
 
 /* Device bytes a handle with these parameters allocates (for admission

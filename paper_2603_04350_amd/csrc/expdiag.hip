@@ -1166,42 +1166,56 @@ void parallel_ranges(long n, F&& f) {
 }
 
 // Per-kappa tables E = e^{dt mu}, c1, c2 (eq. etd1_update / etd2_update
-// weights), mu = -a |k|^2 - c - i b.k'.  Without advection they depend on
-// kappa only through the integer |k|^2, so each value of |k|^2 that occurs
-// is evaluated once (real, long double) and then gathered; with advection
-// every kappa is evaluated (complex long double).  k' is the derivative
-// wavenumber: k, except 0 at the Nyquist index of its axis (so that
-// b.grad maps real fields to real fields).  Host threads: up to eight.
-void symbol_tables(expdiag_ctx* h, std::vector<cx<double>>& E,
-                   std::vector<cx<double>>& c1, std::vector<cx<double>>& c2) {
+// weights), mu = -a |k|^2 - c - i b.k' (- i a_im |k|^2 - i c_im for complex
+// coefficients).  k' is the derivative wavenumber: k, except 0 at the
+// Nyquist index of its axis (so that b.grad maps real fields to real
+// fields).  A kappa index i is (i0, i1, kl) of [n0][n1][nh] (the dims
+// present), kl the last-axis index (half spectrum: 0..n/2; full spectrum
+// of a complex state: 0..n-1).
+//
+// Without advection or complex coefficients the tables depend on kappa
+// only through the integer |k|^2: each value that occurs (a sum of one
+// square per axis) is evaluated once, in long double, and the device
+// gathers the per-kappa tables (symbol_gather_kernel), so the host work
+// does not grow with the number of modes.  Otherwise every kappa is
+// evaluated on the host (complex long double).  Host threads: up to eight.
+struct SymbolTables {
+  bool per_kappa = false;                 // E, c1, c2 below, per kappa
+  std::vector<cx<double>> E, c1, c2;
+  std::vector<int> slot;                  // |k|^2 -> value index
+  std::vector<double> vals;               // [3][nv]: E, c1, c2 per |k|^2
+};
+
+bool complex_symbols(const expdiag_ctx* h) {
+  const double* bv = h->p.b;
+  const int d = h->dim;
+  return (bv[0] != 0.0) || (d >= 2 && bv[1] != 0.0) ||
+         (d >= 3 && bv[2] != 0.0) || h->p.a_im != 0.0 || h->p.c_im != 0.0;
+}
+
+void symbol_tables(expdiag_ctx* h, SymbolTables& st) {
   const int d = h->dim;
   const long Nk = h->Nk;
   const int n0 = h->n[0], n1 = d >= 2 ? h->n[1] : 1;
-  const int outer0 = d >= 2 ? n0 : 1;
   const int outer1 = d >= 3 ? n1 : 1;
+  const int nl = h->n[d - 1];
   auto wn = [](int j, int n) { return j <= n / 2 ? j : j - n; };
-  // derivative wavenumber of index j on an axis of n points
   auto wd = [](int j, int n) { return 2 * j == n ? 0 : (j < n / 2 ? j : j - n); };
   const long double a = h->p.a, c = h->p.c, dt = h->dt;
-  const bool etd2 = h->scheme == EXPDIAG_ETD2;
-  E.resize(Nk);
-  c1.resize(Nk);
-  c2.resize(Nk);
-  const double* bv = h->p.b;
   const long double ai = h->p.a_im, ci = h->p.c_im;
-  const bool adv = (bv[0] != 0.0) || (d >= 2 && bv[1] != 0.0) ||
-                   (d >= 3 && bv[2] != 0.0) || ai != 0.0L || ci != 0.0L;
-  const int nlast = h->n[d - 1];
-  if (adv) {
-    // axis of each index: (i0, i1, kl) -> the dims present
-    const int nl = h->n[d - 1];
+  const bool etd2 = h->scheme == EXPDIAG_ETD2;
+  const double* bv = h->p.b;
+  if (complex_symbols(h)) {
+    st.per_kappa = true;
+    st.E.resize(Nk);
+    st.c1.resize(Nk);
+    st.c2.resize(Nk);
     auto eval = [&](long lo, long hi) {
       for (long i = lo; i < hi; ++i) {
         const int kl = static_cast<int>(i % h->nh);
         const long r = i / h->nh;
         const int i1 = d >= 3 ? static_cast<int>(r % outer1) : 0;
         const int i0 = d >= 2 ? static_cast<int>(d >= 3 ? r / outer1 : r) : 0;
-        // (half spectrum: kl <= n/2, so wn(kl) = kl; full spectrum: all kl)
         long double k2 = static_cast<long double>(wn(kl, nl)) * wn(kl, nl);
         long double bk = bv[d - 1] * static_cast<long double>(wd(kl, nl));
         if (d >= 2) {
@@ -1214,44 +1228,41 @@ void symbol_tables(expdiag_ctx* h, std::vector<cx<double>>& E,
         }
         const cld z = dt * cld(-a * k2 - c, -bk - ai * k2 - ci);
         const cld w1 = dt * phi1c(z);
-        E[i] = to_cx(std::exp(z));
+        st.E[i] = to_cx(std::exp(z));
         if (etd2) {
           const cld w2 = dt * phi2c(z);
-          c1[i] = to_cx(w1 + w2);
-          c2[i] = to_cx(-w2);
+          st.c1[i] = to_cx(w1 + w2);
+          st.c2[i] = to_cx(-w2);
         } else {
-          c1[i] = to_cx(w1);
-          c2[i] = mk(0.0, 0.0);
+          st.c1[i] = to_cx(w1);
+          st.c2[i] = mk(0.0, 0.0);
         }
       }
     };
     parallel_ranges(Nk, eval);
     return;
   }
-  std::vector<int> k2(Nk);
-  long idx = 0, k2max = 0;
-  for (int i0 = 0; i0 < outer0; ++i0) {
-    const long a0 = d >= 2 ? static_cast<long>(wn(i0, n0)) * wn(i0, n0) : 0;
-    for (int i1 = 0; i1 < outer1; ++i1) {
-      const long a1 = d >= 3 ? static_cast<long>(wn(i1, n1)) * wn(i1, n1) : 0;
-      for (int kl = 0; kl < h->nh; ++kl) {
-        const long wl = wn(kl, nlast);
-        const long v = a0 + a1 + wl * wl;
-        k2[idx++] = static_cast<int>(v);
-        k2max = std::max(k2max, v);
-      }
-    }
-  }
-  std::vector<int> slot(k2max + 1, -1);
-  std::vector<int> vals;
-  for (long i = 0; i < Nk; ++i) {
-    if (slot[k2[i]] < 0) {
-      slot[k2[i]] = static_cast<int>(vals.size());
-      vals.push_back(k2[i]);
+  // |k|^2 = s0 + s1 + s2, one square j^2 (j = 0..n/2) per axis present
+  const long h0 = d >= 2 ? n0 / 2 : 0, h1 = d >= 3 ? n1 / 2 : 0;
+  const long hl = nl / 2;
+  const long k2max = h0 * h0 + h1 * h1 + hl * hl;
+  std::vector<char> present(k2max + 1, 0);
+  for (long j0 = 0; j0 <= h0; ++j0)
+    for (long j1 = 0; j1 <= h1; ++j1)
+      for (long jl = 0; jl <= hl; ++jl) present[j0 * j0 + j1 * j1 + jl * jl] = 1;
+  st.slot.assign(k2max + 1, -1);
+  std::vector<long> vals;
+  for (long v = 0; v <= k2max; ++v) {
+    if (present[v]) {
+      st.slot[v] = static_cast<int>(vals.size());
+      vals.push_back(v);
     }
   }
   const long nv = static_cast<long>(vals.size());
-  std::vector<double> tE(nv), t1(nv), t2(nv);
+  st.vals.assign(3 * nv, 0.0);
+  double* tE = st.vals.data();
+  double* t1 = tE + nv;
+  double* t2 = t1 + nv;
   auto eval = [&](long lo, long hi) {
     for (long i = lo; i < hi; ++i) {
       const long double z = dt * (-a * static_cast<long double>(vals[i]) - c);
@@ -1268,18 +1279,43 @@ void symbol_tables(expdiag_ctx* h, std::vector<cx<double>>& E,
     }
   };
   parallel_ranges(nv, eval);
-  for (long i = 0; i < Nk; ++i) {
-    const int j = slot[k2[i]];
-    E[i] = mk(tE[j], 0.0);
-    c1[i] = mk(t1[j], 0.0);
-    c2[i] = mk(t2[j], 0.0);
+}
+
+// Per-kappa real tables from the per-|k|^2 values: kappa -> (i0, i1, kl)
+// -> |k|^2 -> slot -> value (the same integer |k|^2 the host enumerated).
+__global__ void symbol_gather_kernel(cx<double>* __restrict__ E,
+                                     cx<double>* __restrict__ c1,
+                                     cx<double>* __restrict__ c2, long Nk,
+                                     int dim, int n0, int n1, int nl, int nh,
+                                     const int* __restrict__ slot,
+                                     const double* __restrict__ vals,
+                                     int nv) {
+  const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= Nk) return;
+  const int kl = static_cast<int>(i % nh);
+  const long r = i / nh;
+  const int i1 = dim >= 3 ? static_cast<int>(r % n1) : 0;
+  const int i0 = dim >= 2 ? static_cast<int>(dim >= 3 ? r / n1 : r) : 0;
+  const long wl = kl <= nl / 2 ? kl : kl - nl;
+  long k2 = wl * wl;
+  if (dim >= 2) {
+    const long w0 = i0 <= n0 / 2 ? i0 : i0 - n0;
+    k2 += w0 * w0;
   }
+  if (dim >= 3) {
+    const long w1 = i1 <= n1 / 2 ? i1 : i1 - n1;
+    k2 += w1 * w1;
+  }
+  const int j = slot[k2];
+  E[i] = mk(vals[j], 0.0);
+  c1[i] = mk(vals[nv + j], 0.0);
+  c2[i] = mk(vals[2 * nv + j], 0.0);
 }
 
 int build_tables(expdiag_ctx* h) {
   const long Nk = h->Nk;
-  std::vector<cx<double>> E, c1, c2;
-  symbol_tables(h, E, c1, c2);
+  SymbolTables sym;
+  symbol_tables(h, sym);
   const int Nt = h->Nt;
   // The transform runs over N time points: Nt, or for EBDF2 the Nt - 1
   // unknown slices 2..Nt, which sit at row offset o = 1 of a window.
@@ -1333,13 +1369,60 @@ int build_tables(expdiag_ctx* h) {
     HIPCHK(h, hipMemcpy(h->Wi, wi.data(), wi.size() * sizeof(double),
                         hipMemcpyHostToDevice));
   }
-  h->cplx = false;
-  for (long i = 0; i < Nk && !h->cplx; ++i)
-    h->cplx = E[i].y != 0.0 || c1[i].y != 0.0 || c2[i].y != 0.0;
+  h->cplx = complex_symbols(h);
   const TwiddleTables& tw = twiddle_tables();
-  HIPCHK(h, hipMemcpy(h->E, E.data(), Nk * sizeof(cx<double>), hipMemcpyHostToDevice));
-  HIPCHK(h, hipMemcpy(h->c1, c1.data(), Nk * sizeof(cx<double>), hipMemcpyHostToDevice));
-  HIPCHK(h, hipMemcpy(h->c2, c2.data(), Nk * sizeof(cx<double>), hipMemcpyHostToDevice));
+  // the per-|k|^2 values and slots are staged in the handle's scratch T
+  // (idle while tables are built) and gathered on the handle's stream
+  const size_t slot_bytes =
+      ((sym.slot.size() * sizeof(int) + 15) / 16) * 16;
+  const size_t stage_bytes = slot_bytes + sym.vals.size() * sizeof(double);
+  const size_t t_bytes = static_cast<size_t>(h->Nt) * Nk * sizeof(cx<double>);
+  if (!sym.per_kappa && stage_bytes > t_bytes) {
+    // (only grids too small for the staging area) gather on the host
+    const long nv = static_cast<long>(sym.vals.size() / 3);
+    sym.E.resize(Nk);
+    sym.c1.resize(Nk);
+    sym.c2.resize(Nk);
+    const int d = h->dim, n0 = h->n[0], n1 = d >= 2 ? h->n[1] : 1;
+    const int nl = h->n[d - 1];
+    auto wn = [](long j, long n) { return j <= n / 2 ? j : j - n; };
+    for (long i = 0; i < Nk; ++i) {
+      const long kl = i % h->nh, r = i / h->nh;
+      const long i1 = d >= 3 ? r % n1 : 0;
+      const long i0 = d >= 2 ? (d >= 3 ? r / n1 : r) : 0;
+      long k2 = wn(kl, nl) * wn(kl, nl);
+      if (d >= 2) k2 += wn(i0, n0) * wn(i0, n0);
+      if (d >= 3) k2 += wn(i1, n1) * wn(i1, n1);
+      const int j = sym.slot[k2];
+      sym.E[i] = mk(sym.vals[j], 0.0);
+      sym.c1[i] = mk(sym.vals[nv + j], 0.0);
+      sym.c2[i] = mk(sym.vals[2 * nv + j], 0.0);
+    }
+    sym.per_kappa = true;
+  }
+  if (sym.per_kappa) {
+    HIPCHK(h, hipMemcpy(h->E, sym.E.data(), Nk * sizeof(cx<double>),
+                        hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(h->c1, sym.c1.data(), Nk * sizeof(cx<double>),
+                        hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(h->c2, sym.c2.data(), Nk * sizeof(cx<double>),
+                        hipMemcpyHostToDevice));
+  } else {
+    char* stage = reinterpret_cast<char*>(h->T);
+    HIPCHK(h, hipMemcpy(stage, sym.slot.data(), sym.slot.size() * sizeof(int),
+                        hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(stage + slot_bytes, sym.vals.data(),
+                        sym.vals.size() * sizeof(double),
+                        hipMemcpyHostToDevice));
+    const int d = h->dim;
+    hipLaunchKernelGGL(symbol_gather_kernel, dim3((Nk + 255) / 256),
+                       dim3(256), 0, h->stream, h->E, h->c1, h->c2, Nk, d,
+                       h->n[0], d >= 2 ? h->n[1] : 1, h->n[d - 1], h->nh,
+                       reinterpret_cast<const int*>(stage),
+                       reinterpret_cast<const double*>(stage + slot_bytes),
+                       static_cast<int>(sym.vals.size() / 3));
+    HIPCHK(h, hipGetLastError());
+  }
   HIPCHK(h, hipMemcpy(h->gam, gam.data(), Nt * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->igam, igam.data(), Nt * sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(h, hipMemcpy(h->lam, lam.data(), Nt * sizeof(cx<double>), hipMemcpyHostToDevice));
@@ -1735,6 +1818,9 @@ int expdiag_destroy(expdiag_t h) {
 
 int expdiag_set_stream(expdiag_t h, void* hip_stream) {
   if (h == nullptr) return EXPDIAG_EINVAL;
+  // work already enqueued on the old stream (table gathers, transforms)
+  // finishes before the new stream may touch the same buffers
+  HIPCHK(h, hipStreamSynchronize(h->stream));
   h->stream = static_cast<hipStream_t>(hip_stream);
   return EXPDIAG_OK;
 }
