@@ -38,6 +38,13 @@ Readings taken where the paper is silent (also listed in the design doc):
     cstate=True) keeps every field complex and takes no real part.  GMRES
     then runs on the real and imaginary parts as one real vector (inner
     product Re(x^H y)).
+  * IF1 (scheme 4, Sec. 5, eq. fully_discrete_nonlinear): u_n = A u_{n-1}
+    + dt N(u_n).  The iteration is the residual-correction fixed point with
+    the preconditioner Q_alpha - sigma I, sigma = dt times a scalar Jacobian
+    (if1_sigma): one inexact Newton step of eq. newton_2 per Exp-ParaDiag
+    iteration, with the averaged Jacobian reduced to its space-time mean so
+    that step (b) stays pointwise; sigma = 0 is the lagged iteration of eq.
+    disc_imextype_scheme.
   * EBDF2 (scheme 3, Sec. 4, linear problems only): the starting value is
     u_1 = A u_0, the exact exponential step (the paper leaves u_1 open).
     Space-time arrays still hold u_1..u_Nt; the unknown of the paper's
@@ -64,9 +71,12 @@ __all__ = [
     "EBDF2", "ebdf2_tables", "sequential_ebdf2", "residual_ebdf2",
     "r_apply_ebdf2", "ralpha_apply_ebdf2", "precond_apply_ebdf2",
     "gmres_solve_ebdf2", "dense_operators_ebdf2",
+    "IF1", "sequential_if1", "residual_if1", "precond_apply_if1",
+    "if1_sigma", "dense_newton_if1", "outer_iteration_if1",
 ]
 
 EBDF2 = 3  # scheme code of the second-order exponential BDF (Sec. 4)
+IF1 = 4    # scheme code of the implicit integrating-factor scheme (Sec. 5)
 
 
 # ---------------------------------------------------------------------------
@@ -132,6 +142,7 @@ class Setup:
     a_im: float = 0.0
     c_im: float = 0.0
     cstate: bool = False
+    jac: int = 1            # IF1 preconditioner shift: see if1_sigma
     mu: np.ndarray = field(init=False, repr=False)
     E: np.ndarray = field(init=False, repr=False)
     w1: np.ndarray = field(init=False, repr=False)
@@ -224,6 +235,8 @@ def sequential(st: Setup, u0):
     """
     if st.scheme == EBDF2:
         return sequential_ebdf2(st, u0)
+    if st.scheme == IF1:
+        return sequential_if1(st, u0)
     U = np.empty((st.Nt,) + u0.shape, dtype=st.dtype)
     prev2, prev = u0, u0
     for j in range(st.Nt):
@@ -342,9 +355,17 @@ def fixed_point(st: Setup, u0, U0=None, max_iter=200, tol=1e-11, ref=None,
         else U0.copy()
     hist, iterates = [], []
     bdf2 = st.scheme == EBDF2
+    if1 = st.scheme == IF1
     for k in range(max_iter):
-        R = residual_ebdf2(st, u0, U) if bdf2 else residual(st, u0, U)
-        S = precond_apply_ebdf2(st, R) if bdf2 else precond_apply(st, R)
+        if bdf2:
+            R = residual_ebdf2(st, u0, U)
+            S = precond_apply_ebdf2(st, R)
+        elif if1:
+            R = residual_if1(st, u0, U)
+            S = precond_apply_if1(st, R, if1_sigma(st, u0, U, k))
+        else:
+            R = residual(st, u0, U)
+            S = precond_apply(st, R)
         U = U + S
         upd = np.linalg.norm(S) / max(np.linalg.norm(U), 1e-300)
         err = rel_err(U, ref) if ref is not None else float("nan")
@@ -719,3 +740,100 @@ def dense_operators_ebdf2(st: Setup):
         "R": I - 4.0 / 3.0 * np.kron(C0, A) + 1.0 / 3.0 * np.kron(C1, B),
         "Ra": I - 4.0 / 3.0 * np.kron(C0a, A) + 1.0 / 3.0 * np.kron(C1a, B),
     }
+
+
+# ---------------------------------------------------------------------------
+# IF1: the implicit integrating-factor scheme of Sec. 5
+# ---------------------------------------------------------------------------
+def sequential_if1(st: Setup, u0, tol=1e-15, max_newton=60):
+    """u_1..u_Nt of eq. fully_discrete_nonlinear,
+    u_n = A u_{n-1} + dt N(u_n): N acts pointwise, so each step is one
+    scalar equation u - dt N(u) = (A u_{n-1})(x) per grid point, solved by
+    Newton's method from u = (A u_{n-1})(x) to round-off."""
+    U = np.empty((st.Nt,) + u0.shape, dtype=st.dtype)
+    prev = u0
+    for n in range(st.Nt):
+        rhs = st.A(prev)
+        u = rhs.copy()
+        for _ in range(max_newton):
+            du = (u - st.dt * st.N(u) - rhs) / (1.0 - st.dt * st.dN(u))
+            u = u - du
+            if np.max(np.abs(du)) <= tol * max(1.0, np.max(np.abs(u))):
+                break
+        U[n] = u
+        prev = u
+    return U
+
+
+def residual_if1(st: Setup, u0, U):
+    """R(U) = f + dt N_0(U) - Q U (the all-at-once form of eq.
+    fully_discrete_nonlinear): slice n is A u_{n-1} + dt N(u_n) - u_n."""
+    P1 = _shift(st, U, u0)
+    return st.A(P1) + st.dt * st.N(U) - U
+
+
+def if1_sigma(st: Setup, u0, U, k):
+    """Scalar Jacobian shift of the IF1 preconditioner Q_alpha - sigma I.
+    jac = 0: sigma = 0, the lagged iteration of eq. disc_imextype_scheme;
+    jac = 1: dt times the space-time mean of N'(U^k) (the averaged Jacobian
+    of eq. newton_2, averaged over space as well), from u_0 at the first
+    iteration; jac = 2: dt times the spatial mean of N'(u_0) (the
+    Jacobian-at-u_0 variant of Sec. 5, averaged over space)."""
+    if st.jac == 0:
+        return 0.0
+    if st.jac == 2 or k == 0:
+        return st.dt * float(np.mean(st.dN(u0)).real)
+    return st.dt * float(np.mean(st.dN(U)).real)
+
+
+def precond_apply_if1(st: Setup, R, sigma):
+    """(Q_alpha - sigma I)^{-1} R by the steps of eq.
+    exp_ParaDiag_steps_newton with the averaged Jacobian reduced to the
+    scalar sigma = dt nbar, so that step (b) stays pointwise:
+    S_q,m = (I - lambda_{0,m} A - sigma)^{-1} S_p,m."""
+    g = st.gamma.reshape((st.Nt,) + (1,) * st.dim)
+    Sa = time_dft(g * R)
+    Sb = np.empty_like(Sa)
+    for m in range(st.Nt):
+        Sb[m] = st.spectral_apply(Sa[m], 1.0 / (1.0 - st.lam[m] * st.E - sigma))
+    return st._out(time_idft(Sb) / g)
+
+
+def dense_newton_if1(st: Setup, u0, tol=1e-14, max_iter=50, D=None):
+    """The all-at-once IF1 system (I - C_0 (x) A) U - dt N_0(U) = f by dense
+    Newton with LU on the assembled Jacobian."""
+    D = D or dense_operators(st)
+    Ns, Nt = u0.size, st.Nt
+    f = np.zeros(Nt * Ns)
+    f[:Ns] = D["A"] @ u0.ravel()
+    U = np.zeros(Nt * Ns)
+    for _ in range(max_iter):
+        R = D["Q"] @ U - st.dt * st.N(U) - f
+        if np.linalg.norm(R) <= tol * max(1.0, np.linalg.norm(U)):
+            break
+        J = D["Q"] - st.dt * np.diag(st.dN(U))
+        U = U - np.linalg.solve(J, R)
+    return U.reshape((Nt,) + u0.shape)
+
+
+def outer_iteration_if1(st: Setup, u0, iters, D=None):
+    """The paper's Exp-ParaDiag iteration for IF1 (eq. fully_disc_wr_nonlinear)
+    with exact inner solves: U^k solves (I - C_0^alpha (x) A) U - dt N_0(U)
+    = b^{k-1}, b^{k-1} = (A (u_0 - alpha u_Nt^{k-1}), 0, .., 0), by dense
+    Newton; U^0 = 0.  Returns the iterates."""
+    D = D or dense_operators(st)
+    Ns, Nt = u0.size, st.Nt
+    U = np.zeros(Nt * Ns)
+    out = []
+    for _ in range(iters):
+        b = np.zeros(Nt * Ns)
+        b[:Ns] = D["A"] @ (u0.ravel() - st.alpha * U[-Ns:])
+        V = U.copy()
+        for _ in range(50):
+            R = D["Qa"] @ V - st.dt * st.N(V) - b
+            if np.linalg.norm(R) <= 1e-15 * max(1.0, np.linalg.norm(V)):
+                break
+            V = V - np.linalg.solve(D["Qa"] - st.dt * np.diag(st.dN(V)), R)
+        U = V
+        out.append(U.reshape((Nt,) + u0.shape).copy())
+    return out

@@ -183,3 +183,29 @@ def test_advection_nyquist_derivative_kept(monkeypatch):
             s.E = np.exp(s.dt * s.mu)
     _patch_setup(monkeypatch, keep)
     assert _fails(PC.test_complex_symbol_is_hermitian)
+
+
+# ---------------------------------------------------------------------------
+# IF1 (Sec. 5)
+# ---------------------------------------------------------------------------
+import tests.test_oracle_if1 as PI  # noqa: E402
+
+
+def test_if1_nonlinearity_lagged_a_slice(monkeypatch):
+    def explicit(st, u0):
+        U = np.empty((st.Nt,) + u0.shape)
+        prev = u0
+        for n in range(st.Nt):
+            U[n] = st.A(prev) + st.dt * st.N(prev)
+            prev = U[n]
+        return U
+    monkeypatch.setattr(OE, "sequential_if1", explicit)
+    monkeypatch.setattr(PI.O, "sequential_if1", explicit)
+    assert _fails(PI.test_if1_sequential_equals_dense_newton, 1, 8, 6, 0.0)
+
+
+def test_if1_sigma_sign_flipped(monkeypatch):
+    orig = OE.precond_apply_if1
+    monkeypatch.setattr(OE, "precond_apply_if1",
+                        lambda st, R, sigma: orig(st, R, -sigma))
+    assert _fails(PI.test_if1_linear_reaction_iterates_closed_form, 1)
