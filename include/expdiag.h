@@ -15,6 +15,15 @@
  *                 u_{-1} := u_0
  * For N == 0 both reduce to the paper's first-order scheme u_n = A u_{n-1}
  * (Sec. 2, eq. disc_wr).
+ *   EXPDIAG_IF1:  u_n = A u_{n-1} + dt N(u_n), the implicit integrating-
+ *                 factor scheme of Sec. 5 (eq. fully_discrete_nonlinear).
+ *                 Each Exp-ParaDiag iteration is one inexact Newton step of
+ *                 eq. newton_2 with the averaged Jacobian reduced to a
+ *                 scalar: the preconditioner is Q_alpha - sigma I, sigma =
+ *                 dt times the space-time mean of N'(U^k) (jacobian = 1),
+ *                 of N'(u0) (jacobian = 2), or 0 (jacobian = 0: the lagged
+ *                 iteration of eq. disc_imextype_scheme).  Radix FFT time
+ *                 transform only; expdiag_precond_apply applies sigma = 0.
  *   EXPDIAG_EBDF2 (linear problems, N == 0): the second-order exponential
  *                 BDF of Sec. 4 (eq. 2nd_order_scheme),
  *                 u_n = 4/3 A u_{n-1} - 1/3 A^2 u_{n-2}, started from
@@ -63,6 +72,7 @@ extern "C" {
 #define EXPDIAG_ETD1 1
 #define EXPDIAG_ETD2 2
 #define EXPDIAG_EBDF2 3
+#define EXPDIAG_IF1 4
 
 #define EXPDIAG_FP64 0
 #define EXPDIAG_MIXED 1
@@ -91,6 +101,7 @@ typedef struct {
  * longer maps real fields to real fields).  GMRES then treats real and
  * imaginary parts as one real vector (inner product Re(x^H y)).  The server
  * does not take complex-state requests (EUNSUPPORTED).
+ * jacobian: EXPDIAG_IF1 only (0, 1 or 2; see the scheme list above).
  * precision: EXPDIAG_FP64, or EXPDIAG_MIXED (fp32 spatial FFTs and
  * nonlinearity in a bulk phase, fp64 residual and iterate afterwards; the
  * time transform is always fp64).
@@ -103,6 +114,7 @@ typedef struct {
   double b[3];
   double a_im, c_im;
   int complex_state;
+  int jacobian;
 } expdiag_problem;
 
 /* Build a handle: spectral symbols E = exp(dt mu), dt phi1(dt mu),

@@ -303,6 +303,16 @@ int dense_blocks(long Nk) {
 int time_len(const expdiag_ctx* h) {
   return h->scheme == EXPDIAG_EBDF2 ? h->Nt - 1 : h->Nt;
 }
+// Pass A: the slices whose N the residual needs and the N^ slot of the
+// first.  ETD: u_0..u_{Nt-1} for rows 0..Nt-1, u_0 from the initial
+// condition (slot 0, prepare_u0), so U slices 0..Nt-2 go to slots 1..Nt-1.
+// IF1 (N(u_l) in row l): all Nt slices of U to slots 0..Nt-1.
+long pass_a_slices(const expdiag_ctx* h) {
+  return h->scheme == EXPDIAG_IF1 ? h->Nt : h->Nt - 1;
+}
+long pass_a_slot(const expdiag_ctx* h) {
+  return h->scheme == EXPDIAG_IF1 ? 0 : 1;
+}
 // EBDF2 windows take the radix FFT when Nt - 1 is a power of two (2..512)
 // and the dense transform when Nt is one (8..128).
 bool bdf2_fft_ok(int Nt) { return Nt >= 3 && Nt <= 513 && is_pow2(Nt - 1); }
@@ -382,6 +392,13 @@ PassBArgs passb_args(expdiag_ctx* h) {
   a.etd2 = h->scheme == EXPDIAG_ETD2 ? 1 : 0;
   a.nblocks = passb_blocks(h);
   a.inv_ns = 1.0 / static_cast<double>(h->Ns);
+  a.same_slice = h->scheme == EXPDIAG_IF1 ? 1 : 0;
+  a.jac_mode = h->scheme == EXPDIAG_IF1 ? h->p.jacobian : 0;
+  a.sigma = 0.0;
+  a.jac_c[0] = h->dt * h->p.n1;
+  a.jac_c[1] = 2.0 * h->dt * h->p.n2;
+  a.jac_c[2] = 3.0 * h->dt * h->p.n3;
+  a.inv_ntns = 1.0 / (static_cast<double>(h->Nt) * h->Ns);
   // the same long-double values as the gamma table
   const int N = time_len(h);
   const int R = std::min(N, 4), tpl = N / R;
@@ -638,7 +655,8 @@ __global__ void narrow_kernel(const cx<double>* __restrict__ in,
 // fp32 copy in slot 0 of the fp32 view.
 int prepare_u0(expdiag_ctx* h, const double* u0) {
   RCHK(fwd_slices<ROW_R2C>(h, u0, h->u0h, 1));
-  if (!h->nonlinear) return 0;
+  // (IF1 takes N at every slice of U, never at u_0)
+  if (!h->nonlinear || h->scheme == EXPDIAG_IF1) return 0;
   RCHK(fwd_slices<ROW_NR2C>(h, u0, h->Nh, 1));
   if (h->mixed) {
     hipLaunchKernelGGL(narrow_kernel, dim3((h->Nk + 255) / 256), dim3(256), 0,
@@ -699,12 +717,12 @@ void plan_passb(Plan& P, int stage, int Nt, const PassBArgs& a, size_t nb,
 template <typename T>
 void plan_pass_a(Plan& P, expdiag_ctx* h, const Ctl* ctl, int ph) {
   const int d = h->dim;
-  const long ns = h->Nt - 1;
+  const long ns = pass_a_slices(h);
   const long nh2 = 2L * h->nh;
   const int nl = h->n[d - 1];
   const double sc = 1.0 / static_cast<double>(h->Ns);
   cx<T>* Tt = reinterpret_cast<cx<T>*>(h->T);
-  cx<T>* N1 = nh_view<T>(h) + h->Nk;  // slot 1
+  cx<T>* N1 = nh_view<T>(h) + pass_a_slot(h) * h->Nk;
   if (d == 1) {
     plan_row<T, double, T>(P, 2, nl / 2, ROW_FUSED,
                            make_row(h, h->Uh, N1, ns, nh2, nh2, sc, ctl, ph));
@@ -740,7 +758,7 @@ void plan_pass_a(Plan& P, expdiag_ctx* h, const Ctl* ctl, int ph) {
 bool plan_pass_a_mp(Plan& P, expdiag_ctx* h, const Ctl* ctl,
                     const PassBArgs& red) {
   const int d = h->dim;
-  const long ns = h->Nt - 1;
+  const long ns = pass_a_slices(h);
   const long nh2 = 2L * h->nh;
   const int nl = h->n[d - 1];
   const int M = nl / 2;
@@ -748,8 +766,8 @@ bool plan_pass_a_mp(Plan& P, expdiag_ctx* h, const Ctl* ctl,
   const bool mx = h->mixed;
   cx<double>* T64 = h->T;
   cx<float>* T32 = h->T32;
-  cx<double>* N64 = nh_view<double>(h) + h->Nk;  // slot 1
-  cx<float>* N32 = nh_view<float>(h) + h->Nk;
+  cx<double>* N64 = nh_view<double>(h) + pass_a_slot(h) * h->Nk;
+  cx<float>* N32 = nh_view<float>(h) + pass_a_slot(h) * h->Nk;
   auto row2 = [&](int stage, const RowJob& j32, const RowJob& j64,
                   int ti32) {
     Group& g = plan_group(P, stage, K_ROW, 2, M, ROW_FUSED, ti32, 1);
@@ -1204,6 +1222,7 @@ void symbol_tables(expdiag_ctx* h, SymbolTables& st) {
   const long double a = h->p.a, c = h->p.c, dt = h->dt;
   const long double ai = h->p.a_im, ci = h->p.c_im;
   const bool etd2 = h->scheme == EXPDIAG_ETD2;
+  const bool if1 = h->scheme == EXPDIAG_IF1;
   const double* bv = h->p.b;
   if (complex_symbols(h)) {
     st.per_kappa = true;
@@ -1227,7 +1246,8 @@ void symbol_tables(expdiag_ctx* h, SymbolTables& st) {
           bk += bv[1] * static_cast<long double>(wd(i1, n1));
         }
         const cld z = dt * cld(-a * k2 - c, -bk - ai * k2 - ci);
-        const cld w1 = dt * phi1c(z);
+        // IF1 weighs N(u_n) by dt itself (eq. fully_discrete_nonlinear)
+        const cld w1 = if1 ? cld(dt) : dt * phi1c(z);
         st.E[i] = to_cx(std::exp(z));
         if (etd2) {
           const cld w2 = dt * phi2c(z);
@@ -1266,7 +1286,7 @@ void symbol_tables(expdiag_ctx* h, SymbolTables& st) {
   auto eval = [&](long lo, long hi) {
     for (long i = lo; i < hi; ++i) {
       const long double z = dt * (-a * static_cast<long double>(vals[i]) - c);
-      const long double w1 = dt * phi1l(z);
+      const long double w1 = if1 ? dt : dt * phi1l(z);
       tE[i] = static_cast<double>(expl(z));
       if (etd2) {
         const long double w2 = dt * phi2l(z);
@@ -1586,7 +1606,7 @@ size_t expdiag_footprint_bytes(const expdiag_grid* g, int Nt, int scheme,
   Sizes s{};
   if (check_grid(g, &s) != 0) return 0;
   if (scheme != EXPDIAG_ETD1 && scheme != EXPDIAG_ETD2 &&
-      scheme != EXPDIAG_EBDF2)
+      scheme != EXPDIAG_EBDF2 && scheme != EXPDIAG_IF1)
     return 0;
   if (scheme == EXPDIAG_EBDF2) {
     if (!bdf2_fft_ok(Nt) && !dense_ok(Nt)) return 0;
@@ -1616,8 +1636,10 @@ int validate_params(int Nt, double dt, double alpha, int scheme,
   if (!(alpha > 0.0 && alpha < 1.0))
     return fail(nullptr, EXPDIAG_EINVAL, "alpha must lie in (0, 1)");
   if (scheme != EXPDIAG_ETD1 && scheme != EXPDIAG_ETD2 &&
-      scheme != EXPDIAG_EBDF2)
+      scheme != EXPDIAG_EBDF2 && scheme != EXPDIAG_IF1)
     return fail(nullptr, EXPDIAG_EINVAL, "unknown scheme %d", scheme);
+  if (p->jacobian < 0 || p->jacobian > 2)
+    return fail(nullptr, EXPDIAG_EINVAL, "jacobian must be 0, 1 or 2");
   if (scheme == EXPDIAG_EBDF2 &&
       (p->n1 != 0.0 || p->n2 != 0.0 || p->n3 != 0.0))
     return fail(nullptr, EXPDIAG_EUNSUPPORTED,
@@ -1860,6 +1882,18 @@ int pass_a_now(expdiag_ctx* h) {
 }
 
 // run `chunk` iterations of the handle's plan (graph replay or launches)
+// IF1 with a mean Jacobian: the first shift from u_0 (after the control
+// block `dctl` has been uploaded on stream `st`).
+int if1_sigma_init(expdiag_ctx* h, Ctl* dctl, hipStream_t st) {
+  if (h->scheme != EXPDIAG_IF1 || h->p.jacobian == 0) return 0;
+  const PassBArgs a = passb_args(h);
+  hipLaunchKernelGGL(if1_sigma_init_kernel<CTL_THREADS>, dim3(1),
+                     dim3(CTL_THREADS), 0, st, h->u0h, h->Nk, parseval_nh(h),
+                     a.inv_ns, a.jac_c[0], a.jac_c[1], a.jac_c[2], dctl);
+  HIPCHK(h, hipGetLastError());
+  return 0;
+}
+
 int run_iterations(expdiag_ctx* h, int chunk) {
   for (int i = 0; i < chunk; ++i) {
     if (h->use_graph && !h->prof) {
@@ -1945,6 +1979,7 @@ int expdiag_iterate(expdiag_t h, const double* u0, double* U, int max_iter,
   *h->h_mirror = *h->h_ctl;
   HIPCHK(h, hipMemcpyAsync(h->ctl, h->h_ctl, sizeof(Ctl),
                            hipMemcpyHostToDevice, h->stream));
+  RCHK(if1_sigma_init(h, h->ctl, h->stream));
   int enqueued = 0;
   int chunk = std::min(8, max_iter);
   double rel_prev = -1.0;

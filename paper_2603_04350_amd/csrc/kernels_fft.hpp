@@ -36,6 +36,7 @@ struct Ctl {
   double last_rel;
   double last_rnorm;
   double last_unorm;
+  double sigma;     // IF1: Jacobian shift of the preconditioner (dt nbar)
 };
 
 // Phase of the job's instance (1 without a control block), or -1 when it

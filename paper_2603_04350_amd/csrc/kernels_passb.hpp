@@ -62,6 +62,18 @@ struct PassBArgs {
   int etd2;
   int nblocks;
   double inv_ns;
+  // IF1 (the nonlinear term of row l is N(u_l), not N(u_{l-1})): same_slice
+  // keeps the row-0 term of the Jacobian product; the preconditioner is
+  // Q_alpha - sigma I with sigma = `sigma` (single launches) or the control
+  // block's value (iterations, jac_mode != 0).  jac_mode 1: after each
+  // iteration sigma = jac_c[0] + jac_c[1] mean(u) + jac_c[2] mean(u^2) over
+  // space-time (dt times the mean of N'(u)); the block holding kappa = 0
+  // adds sum_l Re U^_l(0) as partial 3.  inv_ntns = 1 / (Nt Ns).
+  int same_slice;
+  int jac_mode;
+  double sigma;
+  double jac_c[3];
+  double inv_ntns;
   // gamma_{s TPL} and 1/gamma_{s TPL}, s < R, of the radix-FFT pass B
   // (R = min(Nt, 4), TPL = Nt/R): row t + s TPL of a thread scales by
   // gamma_t gamma_{s TPL}
@@ -138,6 +150,11 @@ __device__ inline void advance_ctl(const PassBArgs& a, const double* tot) {
   }
   const int phase0 = c->phase;
   int done = 0;
+  if (a.jac_mode == 1) {
+    const double mu1 = tot[3] * a.inv_ntns;
+    const double mu2 = tot[2] * a.inv_ns * a.inv_ntns;
+    c->sigma = a.jac_c[0] + a.jac_c[1] * mu1 + a.jac_c[2] * mu2;
+  }
   if (!(rel == rel) || !(rn == rn) || rel > 1e300) {
     done = 2;
   } else if (c->phase == 0) {
@@ -244,6 +261,8 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
   if (two) c2 = SY::load(a.c2, kc);
   const double gam_t = gld(a.gam, t), igam_t = gld(a.igam, t);
   const cx<double> lam_t = gld(a.lam, t);
+  double sigma = a.sigma;
+  if (MODE == PB_ITERATE && a.jac_mode != 0) sigma = gld(&a.ctl->sigma, 0);
   constexpr int NST = fft_stage_count<NT, R>();
   cx<double> wst[NST > 1 ? NST : 2];
   fft_stage_twiddles<double, NT, R>(wst, t, a.tw);
@@ -274,7 +293,7 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
       const int l = t + s * TPL;
       const cx<double> prev = (l == 0) ? first : lds[(l - 1) * LS + c];
       cx<double> n_cur = zero;
-      if (nl && valid && (MODE != PB_OPAPPLY || l >= 1))
+      if (nl && valid && (MODE != PB_OPAPPLY || l >= 1 || a.same_slice))
         n_cur = cvt<double>(nr[s]);
       // PB_OPAPPLY, (Q - G'(U)) v: v_l - E v_{l-1} - (c1 J_l + c2 J_{l-1})
       // with J_l = FFT[N'(u_{l-1}) v_{l-1}] (J_0 = 0: u_0 is fixed); else
@@ -336,7 +355,7 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
       static_assert(R == 1 || R == 2 || R == 4, "rotations for R <= 4");
     }
     const cx<double> z = smul(lam, E);
-    const double dr = 1.0 - z.x, di = -z.y;
+    const double dr = 1.0 - z.x - sigma, di = -z.y;
     const double inv = 1.0 / (NT * (dr * dr + di * di));
     v[s] = cmul(v[s], mk(dr * inv, -di * inv));
   }
@@ -344,7 +363,9 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
   // step (c): inverse time transform with the - sign, then Gamma^{-1}
   fft_line_pre<double, NT, -1>(v, lds + c, LS, t, wst);
 
+  double sum0 = 0.0;  // sum_l Re U^_l(kappa = 0), for the IF1 mean Jacobian
   if constexpr (MODE == PB_ITERATE) {
+    const bool k0 = a.jac_mode == 1 && kap == 0;
 #pragma unroll
     for (int s = 0; s < R; ++s) {
       const int l = t + s * TPL;
@@ -352,6 +373,7 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
       const cx<double> un = u[s] + sv;
       nrm_s += pw * norm2(sv);
       nrm_u += pw * norm2(un);
+      if (k0) sum0 += un.x;
       if (valid) gst(a.U, l * Nk + kap, un);
     }
   } else {
@@ -363,7 +385,7 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
       if (valid) gst(a.Sout, l * Nk + kap, sv);
     }
   }
-  double acc[4] = {nrm_r, nrm_s, nrm_u, 0.0};
+  double acc[4] = {nrm_r, nrm_s, nrm_u, sum0};
   double tot[4];
   block_sum<4, SH::THREADS>(acc, red, tot);
   if (threadIdx.x == 0) {
@@ -432,6 +454,7 @@ __device__ __forceinline__ void reduce_instance(const PassBArgs& a,
       acc[0] += lo[i].x;
       acc[1] += lo[i].y;
       acc[2] += hi[i].x;
+      acc[3] += hi[i].y;
     }
   }
   double tot[4];
@@ -439,6 +462,31 @@ __device__ __forceinline__ void reduce_instance(const PassBArgs& a,
   if (threadIdx.x == 0) {
     ctl->pending = 0;
     advance_ctl(a, tot);
+  }
+}
+
+// IF1 with a mean Jacobian: the first shift, sigma = jac_c[0] +
+// jac_c[1] mean(u_0) + jac_c[2] mean(u_0^2), from the spectrum of u_0
+// (mean(u_0) = Re u0^(0) / Ns, mean(u_0^2) = sum_k w_k |u0^_k|^2 / Ns^2).
+// One block; fixed-order sums.
+template <int THREADS>
+__global__ void __launch_bounds__(THREADS)
+    if1_sigma_init_kernel(const cx<double>* __restrict__ u0h, long Nk,
+                          int nh, double inv_ns, double c0, double c1,
+                          double c2, Ctl* ctl) {
+  __shared__ double red[(THREADS / 64) * 4];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long k = threadIdx.x; k < Nk; k += THREADS) {
+    const int kl = static_cast<int>(k % nh);
+    const double pw = (kl == 0 || kl == nh - 1) ? 1.0 : 2.0;
+    acc[0] += pw * norm2(gld(u0h, k));
+  }
+  double tot[4];
+  block_sum<4, THREADS>(acc, red, tot);
+  if (threadIdx.x == 0) {
+    const double mu1 = gld(u0h, 0).x * inv_ns;
+    const double mu2 = tot[0] * inv_ns * inv_ns;
+    ctl->sigma = c0 + c1 * mu1 + c2 * mu2;
   }
 }
 

@@ -24,6 +24,7 @@ EXPDIAG_EUNSUPPORTED = -5
 EXPDIAG_ETD1 = 1
 EXPDIAG_ETD2 = 2
 EXPDIAG_EBDF2 = 3
+EXPDIAG_IF1 = 4
 EXPDIAG_FP64 = 0
 EXPDIAG_MIXED = 1
 
@@ -52,7 +53,7 @@ class Problem(ctypes.Structure):
                 ("gmres_restart", ctypes.c_int),
                 ("b", ctypes.c_double * 3),
                 ("a_im", ctypes.c_double), ("c_im", ctypes.c_double),
-                ("complex_state", ctypes.c_int)]
+                ("complex_state", ctypes.c_int), ("jacobian", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):
@@ -149,15 +150,16 @@ def make_grid(shape: Sequence[int]) -> Grid:
 
 def make_problem(a, c=0.0, n1=0.0, n2=0.0, n3=0.0, precision=EXPDIAG_FP64,
                  gmres_restart=0, b=(0.0, 0.0, 0.0), a_im=0.0, c_im=0.0,
-                 complex_state=None) -> Problem:
-    """complex_state defaults to 1 when a_im or c_im is nonzero."""
+                 complex_state=None, jacobian=1) -> Problem:
+    """complex_state defaults to 1 when a_im or c_im is nonzero; jacobian
+    (IF1 only): 0 none, 1 mean N'(U^k), 2 mean N'(u0)."""
     bb = tuple(float(v) for v in b) + (0.0,) * (3 - len(b))
     if complex_state is None:
         complex_state = 1 if (a_im != 0.0 or c_im != 0.0) else 0
     return Problem(float(a), float(c), float(n1), float(n2), float(n3),
                    int(precision), int(gmres_restart),
                    (ctypes.c_double * 3)(*bb[:3]), float(a_im), float(c_im),
-                   int(complex_state))
+                   int(complex_state), int(jacobian))
 
 
 def _ptr(t, numel=None, name="array"):
@@ -284,12 +286,12 @@ class Solver:
     def __init__(self, shape, Nt, dt, alpha, scheme=EXPDIAG_ETD1, a=1.0,
                  c=0.0, n1=0.0, n2=0.0, n3=0.0, precision=EXPDIAG_FP64,
                  gmres_restart=0, stream=None, b=(0.0, 0.0, 0.0), a_im=0.0,
-                 c_im=0.0, complex_state=None):
+                 c_im=0.0, complex_state=None, jacobian=1):
         self.shape = tuple(int(v) for v in shape)
         self.Nt = int(Nt)
         self.problem = make_problem(a, c, n1, n2, n3, precision,
                                     gmres_restart, b, a_im, c_im,
-                                    complex_state)
+                                    complex_state, jacobian)
         self.h = expdiag_create(self.shape, Nt, dt, alpha, scheme,
                                 self.problem, stream)
 
@@ -301,7 +303,8 @@ class Solver:
                    inst.precision if precision is None else precision,
                    gmres_restart, stream, getattr(inst, "b", (0.0, 0.0, 0.0)),
                    getattr(inst, "a_im", 0.0), getattr(inst, "c_im", 0.0),
-                   1 if getattr(inst, "cstate", False) else None)
+                   1 if getattr(inst, "cstate", False) else None,
+                   getattr(inst, "jac", 1))
 
     def close(self):
         if self.h is not None:

@@ -55,7 +55,9 @@ def _create(lib, shape, Nt, dt, alpha, scheme, prob):
     ((64,), 8, 0.0, 1e-2, 1, X.make_problem(1.0), X.EXPDIAG_EINVAL),
     ((64,), 8, 0.1, 0.0, 1, X.make_problem(1.0), X.EXPDIAG_EINVAL),
     ((64,), 8, 0.1, 1.0, 1, X.make_problem(1.0), X.EXPDIAG_EINVAL),
-    ((64,), 8, 0.1, 1e-2, 4, X.make_problem(1.0), X.EXPDIAG_EINVAL),
+    ((64,), 8, 0.1, 1e-2, 5, X.make_problem(1.0), X.EXPDIAG_EINVAL),
+    ((64,), 8, 0.1, 1e-2, X.EXPDIAG_IF1, X.make_problem(1.0, jacobian=3),
+     X.EXPDIAG_EINVAL),
     # EBDF2: linear problems, 8 <= Nt <= 128
     ((64,), 8, 0.1, 1e-2, X.EXPDIAG_EBDF2, X.make_problem(1.0, n1=1.0),
      X.EXPDIAG_EUNSUPPORTED),

@@ -69,6 +69,7 @@ class Instance:
     a_im: float = 0.0
     c_im: float = 0.0
     cstate: bool = False
+    jac: int = 1
 
     @property
     def dt(self) -> float:
