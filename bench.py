@@ -31,6 +31,8 @@ value = space-time DOF-iterations per second of the plain FP64 solve
     time transform on FP64 MFMA, pass B against both peaks);
   * advection: the headline instance with an advection term -b.grad u,
     b = (2, 1), whose symbol is complex (complex E and phi tables);
+  * if1: the headline instance with the implicit IF1 scheme of the paper's
+    nonlinear section (lagged iteration);
   * schroedinger: u_t = i Lap u - 2i u on the same grid, a complex state
     (full spectrum, C2C boundary transforms), from a wave packet;
   * served: batch-shaped 2D requests mixed with 3D 128^3 x 32 heat /
@@ -289,6 +291,33 @@ def bench_schroedinger(steps, warmup):
     }
     s.close()
     return out
+
+
+def bench_if1(steps, warmup):
+    """The headline instance solved with the implicit IF1 scheme (Sec. 5),
+    lagged iteration (jacobian = 0)."""
+    import dataclasses
+    import workloads as W
+    inst = dataclasses.replace(W.allen_cahn2d(scheme=4), jac=0)
+    fp = bench_single(inst, 0, steps, warmup)
+    dom = fp["dominant"]
+    kb = fp["kernels"][dom]
+    return {
+        "workload": "2D Allen-Cahn eps=0.05, periodic 256x256, Nt=64, T=2, "
+                    "IF1 u_n = A u_{n-1} + dt N(u_n), lagged iteration, "
+                    "alpha=1e-3, u0~U[-0.9,0.9] seed 0",
+        "ms_per_solve": fp["ms_per_solve"],
+        "iters_per_solve": fp["iters"],
+        "us_per_iter": fp["us_per_iter"],
+        "dof_iters_per_s": fp["dof_iters_per_s"],
+        "dominant": dom,
+        "roofline": {"kernel": dom, "bound": "hbm",
+                     "achieved": round(kb["GBps"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s",
+                     "frac": round(kb["GBps"] / HBM_PEAK_GBS, 4),
+                     "avg_launch_us": kb["avg_us"]},
+        "U": fp["U"],
+    }
 
 
 def bench_batched(count):
@@ -603,6 +632,10 @@ def main():
         se = bench_schroedinger(args.steps, args.warmup)
         U_se = se.pop("U")
         line["schroedinger"] = se
+        _log("IF1 (implicit scheme)")
+        if1 = bench_if1(args.steps, args.warmup)
+        U_if1 = if1.pop("U")
+        line["if1"] = if1
     if not args.no_batch:
         _log(f"batched: {args.batch} instances")
         line["batched"] = bench_batched(args.batch)
@@ -624,6 +657,10 @@ def main():
             isc = W.schroedinger2d()
             line["schroedinger"]["err_vs_oracle"] = float(O.rel_err(
                 U_se, O.sequential(O.Setup.from_instance(isc), isc.u0)))
+            iif = W.allen_cahn2d(scheme=4)
+            sif = O.Setup.from_instance(iif)
+            line["if1"]["err_vs_oracle"] = float(O.rel_err(
+                U_if1, O.sequential(sif, iif.u0)))
     if rank == 0:
         print(json.dumps(line), flush=True)
 
