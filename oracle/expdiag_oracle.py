@@ -51,10 +51,23 @@ Readings taken where the paper is silent (also listed in the design doc):
     system is v = (u_2..u_Nt), and f_2 is built from u_0 and that u_1, so
     the iteration on v does not depend on what slice 1 holds.  Slice 1's
     own residual row is A u_0 - u_1 and its preconditioner is the identity.
+  * EBDF3..EBDF6 (schemes 5..8, Sec. bdfs, linear problems only): the same
+    construction with start values u_j = A^j u_0, j = 1..s-1, unknowns
+    v = (u_s..u_Nt) on N = Nt - s + 1 slices and C_{j-1}^alpha =
+    (C_0^alpha)^j, the matrix whose alpha entries sit where the paper lists
+    them for C_1..C_5 (its list names C_3 twice; the second is C_4 and the
+    one called C_4 is C_5).  Step (b) then inverts
+    I - sum_j beta_j lambda_{0,m}^j A^j.  The fixed point of eq.
+    pcond-2nd-order carries over (the paper only runs GMRES for s >= 3).
+  * BiCGStab (Table cpu_time_combined) runs on the same left-preconditioned
+    system as GMRES, with the shadow residual r^_0 = r_0.
 
 parity: every function here is pinned by tests/test_oracle_pins.py and, for
 EBDF2, tests/test_oracle_ebdf2.py (closed forms, dense LU, mpmath, textbook
-GMRES, convergence order, the exact spectra of Sec. 4).
+GMRES, convergence order, the exact spectra of Sec. 4); EBDF3..6 and
+BiCGStab by tests/test_oracle_ebdf_bicgstab.py (BDF coefficients from the
+backward-difference definition, exactness on A^n u_0, dense LU of the
+assembled systems, matrix powers of C_0^alpha, scipy's BiCGStab).
 """
 from __future__ import annotations
 
@@ -73,10 +86,16 @@ __all__ = [
     "gmres_solve_ebdf2", "dense_operators_ebdf2",
     "IF1", "sequential_if1", "residual_if1", "precond_apply_if1",
     "if1_sigma", "dense_newton_if1", "outer_iteration_if1",
+    "EBDF3", "EBDF4", "EBDF5", "EBDF6", "EBDF_COEFFS", "ebdf_order",
+    "ebdf_beta", "ebdf_tables", "sequential_ebdf", "r_apply_ebdf",
+    "ralpha_apply_ebdf", "residual_ebdf", "precond_apply_ebdf",
+    "gmres_solve_ebdf", "dense_operators_ebdf", "bicgstab",
+    "bicgstab_solve", "newton_bicgstab",
 ]
 
 EBDF2 = 3  # scheme code of the second-order exponential BDF (Sec. 4)
 IF1 = 4    # scheme code of the implicit integrating-factor scheme (Sec. 5)
+EBDF3, EBDF4, EBDF5, EBDF6 = 5, 6, 7, 8  # exponential BDF3..6 (Sec. bdfs)
 
 
 # ---------------------------------------------------------------------------
@@ -235,6 +254,8 @@ def sequential(st: Setup, u0):
     """
     if st.scheme == EBDF2:
         return sequential_ebdf2(st, u0)
+    if ebdf_order(st.scheme):
+        return sequential_ebdf(st, u0)
     if st.scheme == IF1:
         return sequential_if1(st, u0)
     U = np.empty((st.Nt,) + u0.shape, dtype=st.dtype)
@@ -343,7 +364,8 @@ def fixed_point(st: Setup, u0, U0=None, max_iter=200, tol=1e-11, ref=None,
 
     Eq. pcond-1st-order (linear) with the nonlinearity lagged one iteration
     (Sec. 6.2); for EBDF2 the iteration of eq. pcond-2nd-order,
-    v^{k+1} = v^k + R_alpha^{-1}(f_2 - R v^k), on slices 2..Nt.
+    v^{k+1} = v^k + R_alpha^{-1}(f_2 - R v^k), on slices 2..Nt, and its
+    order-s analogue on slices s..Nt for EBDF3..EBDF6.
     U^0 = 0 unless given (Sec. 6 starts from zeros).
     Stops when ||s^k|| <= tol ||u^{k+1}||, or, if `ref` is given and
     ref_tol is set, when rel_err(u^{k+1}, ref) <= ref_tol.
@@ -355,11 +377,15 @@ def fixed_point(st: Setup, u0, U0=None, max_iter=200, tol=1e-11, ref=None,
         else U0.copy()
     hist, iterates = [], []
     bdf2 = st.scheme == EBDF2
+    bdfs = ebdf_order(st.scheme) if not bdf2 else 0
     if1 = st.scheme == IF1
     for k in range(max_iter):
         if bdf2:
             R = residual_ebdf2(st, u0, U)
             S = precond_apply_ebdf2(st, R)
+        elif bdfs:
+            R = residual_ebdf(st, u0, U)
+            S = precond_apply_ebdf(st, R)
         elif if1:
             R = residual_if1(st, u0, U)
             S = precond_apply_if1(st, R, if1_sigma(st, u0, U, k))
@@ -837,3 +863,307 @@ def outer_iteration_if1(st: Setup, u0, iters, D=None):
         U = V
         out.append(U.reshape((Nt,) + u0.shape).copy())
     return out
+
+
+# ---------------------------------------------------------------------------
+# EBDF3..EBDF6: the exponential BDF schemes of order s of Sec. bdfs
+# ---------------------------------------------------------------------------
+# u_n = sum_{j=1..s} beta_j A^j u_{n-j}, n >= s, with the coefficients the
+# paper prints in eqs. 3rd_order_scheme, fourth_order_scheme,
+# fifth_order_scheme and sixth_order_scheme (order 2: eq. 2nd_order_scheme),
+# as (numerator, denominator) pairs.
+EBDF_COEFFS = {
+    2: ((4, -1), 3),
+    3: ((18, -9, 2), 11),
+    4: ((48, -36, 16, -3), 25),
+    5: ((300, -300, 200, -75, 12), 137),
+    6: ((360, -450, 400, -225, 72, -10), 147),
+}
+
+
+def ebdf_order(scheme):
+    """Order s of an exponential BDF scheme code (EBDF2 = 3, EBDF3..EBDF6 =
+    5..8), 0 for the other schemes."""
+    if scheme == EBDF2:
+        return 2
+    return scheme - 2 if scheme in (EBDF3, EBDF4, EBDF5, EBDF6) else 0
+
+
+def ebdf_beta(s):
+    """beta_1..beta_s of the order-s scheme as floats."""
+    num, den = EBDF_COEFFS[s]
+    return [b / den for b in num]
+
+
+def _Apow(st: Setup, v, j):
+    """A^j v through the symbol E^j (j >= 0)."""
+    if j == 0:
+        return v.copy()
+    return st._out(st.spectral_apply(v, st.E ** j))
+
+
+def ebdf_tables(st: Setup, s):
+    """Time tables of the N = Nt - s + 1 slice system: gamma_l =
+    alpha^{l/N}, lambda_{0,m} = alpha^{1/N} e^{2 pi i m/N} and the
+    eigenvalues lambda_{0,m}^j of C_{j-1}^alpha, j = 1..s (reading:
+    C_{j-1}^alpha = (C_0^alpha)^j, which is what the alpha positions the
+    paper gives for C_1..C_5 describe)."""
+    N = st.Nt - s + 1
+    l = np.arange(N, dtype=np.float64)
+    gamma = st.alpha ** (l / N)
+    lam0 = st.alpha ** (1.0 / N) * np.exp(2j * np.pi * l / N)
+    lams = [lam0 ** j for j in range(1, s + 1)]
+    return gamma, lams
+
+
+def _ebdf_start(st: Setup, u0, s):
+    """Slices u_0..u_{s-1}: u_0 and the start values u_j = A^j u_0 (the
+    exact exponential steps; the paper leaves u_1..u_{s-1} open)."""
+    return [u0] + [_Apow(st, u0, j) for j in range(1, s)]
+
+
+def sequential_ebdf(st: Setup, u0, s=None):
+    """u_1..u_Nt of the order-s exponential BDF, started from u_j = A^j u_0,
+    j < s."""
+    s = s or ebdf_order(st.scheme)
+    beta = ebdf_beta(s)
+    hist = _ebdf_start(st, u0, s)
+    for n in range(s, st.Nt + 1):
+        un = sum(beta[j - 1] * _Apow(st, hist[n - j], j)
+                 for j in range(1, s + 1))
+        hist.append(un)
+    return np.array(hist[1:st.Nt + 1], dtype=st.dtype)
+
+
+def r_apply_ebdf(st: Setup, V, s=None):
+    """R_s v, R_s = I - sum_j beta_j C_{j-1} (x) A^j (eqs.
+    all_at_once_3rdorder .. all_at_once_6thorder), v = (v_s..v_Nt): row i
+    is v_i - sum_j beta_j A^j v_{i-j}, entries before v_s being zero."""
+    s = s or ebdf_order(st.scheme)
+    beta = ebdf_beta(s)
+    out = V.copy()
+    for j in range(1, s + 1):
+        if j < V.shape[0]:
+            out[j:] -= beta[j - 1] * _Apow(st, V[:-j], j)
+    return out
+
+
+def ralpha_apply_ebdf(st: Setup, V, s=None):
+    """R_s^alpha v: C_{j-1}^alpha adds alpha at rows i = 0..j-1, columns
+    N - j + i (0-based), the positions the paper lists."""
+    s = s or ebdf_order(st.scheme)
+    beta = ebdf_beta(s)
+    N = V.shape[0]
+    out = r_apply_ebdf(st, V, s)
+    for j in range(1, s + 1):
+        for i in range(min(j, N)):
+            out[i] -= beta[j - 1] * st.alpha * _Apow(st, V[N - j + i], j)
+    return out
+
+
+def residual_ebdf(st: Setup, u0, U, s=None):
+    """Residual of the order-s window on slices u_1..u_Nt.
+
+    Start slices j = 1..s-1: A^j u_0 - u_j.  Slices n = s..Nt: f_s - R_s v
+    with v = (u_s..u_Nt), f_s built from u_0 and the start values A^j u_0
+    (not from U's start slices), i.e. sum_j beta_j A^j w_{n-j} - u_n with
+    w_m = u_m for m >= s and A^m u_0 below.
+    """
+    s = s or ebdf_order(st.scheme)
+    beta = ebdf_beta(s)
+    start = _ebdf_start(st, u0, s)
+    R = np.empty_like(U)
+    for j in range(1, s):
+        R[j - 1] = start[j] - U[j - 1]
+    for n in range(s, st.Nt + 1):
+        acc = np.zeros_like(U[0])
+        for j in range(1, s + 1):
+            m = n - j
+            w = U[m - 1] if m >= s else start[m]
+            acc = acc + beta[j - 1] * _Apow(st, w, j)
+        R[n - 1] = acc - U[n - 1]
+    return R
+
+
+def precond_apply_ebdf(st: Setup, R, s=None):
+    """Start slices unchanged; slices s..Nt: (R_s^alpha)^{-1} by steps
+    (a)-(c) on N = Nt - s + 1 time points, step (b) inverting
+    I - sum_j beta_j lambda_{j-1,m} A^j per frequency m."""
+    s = s or ebdf_order(st.scheme)
+    beta = ebdf_beta(s)
+    gamma, lams = ebdf_tables(st, s)
+    N = st.Nt - s + 1
+    o = s - 1
+    g = gamma.reshape((N,) + (1,) * st.dim)
+    Sp = time_dft(g * R[o:])
+    Sq = np.empty_like(Sp)
+    for m in range(N):
+        sym = 1.0 - sum(beta[j - 1] * lams[j - 1][m] * st.E ** j
+                        for j in range(1, s + 1))
+        Sq[m] = st.spectral_apply(Sp[m], 1.0 / sym)
+    S = np.empty_like(R)
+    S[:o] = R[:o]
+    S[o:] = st._out(time_idft(Sq) / g)
+    return S
+
+
+def gmres_solve_ebdf(st: Setup, u0, restart=20, tol=1e-10, max_iter=200,
+                     s=None):
+    """GMRES on (R_s^alpha)^{-1} R_s v = (R_s^alpha)^{-1} f_s, v^0 = 0
+    (the GMRES preconditioners of Sec. bdfs); returns the window with the
+    start slices A^j u_0."""
+    s = s or ebdf_order(st.scheme)
+    o = s - 1
+    zeros = np.zeros((st.Nt,) + u0.shape, dtype=st.dtype)
+    fs = residual_ebdf(st, u0, zeros, s)[o:]
+
+    def prec(v):
+        full = np.zeros((st.Nt,) + u0.shape, dtype=st.dtype)
+        full[o:] = v
+        return precond_apply_ebdf(st, full, s)[o:]
+
+    b = prec(fs)
+    op = lambda v: prec(r_apply_ebdf(st, v, s))
+    rop, rb, rx0, back = _real_view(st, op, b, np.zeros_like(fs))
+    v, it, hist = gmres(rop, rb, rx0, restart, tol, max_iter)
+    U = np.empty((st.Nt,) + u0.shape, dtype=st.dtype)
+    U[:o] = np.array(_ebdf_start(st, u0, s)[1:], dtype=st.dtype).reshape(
+        (o,) + u0.shape)
+    U[o:] = back(v)
+    return U, it, hist
+
+
+def dense_operators_ebdf(st: Setup, s=None):
+    """Dense A, A^j, C_{j-1}, C_{j-1}^alpha (alpha entries placed at the
+    positions the paper lists for C_1..C_5), R_s and R_s^alpha for
+    N = Nt - s + 1 slices, assembled entry by entry."""
+    s = s or ebdf_order(st.scheme)
+    beta = ebdf_beta(s)
+    D = dense_operators(st)
+    A = D["A"]
+    N = st.Nt - s + 1
+    Ap = [np.eye(A.shape[0])]
+    for _ in range(s):
+        Ap.append(Ap[-1] @ A)
+    C, Ca = [], []
+    for j in range(1, s + 1):
+        Cj = np.zeros((N, N))
+        for i in range(j, N):
+            Cj[i, i - j] = 1.0
+        Cja = Cj.copy()
+        for i in range(min(j, N)):
+            Cja[i, N - j + i] = st.alpha
+        C.append(Cj)
+        Ca.append(Cja)
+    I = np.eye(N * A.shape[0])
+    R = I - sum(beta[j - 1] * np.kron(C[j - 1], Ap[j]) for j in range(1, s + 1))
+    Ra = I - sum(beta[j - 1] * np.kron(Ca[j - 1], Ap[j])
+                 for j in range(1, s + 1))
+    return {"A": A, "Ap": Ap, "C": C, "Ca": Ca, "R": R, "Ra": Ra}
+
+
+# ---------------------------------------------------------------------------
+# BiCGStab with the Exp-ParaDiag preconditioner (the bracketed timings of
+# Table cpu_time_combined)
+# ---------------------------------------------------------------------------
+def bicgstab(matvec, b, x0, tol=1e-10, max_iter=200):
+    """BiCGStab (van der Vorst 1992; Saad, Iterative Methods for Sparse
+    Linear Systems, Alg. 7.7) on matvec(x) = b with shadow vector r^_0 =
+    r_0.  Stops when ||r_j|| <= tol ||b|| (r_j the recurred residual) or
+    when an intermediate s_j is that small.  Returns (x, iterations,
+    history of ||r_j||)."""
+    x = x0.copy()
+    bnorm = np.linalg.norm(b)
+    if bnorm == 0.0:
+        return np.zeros_like(b), 0, [0.0]
+    r = b - matvec(x)
+    rhat = r.copy()
+    hist = [np.linalg.norm(r)]
+    if hist[0] <= tol * bnorm:
+        return x, 0, hist
+    p = r.copy()
+    rho = np.vdot(rhat, r).real
+    it = 0
+    while it < max_iter:
+        v = matvec(p)
+        al = rho / np.vdot(rhat, v).real
+        s = r - al * v
+        it += 1
+        sn = np.linalg.norm(s)
+        if sn <= tol * bnorm:
+            x = x + al * p
+            hist.append(sn)
+            break
+        t = matvec(s)
+        om = np.vdot(t, s).real / np.vdot(t, t).real
+        x = x + al * p + om * s
+        r = s - om * t
+        hist.append(np.linalg.norm(r))
+        if hist[-1] <= tol * bnorm:
+            break
+        rho_new = np.vdot(rhat, r).real
+        be = (rho_new / rho) * (al / om)
+        rho = rho_new
+        p = r + be * (p - om * v)
+    return x, it, hist
+
+
+def bicgstab_solve(st: Setup, u0, tol=1e-10, max_iter=200):
+    """Linear problems: BiCGStab on the left-preconditioned system GMRES
+    solves (Q_alpha^{-1} Q u = Q_alpha^{-1} f; for the exponential BDF
+    schemes (R^alpha)^{-1} R v = (R^alpha)^{-1} f on the unknown slices),
+    u^0 = 0.  Returns (U, iterations, history)."""
+    s = ebdf_order(st.scheme)
+    if s:
+        o = s - 1
+        zeros = np.zeros((st.Nt,) + u0.shape, dtype=st.dtype)
+        fs = residual_ebdf(st, u0, zeros, s)[o:]
+
+        def prec(v):
+            full = np.zeros((st.Nt,) + u0.shape, dtype=st.dtype)
+            full[o:] = v
+            return precond_apply_ebdf(st, full, s)[o:]
+
+        b = prec(fs)
+        op = lambda v: prec(r_apply_ebdf(st, v, s))
+        rop, rb, rx0, back = _real_view(st, op, b, np.zeros_like(fs))
+        v, it, hist = bicgstab(rop, rb, rx0, tol, max_iter)
+        U = np.empty((st.Nt,) + u0.shape, dtype=st.dtype)
+        U[:o] = np.array(_ebdf_start(st, u0, s)[1:], dtype=st.dtype).reshape(
+            (o,) + u0.shape)
+        U[o:] = back(v)
+        return U, it, hist
+    zeros = np.zeros((st.Nt,) + u0.shape, dtype=st.dtype)
+    b = precond_apply(st, residual(st, u0, zeros))
+    op = lambda v: precond_apply(st, q_apply(st, v))
+    rop, rb, rx0, back = _real_view(st, op, b, zeros)
+    x, it, hist = bicgstab(rop, rb, rx0, tol, max_iter)
+    return back(x), it, hist
+
+
+def newton_bicgstab(st: Setup, u0, tol=1e-10, max_newton=30, max_inner=200,
+                    eta_max=1e-3):
+    """newton_gmres with BiCGStab as the inner solver of
+    Q_alpha^{-1}(Q - G'(U)) d = Q_alpha^{-1} R(U) (ETD1/ETD2 with the
+    lagged nonlinearity).  Returns (U, newton_steps, inner_total, history of
+    ||R_j||)."""
+    U = np.zeros((st.Nt,) + u0.shape)
+    R = residual(st, u0, U)
+    r0 = np.linalg.norm(R)
+    hist = [r0]
+    inner_total = 0
+    for j in range(max_newton):
+        rn = np.linalg.norm(R)
+        if rn <= tol * r0:
+            return U, j, inner_total, hist
+        eta = min(eta_max, rn / r0)
+        Uc = U
+        op = lambda v: precond_apply(st, q_apply(st, v)
+                                     - gprime_apply(st, u0, Uc, v))
+        d, it, _ = bicgstab(op, precond_apply(st, R), np.zeros_like(U), eta,
+                            max_inner)
+        inner_total += it
+        U = U + d
+        R = residual(st, u0, U)
+        hist.append(np.linalg.norm(R))
+    return U, max_newton, inner_total, hist

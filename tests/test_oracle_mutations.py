@@ -209,3 +209,106 @@ def test_if1_sigma_sign_flipped(monkeypatch):
     monkeypatch.setattr(OE, "precond_apply_if1",
                         lambda st, R, sigma: orig(st, R, -sigma))
     assert _fails(PI.test_if1_linear_reaction_iterates_closed_form, 1)
+
+
+# ---------------------------------------------------------------------------
+# EBDF3..6 (Sec. bdfs) and BiCGStab
+# ---------------------------------------------------------------------------
+import tests.test_oracle_ebdf_bicgstab as PS  # noqa: E402
+
+
+def _patch_pkg(monkeypatch, name, fn):
+    monkeypatch.setattr(OE, name, fn)
+    monkeypatch.setattr(PS.O, name, fn)
+
+
+def test_ebdfs_eigenvalue_powers_dropped(monkeypatch):
+    orig = OE.ebdf_tables
+
+    def bad(st, s):
+        g, lams = orig(st, s)
+        return g, [lams[0]] * s
+    _patch_pkg(monkeypatch, "ebdf_tables", bad)
+    assert _fails(PS.test_precond_is_dense_solve, 4, 0.5)
+    assert _fails(PS.test_alpha_circulants_are_powers, 3)
+
+
+def test_ebdfs_last_coefficient_dropped(monkeypatch):
+    orig = OE.ebdf_beta
+    _patch_pkg(monkeypatch, "ebdf_beta", lambda s: orig(s)[:-1] + [0.0])
+    assert _fails(PS.test_sequential_is_exact_on_linear_problem, 5, 1)
+    assert _fails(PS.test_coefficients_are_the_bdf_coefficients, 5)
+
+
+def test_ebdfs_power_off_by_one(monkeypatch):
+    orig = OE._Apow
+    monkeypatch.setattr(OE, "_Apow", lambda st, v, j: orig(st, v, j + 1))
+    assert _fails(PS.test_sequential_is_exact_on_linear_problem, 3, 1)
+
+
+def test_ebdfs_fs_from_stored_start_slices(monkeypatch):
+    orig = OE._ebdf_start
+
+    def residual_from_U(st, u0, U, s=None):
+        s = s or OE.ebdf_order(st.scheme)
+        beta = OE.ebdf_beta(s)
+        start = orig(st, u0, s)
+        R = np.empty_like(U)
+        for j in range(1, s):
+            R[j - 1] = start[j] - U[j - 1]
+        for n in range(s, st.Nt + 1):
+            acc = np.zeros_like(U[0])
+            for j in range(1, s + 1):
+                m = n - j
+                w = U[m - 1] if m >= 1 else u0
+                acc = acc + beta[j - 1] * OE._Apow(st, w, j)
+            R[n - 1] = acc - U[n - 1]
+        return R
+    _patch_pkg(monkeypatch, "residual_ebdf", residual_from_U)
+    assert _fails(PS.test_residual_and_operators_match_dense, 4, 1)
+
+
+def test_ebdfs_alpha_one_column_off(monkeypatch):
+    orig = OE.r_apply_ebdf
+
+    def bad(st, V, s=None):
+        s = s or OE.ebdf_order(st.scheme)
+        beta = OE.ebdf_beta(s)
+        N = V.shape[0]
+        out = orig(st, V, s)
+        for j in range(1, s + 1):
+            for i in range(min(j, N)):
+                out[i] -= beta[j - 1] * st.alpha * OE._Apow(
+                    st, V[N - j + i - 1], j)
+        return out
+    _patch_pkg(monkeypatch, "ralpha_apply_ebdf", bad)
+    assert _fails(PS.test_residual_and_operators_match_dense, 3, 1)
+
+
+def test_bicgstab_omega_sign_flipped(monkeypatch):
+    src = OE.bicgstab
+
+    def bad(matvec, b, x0, tol=1e-10, max_iter=200):
+        # BiCGStab with the stabilising step taken backwards
+        x = x0.copy()
+        r = b - matvec(x)
+        rhat = r.copy()
+        p = r.copy()
+        rho = np.vdot(rhat, r).real
+        it = 0
+        while it < max_iter:
+            v = matvec(p)
+            al = rho / np.vdot(rhat, v).real
+            s = r - al * v
+            t = matvec(s)
+            om = -np.vdot(t, s).real / np.vdot(t, t).real
+            x = x + al * p + om * s
+            r = s - om * t
+            it += 1
+            rho_new = np.vdot(rhat, r).real
+            p = r + (rho_new / rho) * (al / om) * (p - om * v)
+            rho = rho_new
+        return x, it, []
+    assert src is not bad
+    _patch_pkg(monkeypatch, "bicgstab", bad)
+    assert _fails(PS.test_bicgstab_iterates_match_scipy, 2)
