@@ -57,7 +57,7 @@ TOL = 1e-11
 
 DEVICE_SOURCES = ("cx.hpp", "fft_core.hpp", "kernels_fft.hpp",
                   "kernels_passb.hpp", "kernels_krylov.hpp",
-                  "kernels_dense.hpp", "kernels_bdf2.hpp")
+                  "kernels_dense.hpp", "kernels_bdf.hpp")
 
 
 def _src_hash():

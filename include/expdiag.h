@@ -32,6 +32,17 @@
  *                 residual f_2 - R v takes u_1 = A u_0 whatever slice 1
  *                 holds, and whose preconditioner is R_alpha of eq.
  *                 pcond-2nd-order on Nt - 1 time points.
+ *   EXPDIAG_EBDF3 .. EXPDIAG_EBDF6 (linear problems, N == 0): the
+ *                 exponential BDF of order s = 3..6 of Sec. bdfs (eqs.
+ *                 3rd_order_scheme .. sixth_order_scheme),
+ *                 u_n = sum_{i=1..s} beta_i A^i u_{n-i}, started from
+ *                 u_m = A^m u_0, m < s.  Slices 1..s-1 of a window are
+ *                 those fixed starts; the unknowns are u_s..u_Nt (eqs.
+ *                 all_at_once_3rdorder .. all_at_once_6thorder), with f_s
+ *                 built from u_0 and the start values, and the
+ *                 preconditioner R_s^alpha (C_{i-1}^alpha = (C_0^alpha)^i,
+ *                 the alpha-circulants of Sec. bdfs) on Nt - s + 1 time
+ *                 points.  EBDF2 is the case s = 2.
  *
  * Conventions for every entry point:
  *   - Array arguments are DEVICE pointers to float64 data owned by the caller
@@ -73,6 +84,10 @@ extern "C" {
 #define EXPDIAG_ETD2 2
 #define EXPDIAG_EBDF2 3
 #define EXPDIAG_IF1 4
+#define EXPDIAG_EBDF3 5
+#define EXPDIAG_EBDF4 6
+#define EXPDIAG_EBDF5 7
+#define EXPDIAG_EBDF6 8
 
 #define EXPDIAG_FP64 0
 #define EXPDIAG_MIXED 1
@@ -124,13 +139,14 @@ typedef struct {
  * device workspace (size given by expdiag_footprint_bytes).
  *   g        grid (host pointer)
  *   Nt       number of time steps in the window, power of two, 2..512.
- *            EBDF2 transforms the Nt - 1 unknown slices: Nt - 1 a power of
- *            two, 2..512, takes the radix FFT; otherwise Nt must be a power
- *            of two in 8..128 and takes the dense transform
+ *            An order-s exponential BDF (EBDF2..EBDF6) transforms the
+ *            Nt - s + 1 unknown slices: Nt - s + 1 a power of two, 2..512,
+ *            takes the radix FFT; otherwise Nt must be a power of two in
+ *            8..128 and takes the dense transform
  *   dt       time step (> 0); the window is T = Nt dt
  *   alpha    circulant parameter, 0 < alpha < 1
- *   scheme   EXPDIAG_ETD1, EXPDIAG_ETD2, or EXPDIAG_EBDF2 (linear problems
- *            only; EUNSUPPORTED otherwise)
+ *   scheme   EXPDIAG_ETD1, EXPDIAG_ETD2, EXPDIAG_IF1, or EXPDIAG_EBDF2 ..
+ *            EXPDIAG_EBDF6 (linear problems only; EUNSUPPORTED otherwise)
  *   p        PDE coefficients and options (host pointer)
  *   hip_stream  hipStream_t to enqueue on (NULL = default stream)
  *   out      receives the handle
@@ -156,7 +172,9 @@ size_t expdiag_footprint_bytes(const expdiag_grid* g, int Nt, int scheme,
  * pcond-1st-order, with Q = I - C_0 (x) A and f = (A u0 + dt phi1 N(u0),
  * 0, .., 0)); slice n of R is A u_{n-1} + G_n - u_n with u_0 = u0.
  * EBDF2: slice 1 is A u0 - u_1, slices 2..Nt are f_2 - R v (eq.
- * all_at_once_2ndorder) with v = (u_2..u_Nt) and u_1 := A u0 in f_2.
+ * all_at_once_2ndorder) with v = (u_2..u_Nt) and u_1 := A u0 in f_2;
+ * EBDF3..6 likewise: slice m < s is A^m u0 - u_m, slices s..Nt are
+ * f_s - R_s v with u_m := A^m u0 in f_s.
  *   u0    Ns doubles (device)     U, R   Nt*Ns doubles (device, distinct)
  *   rnorm if non-NULL, host pointer receiving ||R||_2 (the call then
  *         synchronises); if NULL the call only enqueues. */
@@ -169,14 +187,17 @@ int expdiag_residual(expdiag_t h, const double* u0, const double* U,
  * time transform.  R and S are Nt*Ns doubles (device); S may equal R.
  * EBDF2: slice 1 is copied, slices 2..Nt get R_alpha^{-1} by the steps of
  * eq. exp_ParaDiag_steps_2ndorder (shifted solves
- * (I - 4/3 lambda_0 A + 1/3 lambda_1 A^2)^{-1}) on Nt - 1 points.
+ * (I - 4/3 lambda_0 A + 1/3 lambda_1 A^2)^{-1}) on Nt - 1 points; EBDF3..6:
+ * slices 1..s-1 copied, slices s..Nt get (R_s^alpha)^{-1} with shifted
+ * solves (I - sum_i beta_i lambda_0^i A^i)^{-1} on Nt - s + 1 points.
  * Enqueue only. */
 int expdiag_precond_apply(expdiag_t h, const double* R, double* S);
 
 /* Preconditioned fixed point u^{k+1} = u^k + Q_alpha^{-1}(f + G(u^k) - Q u^k)
  * (eq. pcond-1st-order; nonlinear term lagged as in Sec. 6.2); for EBDF2
  * v^{k+1} = v^k + R_alpha^{-1}(f_2 - R v^k) (eq. pcond-2nd-order), slice 1
- * being set to A u0.
+ * being set to A u0, and for EBDF3..6 the same with R_s, slices m < s set
+ * to A^m u0.
  *   u0        initial condition, Ns doubles (device)
  *   U         in: initial iterate (zeros in the paper's experiments),
  *             out: final iterate; Nt*Ns doubles (device)
@@ -192,7 +213,8 @@ int expdiag_iterate(expdiag_t h, const double* u0, double* U, int max_iter,
 /* Left-preconditioned GMRES(restart) (Sec. 3.2, Theorem thm_gmres1's
  * system Q_alpha^{-1} Q u = Q_alpha^{-1} f) for linear problems (EBDF2:
  * R_alpha^{-1} R v = R_alpha^{-1} f_2 of Sec. 4.2, slice 1 set to A u0
- * first); for
+ * first; EBDF3..6: the GMRES preconditioners of Sec. bdfs, slices m < s
+ * set to A^m u0 first); for
  * nonlinear problems, Newton's method on R(U) = 0 whose correction
  * equations (Q - G'(U)) d = R(U) are solved by the same preconditioned
  * GMRES with forcing term min(1e-3, ||R_j|| / ||R_0||).
@@ -206,6 +228,22 @@ int expdiag_iterate(expdiag_t h, const double* u0, double* U, int max_iter,
  * U: in initial guess, out solution.  Synchronises the stream. */
 int expdiag_gmres(expdiag_t h, const double* u0, double* U, int restart,
                   int max_iter, double tol, int* iters, double* rel_resid);
+
+/* Preconditioned BiCGStab (the bracketed timings of Table cpu_time_combined;
+ * van der Vorst's method, shadow residual r^_0 = r_0) on the same
+ * left-preconditioned system as expdiag_gmres, with the same Newton outer
+ * loop for nonlinear problems (BiCGStab as the inner solver, same forcing
+ * term).  Each iteration applies the preconditioned operator twice; the
+ * scalars stay on the device and the call synchronises once per iteration.
+ * Needs a handle created with gmres_restart >= 5 (it uses six vectors of
+ * that Krylov workspace); EINVAL otherwise.
+ *   max_iter  cap on total BiCGStab iterations
+ *   tol       as expdiag_gmres (an iteration also ends the run when its
+ *             intermediate residual s already meets it)
+ *   iters, rel_resid  as expdiag_gmres
+ * U: in initial guess, out solution.  Synchronises the stream. */
+int expdiag_bicgstab(expdiag_t h, const double* u0, double* U, int max_iter,
+                     double tol, int* iters, double* rel_resid);
 
 /* Kernel-class timing.  While enabled (mask != 0) every launch's
  * algorithmic bytes (the data it must read and write once) and count are
@@ -229,8 +267,8 @@ int expdiag_set_graph(expdiag_t h, int on);
  * registers and LDS (any Nt), 1 = dense complex Nt x Nt GEMM on FP64 MFMA
  * (8 <= Nt <= 128).  Both compute the same operator; results agree to
  * rounding.  set() rebuilds the handle's plan (EUNSUPPORTED if the variant
- * does not cover Nt; an EBDF2 handle has the one variant its Nt - 1 points
- * allow); get() returns the current one. */
+ * does not cover Nt; an EBDF handle has the one variant its Nt - s + 1
+ * points allow); get() returns the current one. */
 int expdiag_set_time_variant(expdiag_t h, int variant);
 int expdiag_get_time_variant(expdiag_t h);
 
@@ -240,8 +278,8 @@ int expdiag_get_time_variant(expdiag_t h);
  * gfx950/d<d>/<n0>x<n1>x<n2>/Nt<Nt>/<fp64|mixed>; a cached entry is used
  * without measuring.  variant, us_fft, us_dense (host, nullable) receive
  * the choice and the per-launch times (us_dense = -1 when not applicable).
- * EBDF2 handles have one variant: it is timed and kept (the other time is
- * -1), and the cache is neither read nor written. */
+ * EBDF and IF1 handles have one variant: it is timed and kept (the other
+ * time is -1), and the cache is neither read nor written. */
 int expdiag_autotune(expdiag_t h, const char* cache_path, int* variant,
                      double* us_fft, double* us_dense);
 

@@ -39,7 +39,7 @@
 
 #include "../../include/expdiag.h"
 #include "kernels_dense.hpp"
-#include "kernels_bdf2.hpp"
+#include "kernels_bdf.hpp"
 #include "kernels_fft.hpp"
 #include "kernels_krylov.hpp"
 #include "kernels_passb.hpp"
@@ -298,10 +298,18 @@ bool dense_ok(int Nt) {
 int dense_blocks(long Nk) {
   return static_cast<int>((Nk + DENSE_C - 1) / DENSE_C);
 }
-// Time points of the transform in pass B: Nt, or Nt - 1 for EBDF2, whose
-// window row 0 is the fixed start u_1 = A u_0.
+// Order s of an exponential BDF scheme (EBDF2, EBDF3..EBDF6), else 0.
+int bdf_order(int scheme) {
+  if (scheme == EXPDIAG_EBDF2) return 2;
+  if (scheme >= EXPDIAG_EBDF3 && scheme <= EXPDIAG_EBDF6)
+    return scheme - EXPDIAG_EBDF3 + 3;
+  return 0;
+}
+// Time points of the transform in pass B: Nt, or Nt - s + 1 for an order-s
+// exponential BDF, whose window rows 0..s-2 are the fixed starts A^m u_0.
 int time_len(const expdiag_ctx* h) {
-  return h->scheme == EXPDIAG_EBDF2 ? h->Nt - 1 : h->Nt;
+  const int s = bdf_order(h->scheme);
+  return s > 0 ? h->Nt - s + 1 : h->Nt;
 }
 // Pass A: the slices whose N the residual needs and the N^ slot of the
 // first.  ETD: u_0..u_{Nt-1} for rows 0..Nt-1, u_0 from the initial
@@ -313,9 +321,16 @@ long pass_a_slices(const expdiag_ctx* h) {
 long pass_a_slot(const expdiag_ctx* h) {
   return h->scheme == EXPDIAG_IF1 ? 0 : 1;
 }
-// EBDF2 windows take the radix FFT when Nt - 1 is a power of two (2..512)
-// and the dense transform when Nt is one (8..128).
-bool bdf2_fft_ok(int Nt) { return Nt >= 3 && Nt <= 513 && is_pow2(Nt - 1); }
+// Order-s exponential BDF windows take the radix FFT when N = Nt - s + 1
+// is a power of two (2..512) and the dense transform when Nt is one
+// (8..128, N >= 2).
+bool bdf_fft_ok(int Nt, int s) {
+  const int N = Nt - s + 1;
+  return N >= 2 && N <= 512 && is_pow2(N);
+}
+bool bdf_ok(int Nt, int s) {
+  return bdf_fft_ok(Nt, s) || (dense_ok(Nt) && Nt - s + 1 >= 2);
+}
 // Spectral index width the kernels weight inner products by: entries at
 // kl = kappa % nh in {0, nh - 1} count once, the others twice (Parseval on
 // a half spectrum).  A full spectrum (complex state) weights every entry
@@ -393,6 +408,7 @@ PassBArgs passb_args(expdiag_ctx* h) {
   a.nblocks = passb_blocks(h);
   a.inv_ns = 1.0 / static_cast<double>(h->Ns);
   a.same_slice = h->scheme == EXPDIAG_IF1 ? 1 : 0;
+  a.bdf_s = bdf_order(h->scheme);
   a.jac_mode = h->scheme == EXPDIAG_IF1 ? h->p.jacobian : 0;
   a.sigma = 0.0;
   a.jac_c[0] = h->dt * h->p.n1;
@@ -456,24 +472,35 @@ double passb_bytes(const PassBArgs& a, int Nt, int mode, size_t nb) {
 template <int MODE, typename TN>
 int launch_passb1(expdiag_ctx* h, const PassBArgs& a) {
   ProfScope ps(h, P_PASSB, passb_bytes(a, h->Nt, MODE, sizeof(cx<TN>)));
-  if (h->scheme == EXPDIAG_EBDF2) {
+  if (const int s = bdf_order(h->scheme); s > 0) {
+    // order 2 has its own instantiation; 3..6 share one that reads s
     bool ok = false;
     if (h->tvariant == 1) {
       ok = dispatch_pow2<DENSE_NT_MIN, DENSE_NT_MAX>(h->Nt, [&](auto Nc) {
         constexpr int NN = decltype(Nc)::value;
-        hipLaunchKernelGGL((passb_bdf2_kernel1<NN, MODE>),
-                           dim3(dense_blocks(h->Nk)), dim3(DENSE_THREADS), 0,
-                           h->stream, a);
+        const dim3 grid(dense_blocks(h->Nk)), th(DENSE_THREADS);
+        if (s == 2)
+          hipLaunchKernelGGL((passb_bdf_kernel1<NN, 2, MODE>), grid, th, 0,
+                             h->stream, a);
+        else
+          hipLaunchKernelGGL((passb_bdf_kernel1<NN, 0, MODE>), grid, th, 0,
+                             h->stream, a);
       });
     } else {
-      ok = dispatch_pow2<2, 512>(h->Nt - 1, [&](auto Nc) {
+      ok = dispatch_pow2<2, 512>(time_len(h), [&](auto Nc) {
         constexpr int NN = decltype(Nc)::value;
-        hipLaunchKernelGGL((passb_bdf2_fft_kernel1<NN, MODE>),
-                           dim3(passb_blocks_nt(NN, h->Nk)),
-                           dim3(PassBShape<NN>::THREADS), 0, h->stream, a);
+        const dim3 grid(passb_blocks_nt(NN, h->Nk));
+        const dim3 th(PassBShape<NN>::THREADS);
+        if (s == 2)
+          hipLaunchKernelGGL((passb_bdf_fft_kernel1<NN, 2, MODE>), grid, th,
+                             0, h->stream, a);
+        else
+          hipLaunchKernelGGL((passb_bdf_fft_kernel1<NN, 0, MODE>), grid, th,
+                             0, h->stream, a);
       });
     }
-    if (!ok) return fail(h, EXPDIAG_EUNSUPPORTED, "EBDF2 Nt %d", h->Nt);
+    if (!ok)
+      return fail(h, EXPDIAG_EUNSUPPORTED, "EBDF%d Nt %d", s, h->Nt);
     HIPCHK(h, hipGetLastError());
     return 0;
   }
@@ -704,13 +731,15 @@ void plan_col(Plan& P, int stage, int L, const ColJob& j) {
              (sizeof(TI) + sizeof(TO));
 }
 
-void plan_passb(Plan& P, int stage, int Nt, const PassBArgs& a, size_t nb,
-                int variant, bool reduce_after) {
-  Group& g = plan_group(P, stage, K_PASSB, variant, Nt, PB_ITERATE, 0, 0);
+// `len` keys the group (the transform length of the radix kernels, the
+// window length of the dense ones); `rows` is the window length.
+void plan_passb(Plan& P, int stage, int len, int rows, const PassBArgs& a,
+                size_t nb, int variant, bool reduce_after) {
+  Group& g = plan_group(P, stage, K_PASSB, variant, len, PB_ITERATE, 0, 0);
   g.pj.push_back(a);
   if (reduce_after) g.red.push_back(a);
   g.start.push_back(g.start.back() + a.nblocks);
-  g.bytes += passb_bytes(a, Nt, PB_ITERATE, nb);
+  g.bytes += passb_bytes(a, rows, PB_ITERATE, nb);
 }
 
 // pass A of one instance in precision T, gated on phase `ph`
@@ -835,15 +864,19 @@ void plan_iteration(Plan& P, expdiag_ctx* h, Ctl* ctl, Ctl* mirror,
   if (h->nonlinear && h->mixed) a.Nh32 = nh_view<float>(h);
   const bool hosted = h->nonlinear && plan_pass_a_mp(P, h, ctl, a);
   // pass B variant: 0 radix FFT, 1 dense, 2 EBDF2 dense, 3 EBDF2 radix FFT,
-  // 4 radix FFT with complex symbols (the group length is the transform
-  // length for the radix kernels)
+  // 4 radix FFT with complex symbols, 5 and 6 the dense and radix FFT
+  // kernels of EBDF3..6 (the group length is the transform length for the
+  // radix kernels)
   int variant = h->tvariant;
-  if (h->scheme == EXPDIAG_EBDF2)
+  const int s = bdf_order(h->scheme);
+  if (s == 2)
     variant = h->tvariant == 1 ? 2 : 3;
+  else if (s > 2)
+    variant = h->tvariant == 1 ? 5 : 6;
   else if (variant == 0 && h->cplx)
     variant = 4;
-  const int len = variant == 3 ? time_len(h) : h->Nt;
-  plan_passb(P, 5, len, a, sizeof(cx<double>), variant, !hosted);
+  const int len = variant == 3 || variant == 6 ? time_len(h) : h->Nt;
+  plan_passb(P, 5, len, h->Nt, a, sizeof(cx<double>), variant, !hosted);
 }
 
 // Algorithmic bytes of one iteration of a plan.
@@ -1002,17 +1035,25 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st,
             klaunch(ps, passb_dense_kernel<NN, PB_ITERATE, double>, dim3(grid),
                     dim3(DENSE_THREADS), st, J, g.dstart, nj);
           });
-        } else if (g.tcode == 2) {
+        } else if (g.tcode == 2 || g.tcode == 5) {
           ok = dispatch_pow2<DENSE_NT_MIN, DENSE_NT_MAX>(g.len, [&](auto Nc) {
             constexpr int NN = decltype(Nc)::value;
-            klaunch(ps, passb_bdf2_kernel<NN>, dim3(grid),
-                    dim3(DENSE_THREADS), st, J, g.dstart, nj);
+            if (g.tcode == 2)
+              klaunch(ps, passb_bdf_kernel<NN, 2>, dim3(grid),
+                      dim3(DENSE_THREADS), st, J, g.dstart, nj);
+            else
+              klaunch(ps, passb_bdf_kernel<NN, 0>, dim3(grid),
+                      dim3(DENSE_THREADS), st, J, g.dstart, nj);
           });
-        } else if (g.tcode == 3) {
+        } else if (g.tcode == 3 || g.tcode == 6) {
           ok = dispatch_pow2<2, 512>(g.len, [&](auto Nc) {
             constexpr int NN = decltype(Nc)::value;
-            klaunch(ps, passb_bdf2_fft_kernel<NN>, dim3(grid),
-                    dim3(PassBShape<NN>::THREADS), st, J, g.dstart, nj);
+            if (g.tcode == 3)
+              klaunch(ps, passb_bdf_fft_kernel<NN, 2>, dim3(grid),
+                      dim3(PassBShape<NN>::THREADS), st, J, g.dstart, nj);
+            else
+              klaunch(ps, passb_bdf_fft_kernel<NN, 0>, dim3(grid),
+                      dim3(PassBShape<NN>::THREADS), st, J, g.dstart, nj);
           });
         } else {
           ok = dispatch_pow2<2, 512>(g.len, [&](auto Nc) {
@@ -1337,11 +1378,11 @@ int build_tables(expdiag_ctx* h) {
   SymbolTables sym;
   symbol_tables(h, sym);
   const int Nt = h->Nt;
-  // The transform runs over N time points: Nt, or for EBDF2 the Nt - 1
-  // unknown slices 2..Nt, which sit at row offset o = 1 of a window.
-  const bool bdf2 = h->scheme == EXPDIAG_EBDF2;
-  const int N = bdf2 ? Nt - 1 : Nt;
-  const int o = bdf2 ? 1 : 0;
+  // The transform runs over N time points: Nt, or for an order-s
+  // exponential BDF the N = Nt - s + 1 unknown slices s..Nt, which sit at
+  // row offset o = s - 1 of a window.
+  const int N = time_len(h);
+  const int o = Nt - N;
   std::vector<double> gam(Nt, 1.0), igam(Nt, 1.0);
   std::vector<cx<double>> lam(Nt, mk(0.0, 0.0));
   // e^{2 pi i j/N}, j < N: every angle the time tables use
@@ -1606,18 +1647,18 @@ size_t expdiag_footprint_bytes(const expdiag_grid* g, int Nt, int scheme,
   Sizes s{};
   if (check_grid(g, &s) != 0) return 0;
   if (scheme != EXPDIAG_ETD1 && scheme != EXPDIAG_ETD2 &&
-      scheme != EXPDIAG_EBDF2 && scheme != EXPDIAG_IF1)
+      scheme != EXPDIAG_IF1 && bdf_order(scheme) == 0)
     return 0;
-  if (scheme == EXPDIAG_EBDF2) {
-    if (!bdf2_fft_ok(Nt) && !dense_ok(Nt)) return 0;
+  if (bdf_order(scheme) > 0) {
+    if (!bdf_ok(Nt, bdf_order(scheme))) return 0;
   } else if (!is_pow2(Nt) || Nt < 2 || Nt > 512) {
     return 0;
   }
   if (precision != EXPDIAG_FP64 && precision != EXPDIAG_MIXED) return 0;
   if (gmres_restart < 0 || gmres_restart > 64) return 0;
   // the nonlinearity is not known here: report the nonlinear footprint
-  // (EBDF2 is linear only)
-  return footprint(s, g->dim, Nt, scheme != EXPDIAG_EBDF2,
+  // (the exponential BDF schemes are linear only)
+  return footprint(s, g->dim, Nt, bdf_order(scheme) == 0,
                    precision == EXPDIAG_MIXED, gmres_restart);
 }
 
@@ -1628,7 +1669,8 @@ namespace {
 int validate_params(int Nt, double dt, double alpha, int scheme,
                     const expdiag_problem* p) {
   if (Nt < 2) return fail(nullptr, EXPDIAG_EINVAL, "Nt must be >= 2");
-  if (scheme != EXPDIAG_EBDF2 && (!is_pow2(Nt) || Nt > 512))
+  const int bs = bdf_order(scheme);
+  if (bs == 0 && (!is_pow2(Nt) || Nt > 512))
     return fail(nullptr, EXPDIAG_EUNSUPPORTED,
                 "Nt must be a power of two <= 512");
   if (!(dt > 0.0) || !std::isfinite(dt))
@@ -1636,18 +1678,18 @@ int validate_params(int Nt, double dt, double alpha, int scheme,
   if (!(alpha > 0.0 && alpha < 1.0))
     return fail(nullptr, EXPDIAG_EINVAL, "alpha must lie in (0, 1)");
   if (scheme != EXPDIAG_ETD1 && scheme != EXPDIAG_ETD2 &&
-      scheme != EXPDIAG_EBDF2 && scheme != EXPDIAG_IF1)
+      scheme != EXPDIAG_IF1 && bs == 0)
     return fail(nullptr, EXPDIAG_EINVAL, "unknown scheme %d", scheme);
   if (p->jacobian < 0 || p->jacobian > 2)
     return fail(nullptr, EXPDIAG_EINVAL, "jacobian must be 0, 1 or 2");
-  if (scheme == EXPDIAG_EBDF2 &&
-      (p->n1 != 0.0 || p->n2 != 0.0 || p->n3 != 0.0))
+  if (bs > 0 && (p->n1 != 0.0 || p->n2 != 0.0 || p->n3 != 0.0))
     return fail(nullptr, EXPDIAG_EUNSUPPORTED,
-                "EBDF2 is for linear problems (n1 = n2 = n3 = 0)");
-  if (scheme == EXPDIAG_EBDF2 && !bdf2_fft_ok(Nt) && !dense_ok(Nt))
+                "EBDF%d is for linear problems (n1 = n2 = n3 = 0)", bs);
+  if (bs > 0 && !bdf_ok(Nt, bs))
     return fail(nullptr, EXPDIAG_EUNSUPPORTED,
-                "EBDF2 needs Nt - 1 a power of two <= 512, or Nt a power "
-                "of two in %d..%d", DENSE_NT_MIN, DENSE_NT_MAX);
+                "EBDF%d needs Nt - %d a power of two in 2..512, or Nt a "
+                "power of two in %d..%d", bs, bs - 1, DENSE_NT_MIN,
+                DENSE_NT_MAX);
   if (!(p->a >= 0.0) || !(p->c >= 0.0) || !std::isfinite(p->a) ||
       !std::isfinite(p->c) || !std::isfinite(p->n1) ||
       !std::isfinite(p->n2) || !std::isfinite(p->n3))
@@ -1680,13 +1722,22 @@ int reinit_params(expdiag_ctx* h, double dt, double alpha, int scheme,
   RCHK(validate_params(h->Nt, dt, alpha, scheme, p));
   if ((p->complex_state == 1) != h->cstate)
     return fail(h, EXPDIAG_EINVAL, "complex_state differs from the handle's");
-  h->dt = dt;
-  h->alpha = alpha;
-  if (scheme == EXPDIAG_EBDF2)
-    h->tvariant = bdf2_fft_ok(h->Nt) ? 0 : 1;  // by N = Nt - 1
-  else if (h->scheme == EXPDIAG_EBDF2)
+  const int old_scheme = h->scheme, old_tv = h->tvariant;
+  const int bs = bdf_order(scheme);
+  if (bs > 0)
+    h->tvariant = bdf_fft_ok(h->Nt, bs) ? 0 : 1;  // by N = Nt - s + 1
+  else if (bdf_order(h->scheme) > 0)
     h->tvariant = 0;
   h->scheme = scheme;
+  if (passb_blocks(h) > h->max_partials) {
+    // a longer transform than the handle was sized for
+    h->scheme = old_scheme;
+    h->tvariant = old_tv;
+    return fail(h, EXPDIAG_EINVAL,
+                "scheme %d needs a larger handle than this one", scheme);
+  }
+  h->dt = dt;
+  h->alpha = alpha;
   h->p = *p;
   h->p.gmres_restart = h->restart_cap;
   return build_tables(h);
@@ -1729,7 +1780,8 @@ int create_impl(const expdiag_grid* g, int Nt, double dt, double alpha,
   h->mixed = p->precision == EXPDIAG_MIXED;
   h->cstate = p->complex_state == 1;
   h->restart_cap = p->gmres_restart;
-  if (scheme == EXPDIAG_EBDF2) h->tvariant = bdf2_fft_ok(Nt) ? 0 : 1;
+  if (bdf_order(scheme) > 0)
+    h->tvariant = bdf_fft_ok(Nt, bdf_order(scheme)) ? 0 : 1;
 
   const size_t st = static_cast<size_t>(Nt) * h->Nk * sizeof(cx<double>);
   int rc = 0;

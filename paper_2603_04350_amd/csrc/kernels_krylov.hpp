@@ -128,6 +128,119 @@ __global__ void __launch_bounds__(KRY_THREADS)
   if (e < n) out[e] = in[e] * s;
 }
 
+// ---- BiCGStab (Table cpu_time_combined's preconditioned BiCGStab) -------
+// Scalars live on the device in one array k[] so that an iteration needs a
+// single host synchronisation (its convergence test): the reductions write
+// the inner products, bicg_coef_kernel turns them into alpha, omega, beta,
+// and the vector kernels read those.
+enum {
+  BI_RV = 0,      // <r^, v>   (kdot with V = r^, w = v; [1] is <v, v>)
+  BI_SS = 2,      // <s, s>
+  BI_ST = 3,      // <s, t>    (kdot with V = s, w = t; [4] is <t, t>)
+  BI_TT = 4,
+  BI_RHR = 5,     // <r^, r>   (after the x, r update; [6] is <r, r>)
+  BI_RR = 6,
+  BI_RHO = 8,     // rho = <r^, r> of the previous iteration
+  BI_ALPHA = 9,
+  BI_OMEGA = 10,
+  BI_BETA = 11,
+  BI_SLOTS = 12
+};
+
+// phase 0: alpha = rho / <r^, v>
+// phase 1: omega = <s, t> / <t, t>, or 0 when ||s||^2 <= stop2 (the
+//          iteration ends at x + alpha p, as BiCGStab's half-step exit)
+// phase 2: beta = (<r^, r> / rho)(alpha / omega), rho = <r^, r>
+__global__ void bicg_coef_kernel(double* __restrict__ k, int phase,
+                                 double stop2) {
+  if (threadIdx.x != 0) return;
+  if (phase == 0) {
+    k[BI_ALPHA] = k[BI_RHO] / k[BI_RV];
+  } else if (phase == 1) {
+    k[BI_OMEGA] = k[BI_SS] <= stop2 ? 0.0 : k[BI_ST] / k[BI_TT];
+  } else {
+    const double om = k[BI_OMEGA];
+    k[BI_BETA] = om == 0.0 ? 0.0 : (k[BI_RHR] / k[BI_RHO]) * (k[BI_ALPHA] / om);
+    k[BI_RHO] = k[BI_RHR];
+  }
+}
+
+// s = r - alpha v; block partials of <s, s> into part[b*ld]
+__global__ void __launch_bounds__(KRY_THREADS)
+    kbicg_s_kernel(cx<double>* __restrict__ s, const cx<double>* __restrict__ r,
+                   const cx<double>* __restrict__ v,
+                   const double* __restrict__ k, long n, long Nk, int nh,
+                   double* __restrict__ part, int ld) {
+  __shared__ double red[KRY_THREADS / 64];
+  const double al = k[BI_ALPHA];
+  const long base = static_cast<long>(blockIdx.x) * KRY_PER_BLOCK;
+  cx<double> rv[KRY_PER_THREAD], vv[KRY_PER_THREAD];
+#pragma unroll
+  for (int q = 0; q < KRY_PER_THREAD; ++q) {
+    const long e = base + threadIdx.x + q * KRY_THREADS;
+    rv[q] = e < n ? r[e] : mk(0.0, 0.0);
+    vv[q] = e < n ? v[e] : mk(0.0, 0.0);
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int q = 0; q < KRY_PER_THREAD; ++q) {
+    const long e = base + threadIdx.x + q * KRY_THREADS;
+    if (e < n) {
+      const cx<double> x = rv[q] - vv[q] * al;
+      s[e] = x;
+      acc += half_weight(e, Nk, nh) * norm2(x);
+    }
+  }
+  const double t = kry_block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x * ld] = t;
+}
+
+// x += alpha p + omega s; r = s - omega t; block partials of <r^, r> and
+// <r, r> into part[b*ld], part[b*ld + 1]
+__global__ void __launch_bounds__(KRY_THREADS)
+    kbicg_xr_kernel(cx<double>* __restrict__ x, cx<double>* __restrict__ r,
+                    const cx<double>* __restrict__ p,
+                    const cx<double>* __restrict__ s,
+                    const cx<double>* __restrict__ t,
+                    const cx<double>* __restrict__ rh,
+                    const double* __restrict__ k, long n, long Nk, int nh,
+                    double* __restrict__ part, int ld) {
+  __shared__ double red[KRY_THREADS / 64];
+  const double al = k[BI_ALPHA], om = k[BI_OMEGA];
+  const long base = static_cast<long>(blockIdx.x) * KRY_PER_BLOCK;
+  double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+  for (int q = 0; q < KRY_PER_THREAD; ++q) {
+    const long e = base + threadIdx.x + q * KRY_THREADS;
+    if (e < n) {
+      const cx<double> pe = p[e], se = s[e], te = t[e], he = rh[e];
+      const cx<double> xe = x[e];
+      x[e] = xe + pe * al + se * om;
+      const cx<double> re = se - te * om;
+      r[e] = re;
+      const double w = half_weight(e, Nk, nh);
+      a0 += w * (he.x * re.x + he.y * re.y);
+      a1 += w * norm2(re);
+    }
+  }
+  const double t0 = kry_block_sum(a0, red);
+  const double t1 = kry_block_sum(a1, red);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x * ld] = t0;
+    part[blockIdx.x * ld + 1] = t1;
+  }
+}
+
+// p = r + beta (p - omega v)
+__global__ void __launch_bounds__(KRY_THREADS)
+    kbicg_p_kernel(cx<double>* __restrict__ p, const cx<double>* __restrict__ r,
+                   const cx<double>* __restrict__ v,
+                   const double* __restrict__ k, long n) {
+  const double be = k[BI_BETA], om = k[BI_OMEGA];
+  const long e = static_cast<long>(blockIdx.x) * KRY_THREADS + threadIdx.x;
+  if (e < n) p[e] = r[e] + (p[e] - v[e] * om) * be;
+}
+
 // zero fill (a plain kernel rather than a memset so that it can sit in a
 // captured graph)
 __global__ void __launch_bounds__(KRY_THREADS)

@@ -70,6 +70,7 @@ struct PassBArgs {
   // space-time (dt times the mean of N'(u)); the block holding kappa = 0
   // adds sum_l Re U^_l(0) as partial 3.  inv_ntns = 1 / (Nt Ns).
   int same_slice;
+  int bdf_s;  // order s of an exponential BDF window (2..6), else 0
   int jac_mode;
   double sigma;
   double jac_c[3];

@@ -25,13 +25,18 @@ EXPDIAG_ETD1 = 1
 EXPDIAG_ETD2 = 2
 EXPDIAG_EBDF2 = 3
 EXPDIAG_IF1 = 4
+EXPDIAG_EBDF3 = 5
+EXPDIAG_EBDF4 = 6
+EXPDIAG_EBDF5 = 7
+EXPDIAG_EBDF6 = 8
 EXPDIAG_FP64 = 0
 EXPDIAG_MIXED = 1
 
 EXPORTED = (
     "expdiag_create", "expdiag_destroy", "expdiag_set_stream",
     "expdiag_footprint_bytes", "expdiag_residual", "expdiag_precond_apply",
-    "expdiag_iterate", "expdiag_gmres", "expdiag_profile_enable",
+    "expdiag_iterate", "expdiag_gmres", "expdiag_bicgstab",
+    "expdiag_profile_enable",
     "expdiag_profile_read", "expdiag_strerror", "expdiag_last_error",
     "expdiag_set_graph", "expdiag_batch_create", "expdiag_batch_destroy",
     "expdiag_batch_iterate", "expdiag_batch_last_error",
@@ -99,6 +104,8 @@ def load(path: str = LIB_PATH):
                                   ctypes.POINTER(ci), ctypes.POINTER(cd)]
     L.expdiag_gmres.argtypes = [vp, vp, vp, ci, ci, cd,
                                 ctypes.POINTER(ci), ctypes.POINTER(cd)]
+    L.expdiag_bicgstab.argtypes = [vp, vp, vp, ci, cd,
+                                   ctypes.POINTER(ci), ctypes.POINTER(cd)]
     L.expdiag_profile_enable.argtypes = [vp, ci]
     L.expdiag_profile_read.argtypes = [vp, ctypes.POINTER(cd),
                                        ctypes.POINTER(ctypes.c_long),
@@ -262,6 +269,16 @@ def expdiag_gmres(h, u0, U, restart, max_iter, tol):
     return rc, it.value, rel.value
 
 
+def expdiag_bicgstab(h, u0, U, max_iter, tol):
+    it = ctypes.c_int(0)
+    rel = ctypes.c_double(0.0)
+    rc = load().expdiag_bicgstab(h, _ptr(u0, name="u0"), _ptr(U, name="U"),
+                                 int(max_iter), float(tol), ctypes.byref(it),
+                                 ctypes.byref(rel))
+    _check(rc, h, ok=(EXPDIAG_OK, EXPDIAG_NOT_CONVERGED))
+    return rc, it.value, rel.value
+
+
 def expdiag_profile_enable(h, mask=0x1F):
     """mask: bit i brackets launches of class i with events; 0 disables."""
     return _check(load().expdiag_profile_enable(h, int(mask)), h)
@@ -334,6 +351,9 @@ class Solver:
 
     def gmres(self, u0, U, restart=20, max_iter=400, tol=1e-10):
         return expdiag_gmres(self.h, u0, U, restart, max_iter, tol)
+
+    def bicgstab(self, u0, U, max_iter=400, tol=1e-10):
+        return expdiag_bicgstab(self.h, u0, U, max_iter, tol)
 
 
 def expdiag_set_graph(h, on=True):

@@ -55,7 +55,8 @@ def _create(lib, shape, Nt, dt, alpha, scheme, prob):
     ((64,), 8, 0.0, 1e-2, 1, X.make_problem(1.0), X.EXPDIAG_EINVAL),
     ((64,), 8, 0.1, 0.0, 1, X.make_problem(1.0), X.EXPDIAG_EINVAL),
     ((64,), 8, 0.1, 1.0, 1, X.make_problem(1.0), X.EXPDIAG_EINVAL),
-    ((64,), 8, 0.1, 1e-2, 5, X.make_problem(1.0), X.EXPDIAG_EINVAL),
+    ((64,), 8, 0.1, 1e-2, 9, X.make_problem(1.0), X.EXPDIAG_EINVAL),
+    ((64,), 8, 0.1, 1e-2, 0, X.make_problem(1.0), X.EXPDIAG_EINVAL),
     ((64,), 8, 0.1, 1e-2, X.EXPDIAG_IF1, X.make_problem(1.0, jacobian=3),
      X.EXPDIAG_EINVAL),
     # EBDF2: linear problems, 8 <= Nt <= 128
@@ -70,6 +71,17 @@ def _create(lib, shape, Nt, dt, alpha, scheme, prob):
     ((64,), 1025, 0.1, 1e-2, X.EXPDIAG_EBDF2, X.make_problem(1.0),
      X.EXPDIAG_EUNSUPPORTED),
     ((64,), 65, 0.1, 1e-2, X.EXPDIAG_ETD1, X.make_problem(1.0),
+     X.EXPDIAG_EUNSUPPORTED),
+    # EBDF3..6: linear; Nt - s + 1 a power of two 2..512, or Nt one 8..128
+    ((64,), 16, 0.1, 1e-2, X.EXPDIAG_EBDF4, X.make_problem(1.0, n3=-1.0),
+     X.EXPDIAG_EUNSUPPORTED),
+    ((64,), 65, 0.1, 1e-2, X.EXPDIAG_EBDF3, X.make_problem(1.0),
+     X.EXPDIAG_EUNSUPPORTED),
+    ((64,), 6, 0.1, 1e-2, X.EXPDIAG_EBDF6, X.make_problem(1.0),
+     X.EXPDIAG_EUNSUPPORTED),
+    ((64,), 4, 0.1, 1e-2, X.EXPDIAG_EBDF4, X.make_problem(1.0),
+     X.EXPDIAG_EUNSUPPORTED),
+    ((64,), 518, 0.1, 1e-2, X.EXPDIAG_EBDF6, X.make_problem(1.0),
      X.EXPDIAG_EUNSUPPORTED),
     # complex coefficients need a complex state; a complex state is linear
     ((64,), 8, 0.1, 1e-2, 1, X.make_problem(0.0, a_im=1.0, complex_state=0),
@@ -124,3 +136,11 @@ def test_footprint_bytes(lib):
     assert X.expdiag_footprint_bytes((256, 256), 65, X.EXPDIAG_EBDF2) > \
         2 * state
     assert X.expdiag_footprint_bytes((256, 256), 65, X.EXPDIAG_ETD1) == 0
+    # EBDF3..6 likewise: Nt - s + 1 a power of two, or Nt one in 8..128
+    for sch, Nt_fft in ((X.EXPDIAG_EBDF3, 66), (X.EXPDIAG_EBDF4, 67),
+                        (X.EXPDIAG_EBDF5, 68), (X.EXPDIAG_EBDF6, 69)):
+        assert 2 * state <= X.expdiag_footprint_bytes(
+            (256, 256), 64, sch) < 3 * state
+        assert X.expdiag_footprint_bytes((256, 256), Nt_fft, sch) > 2 * state
+        assert X.expdiag_footprint_bytes((256, 256), 65, sch) == 0
+    assert X.expdiag_footprint_bytes((256, 256), 64, 9) == 0
