@@ -162,16 +162,17 @@ def bench_single(inst, prec, steps, warmup):
     return out
 
 
-def bench_ebdf2(steps, warmup, Nt):
-    """Second-order exponential BDF window (Sec. 4) on the headline grid:
-    solves from zero to ||S||/||U|| <= TOL, then the pass B launches timed
-    with kernel-attached events.  Nt = 65 (64 unknown slices) takes the
-    radix FFT pass B, HBM-bound: algorithmic bytes 32 per window entry plus
-    the per-kappa tables.  Nt = 64 (63 unknown slices) takes the dense
-    pass B, one 2Nt x 2Nt real GEMM pair per 16 kappa columns on FP64
-    MFMA: executed flops 2 * 2 * (2Nt)^2 * 16 per block."""
+def bench_ebdf2(steps, warmup, Nt, order=2):
+    """Exponential BDF window of order 2 (Sec. 4) or 3..6 (Sec. bdfs) on the
+    headline grid: solves from zero to ||S||/||U|| <= TOL, then the pass B
+    launches timed with kernel-attached events.  Nt - order + 1 a power of
+    two (64 unknown slices for Nt = 63 + order) takes the radix FFT pass B,
+    HBM-bound: algorithmic bytes 32 per window entry plus the per-kappa
+    tables.  Nt = 64 takes the dense pass B, one 2Nt x 2Nt real GEMM pair
+    per 16 kappa columns on FP64 MFMA: executed flops 2 * 2 * (2Nt)^2 * 16
+    per block."""
     import workloads as W
-    inst = W.diffusion2d_ebdf2(Nt=Nt, T=2.0)
+    inst = W.diffusion2d_ebdf(order, Nt=Nt, T=2.0)
     fp = bench_single(inst, 0, steps, warmup)
     kb = fp["kernels"]["passb"]
     us = kb["avg_us"] if "avg_us" in kb else kb["avg_us_all_classes_timed"]
@@ -179,9 +180,9 @@ def bench_ebdf2(steps, warmup, Nt):
     dense = (Nt & (Nt - 1)) == 0
     out = {
         "workload": f"2D diffusion u_t = eps^2 Lap u, eps=0.05, periodic "
-                    f"256x256, Nt={Nt} ({Nt - 1} unknown slices), T=2, "
-                    f"EBDF2 Exp-ParaDiag fixed point, alpha=1e-3, "
-                    f"u0~U[-0.9,0.9] seed 0",
+                    f"256x256, Nt={Nt} ({Nt - order + 1} unknown slices), "
+                    f"T=2, EBDF{order} Exp-ParaDiag fixed point, "
+                    f"alpha=1e-3, u0~U[-0.9,0.9] seed 0",
         "time_transform": "dense MFMA" if dense else "radix FFT",
         "ms_per_solve": fp["ms_per_solve"],
         "iters_per_solve": fp["iters"],
@@ -206,6 +207,55 @@ def bench_ebdf2(steps, warmup, Nt):
             "bound": "mfma", "achieved": round(tflops, 2),
             "peak": MFMA_F64_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(tflops / MFMA_F64_PEAK_TFLOPS, 4)}
+    return out
+
+
+def bench_krylov(steps, warmup):
+    """GMRES(20) against BiCGStab on the left-preconditioned system, the
+    comparison of Table cpu_time_combined: purely diffusive problem, a in
+    {1e-1, 1e-5}, dt = 0.01, first-order (ETD1, Nt = 64) and EBDF2
+    (Nt = 65) windows on the 256^2 grid, from zero to a relative
+    preconditioned residual of 1e-10.  Each BiCGStab iteration applies the
+    operator twice, each GMRES iteration once."""
+    import torch
+    import workloads as W
+    from paper_2603_04350_amd import expdiag as X
+    dev = "cuda:0"
+    out = {}
+    for scheme, Nt, name in ((1, 64, "etd1"), (3, 65, "ebdf2")):
+        for a in (1e-1, 1e-5):
+            inst = W.heat2d_table(a, Nt=Nt, scheme=scheme)
+            u0 = torch.from_numpy(inst.u0).to(dev)
+            U = torch.zeros((Nt,) + inst.shape, dtype=torch.float64,
+                            device=dev)
+            s = X.Solver.from_instance(inst, gmres_restart=20)
+            row = {}
+            for meth in ("gmres", "bicgstab"):
+                def solve():
+                    U.zero_()
+                    if meth == "gmres":
+                        return s.gmres(u0, U, restart=20, max_iter=200,
+                                       tol=1e-10)
+                    return s.bicgstab(u0, U, max_iter=200, tol=1e-10)
+                for _ in range(warmup):
+                    solve()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    rc, it, rel = solve()
+                torch.cuda.synchronize()
+                ms = 1e3 * (time.perf_counter() - t0) / steps
+                row[meth] = {"ms_per_solve": ms, "iters": it,
+                             "operator_applications":
+                                 it * (2 if meth == "bicgstab" else 1),
+                             "rel_resid": rel}
+            row["bicgstab_speedup"] = (row["gmres"]["ms_per_solve"]
+                                       / row["bicgstab"]["ms_per_solve"])
+            s.close()
+            out[f"{name}_a{a:g}"] = row
+    out["workload"] = ("u_t = a Lap u, periodic 256x256, dt=0.01, "
+                       "alpha=1e-3, u0~U[-0.9,0.9] seed 0; ETD1 Nt=64 and "
+                       "EBDF2 Nt=65; tol 1e-10 (preconditioned residual)")
     return out
 
 
@@ -495,9 +545,10 @@ def cpu_baseline_ebdf2(U_gpu, sample_iters):
 def profile_run(steps):
     """Fixed-count solves only (tol = 0, so every launch does full work),
     for a profiler wrapped around this process: the Allen-Cahn instance in
-    fp64 (22 iterations, its count to tolerance) and the EBDF2 windows with
-    Nt = 65 and 64 (5 iterations).  Prints the event-timed average launch
-    time of each kernel class for comparison with the profiler's."""
+    fp64 (22 iterations, its count to tolerance), the EBDF2 windows with
+    Nt = 65 and 64 and the EBDF4 window with Nt = 67 (5 iterations).  Prints
+    the event-timed average launch time of each kernel class for comparison
+    with the profiler's."""
     import torch
     import workloads as W
     from paper_2603_04350_amd import expdiag as X
@@ -505,7 +556,8 @@ def profile_run(steps):
     for name, inst, iters in (
             ("allen_cahn2d_fp64", W.allen_cahn2d(), 22),
             ("ebdf2_Nt65", W.diffusion2d_ebdf2(Nt=65, T=2.0), 5),
-            ("ebdf2_Nt64", W.diffusion2d_ebdf2(Nt=64, T=2.0), 5)):
+            ("ebdf2_Nt64", W.diffusion2d_ebdf2(Nt=64, T=2.0), 5),
+            ("ebdf4_Nt67", W.diffusion2d_ebdf(4, Nt=67, T=2.0), 5)):
         u0 = torch.from_numpy(inst.u0).to("cuda:0")
         U = torch.zeros((inst.Nt,) + inst.shape, dtype=torch.float64,
                         device="cuda:0")
@@ -538,7 +590,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-ebdf2", action="store_true",
-                    help="skip the EBDF2 and advection sections")
+                    help="skip the EBDF, Krylov, advection, Schroedinger "
+                         "and IF1 sections")
     ap.add_argument("--quick", action="store_true",
                     help="fp64 single-instance solves only")
     ap.add_argument("--profile", action="store_true",
@@ -623,6 +676,18 @@ def main():
         ebd.pop("U")
         eb["dense_variant_Nt64"] = ebd
         line["ebdf2"] = eb
+        _log("ebdf4 (radix FFT, Nt = 67; dense, Nt = 64) and ebdf6 (Nt = 69)")
+        e4 = bench_ebdf2(args.steps, args.warmup, 67, order=4)
+        e4.pop("U")
+        e4d = bench_ebdf2(args.steps, args.warmup, 64, order=4)
+        e4d.pop("U")
+        e4["dense_variant_Nt64"] = e4d
+        e6 = bench_ebdf2(args.steps, args.warmup, 69, order=6)
+        e6.pop("U")
+        line["ebdf4"] = e4
+        line["ebdf6"] = e6
+        _log("krylov: GMRES vs BiCGStab")
+        line["krylov"] = bench_krylov(args.steps, args.warmup)
     if not args.no_ebdf2:
         _log("advection (complex symbol)")
         adv = bench_advection(args.steps, args.warmup)

@@ -154,6 +154,28 @@ def diffusion2d_ebdf2(seed: int = 0, n: int = 256, Nt: int = 64,
                     scheme=3, u0=uniform_field(rng, 2, n))
 
 
+def diffusion2d_ebdf(order: int, seed: int = 0, n: int = 256,
+                     Nt: int = 64, T: float = 2.0, alpha: float = 1e-3,
+                     eps: float = 0.05) -> Instance:
+    """diffusion2d_ebdf2's problem stepped by the exponential BDF of order
+    2..6 (schemes 3, 5, 6, 7, 8)."""
+    rng = np.random.default_rng(seed)
+    scheme = 3 if order == 2 else order + 2
+    return Instance(f"diffusion2d_ebdf{order}", 2, n, Nt, T, alpha,
+                    a=eps * eps, scheme=scheme, u0=uniform_field(rng, 2, n))
+
+
+def heat2d_table(a: float, seed: int = 0, n: int = 256, Nt: int = 64,
+                 dt: float = 0.01, alpha: float = 1e-3,
+                 scheme: int = 1) -> Instance:
+    """The purely diffusive problem of Table cpu_time_combined (u_t = a Lap
+    u, a in {1e-1, 1e-5}, dt = 0.01) on the periodic 256^2 box, Nt steps,
+    first-order (scheme 1) or EBDF2 (scheme 3) time stepping."""
+    rng = np.random.default_rng(seed)
+    return Instance("heat2d_table", 2, n, Nt, Nt * dt, alpha, a=a,
+                    scheme=scheme, u0=uniform_field(rng, 2, n))
+
+
 def advection2d(seed: int = 0, n: int = 256, Nt: int = 64, T: float = 2.0,
                 alpha: float = 1e-3, eps: float = 0.05,
                 b: tuple = (2.0, 1.0), nonlinear: bool = True) -> Instance:
