@@ -129,35 +129,46 @@ def bench_single(inst, prec, steps, warmup):
         U.zero_()
         return s.iterate(u0, U, max_iter=it, tol=0.0)
 
-    # which kernel class dominates: one pass with events around every launch
+    # timed region 2: the same solves with HIP start/stop events attached to
+    # every launch (hipExtLaunchKernel, on the library's stream).  With every
+    # launch bracketed, each pair measures its own kernel and the averages
+    # agree with rocprofv3's kernel times; events on one class alone also
+    # count that launch's wait for the unbracketed kernel before it (1-2 us
+    # more per launch), which is reported beside them.
     X.expdiag_profile_enable(s.h, 0x1F)
-    for _ in range(2):
-        step_fixed()
-    ms, cnt, by, tm = X.expdiag_profile_read(s.h)
-    dom = max(range(len(ms)), key=lambda i: ms[i])
-    # timed region 2: the same solves with HIP events around every launch of
-    # the dominant class only (on the library's stream)
-    X.expdiag_profile_enable(s.h, 1 << dom)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         step_fixed()
     torch.cuda.synchronize()
     wall2 = time.perf_counter() - t0
-    ms2, cnt2, by2, tm2 = X.expdiag_profile_read(s.h)
+    ms, cnt, by, tm = X.expdiag_profile_read(s.h)
+    dom = max(range(len(ms)), key=lambda i: ms[i])
+    X.expdiag_profile_enable(s.h, 1 << dom)
+    for _ in range(2):
+        step_fixed()
+    ms1, cnt1, by1, tm1 = X.expdiag_profile_read(s.h)
     X.expdiag_profile_enable(s.h, 0)
     out["ms_per_solve_instrumented"] = 1e3 * wall2 / steps
     out["dominant"] = X.PROFILE_CLASSES[dom]
     out["kernels"] = {}
     for i in range(len(ms)):
-        d = {"launches_per_solve": cnt[i] / 2,
+        d = {"launches_per_solve": cnt[i] / steps,
              "bytes_per_launch": by[i] / cnt[i] if cnt[i] else 0.0,
-             "avg_us_all_classes_timed": 1e3 * ms[i] / tm[i] if tm[i] else 0.0}
-        if i == dom:
-            d["avg_us"] = 1e3 * ms2[i] / tm2[i]
-            d["timed_launches"] = tm2[i]
+             "avg_us": 1e3 * ms[i] / tm[i] if tm[i] else 0.0,
+             "timed_launches": tm[i]}
+        if tm[i]:
             d["GBps"] = d["bytes_per_launch"] / (d["avg_us"] * 1e-6) / 1e9
+        if i == dom:
+            d["avg_us_events_on_this_class_only"] = 1e3 * ms1[i] / tm1[i]
         out["kernels"][X.PROFILE_CLASSES[i]] = d
+    # algorithmic bytes of one iteration (launches of the iteration plan per
+    # solve, over the solve's iterations) against the untimed wall clock
+    it_bytes = sum(d["bytes_per_launch"] * d["launches_per_solve"]
+                   for d in out["kernels"].values()) / max(it, 1)
+    out["iteration_bytes"] = it_bytes
+    out["iteration_hbm_frac"] = it_bytes / (out["us_per_iter"] * 1e-6) / \
+        (HBM_PEAK_GBS * 1e9)
     s.close()
     return out
 
@@ -666,6 +677,14 @@ def main():
         "kernels_mixed": {k: {kk: round(vv, 3) for kk, vv in v.items()}
                           for k, v in mx["kernels"].items()},
         "roofline": roof,
+        "iteration_hbm": {
+            "algorithmic_bytes": fp["iteration_bytes"],
+            "us_per_iter": fp["us_per_iter"],
+            "achieved_GBps": fp["iteration_bytes"] / fp["us_per_iter"] / 1e3,
+            "frac": round(fp["iteration_hbm_frac"], 4),
+            "note": "all kernels of an iteration against the untimed wall "
+                    "clock per iteration (launch gaps and the entry/exit "
+                    "transforms included)"},
         "src_hash": src_hash,
     }
     if not args.no_ebdf2:

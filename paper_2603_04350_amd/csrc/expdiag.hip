@@ -147,6 +147,12 @@ struct expdiag_ctx {
   double* h_red = nullptr;
   double* h_kdots = nullptr;
 
+  // completion events of the (at most two) chunks of iterations in flight,
+  // and the iterations the previous solve of this handle took (the first
+  // chunk's size; 0 before the first solve)
+  hipEvent_t chunk_ev[2] = {nullptr, nullptr};
+  int last_iters = 0;
+
   // iteration plan and its graph
   Plan plan;
   hipGraph_t graph = nullptr;
@@ -1584,6 +1590,8 @@ void release(expdiag_ctx* h) {
   if (h->h_red != nullptr) (void)hipHostFree(h->h_red);
   if (h->h_kdots != nullptr) (void)hipHostFree(h->h_kdots);
   if (h->cap_stream != nullptr) (void)hipStreamDestroy(h->cap_stream);
+  for (auto& e : h->chunk_ev)
+    if (e != nullptr) (void)hipEventDestroy(e);
   for (auto& e : h->events) {
     (void)hipEventDestroy(e.a);
     (void)hipEventDestroy(e.b);
@@ -1591,8 +1599,10 @@ void release(expdiag_ctx* h) {
   h->events.clear();
 }
 
-// Snapshot of a host-mapped control block written by the device (read
-// after the stream that writes it has been synchronised).
+// Snapshot of a host-mapped control block written by the device.  Read
+// while later iterations run, fields may come from two different updates;
+// callers use such snapshots only to size the next chunk and take final
+// results after synchronising the stream.
 Ctl read_mirror(const Ctl* p) {
   Ctl c;
   std::memcpy(&c, static_cast<const void*>(p), sizeof(Ctl));
@@ -1840,6 +1850,10 @@ int create_impl(const expdiag_grid* g, int Nt, double dt, double alpha,
   if (rc == 0 && hipStreamCreateWithFlags(&h->cap_stream,
                                           hipStreamNonBlocking) != hipSuccess)
     rc = fail(h, EXPDIAG_EHIP, "capture stream");
+  for (auto& e : h->chunk_ev)
+    if (rc == 0 &&
+        hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+      rc = fail(h, EXPDIAG_EHIP, "chunk events");
   if (rc == 0) rc = build_tables(h);
   if (rc == 0 && light) {
     h->use_graph = false;
@@ -2029,28 +2043,52 @@ int expdiag_iterate(expdiag_t h, const double* u0, double* U, int max_iter,
   RCHK(fwd_slices<ROW_R2C>(h, U, h->Uh, h->Nt));
   *h->h_ctl = initial_ctl(h, max_iter, tol);
   *h->h_mirror = *h->h_ctl;
-  HIPCHK(h, hipMemcpyAsync(h->ctl, h->h_ctl, sizeof(Ctl),
-                           hipMemcpyHostToDevice, h->stream));
+  hipLaunchKernelGGL(ctl_set_kernel, dim3(1), dim3(64), 0, h->stream, h->ctl,
+                     *h->h_ctl);
+  HIPCHK(h, hipGetLastError());
   RCHK(if1_sigma_init(h, h->ctl, h->stream));
+  // Chunks of iterations, two in flight: while the device runs one, the
+  // host sizes the next from the state the previous one left, so the
+  // stream does not drain between chunks.  The first chunk is the previous
+  // solve's iteration count (8 before any), the second a short (long)
+  // speculative one; later ones are what the observed contraction predicts
+  // beyond the iterations already enqueued.  Iterations enqueued past
+  // convergence find the instance done and return at once; never more than
+  // max_iter are enqueued.
   int enqueued = 0;
-  int chunk = std::min(8, max_iter);
   double rel_prev = -1.0;
   int it_prev = 0;
-  while (true) {
-    RCHK(run_iterations(h, chunk));
-    enqueued += chunk;
-    HIPCHK(h, hipStreamSynchronize(h->stream));
+  int in_flight = 0, oldest = 0;
+  auto enqueue = [&](int n, int slot) -> int {
+    RCHK(run_iterations(h, n));
+    enqueued += n;
+    HIPCHK(h, hipEventRecord(h->chunk_ev[slot], h->stream));
+    ++in_flight;
+    return 0;
+  };
+  const bool known = h->last_iters > 0;
+  RCHK(enqueue(std::min({known ? h->last_iters : 8, 64, max_iter}), 0));
+  if (enqueued < max_iter)
+    RCHK(enqueue(std::min(known ? 2 : 8, max_iter - enqueued), 1));
+  while (in_flight > 0) {
+    HIPCHK(h, hipEventSynchronize(h->chunk_ev[oldest]));
+    --in_flight;
     const Ctl c = read_mirror(h->h_mirror);
     if (c.done != 0 || c.iters >= max_iter) break;
-    if (enqueued >= max_iter + 64) break;  // safety: device state stalled
-    // never more than the iterations still allowed (c.iters < max_iter)
-    chunk = std::min(next_chunk(c, rel_prev, it_prev), max_iter - c.iters);
+    int add = 8;  // no contraction observed yet: keep a chunk queued
+    if (rel_prev >= 0.0 && c.iters > it_prev)
+      add = next_chunk(c, rel_prev, it_prev) - (enqueued - c.iters);
     rel_prev = c.last_rel;
     it_prev = c.iters;
+    add = std::min(add, max_iter - enqueued);
+    if (add <= 0 && in_flight == 0) add = std::min(1, max_iter - enqueued);
+    if (add > 0) RCHK(enqueue(add, oldest));
+    oldest ^= 1;
   }
   RCHK(inv_slices(h, h->Uh, U, h->Nt));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   const Ctl c = read_mirror(h->h_mirror);
+  h->last_iters = c.iters;
   if (iters != nullptr) *iters = c.iters;
   if (rel_update != nullptr) *rel_update = c.last_rel;
   if (c.done == 2) return fail(h, EXPDIAG_EDIVERGED, "non-finite residual");

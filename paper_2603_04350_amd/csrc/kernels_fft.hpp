@@ -140,12 +140,14 @@ struct RowJob {
 // Forward half of a row: Z = FFT_M(z) of v (z_j = x_{2j} + i x_{2j+1}),
 // then X_k = E_k + W^k O_k stored for k = 0..M (valid rows only).  The
 // caller has synchronised so that nobody still reads this row's LDS.
-// wst: stage twiddles (fft_stage_twiddles); wk[s] = W^{t + s*TPR}.
+// wst: stage twiddles (fft_stage_twiddles); wt = W^t, and W^{t + s*TPR} =
+// wt e^{-i pi s/R} is formed where it is used (holding all R across the
+// transform would cost 4R registers in fp64).
 template <typename T, int M, typename TO, int R>
 __device__ __forceinline__ void row_forward(const RowJob& jb, long row,
                                             bool valid, int t, cx<T> (&v)[R],
                                             cx<T>* lrow, const cx<T>* wst,
-                                            const cx<T> (&wk)[R]) {
+                                            cx<T> wt) {
   using S = RowShape<M>;
   constexpr int TPR = S::TPR;
   fft_stages<T, M, R, -1, 1, true, true, S::WAVE, 0, true>(
@@ -165,7 +167,8 @@ __device__ __forceinline__ void row_forward(const RowJob& jb, long row,
       x0e = e;
       x0o = o;
     }
-    const cx<T> x = e + cmul(wk[s], o);
+    const cx<T> wk = s == 0 ? wt : cmul(wt, eighth_root<T>(s * (8 / R)));
+    const cx<T> x = e + cmul(wk, o);
     gst(dst, k, cvt<TO>(x));
   }
   if (t == 0) gst(dst, M, cvt<TO>(x0e - x0o));
@@ -211,10 +214,6 @@ __device__ __forceinline__ void row_body(const RowJob& jb, long lb,
   cx<T> wst[NST > 1 ? NST : 2];
   fft_stage_twiddles<T, M, R>(wst, t, tw);
   pin_loaded(wst);
-  cx<T> wk[R];
-#pragma unroll
-  for (int s = 0; s < R; ++s)
-    wk[s] = s == 0 ? wt : cmul(wt, eighth_root<T>(s * (8 / R)));
 
   if constexpr (MODE == ROW_R2C || MODE == ROW_NR2C) {
 #pragma unroll
@@ -245,8 +244,9 @@ __device__ __forceinline__ void row_body(const RowJob& jb, long lb,
         xk.y = 0;
         xm.y = 0;
       }
+      const cx<T> wk = s == 0 ? wt : cmul(wt, eighth_root<T>(s * (8 / R)));
       const cx<T> e2 = xk + conj(xm);
-      const cx<T> o2 = cmulc(xk - conj(xm), wk[s]);
+      const cx<T> o2 = cmulc(xk - conj(xm), wk);
       v[s] = (e2 + mul_si<1>(o2)) * scale;
     }
     line_sync<S::WAVE>();
@@ -278,7 +278,13 @@ __device__ __forceinline__ void row_body(const RowJob& jb, long lb,
     }
     line_sync<S::WAVE>();
   }
-  row_forward<T, M, TO>(jb, row, valid, t, v, lrow, wst, wk);
+  // a fresh copy of the lane index, so that the forward transform forms its
+  // LDS addresses anew instead of keeping the inverse transform's (the same
+  // addresses, which the compiler would otherwise hold across the
+  // nonlinearity)
+  int t2 = t;
+  asm volatile("" : "+v"(t2));
+  row_forward<T, M, TO>(jb, row, valid, t2, v, lrow, wst, wt);
 }
 
 // Complex rows of length M (the last axis of a complex state): row r of

@@ -361,8 +361,12 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
     v[s] = cmul(v[s], mk(dr * inv, -di * inv));
   }
   __syncthreads();
-  // step (c): inverse time transform with the - sign, then Gamma^{-1}
-  fft_line_pre<double, NT, -1>(v, lds + c, LS, t, wst);
+  // step (c): inverse time transform with the - sign, then Gamma^{-1}.  A
+  // fresh copy of the lane index makes it form its LDS addresses anew
+  // rather than hold step (a)'s (the same ones) across step (b).
+  int t2 = t;
+  asm volatile("" : "+v"(t2));
+  fft_line_pre<double, NT, -1>(v, lds + c, LS, t2, wst);
 
   double sum0 = 0.0;  // sum_l Re U^_l(kappa = 0), for the IF1 mean Jacobian
   if constexpr (MODE == PB_ITERATE) {
@@ -489,6 +493,12 @@ __global__ void __launch_bounds__(THREADS)
     const double mu2 = tot[0] * inv_ns * inv_ns;
     ctl->sigma = c0 + c1 * mu1 + c2 * mu2;
   }
+}
+
+// Control-block initialisation on the stream (a kernel starts at once; a
+// small host-to-device copy first waits for a copy engine).
+__global__ void ctl_set_kernel(Ctl* __restrict__ dst, Ctl v) {
+  if (threadIdx.x == 0) *dst = v;
 }
 
 // One block per job of a pass B job table.
