@@ -337,6 +337,22 @@ bool bdf_fft_ok(int Nt, int s) {
 bool bdf_ok(int Nt, int s) {
   return bdf_fft_ok(Nt, s) || (dense_ok(Nt) && Nt - s + 1 >= 2);
 }
+// f(std::integral_constant<int, SC>) for an order s = 2..6 (false
+// otherwise): the radix pass B of orders 2..4 is compiled for its order
+// (SC = s); orders 5 and 6 take the kernel that reads s per job (SC = 0),
+// because compiled in they spill (96 and 168 bytes per lane at N = 64) and
+// measured 37 and 49 us against 31 and 32 us per launch.
+template <typename F>
+bool dispatch_bdf_order(int s, F&& f) {
+  switch (s) {
+    case 2: f(std::integral_constant<int, 2>{}); return true;
+    case 3: f(std::integral_constant<int, 3>{}); return true;
+    case 4: f(std::integral_constant<int, 4>{}); return true;
+    case 5:
+    case 6: f(std::integral_constant<int, 0>{}); return true;
+    default: return false;
+  }
+}
 // Spectral index width the kernels weight inner products by: entries at
 // kl = kappa % nh in {0, nh - 1} count once, the others twice (Parseval on
 // a half spectrum).  A full spectrum (complex state) weights every entry
@@ -479,7 +495,8 @@ template <int MODE, typename TN>
 int launch_passb1(expdiag_ctx* h, const PassBArgs& a) {
   ProfScope ps(h, P_PASSB, passb_bytes(a, h->Nt, MODE, sizeof(cx<TN>)));
   if (const int s = bdf_order(h->scheme); s > 0) {
-    // order 2 has its own instantiation; 3..6 share one that reads s
+    // radix FFT: one instantiation per order; dense (MFMA-bound either way):
+    // order 2 has its own, 3..6 share one that reads s
     bool ok = false;
     if (h->tvariant == 1) {
       ok = dispatch_pow2<DENSE_NT_MIN, DENSE_NT_MAX>(h->Nt, [&](auto Nc) {
@@ -497,12 +514,11 @@ int launch_passb1(expdiag_ctx* h, const PassBArgs& a) {
         constexpr int NN = decltype(Nc)::value;
         const dim3 grid(passb_blocks_nt(NN, h->Nk));
         const dim3 th(PassBShape<NN>::THREADS);
-        if (s == 2)
-          hipLaunchKernelGGL((passb_bdf_fft_kernel1<NN, 2, MODE>), grid, th,
+        ok = dispatch_bdf_order(s, [&](auto Sc) {
+          constexpr int SS = decltype(Sc)::value;
+          hipLaunchKernelGGL((passb_bdf_fft_kernel1<NN, SS, MODE>), grid, th,
                              0, h->stream, a);
-        else
-          hipLaunchKernelGGL((passb_bdf_fft_kernel1<NN, 0, MODE>), grid, th,
-                             0, h->stream, a);
+        });
       });
     }
     if (!ok)
@@ -870,18 +886,18 @@ void plan_iteration(Plan& P, expdiag_ctx* h, Ctl* ctl, Ctl* mirror,
   if (h->nonlinear && h->mixed) a.Nh32 = nh_view<float>(h);
   const bool hosted = h->nonlinear && plan_pass_a_mp(P, h, ctl, a);
   // pass B variant: 0 radix FFT, 1 dense, 2 EBDF2 dense, 3 EBDF2 radix FFT,
-  // 4 radix FFT with complex symbols, 5 and 6 the dense and radix FFT
-  // kernels of EBDF3..6 (the group length is the transform length for the
-  // radix kernels)
+  // 4 radix FFT with complex symbols, 5 the dense kernel of EBDF3..6 (the
+  // order read per job), 30 + s the radix FFT kernel of EBDFs (the group
+  // length is the transform length for the radix kernels)
   int variant = h->tvariant;
   const int s = bdf_order(h->scheme);
   if (s == 2)
     variant = h->tvariant == 1 ? 2 : 3;
   else if (s > 2)
-    variant = h->tvariant == 1 ? 5 : 6;
+    variant = h->tvariant == 1 ? 5 : 30 + s;
   else if (variant == 0 && h->cplx)
     variant = 4;
-  const int len = variant == 3 || variant == 6 ? time_len(h) : h->Nt;
+  const int len = variant == 3 || variant > 30 ? time_len(h) : h->Nt;
   plan_passb(P, 5, len, h->Nt, a, sizeof(cx<double>), variant, !hosted);
 }
 
@@ -1051,15 +1067,15 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st,
               klaunch(ps, passb_bdf_kernel<NN, 0>, dim3(grid),
                       dim3(DENSE_THREADS), st, J, g.dstart, nj);
           });
-        } else if (g.tcode == 3 || g.tcode == 6) {
+        } else if (g.tcode == 3 || g.tcode > 30) {
           ok = dispatch_pow2<2, 512>(g.len, [&](auto Nc) {
             constexpr int NN = decltype(Nc)::value;
-            if (g.tcode == 3)
-              klaunch(ps, passb_bdf_fft_kernel<NN, 2>, dim3(grid),
+            ok = dispatch_bdf_order(g.tcode == 3 ? 2 : g.tcode - 30,
+                                    [&](auto Sc) {
+              constexpr int SS = decltype(Sc)::value;
+              klaunch(ps, passb_bdf_fft_kernel<NN, SS>, dim3(grid),
                       dim3(PassBShape<NN>::THREADS), st, J, g.dstart, nj);
-            else
-              klaunch(ps, passb_bdf_fft_kernel<NN, 0>, dim3(grid),
-                      dim3(PassBShape<NN>::THREADS), st, J, g.dstart, nj);
+            });
           });
         } else {
           ok = dispatch_pow2<2, 512>(g.len, [&](auto Nc) {

@@ -25,8 +25,11 @@
 // of two (the host embeds the N x N matrices at row and column offset o of
 // the Nt x Nt real-block operands, so rows < o and frequencies >= N stay
 // zero), and the radix FFT of kernels_passb.hpp when N is a power of two.
-// SC is the order when it is fixed at compile time (2); SC = 0 reads it
-// from PassBArgs::bdf_s (3..6) and unrolls to six.
+// SC is the order when it is fixed at compile time (the radix kernels of
+// orders 2..4, where the run-time order cost 10-20%); SC = 0 reads it from
+// PassBArgs::bdf_s and unrolls to six (radix orders 5 and 6, which spill
+// when compiled in, and the dense kernels of orders 3..6, bound by the
+// MFMA time transform either way).
 #pragma once
 #include "kernels_dense.hpp"
 

@@ -193,9 +193,10 @@ def test_ebdf_variant_and_autotune(case, variant):
 
 
 def test_ebdf_orders_in_one_batch():
-    """EBDF3 and EBDF5 windows with the same transform length share one
-    launch group (the order is read per job); with EBDF2 and ETD1 instances
-    beside them every result is bitwise the one its handle gives alone."""
+    """EBDF3, EBDF5 and EBDF6 windows (radix kernels of their own order,
+    and the dense kernel that reads the order per job) with EBDF2 and ETD1
+    instances in one batch: every result is bitwise the one its handle
+    gives alone."""
     import torch
     from paper_2603_04350_amd import Batch, Solver
     sts = [O.Setup(2, 16, 18, 1.0 / 18, 1e-3, 0.3, 0.1, scheme=O.EBDF3),
