@@ -336,3 +336,47 @@ def test_newton_bicgstab_reaches_dense_newton(scheme):
     U, newton, inner, hist = O.newton_bicgstab(st, u0, tol=1e-12)
     assert O.rel_err(U, O.dense_newton(st, u0)) < 1e-11
     assert O.rel_err(U, O.sequential(st, u0)) < 1e-11
+
+
+# --------------------------------------------------- printed values (golden)
+import os  # noqa: E402
+import re  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_lines(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return [l.strip() for l in f if l.strip() and not l.startswith("#")]
+
+
+def test_printed_coefficients_match_bdf_and_oracle():
+    """The paper's printed beta_i (tests/golden/ebdf_coefficients.txt) are
+    the BDF coefficients of the backward-difference definition, and the
+    oracle uses them."""
+    for line in _golden_lines("ebdf_coefficients.txt"):
+        s, rest = line.split(":")
+        s = int(s)
+        printed = [Fraction(t) for t in rest.split()]
+        assert printed == _bdf_from_differences(s), s
+        num, den = O.EBDF_COEFFS[s]
+        assert printed == [Fraction(b, den) for b in num], s
+
+
+@pytest.mark.parametrize("Nt", [14, 20, 31])
+def test_printed_alpha_positions_match_oracle(Nt):
+    """Each alpha-circulant C_j^alpha the paper lists, in the system of the
+    order whose dimension N = Nt - s + 1 it fits, has alpha exactly at the
+    printed (row, Nt - k) entries, as the oracle assembles it."""
+    for line in _golden_lines("alpha_circulant_positions.txt"):
+        head, rest = line.split(":")
+        name, s = head.split()
+        j, s = int(name[1:]), int(s)
+        pos = [(int(r), Nt - int(k)) for r, k in
+               re.findall(r"\((\d+), Nt-(\d+)\)", rest)]
+        assert len(pos) == j + 1
+        st = _setup(s, Nt=Nt, alpha=0.25)
+        Ca = O.dense_operators_ebdf(st)["Ca"][j]
+        got = [(int(r) + 1, int(c) + 1)
+               for r, c in zip(*np.nonzero(Ca == st.alpha))]
+        assert sorted(got) == sorted(pos), (name, s, got, pos)
