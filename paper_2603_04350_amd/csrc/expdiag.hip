@@ -2082,10 +2082,18 @@ int expdiag_iterate(expdiag_t h, const double* u0, double* U, int max_iter,
     ++in_flight;
     return 0;
   };
+  // The exit transform is enqueued as soon as the enqueued iterations are
+  // expected to suffice (so the tail of a solve has no host round trip);
+  // should more iterations be needed after all, it is enqueued again.
+  bool exit_queued = false;
   const bool known = h->last_iters > 0;
   RCHK(enqueue(std::min({known ? h->last_iters : 8, 64, max_iter}), 0));
   if (enqueued < max_iter)
     RCHK(enqueue(std::min(known ? 2 : 8, max_iter - enqueued), 1));
+  if (known || enqueued >= max_iter) {
+    RCHK(inv_slices(h, h->Uh, U, h->Nt));
+    exit_queued = true;
+  }
   while (in_flight > 0) {
     HIPCHK(h, hipEventSynchronize(h->chunk_ev[oldest]));
     --in_flight;
@@ -2098,10 +2106,17 @@ int expdiag_iterate(expdiag_t h, const double* u0, double* U, int max_iter,
     it_prev = c.iters;
     add = std::min(add, max_iter - enqueued);
     if (add <= 0 && in_flight == 0) add = std::min(1, max_iter - enqueued);
-    if (add > 0) RCHK(enqueue(add, oldest));
+    if (add > 0) {
+      RCHK(enqueue(add, oldest));
+      exit_queued = false;
+    }
+    if (!exit_queued && (add <= 0 || enqueued >= max_iter)) {
+      RCHK(inv_slices(h, h->Uh, U, h->Nt));
+      exit_queued = true;
+    }
     oldest ^= 1;
   }
-  RCHK(inv_slices(h, h->Uh, U, h->Nt));
+  if (!exit_queued) RCHK(inv_slices(h, h->Uh, U, h->Nt));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   const Ctl c = read_mirror(h->h_mirror);
   h->last_iters = c.iters;
