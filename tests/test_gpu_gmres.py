@@ -97,3 +97,25 @@ def test_newton_gmres_3d_and_1d():
             rc, it, rel = s.gmres(_dev(u0), U, restart=20, max_iter=400,
                                   tol=1e-12)
         assert O.rel_err(U.cpu().numpy(), ref) < 1e-10
+
+
+def test_rd2d_full_size_newton_gmres():
+    """The reaction-diffusion configuration at full size: 512^2 x 128, ETD2,
+    Exp-ParaDiag as the GMRES(20) preconditioner to tol 1e-10, mixed
+    precision (fp32 Jacobian products, fp64 residual and time
+    diagonalisation).  The window is held against sequential ETD2 stepping
+    in fp64 (the Newton residual tolerance 1e-10 bounds the error to about
+    that size; the bar is 1e-9)."""
+    import torch
+    from paper_2603_04350_amd import Solver
+    inst = W.rd2d()
+    st = O.Setup.from_instance(inst)
+    ref = O.sequential(st, inst.u0)
+    with Solver.from_instance(inst, gmres_restart=20) as s:
+        U = torch.zeros((inst.Nt,) + inst.shape, dtype=torch.float64,
+                        device="cuda:0")
+        rc, it, rel = s.gmres(_dev(inst.u0), U, restart=20, max_iter=400,
+                              tol=1e-10)
+    assert rc == 0 and rel <= 1e-10
+    err = O.rel_err(U.cpu().numpy(), ref)
+    assert err < 1e-9, (it, rel, err)
