@@ -238,7 +238,7 @@ __device__ __forceinline__ void row_body(const RowJob& jb, long lb,
 #pragma unroll
     for (int s = 0; s < R; ++s) {
       const int k = t + s * TPR;
-      cx<T> xk = lrow[slot<true>(k)];
+      cx<T> xk = cvt<T>(xin[s]);  // this thread's own element
       cx<T> xm = lrow[slot<true>(M - k)];
       if (k == 0) {  // the k = 0 and Nyquist bins of a real row are real
         xk.y = 0;
