@@ -260,6 +260,23 @@ def bench_krylov(steps, warmup):
                              "operator_applications":
                                  it * (2 if meth == "bicgstab" else 1),
                              "rel_resid": rel}
+                # kernel classes of the solve, events on every launch: the
+                # dominant one against the HBM roofline
+                X.expdiag_profile_enable(s.h, 0x1F)
+                solve()
+                pm, pc, pb, pt = X.expdiag_profile_read(s.h)
+                X.expdiag_profile_enable(s.h, 0)
+                dom = max(range(len(pm)), key=lambda i: pm[i])
+                us = 1e3 * pm[dom] / pt[dom]
+                gbps = pb[dom] / pc[dom] / (us * 1e-6) / 1e9
+                row[meth]["classes_ms"] = {
+                    X.PROFILE_CLASSES[i]: round(pm[i], 4)
+                    for i in range(len(pm)) if pt[i]}
+                row[meth]["roofline"] = {
+                    "kernel": X.PROFILE_CLASSES[dom], "bound": "hbm",
+                    "avg_launch_us": us,
+                    "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBS, 4)}
             row["bicgstab_speedup"] = (row["gmres"]["ms_per_solve"]
                                        / row["bicgstab"]["ms_per_solve"])
             s.close()
