@@ -149,3 +149,85 @@ def test_server_continuous_batching():
         assert r["status"] == 0, r
         assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
         assert np.array_equal(Us[k].cpu().numpy(), solo[k]), k
+
+
+TOL_BENCH = 1e-11  # the benchmark's tolerance on ||S|| / ||U||
+
+
+def test_batched_configuration_full_size_sampled():
+    """The batched configuration at full size, as the benchmark runs it: 256
+    Allen-Cahn instances (n in {64, 128, 256}, Nt in {16 .. 128}, alpha in
+    {1e-2, 1e-3}, eps ~ U[0.02, 0.1], mixed precision) in one batch.  Every
+    instance converges; the three largest and three smallest windows equal
+    their solo solves bit for bit and sequential stepping to the mixed bar."""
+    from paper_2603_04350_amd import Batch, Solver
+    insts = W.batch(256, seed=0, precision=1)
+    solvers = [Solver.from_instance(i, precision=1) for i in insts]
+    b = Batch(solvers)
+    Us = [_zeros(i) for i in insts]
+    rc, its, rels, sts = b.iterate([_dev(i.u0) for i in insts], Us,
+                                   max_iter=400, tol=TOL_BENCH)
+    b.close()
+    assert all(s == 0 for s in sts), [k for k, s in enumerate(sts) if s]
+    order = sorted(range(len(insts)), key=lambda k: insts[k].dof)
+    for k in order[:3] + order[-3:]:
+        inst = insts[k]
+        got = Us[k].cpu().numpy()
+        U = _zeros(inst)
+        rc1, it1, _ = solvers[k].iterate(_dev(inst.u0), U, max_iter=400,
+                                         tol=TOL_BENCH)
+        assert it1 == its[k] and np.array_equal(U.cpu().numpy(), got), k
+        ref = O.sequential(O.Setup.from_instance(inst), inst.u0)
+        assert O.rel_err(got, ref) < 1e-10, (k, inst.n, inst.Nt)
+    for s in solvers:
+        s.close()
+
+
+def test_served_configuration_full_size_sampled():
+    """The served configuration at full size, as the benchmark's burst:
+    64 requests of the batch shapes with 3D 128^3 x 32 heat and Allen-Cahn
+    requests among them, all submitted at once.  Every request converges,
+    every 3D result equals its solo solve bit for bit, and one 3D request
+    of each kind matches sequential stepping to the mixed bar."""
+    import time
+    import torch
+    from paper_2603_04350_amd import Solver
+    from paper_2603_04350_amd import expdiag as X
+    _, insts = W.served_stream(64, 1.0, seed=1)
+    assert any(i.dim == 3 for i in insts)
+    u0s = [_dev(i.u0) for i in insts]
+    Us = [_zeros(i) for i in insts]
+    torch.cuda.synchronize()
+    srv = X.expdiag_server_create(64 << 30, 128)
+    ids = {}
+    for k, inst in enumerate(insts):
+        prob = X.make_problem(inst.a, inst.c, inst.n1, inst.n2, inst.n3,
+                              inst.precision)
+        rid = X.expdiag_server_submit(srv, inst.shape, inst.Nt, inst.dt,
+                                      inst.alpha, inst.scheme, prob, u0s[k],
+                                      Us[k], 400, TOL_BENCH)
+        ids[rid] = k
+    done = []
+    t_end = time.time() + 90
+    while len(done) < len(insts) and time.time() < t_end:
+        res, _ = X.expdiag_server_poll(srv)
+        done.extend(res)
+        time.sleep(0.001)
+    X.expdiag_server_destroy(srv)
+    assert len(done) == len(insts)
+    assert all(r["status"] == 0 for r in done)
+    checked = set()
+    for k, inst in enumerate(insts):
+        if inst.dim != 3:
+            continue
+        got = Us[k].cpu().numpy()
+        with Solver.from_instance(inst) as s:
+            U = _zeros(inst)
+            s.iterate(u0s[k], U, max_iter=400, tol=TOL_BENCH)
+        assert np.array_equal(U.cpu().numpy(), got), k
+        kind = inst.name.split("_")[0]
+        if kind not in checked:
+            checked.add(kind)
+            ref = O.sequential(O.Setup.from_instance(inst), inst.u0)
+            assert O.rel_err(got, ref) < 1e-10, (k, inst.name)
+    assert checked, "no 3D request in the stream"
