@@ -701,7 +701,15 @@ def main():
             "frac": round(fp["iteration_hbm_frac"], 4),
             "note": "all kernels of an iteration against the untimed wall "
                     "clock per iteration (launch gaps and the entry/exit "
-                    "transforms included)"},
+                    "transforms included)",
+            # the method's own minimum for a nonlinear fixed-point
+            # iteration: pass A reads U^ and writes G^, pass B reads G^ and
+            # U^ and writes U^, 8 B per real space-time DOF each (40 B/DOF);
+            # the 2D FFT schedule adds the row pass and its intermediate
+            "method_min_bytes": 40 * inst.dof,
+            "design_over_min": fp["iteration_bytes"] / (40 * inst.dof),
+            "min_bytes_frac": round(40 * inst.dof / (fp["us_per_iter"] * 1e-6)
+                                    / (HBM_PEAK_GBS * 1e9), 4)},
         "src_hash": src_hash,
     }
     if not args.no_ebdf2:
