@@ -287,6 +287,68 @@ def bench_krylov(steps, warmup):
     return out
 
 
+def bench_rd2d(steps):
+    """The reaction-diffusion window (512^2 x 128, ETD2, mixed precision)
+    solved to 1e-10 as the paper uses Exp-ParaDiag there: as the
+    preconditioner of Newton-GMRES(20); beside it the fixed point on the
+    same window to ||S||/||U|| <= 1e-11.  Time to tolerance per solve,
+    Newton steps and GMRES iterations, and each result's error against
+    sequential ETD2 stepping (the oracle, fp64)."""
+    import torch
+    import workloads as W
+    import oracle as O
+    from paper_2603_04350_amd import expdiag as X
+    dev = "cuda:0"
+    inst = W.rd2d()
+    u0 = torch.from_numpy(inst.u0).to(dev)
+    U = torch.zeros((inst.Nt,) + inst.shape, dtype=torch.float64, device=dev)
+    ref = O.sequential(O.Setup.from_instance(inst), inst.u0)
+    s = X.Solver.from_instance(inst, gmres_restart=20)
+    out = {"workload": "u_t = 0.1 Lap u + u - u^3, periodic 512x512, "
+                       "Nt=128, T=1, ETD2, alpha=1e-3, u0 = 32 periodic "
+                       "Gaussians (seed 0), mixed precision",
+           "dof": inst.dof}
+    steps = max(1, min(steps, 3))
+    for meth in ("newton_gmres", "fixed_point"):
+        def solve():
+            U.zero_()
+            if meth == "newton_gmres":
+                return s.gmres(u0, U, restart=20, max_iter=400, tol=1e-10)
+            return s.iterate(u0, U, max_iter=400, tol=TOL)
+        solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rc, it, rel = solve()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        row = {"ms_per_solve": ms, "rel": rel,
+               "err_vs_oracle": float(O.rel_err(U.cpu().numpy(), ref))}
+        if meth == "newton_gmres":
+            row["newton_steps"] = it // 1000
+            row["gmres_iters"] = it % 1000
+            # event time per kernel class over one more solve
+            X.expdiag_profile_enable(s.h, 0x1F)
+            solve()
+            pm, pc, pb, pt = X.expdiag_profile_read(s.h)
+            X.expdiag_profile_enable(s.h, 0)
+            row["classes_ms"] = {X.PROFILE_CLASSES[i]: round(pm[i], 3)
+                                 for i in range(len(pm)) if pt[i]}
+            row["classes_launches"] = {X.PROFILE_CLASSES[i]: int(pc[i])
+                                       for i in range(len(pm)) if pt[i]}
+            row["classes_GBps"] = {X.PROFILE_CLASSES[i]:
+                                   round(pb[i] / (pm[i] * 1e-3) / 1e9, 1)
+                                   for i in range(len(pm)) if pt[i]}
+        else:
+            row["iters"] = it
+            row["dof_iters_per_s"] = inst.dof * it / (ms * 1e-3)
+        out[meth] = row
+    s.close()
+    del U, u0
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_advection(steps, warmup):
     """The headline instance with an advection term (complex symbol, real
     state): the same kernels with complex E and phi tables."""
@@ -732,6 +794,8 @@ def main():
         line["ebdf6"] = e6
         _log("krylov: GMRES vs BiCGStab")
         line["krylov"] = bench_krylov(args.steps, args.warmup)
+        _log("reaction-diffusion 512^2 x 128: Newton-GMRES and fixed point")
+        line["rd2d"] = bench_rd2d(args.steps)
     if not args.no_ebdf2:
         _log("advection (complex symbol)")
         adv = bench_advection(args.steps, args.warmup)

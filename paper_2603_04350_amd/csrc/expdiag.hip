@@ -555,7 +555,7 @@ int launch_passb1(expdiag_ctx* h, const PassBArgs& a) {
 
 int launch_reduce(expdiag_ctx* h, int nblocks) {
   ProfScope ps(h, P_RED, static_cast<double>(nblocks) * 32);
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, h->stream,
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(RED_THREADS), 0, h->stream,
                      h->partials, nblocks, 1.0 / static_cast<double>(h->Ns),
                      h->red_out);
   HIPCHK(h, hipGetLastError());

@@ -41,14 +41,20 @@ __device__ __forceinline__ double kry_block_sum(double a, double* red) {
   return s;
 }
 
-// part[b*ld + i] = block-partial <V_i, w> for i < nv; part[b*ld + nv] =
-// block-partial <w, w>.  V_i = V + i*vstride.
+// part[i*ld + b] = block-partial <V_i, w> for i < nv; part[nv*ld + b] =
+// block-partial <w, w>.  V_i = V + i*vstride (V unused when nv = 0).
+// Vectors go in groups of KDOT_GROUP: the group's loads are all in flight
+// before the first product, and one block reduction serves the group.
+constexpr int KDOT_GROUP = 4;
+
 __global__ void __launch_bounds__(KRY_THREADS)
     kdot_kernel(const cx<double>* __restrict__ V, long vstride, int nv,
                 const cx<double>* __restrict__ w, long n, long Nk, int nh,
                 double* __restrict__ part, int ld) {
-  __shared__ double red[KRY_THREADS / 64];
+  constexpr int NW = KRY_THREADS / 64;
+  __shared__ double red[NW * KDOT_GROUP];
   const long base = static_cast<long>(blockIdx.x) * KRY_PER_BLOCK;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   cx<double> wv[KRY_PER_THREAD];
   double pw[KRY_PER_THREAD];
 #pragma unroll
@@ -58,42 +64,96 @@ __global__ void __launch_bounds__(KRY_THREADS)
     wv[q] = ok ? w[e] : mk(0.0, 0.0);
     pw[q] = ok ? half_weight(e, Nk, nh) : 0.0;
   }
-  for (int i = 0; i <= nv; ++i) {
-    double acc = 0.0;
-    if (i < nv) {
-      const cx<double>* vi = V + i * vstride;
+  for (int i0 = 0; i0 <= nv; i0 += KDOT_GROUP) {
+    cx<double> x[KDOT_GROUP][KRY_PER_THREAD];
+#pragma unroll
+    for (int g = 0; g < KDOT_GROUP; ++g) {
+      const int i = i0 + g;
 #pragma unroll
       for (int q = 0; q < KRY_PER_THREAD; ++q) {
         const long e = base + threadIdx.x + q * KRY_THREADS;
-        if (e < n) {
-          const cx<double> x = vi[e];
-          acc += pw[q] * (x.x * wv[q].x + x.y * wv[q].y);
-        }
+        x[g][q] = mk(0.0, 0.0);
+        if (i < nv && e < n) x[g][q] = V[i * vstride + e];
       }
-    } else {
-#pragma unroll
-      for (int q = 0; q < KRY_PER_THREAD; ++q) acc += pw[q] * norm2(wv[q]);
     }
-    const double s = kry_block_sum(acc, red);
-    if (threadIdx.x == 0) part[blockIdx.x * ld + i] = s;
+    double acc[KDOT_GROUP];
+#pragma unroll
+    for (int g = 0; g < KDOT_GROUP; ++g) {
+      const int i = i0 + g;
+      double a = 0.0;
+      if (i < nv) {
+#pragma unroll
+        for (int q = 0; q < KRY_PER_THREAD; ++q) {
+          const long e = base + threadIdx.x + q * KRY_THREADS;
+          if (e < n)
+            a += pw[q] * (x[g][q].x * wv[q].x + x[g][q].y * wv[q].y);
+        }
+      } else if (i == nv) {
+#pragma unroll
+        for (int q = 0; q < KRY_PER_THREAD; ++q) a += pw[q] * norm2(wv[q]);
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+      acc[g] = a;
+    }
+    __syncthreads();  // the previous group's sums have been read
+    if (lane == 0) {
+#pragma unroll
+      for (int g = 0; g < KDOT_GROUP; ++g) red[wid * KDOT_GROUP + g] = acc[g];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int g = 0; g < KDOT_GROUP; ++g) {
+        const int i = i0 + g;
+        if (i > nv) break;
+        double sum = 0.0;
+        for (int q = 0; q < NW; ++q) sum += red[q * KDOT_GROUP + g];
+        part[static_cast<long>(i) * ld + blockIdx.x] = sum;
+      }
+    }
   }
 }
 
-// out[i] = scale * sum_b part[b*ld + i], one block per i, fixed order.
-__global__ void __launch_bounds__(KRY_THREADS)
+// out[i] = scale * sum_b part[i*ld + b], one block per i, fixed order:
+// thread t adds partials t, t + KRED_THREADS, ... in that order, issuing
+// KRED_BATCH of its loads before the first add of each batch (a dependent
+// loop waited one memory latency per partial), then the block sums its
+// threads in a fixed tree.
+constexpr int KRED_THREADS = 1024;
+constexpr int KRED_BATCH = 16;
+
+__global__ void __launch_bounds__(KRED_THREADS)
     kreduce_kernel(const double* __restrict__ part, int nblocks, int ld,
                    double scale, double* __restrict__ out) {
-  __shared__ double red[KRY_THREADS / 64];
+  __shared__ double red[KRED_THREADS / 64];
   const int i = blockIdx.x;
+  const double* row = part + static_cast<long>(i) * ld;
   double acc = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += KRY_THREADS)
-    acc += part[b * ld + i];
-  const double s = kry_block_sum(acc, red);
-  if (threadIdx.x == 0) out[i] = s * scale;
+  for (int b0 = 0; b0 < nblocks; b0 += KRED_THREADS * KRED_BATCH) {
+    double x[KRED_BATCH];
+#pragma unroll
+    for (int q = 0; q < KRED_BATCH; ++q) {
+      const int b = b0 + threadIdx.x + q * KRED_THREADS;
+      x[q] = b < nblocks ? row[b] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < KRED_BATCH; ++q) acc += x[q];
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < KRED_THREADS / 64; ++w) s += red[w];
+    out[i] = s * scale;
+  }
 }
 
 // w += sign * sum_{i<nv} coef[i] V_i ; optionally block partials of <w,w>
-// (after the update) into part[b*ld].
+// (after the update) into part[b].
 __global__ void __launch_bounds__(KRY_THREADS)
     kaxpy_kernel(cx<double>* __restrict__ w, const cx<double>* __restrict__ V,
                  long vstride, int nv, const double* __restrict__ coef,
@@ -104,20 +164,57 @@ __global__ void __launch_bounds__(KRY_THREADS)
   if (threadIdx.x < nv) cf[threadIdx.x] = sign * coef[threadIdx.x];
   __syncthreads();
   const long base = static_cast<long>(blockIdx.x) * KRY_PER_BLOCK;
+  // per element the terms are added in the order i = 0, 1, ...; two
+  // vectors' loads are in flight at once
+  cx<double> x[KRY_PER_THREAD];
+#pragma unroll
+  for (int q = 0; q < KRY_PER_THREAD; ++q) {
+    const long e = base + threadIdx.x + q * KRY_THREADS;
+    x[q] = mk(0.0, 0.0);
+    if (e < n) x[q] = w[e];
+  }
+  int i = 0;
+  for (; i + 1 < nv; i += 2) {
+    cx<double> y0[KRY_PER_THREAD], y1[KRY_PER_THREAD];
+#pragma unroll
+    for (int q = 0; q < KRY_PER_THREAD; ++q) {
+      const long e = base + threadIdx.x + q * KRY_THREADS;
+      y0[q] = mk(0.0, 0.0);
+      y1[q] = mk(0.0, 0.0);
+      if (e < n) {
+        y0[q] = V[i * vstride + e];
+        y1[q] = V[(i + 1) * vstride + e];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < KRY_PER_THREAD; ++q) {
+      x[q] = x[q] + y0[q] * cf[i];
+      x[q] = x[q] + y1[q] * cf[i + 1];
+    }
+  }
+  if (i < nv) {
+    cx<double> y0[KRY_PER_THREAD];
+#pragma unroll
+    for (int q = 0; q < KRY_PER_THREAD; ++q) {
+      const long e = base + threadIdx.x + q * KRY_THREADS;
+      y0[q] = mk(0.0, 0.0);
+      if (e < n) y0[q] = V[i * vstride + e];
+    }
+#pragma unroll
+    for (int q = 0; q < KRY_PER_THREAD; ++q) x[q] = x[q] + y0[q] * cf[i];
+  }
   double acc = 0.0;
 #pragma unroll
   for (int q = 0; q < KRY_PER_THREAD; ++q) {
     const long e = base + threadIdx.x + q * KRY_THREADS;
     if (e < n) {
-      cx<double> x = w[e];
-      for (int i = 0; i < nv; ++i) x = x + V[i * vstride + e] * cf[i];
-      w[e] = x;
-      if (part != nullptr) acc += half_weight(e, Nk, nh) * norm2(x);
+      w[e] = x[q];
+      if (part != nullptr) acc += half_weight(e, Nk, nh) * norm2(x[q]);
     }
   }
   if (part != nullptr) {
     const double s = kry_block_sum(acc, red);
-    if (threadIdx.x == 0) part[blockIdx.x * ld] = s;
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
   }
 }
 
@@ -165,7 +262,7 @@ __global__ void bicg_coef_kernel(double* __restrict__ k, int phase,
   }
 }
 
-// s = r - alpha v; block partials of <s, s> into part[b*ld]
+// s = r - alpha v; block partials of <s, s> into part[b]
 __global__ void __launch_bounds__(KRY_THREADS)
     kbicg_s_kernel(cx<double>* __restrict__ s, const cx<double>* __restrict__ r,
                    const cx<double>* __restrict__ v,
@@ -192,11 +289,11 @@ __global__ void __launch_bounds__(KRY_THREADS)
     }
   }
   const double t = kry_block_sum(acc, red);
-  if (threadIdx.x == 0) part[blockIdx.x * ld] = t;
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 // x += alpha p + omega s; r = s - omega t; block partials of <r^, r> and
-// <r, r> into part[b*ld], part[b*ld + 1]
+// <r, r> into part[b], part[ld + b]
 __global__ void __launch_bounds__(KRY_THREADS)
     kbicg_xr_kernel(cx<double>* __restrict__ x, cx<double>* __restrict__ r,
                     const cx<double>* __restrict__ p,
@@ -226,8 +323,8 @@ __global__ void __launch_bounds__(KRY_THREADS)
   const double t0 = kry_block_sum(a0, red);
   const double t1 = kry_block_sum(a1, red);
   if (threadIdx.x == 0) {
-    part[blockIdx.x * ld] = t0;
-    part[blockIdx.x * ld + 1] = t1;
+    part[blockIdx.x] = t0;
+    part[ld + blockIdx.x] = t1;
   }
 }
 

@@ -553,18 +553,33 @@ __global__ void __launch_bounds__(PassBShape<NT>::THREADS,
 }
 
 // Fixed-order final reduction of per-block partials for the non-iterate
-// modes: out[j] = inv_ns * sum_b partials[b][j].  One block of 256 threads.
-__global__ void __launch_bounds__(256)
+// modes: out[j] = inv_ns * sum_b partials[b][j].  One block of RED_THREADS
+// threads; thread t adds blocks t, t + RED_THREADS, ... in that order, with
+// RED_BATCH blocks' loads issued before the first add of each batch.
+constexpr int RED_THREADS = 1024;
+constexpr int RED_BATCH = 8;
+
+__global__ void __launch_bounds__(RED_THREADS)
     reduce_kernel(const double* __restrict__ partials, int nblocks,
                   double inv_ns, double* __restrict__ out) {
-  __shared__ double red[4 * 4];
+  __shared__ double red[(RED_THREADS / 64) * 4];
   double acc[4] = {0, 0, 0, 0};
-  for (int b = threadIdx.x; b < nblocks; b += 256) {
+  for (int b0 = 0; b0 < nblocks; b0 += RED_THREADS * RED_BATCH) {
+    double x[RED_BATCH][4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j] += partials[b * 4 + j];
+    for (int q = 0; q < RED_BATCH; ++q) {
+      const int b = b0 + threadIdx.x + q * RED_THREADS;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        x[q][j] = b < nblocks ? partials[static_cast<long>(b) * 4 + j] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < RED_BATCH; ++q)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j] += x[q][j];
   }
   double tot[4];
-  block_sum<4, 256>(acc, red, tot);
+  block_sum<4, RED_THREADS>(acc, red, tot);
   if (threadIdx.x != 0) return;
   for (int j = 0; j < 4; ++j) out[j] = tot[j] * inv_ns;
 }
