@@ -86,6 +86,30 @@ def _traffic(kernel, src_hash):
     return None if k is None else k.get("bytes_per_launch")
 
 
+def _copy_rate(nbytes, reps=50):
+    """GB/s (bytes read + bytes written over time) of torch's device copy of
+    `nbytes` bytes: the rate a plain streaming kernel reaches at that size.
+    Copies whose two buffers fit the 256 MB Infinity Cache run faster than
+    ones that stream from HBM."""
+    import torch
+    n = max(1, int(nbytes) // 8)
+    x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    e1.synchronize()
+    us = 1e3 * e0.elapsed_time(e1) / reps
+    del x, y
+    torch.cuda.empty_cache()
+    return 2.0 * n * 8 / (us * 1e-6) / 1e9
+
+
 def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -719,6 +743,13 @@ def main():
         "algorithmic_bytes_per_launch": kern[dom]["bytes_per_launch"],
         "avg_launch_us": kern[dom]["avg_us"],
     }
+    # what a plain device copy reaches at the dominant kernel's size (its
+    # read and write arrays fit the Infinity Cache) and at 1 GiB (HBM)
+    cp_same = _copy_rate(kern[dom]["bytes_per_launch"] / 2)
+    cp_hbm = _copy_rate(1 << 30, reps=10)
+    roof["copy_GBps_same_size"] = round(cp_same, 1)
+    roof["copy_GBps_1GiB"] = round(cp_hbm, 1)
+    roof["frac_of_copy_same_size"] = round(achieved / cp_same, 4)
     line = {
         "metric": "space-time DOF-iters/s + time-to-1e-10 "
                   "(mixed/batched vs plain FP64 GPU)",
