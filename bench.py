@@ -315,60 +315,68 @@ def bench_rd2d(steps):
     """The reaction-diffusion window (512^2 x 128, ETD2, mixed precision)
     solved to 1e-10 as the paper uses Exp-ParaDiag there: as the
     preconditioner of Newton-GMRES(20); beside it the fixed point on the
-    same window to ||S||/||U|| <= 1e-11.  Time to tolerance per solve,
-    Newton steps and GMRES iterations, and each result's error against
-    sequential ETD2 stepping (the oracle, fp64)."""
+    same window to ||S||/||U|| <= 1e-11, with its kernel classes against
+    the HBM roofline (the window, 268 MB per array, streams from HBM).
+    Time to tolerance per solve, Newton steps and GMRES iterations, and each
+    result's error against sequential ETD2 stepping (the oracle, fp64)."""
     import torch
     import workloads as W
     import oracle as O
     from paper_2603_04350_amd import expdiag as X
     dev = "cuda:0"
     inst = W.rd2d()
-    u0 = torch.from_numpy(inst.u0).to(dev)
-    U = torch.zeros((inst.Nt,) + inst.shape, dtype=torch.float64, device=dev)
     ref = O.sequential(O.Setup.from_instance(inst), inst.u0)
-    s = X.Solver.from_instance(inst, gmres_restart=20)
     out = {"workload": "u_t = 0.1 Lap u + u - u^3, periodic 512x512, "
                        "Nt=128, T=1, ETD2, alpha=1e-3, u0 = 32 periodic "
                        "Gaussians (seed 0), mixed precision",
            "dof": inst.dof}
     steps = max(1, min(steps, 3))
-    for meth in ("newton_gmres", "fixed_point"):
-        def solve():
-            U.zero_()
-            if meth == "newton_gmres":
-                return s.gmres(u0, U, restart=20, max_iter=400, tol=1e-10)
-            return s.iterate(u0, U, max_iter=400, tol=TOL)
-        solve()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            rc, it, rel = solve()
-        torch.cuda.synchronize()
-        ms = 1e3 * (time.perf_counter() - t0) / steps
-        row = {"ms_per_solve": ms, "rel": rel,
-               "err_vs_oracle": float(O.rel_err(U.cpu().numpy(), ref))}
-        if meth == "newton_gmres":
-            row["newton_steps"] = it // 1000
-            row["gmres_iters"] = it % 1000
-            # event time per kernel class over one more solve
-            X.expdiag_profile_enable(s.h, 0x1F)
-            solve()
-            pm, pc, pb, pt = X.expdiag_profile_read(s.h)
-            X.expdiag_profile_enable(s.h, 0)
-            row["classes_ms"] = {X.PROFILE_CLASSES[i]: round(pm[i], 3)
-                                 for i in range(len(pm)) if pt[i]}
-            row["classes_launches"] = {X.PROFILE_CLASSES[i]: int(pc[i])
-                                       for i in range(len(pm)) if pt[i]}
-            row["classes_GBps"] = {X.PROFILE_CLASSES[i]:
-                                   round(pb[i] / (pm[i] * 1e-3) / 1e9, 1)
-                                   for i in range(len(pm)) if pt[i]}
-        else:
-            row["iters"] = it
-            row["dof_iters_per_s"] = inst.dof * it / (ms * 1e-3)
-        out[meth] = row
+    u0 = torch.from_numpy(inst.u0).to(dev)
+    U = torch.zeros((inst.Nt,) + inst.shape, dtype=torch.float64, device=dev)
+    s = X.Solver.from_instance(inst, gmres_restart=20)
+
+    def solve():
+        U.zero_()
+        return s.gmres(u0, U, restart=20, max_iter=400, tol=1e-10)
+
+    solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rc, it, rel = solve()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    row = {"ms_per_solve": ms, "rel_resid": rel,
+           "err_vs_oracle": float(O.rel_err(U.cpu().numpy(), ref)),
+           "newton_steps": it // 1000, "gmres_iters": it % 1000}
+    # event time per kernel class over one more solve
+    X.expdiag_profile_enable(s.h, 0x1F)
+    solve()
+    pm, pc, pb, pt = X.expdiag_profile_read(s.h)
+    X.expdiag_profile_enable(s.h, 0)
+    row["classes_ms"] = {X.PROFILE_CLASSES[i]: round(pm[i], 3)
+                         for i in range(len(pm)) if pt[i]}
+    row["classes_launches"] = {X.PROFILE_CLASSES[i]: int(pc[i])
+                               for i in range(len(pm)) if pt[i]}
+    row["classes_GBps"] = {X.PROFILE_CLASSES[i]:
+                           round(pb[i] / (pm[i] * 1e-3) / 1e9, 1)
+                           for i in range(len(pm)) if pt[i]}
+    out["newton_gmres"] = row
     s.close()
     del U, u0
+    torch.cuda.empty_cache()
+    fp = bench_single(inst, 1, steps, 1)
+    Ufp = fp.pop("U")
+    out["fixed_point"] = {
+        "ms_per_solve": fp["ms_per_solve"], "iters": fp["iters"],
+        "rel_update": fp["rel_update"],
+        "dof_iters_per_s": fp["dof_iters_per_s"],
+        "us_per_iter": fp["us_per_iter"],
+        "err_vs_oracle": float(O.rel_err(Ufp, ref)),
+        "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()}
+                    for k, v in fp["kernels"].items()},
+        "iteration_bytes": fp["iteration_bytes"],
+        "iteration_hbm_frac": round(fp["iteration_hbm_frac"], 4)}
     torch.cuda.empty_cache()
     return out
 

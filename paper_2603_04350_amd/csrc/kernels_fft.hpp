@@ -355,15 +355,22 @@ __global__ void __launch_bounds__(RowShape<M>::THREADS)
   row_body<T, M, MODE, TI, TO>(jb, blockIdx.x, tw, lds);
 }
 
-// C adjacent columns per workgroup; LDS of L*C complex (32 KiB in fp64 for
-// L <= 512), which lets five workgroups share a CU.
+// C adjacent columns per workgroup, at least 8 (a 128-byte run of fp64
+// complex per row) while the tile of L*C complex fits 64 KiB of LDS, else
+// 4; for L <= 256 the tile is 32 KiB in fp64, which lets five workgroups
+// share a CU.  WAVES: the waves per SIMD that the LDS of one CU (160 KiB)
+// allows, at most five (the register budget of the launch bounds).
 template <int L>
 struct ColShape {
   static constexpr int R = FftShape<L>::R;
   static constexpr int TPL = FftShape<L>::TPL;
-  static constexpr int C = (256 / TPL) >= 4 ? 256 / TPL : 4;
+  static constexpr int CMIN = L * 8 * 16 <= 65536 ? 8 : 4;
+  static constexpr int C = (256 / TPL) >= CMIN ? 256 / TPL : CMIN;
   static constexpr int THREADS = C * TPL;
   static constexpr int LS = C;  // LDS row (complex slots)
+  static constexpr int BLOCKS_LDS = 163840 / (L * C * 16);
+  static constexpr int WAVES_LDS = BLOCKS_LDS * THREADS / 256;
+  static constexpr int WAVES = WAVES_LDS < 1 ? 1 : (WAVES_LDS > 5 ? 5 : WAVES_LDS);
 };
 
 struct ColJob {
@@ -423,7 +430,7 @@ __device__ __forceinline__ void col_body(const ColJob& jb, int lb,
 // row_kernel_mp): jobs[2i] fp32 (input type TI0, fp32 output), jobs[2i + 1]
 // fp64.
 template <int L, int S, typename TI0>
-__global__ void __launch_bounds__(ColShape<L>::THREADS, 5)
+__global__ void __launch_bounds__(ColShape<L>::THREADS, ColShape<L>::WAVES)
     col_kernel_mp(const ColJob* __restrict__ jobs,
                   const int* __restrict__ start, int njobs,
                   const cx<float>* __restrict__ tw32,
@@ -445,7 +452,7 @@ __global__ void __launch_bounds__(ColShape<L>::THREADS, 5)
 }
 
 template <typename T, int L, int S, typename TI, typename TO>
-__global__ void __launch_bounds__(ColShape<L>::THREADS, 5)
+__global__ void __launch_bounds__(ColShape<L>::THREADS, ColShape<L>::WAVES)
     col_kernel1(ColJob jb, const cx<T>* __restrict__ tw) {
   __shared__ cx<T> lds[L * ColShape<L>::LS];
   if (!job_live(jb.ctl, jb.phase_req)) return;

@@ -519,7 +519,7 @@ __global__ void __launch_bounds__(CTL_THREADS)
 // still transform an instance whose reduction in this launch finds it done:
 // the result is never read.
 template <int L, int S>
-__global__ void __launch_bounds__(ColShape<L>::THREADS, 5)
+__global__ void __launch_bounds__(ColShape<L>::THREADS, ColShape<L>::WAVES)
     col_kernel_host(const ColJob* __restrict__ jobs,
                     const int* __restrict__ start, int njobs,
                     const PassBArgs* __restrict__ red_jobs, int nred,
