@@ -700,6 +700,59 @@ def profile_run(steps):
     print(json.dumps({"event_avg_us": out}), flush=True)
 
 
+def profile_large(steps):
+    """Fixed-count solves of the windows that stream from HBM, for a
+    profiler wrapped around this process: the reaction-diffusion window
+    (512^2 x 128, ETD2, mixed; the fixed point for 17 iterations, its count
+    to tolerance, then one Newton-GMRES(20) solve to 1e-10) and the first 3D
+    Allen-Cahn request of the served stream (128^3 x 32, mixed; 14
+    iterations, its count to tolerance).  The counts are fixed here so that
+    no solve to a tolerance (whose launches past convergence return at once)
+    enters the profile.  Prints the event-timed average launch time of each
+    kernel class."""
+    import torch
+    import workloads as W
+    from paper_2603_04350_amd import expdiag as X
+    _, stream = W.served_stream(64, 1.0, seed=1)
+    ac3d = next(i for i in stream if i.name.startswith("ac3d"))
+    out = {}
+    for name, inst, iters in (("rd2d_fixed_point", W.rd2d(), 17),
+                              ("ac3d_128", ac3d, 14)):
+        u0 = torch.from_numpy(inst.u0).to("cuda:0")
+        U = torch.zeros((inst.Nt,) + inst.shape, dtype=torch.float64,
+                        device="cuda:0")
+        s = X.Solver.from_instance(inst)
+        for _ in range(2):
+            U.zero_()
+            s.iterate(u0, U, max_iter=iters, tol=0.0)
+        X.expdiag_profile_enable(s.h, 0x1F)
+        for _ in range(steps):
+            U.zero_()
+            s.iterate(u0, U, max_iter=iters, tol=0.0)
+        ms, cnt, by, tm = X.expdiag_profile_read(s.h)
+        X.expdiag_profile_enable(s.h, 0)
+        out[name] = {"iters": iters, "event_avg_us": {
+            X.PROFILE_CLASSES[i]: round(1e3 * ms[i] / tm[i], 3)
+            for i in range(len(ms)) if tm[i]}, "bytes_per_launch": {
+            X.PROFILE_CLASSES[i]: by[i] / cnt[i]
+            for i in range(len(ms)) if tm[i]}}
+        s.close()
+        del U, u0
+        torch.cuda.empty_cache()
+        _log(f"profile {name} done")
+    inst = W.rd2d()
+    u0 = torch.from_numpy(inst.u0).to("cuda:0")
+    U = torch.zeros((inst.Nt,) + inst.shape, dtype=torch.float64,
+                    device="cuda:0")
+    s = X.Solver.from_instance(inst, gmres_restart=20)
+    rc, it, rel = s.gmres(u0, U, restart=20, max_iter=400, tol=1e-10)
+    out["rd2d_newton_gmres"] = {"newton_steps": it // 1000,
+                                "gmres_iters": it % 1000}
+    s.close()
+    _log("profile rd2d_newton_gmres done")
+    print(json.dumps({"event_avg_us_large": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -716,6 +769,9 @@ def main():
                          "and IF1 sections")
     ap.add_argument("--quick", action="store_true",
                     help="fp64 single-instance solves only")
+    ap.add_argument("--profile-large", action="store_true",
+                    help="fixed-count solves of the 512^2 x 128 and 3D "
+                         "128^3 x 32 windows only, for profiler runs")
     ap.add_argument("--profile", action="store_true",
                     help="fixed-count solves only, for profiler runs")
     args = ap.parse_args()
@@ -729,6 +785,9 @@ def main():
     rank = int(os.environ.get("RANK", "0"))
     if args.profile:
         profile_run(args.steps)
+        return
+    if args.profile_large:
+        profile_large(args.steps)
         return
     import workloads as W
     inst = W.allen_cahn2d()
