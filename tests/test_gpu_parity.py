@@ -29,6 +29,9 @@ CASES = {
     "heat3d": (3, 8, 4, 1e-2, 1.0, 0.1, 0, 0, 0, 1),
     "ac3d": (3, 16, 8, 1e-3, 0.0025, 0.0, 1.0, 0, -1.0, 1),
     "fisher2d_Nt512": (2, 16, 512, 1e-2, 0.01, 0.0, 1.0, -1.0, 0, 2),
+    # the longest columns (512 and 1024 points: 8 and 4 columns per tile)
+    "ac2d_n512_Nt4": (2, 512, 4, 1e-3, 1e-4, 0.0, 1.0, 0, -1.0, 1),
+    "ac2d_n1024_Nt2": (2, 1024, 2, 1e-2, 1e-5, 0.0, 1.0, 0, -1.0, 2),
 }
 
 
