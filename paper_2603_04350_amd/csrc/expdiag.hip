@@ -136,7 +136,7 @@ struct expdiag_ctx {
   Ctl* ctl = nullptr;
   double* hist = nullptr;     // [HIST_CAP][2]
   cx<double>* V = nullptr;    // Krylov basis [(restart+1)][Nt][Nk]
-  double* kdots = nullptr;    // [3 (restart+2)]
+  double* kdots = nullptr;    // [4 (restart+2)]
   double* kpart = nullptr;    // [blocks][restart+2]
   int kpart_blocks = 0;
 
@@ -1844,7 +1844,7 @@ int create_impl(const expdiag_grid* g, int Nt, double dt, double alpha,
     h->kpart_blocks = static_cast<int>(krylov_blocks(Nt * h->Nk));
     A(&h->kpart, static_cast<size_t>(h->kpart_blocks) *
                      (h->restart_cap + 2) * sizeof(double));
-    A(&h->kdots, 3 * (h->restart_cap + 2) * sizeof(double));
+    A(&h->kdots, 4 * (h->restart_cap + 2) * sizeof(double));
     if (h->nonlinear)
       A(&h->Uphys, static_cast<size_t>(Nt) * h->Ns * sizeof(double));
     if (h->nonlinear && h->mixed)
@@ -1855,7 +1855,7 @@ int create_impl(const expdiag_grid* g, int Nt, double dt, double alpha,
         hipHostMalloc(&h->h_mirror, sizeof(Ctl), hipHostMallocMapped) !=
             hipSuccess ||
         hipHostMalloc(&h->h_red, 8 * sizeof(double)) != hipSuccess ||
-        hipHostMalloc(&h->h_kdots, 3 * (h->restart_cap + 2) *
+        hipHostMalloc(&h->h_kdots, 4 * (h->restart_cap + 2) *
                                        sizeof(double)) != hipSuccess)
       rc = fail(h, EXPDIAG_ENOMEM, "pinned host allocation");
   }

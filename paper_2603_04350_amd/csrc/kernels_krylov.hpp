@@ -115,7 +115,8 @@ __global__ void __launch_bounds__(KRY_THREADS)
   }
 }
 
-// out[i] = scale * sum_b part[i*ld + b], one block per i, fixed order:
+// out[i] = scale * sum_b part[i*ld + b] (times vmul[i] when vmul is given),
+// one block per i, fixed order:
 // thread t adds partials t, t + KRED_THREADS, ... in that order, issuing
 // KRED_BATCH of its loads before the first add of each batch (a dependent
 // loop waited one memory latency per partial), then the block sums its
@@ -125,7 +126,8 @@ constexpr int KRED_BATCH = 16;
 
 __global__ void __launch_bounds__(KRED_THREADS)
     kreduce_kernel(const double* __restrict__ part, int nblocks, int ld,
-                   double scale, double* __restrict__ out) {
+                   double scale, const double* __restrict__ vmul,
+                   double* __restrict__ out) {
   __shared__ double red[KRED_THREADS / 64];
   const int i = blockIdx.x;
   const double* row = part + static_cast<long>(i) * ld;
@@ -148,7 +150,7 @@ __global__ void __launch_bounds__(KRED_THREADS)
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int w = 0; w < KRED_THREADS / 64; ++w) s += red[w];
-    out[i] = s * scale;
+    out[i] = vmul != nullptr ? s * scale * vmul[i] : s * scale;
   }
 }
 
