@@ -13,7 +13,7 @@ Reference: Garai & Chamakuri, "Exp-ParaDiag: Time-Parallel Exponential
 Integrators for Parabolic PDEs" (arXiv 2603.04350).  Citations below name the
 section / equation of that paper.
 
-Readings taken where the paper is silent (also listed in the design doc):
+Readings taken where the paper is silent:
   * Spatial operator: Fourier collocation on periodic [0,2pi)^d, n even,
     L = a*Lap - b.grad - c with symbol mu_k = -a|k|^2 - c - i b.k' (the
     analysis of Sec. 2-3 only needs L_h diagonalisable with spectrum in the
