@@ -78,7 +78,8 @@ import numpy as np
 
 __all__ = [
     "Setup", "phi1", "phi2", "sequential", "residual", "precond_apply",
-    "fixed_point", "q_apply", "qalpha_apply", "gprime_apply", "gmres",
+    "fixed_point", "q_apply", "qalpha_apply", "gprime_apply",
+    "nonlinear_term", "gmres",
     "gmres_solve", "newton_gmres", "rel_err", "dense_operators",
     "dense_solve", "dense_newton", "time_dft", "time_idft",
     "EBDF2", "ebdf2_tables", "sequential_ebdf2", "residual_ebdf2",

@@ -312,3 +312,76 @@ def test_bicgstab_omega_sign_flipped(monkeypatch):
     assert src is not bad
     _patch_pkg(monkeypatch, "bicgstab", bad)
     assert _fails(PS.test_bicgstab_iterates_match_scipy, 2)
+
+
+# ---------------------------------------------------------------------------
+# G'(U) and the error metric
+# ---------------------------------------------------------------------------
+def _patch_oracle(monkeypatch, name, fn):
+    """Replace an oracle function in its module and in the package
+    namespace the pins call it through."""
+    monkeypatch.setattr(OE, name, fn)
+    monkeypatch.setattr(P.O, name, fn)
+
+
+def test_gprime_phi2_terms_dropped(monkeypatch):
+    """ETD2's Jacobian without its W2 (J1 - J2) terms: Newton still reaches
+    the unique solution, so only the difference pin can see it."""
+    orig = OE.gprime_apply
+
+    def bad(st, u0, U, V):
+        if st.scheme == 2:
+            P1 = OE._shift(st, U, u0)
+            V1 = OE._shift(st, V, np.zeros_like(u0))
+            return st.W1(st.dN(P1) * V1)
+        return orig(st, u0, U, V)
+    _patch_oracle(monkeypatch, "gprime_apply", bad)
+    assert _fails(P.test_gprime_equals_richardson_difference, 2, 1, 16, 6)
+    assert _fails(P.test_gprime_linear_reaction_is_scaled_shift)
+    assert not _fails(P.test_gprime_equals_richardson_difference, 1, 1, 16,
+                      6)
+
+
+def test_gprime_unshifted_direction(monkeypatch):
+    """N' at u_{n-1} applied to v_n instead of v_{n-1}."""
+    def bad(st, u0, U, V):
+        P1 = OE._shift(st, U, u0)
+        return st.W1(st.dN(P1) * V)
+    _patch_oracle(monkeypatch, "gprime_apply", bad)
+    assert _fails(P.test_gprime_equals_richardson_difference, 1, 2, 8, 5)
+
+
+def test_gprime_second_lag_sign(monkeypatch):
+    """ETD2's lagged term added instead of subtracted."""
+    def bad(st, u0, U, V):
+        P1 = OE._shift(st, U, u0)
+        V1 = OE._shift(st, V, np.zeros_like(u0))
+        P2 = OE._shift(st, P1, u0)
+        V2 = OE._shift(st, V1, np.zeros_like(u0))
+        J1, J2 = st.dN(P1) * V1, st.dN(P2) * V2
+        return st.W1(J1) + st.W2(J1 + J2)
+    _patch_oracle(monkeypatch, "gprime_apply", bad)
+    assert _fails(P.test_gprime_equals_richardson_difference, 2, 2, 8, 5)
+
+
+def test_nonlinear_derivative_caught_by_difference_pin(monkeypatch):
+    """A wrong N' (the u^2 coefficient dropped) fails the difference pin
+    directly, not only through a Newton step count."""
+    monkeypatch.setattr(OE.Setup, "dN",
+                        lambda self, u: self.n1 + 3.0 * self.n3 * u * u)
+    assert _fails(P.test_gprime_equals_richardson_difference, 1, 1, 16, 6)
+
+
+@pytest.mark.parametrize("bad", [
+    lambda U, V: np.linalg.norm(U - V) / np.linalg.norm(V),
+    lambda U, V: np.abs(U - V).max() / np.abs(V).max(),
+    lambda U, V: (np.sqrt((np.abs(U - V) ** 2).sum(axis=tuple(
+        range(1, U.ndim)))).mean()
+        / np.sqrt((np.abs(V) ** 2).sum(axis=tuple(range(1, U.ndim)))).mean()),
+    lambda U, V: (np.sqrt((np.abs(U - V) ** 2).sum(axis=tuple(
+        range(1, U.ndim)))).max()
+        / np.sqrt((np.abs(U) ** 2).sum(axis=tuple(range(1, U.ndim)))).max()),
+])
+def test_rel_err_wrong_norm(monkeypatch, bad):
+    _patch_oracle(monkeypatch, "rel_err", bad)
+    assert _fails(P.test_rel_err_hand_computed)

@@ -385,3 +385,88 @@ def test_newton_gmres_reaches_sequential(scheme):
     U, steps, inner, hist = O.newton_gmres(st, inst.u0, tol=1e-12)
     assert O.rel_err(U, ref) < 1e-10
     assert steps <= 10
+
+
+# ---------------------------------------------------------------------------
+# G'(U): the derivative of the lagged nonlinear term (Newton's Jacobian of
+# Sec. 5, eq. newton_2, for the ETD schemes), against differences of G
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("scheme,dim,n,Nt", [(1, 1, 16, 6), (2, 1, 16, 6),
+                                             (1, 2, 8, 5), (2, 2, 8, 5),
+                                             (2, 3, 4, 4)])
+def test_gprime_equals_richardson_difference(scheme, dim, n, Nt):
+    """N(u) = n1 u + n2 u^2 + n3 u^3 is a cubic polynomial, so the lagged
+    term G(U) (plus the constant u_0 part of f) is cubic in U.  For a cubic
+    the central difference D(h) = [G(U + hV) - G(U - hV)] / (2h) equals
+    G'(U)V + h^2/6 G'''(U)[V,V,V] exactly, so the Richardson combination
+    (4 D(h) - D(2h)) / 3 is G'(U)V with no truncation error at all: the
+    only difference left is rounding (about eps |G| / h)."""
+    st = O.Setup(dim, n, Nt, 0.05, 1e-2, a=0.1, n1=1.0, n2=0.3, n3=-1.0,
+                 scheme=scheme)
+    rng = np.random.default_rng([dim, n, Nt, scheme])
+    u0 = _field(rng, dim, n)
+    U = rng.uniform(-0.9, 0.9, size=(Nt,) + (n,) * dim)
+    V = rng.uniform(-1.0, 1.0, size=U.shape)
+    h = 1e-2
+
+    def D(s):
+        return (O.nonlinear_term(st, u0, U + s * V)
+                - O.nonlinear_term(st, u0, U - s * V)) / (2.0 * s)
+    fd = (4.0 * D(h) - D(2.0 * h)) / 3.0
+    got = O.gprime_apply(st, u0, U, V)
+    assert np.max(np.abs(got - fd)) <= 1e-11 * np.max(np.abs(fd))
+    # the first slice depends on u_0 only: its row of G' is zero
+    assert np.max(np.abs(got[0])) == 0.0
+
+
+def test_gprime_linear_reaction_is_scaled_shift():
+    """N(u) = beta u: G(U) is linear, G'(U)V = G(V) - G(0) for any U, and
+    per Fourier mode slice n of G'V is dt phi1 beta v_{n-1} (ETD1) or
+    dt[(phi1 + phi2) beta v_{n-1} - phi2 beta v_{n-2}] (ETD2), v_0 = v_{-1}
+    = 0, with phi from mpmath (independent of the oracle's phi)."""
+    beta, n, Nt, dt = 0.7, 16, 6, 0.05
+    rng = np.random.default_rng(11)
+    k = np.fft.fftfreq(n, 1.0 / n)
+    z = dt * (-0.2 * k * k)
+    p1 = np.array([float(_mp_phi1(v)) for v in z])
+    p2 = np.array([float(_mp_phi2(v)) for v in z])
+    for scheme in (1, 2):
+        st = O.Setup(1, n, Nt, dt, 1e-2, a=0.2, n1=beta, scheme=scheme)
+        U = rng.uniform(-0.9, 0.9, size=(Nt, n))
+        V = rng.uniform(-1.0, 1.0, size=(Nt, n))
+        got = np.fft.fft(O.gprime_apply(st, U[0], U, V), axis=1)
+        Vh = np.fft.fft(V, axis=1)
+        pred = np.zeros_like(Vh)
+        for m in range(1, Nt):
+            if scheme == 1:
+                pred[m] = dt * p1 * beta * Vh[m - 1]
+            else:
+                prev2 = Vh[m - 2] if m >= 2 else 0.0
+                pred[m] = dt * ((p1 + p2) * beta * Vh[m - 1]
+                                - p2 * beta * prev2)
+        assert np.max(np.abs(got - pred)) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# the error metric of Sec. 6: L_inf(0,T; L2), normalised
+# ---------------------------------------------------------------------------
+def test_rel_err_hand_computed():
+    """Two slices of two points.  U - V has slice norms 5 (3, 4) and 1
+    (1, 0); V has slice norms 10 (0, 10) and 1 (0, 1): the L_inf(0,T;L2)
+    ratio is 5/10 = 0.5.  A Frobenius ratio would give sqrt(26/101) = 0.507,
+    an entrywise max ratio 4/10, a mean over slices 3/5.5, normalising by U
+    instead of V 5/sqrt(9 + 196)."""
+    V = np.array([[0.0, 10.0], [0.0, 1.0]])
+    U = V + np.array([[3.0, 4.0], [1.0, 0.0]])
+    assert O.rel_err(U, V) == pytest.approx(0.5, rel=1e-15)
+    # complex entries: |3i| and |4| form the same slice norm
+    Vc = V.astype(complex)
+    Uc = Vc + np.array([[3j, 4.0], [-1j, 0.0]])
+    assert O.rel_err(Uc, Vc) == pytest.approx(0.5, rel=1e-15)
+    # 2D slices: the slice norm runs over every spatial point
+    V2 = np.zeros((3, 2, 2))
+    V2[1, 0, 1] = 2.0
+    U2 = V2.copy()
+    U2[2] = [[1.0, 1.0], [1.0, 1.0]]    # slice norm 2
+    U2[0, 1, 1] = 1.0                   # slice norm 1
+    assert O.rel_err(U2, V2) == pytest.approx(1.0, rel=1e-15)
