@@ -229,6 +229,25 @@ int expdiag_iterate(expdiag_t h, const double* u0, double* U, int max_iter,
 int expdiag_gmres(expdiag_t h, const double* u0, double* U, int restart,
                   int max_iter, double tol, int* iters, double* rel_resid);
 
+/* The operator Newton's correction equation applies, preconditioned as
+ * expdiag_gmres applies it: W = Q_alpha^{-1} (Q - G'(U)) V, with G'(U) the
+ * derivative of the lagged nonlinear term at the iterate U (u_0 fixed;
+ * Sec. 5, eq. newton_2, applied to the all-at-once system of eq.
+ * all_at_once_1storder).  ETD1: slice n of G'(U)V is
+ * dt phi1(dt L) [N'(u_{n-1}) v_{n-1}]; ETD2: dt[(phi1+phi2) N'(u_{n-1})
+ * v_{n-1} - phi2 N'(u_{n-2}) v_{n-2}] with v_0 = v_{-1} = 0.  For linear
+ * problems W = Q_alpha^{-1} Q V, GMRES's operator.  Mixed precision (d >=
+ * 2): the products N'(u) v and their spatial FFTs run in fp32, as in the
+ * Newton loop.
+ *   u0      Ns doubles (device)
+ *   U, V    Nt*Ns doubles (device): linearisation point and direction
+ *   W       Nt*Ns doubles (device), distinct from U and V
+ * Needs a handle created with gmres_restart >= 1 (it works in the Krylov
+ * workspace; EINVAL otherwise).  Overwrites the handle's iterate state.
+ * Enqueue only. */
+int expdiag_newton_apply(expdiag_t h, const double* u0, const double* U,
+                         const double* V, double* W);
+
 /* Preconditioned BiCGStab (the bracketed timings of Table cpu_time_combined;
  * van der Vorst's method, shadow residual r^_0 = r_0) on the same
  * left-preconditioned system as expdiag_gmres, with the same Newton outer
@@ -304,6 +323,15 @@ int expdiag_batch_destroy(expdiag_batch_t b);
 int expdiag_batch_iterate(expdiag_batch_t b, const double* const* u0s,
                           double* const* Us, int max_iter, double tol,
                           int* iters, double* rel_update, int* status);
+/* The same with a cap and a tolerance per instance: instance i stops after
+ * max_iters[i] iterations (1..4096) or once ||S^k|| <= tols[i] ||U^{k+1}||
+ * (tols[i] >= 0; 0 runs exactly max_iters[i] iterations).  max_iters and
+ * tols are host arrays of count entries; the other arguments and the
+ * return value are those of expdiag_batch_iterate. */
+int expdiag_batch_iterate_each(expdiag_batch_t b, const double* const* u0s,
+                               double* const* Us, const int* max_iters,
+                               const double* tols, int* iters,
+                               double* rel_update, int* status);
 const char* expdiag_batch_last_error(expdiag_batch_t b);
 
 /* ---- Serving: continuous batching of solve requests -------------------
@@ -313,7 +341,13 @@ const char* expdiag_batch_last_error(expdiag_batch_t b);
  * each admitted solve's space-time state on the device, runs all admitted
  * solves together (the batch plan above, rebuilt when membership changes),
  * and retires each as it converges.  Requests arriving while others run
- * join at the next iteration chunk. */
+ * join at the next iteration chunk.  Should building the launch plan or
+ * running a chunk fail (EHIP), nothing more is launched for that set:
+ * every active and pending request is reported by poll with status
+ * EXPDIAG_EHIP, their handles are released, and later submissions start
+ * afresh.  (Setting the environment variable EXPDIAG_FAIL_PLAN_UPLOAD makes
+ * every plan upload fail, as an out-of-memory upload would, for tests of
+ * this path.) */
 typedef struct expdiag_server* expdiag_server_t;
 typedef struct {
   long long id;

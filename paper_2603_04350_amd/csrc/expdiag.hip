@@ -26,6 +26,7 @@
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -920,6 +921,12 @@ size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 // on `st`; the staging buffer is reused only after `st` has synchronised,
 // which every caller does before rebuilding a plan).
 int plan_upload(expdiag_ctx* h, Plan& P, hipStream_t st) {
+  // failure-path tests force an upload failure from the host (as a failed
+  // arena allocation would leave it: no device tables)
+  if (std::getenv("EXPDIAG_FAIL_PLAN_UPLOAD") != nullptr) {
+    P.uploaded = false;
+    return fail(h, EXPDIAG_EHIP, "plan upload failed (forced)");
+  }
   std::stable_sort(P.groups.begin(), P.groups.end(),
                    [](const Group& x, const Group& y) {
                      return x.stage < y.stage;
@@ -996,6 +1003,8 @@ void plan_free(Plan& P) { plan_clear(P, false); }
 // used for profiling and error text (nullable).
 int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st,
                 const cx<double>* tw64, const cx<float>* tw32) {
+  // a plan whose job tables are not on the device is never launched
+  if (!P.uploaded) return fail(ph, EXPDIAG_EHIP, "plan not uploaded");
   for (auto& g : P.groups) {
     const int grid = g.grid();
     if (grid == 0) continue;
@@ -1115,6 +1124,7 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st,
 // iteration's first stage), so the control blocks are current when the
 // host looks.
 int plan_finish(expdiag_ctx* ph, Plan& P, hipStream_t st) {
+  if (!P.uploaded) return fail(ph, EXPDIAG_EHIP, "plan not uploaded");
   for (auto& g : P.groups) {
     if (g.kind != K_PASSB || g.njobs() == 0) continue;
     ProfScope pr(ph, P_RED, static_cast<double>(g.grid()) * 32, true);

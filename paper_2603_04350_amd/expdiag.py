@@ -36,10 +36,12 @@ EXPORTED = (
     "expdiag_create", "expdiag_destroy", "expdiag_set_stream",
     "expdiag_footprint_bytes", "expdiag_residual", "expdiag_precond_apply",
     "expdiag_iterate", "expdiag_gmres", "expdiag_bicgstab",
+    "expdiag_newton_apply",
     "expdiag_profile_enable",
     "expdiag_profile_read", "expdiag_strerror", "expdiag_last_error",
     "expdiag_set_graph", "expdiag_batch_create", "expdiag_batch_destroy",
-    "expdiag_batch_iterate", "expdiag_batch_last_error",
+    "expdiag_batch_iterate", "expdiag_batch_iterate_each",
+    "expdiag_batch_last_error",
     "expdiag_server_create", "expdiag_server_submit", "expdiag_server_poll",
     "expdiag_server_stats", "expdiag_server_destroy",
     "expdiag_set_time_variant", "expdiag_get_time_variant",
@@ -106,6 +108,7 @@ def load(path: str = LIB_PATH):
                                 ctypes.POINTER(ci), ctypes.POINTER(cd)]
     L.expdiag_bicgstab.argtypes = [vp, vp, vp, ci, cd,
                                    ctypes.POINTER(ci), ctypes.POINTER(cd)]
+    L.expdiag_newton_apply.argtypes = [vp, vp, vp, vp, vp]
     L.expdiag_profile_enable.argtypes = [vp, ci]
     L.expdiag_profile_read.argtypes = [vp, ctypes.POINTER(cd),
                                        ctypes.POINTER(ctypes.c_long),
@@ -123,6 +126,12 @@ def load(path: str = LIB_PATH):
                                         ctypes.POINTER(ci),
                                         ctypes.POINTER(cd),
                                         ctypes.POINTER(ci)]
+    L.expdiag_batch_iterate_each.argtypes = [vp, pp, pp,
+                                             ctypes.POINTER(ci),
+                                             ctypes.POINTER(cd),
+                                             ctypes.POINTER(ci),
+                                             ctypes.POINTER(cd),
+                                             ctypes.POINTER(ci)]
     L.expdiag_batch_last_error.argtypes = [vp]
     L.expdiag_batch_last_error.restype = ctypes.c_char_p
     L.expdiag_server_create.argtypes = [sz, ci, vp, pp]
@@ -279,6 +288,13 @@ def expdiag_bicgstab(h, u0, U, max_iter, tol):
     return rc, it.value, rel.value
 
 
+def expdiag_newton_apply(h, u0, U, V, W):
+    n = U.numel()
+    return _check(load().expdiag_newton_apply(
+        h, _ptr(u0, name="u0"), _ptr(U, name="U"), _ptr(V, n, "V"),
+        _ptr(W, n, "W")), h)
+
+
 def expdiag_profile_enable(h, mask=0x1F):
     """mask: bit i brackets launches of class i with events; 0 disables."""
     return _check(load().expdiag_profile_enable(h, int(mask)), h)
@@ -355,6 +371,9 @@ class Solver:
     def bicgstab(self, u0, U, max_iter=400, tol=1e-10):
         return expdiag_bicgstab(self.h, u0, U, max_iter, tol)
 
+    def newton_apply(self, u0, U, V, W):
+        return expdiag_newton_apply(self.h, u0, U, V, W)
+
 
 def expdiag_set_graph(h, on=True):
     return _check(load().expdiag_set_graph(h, 1 if on else 0), h)
@@ -394,6 +413,27 @@ def expdiag_batch_iterate(b, u0s, Us, max_iter, tol):
     return rc, list(it), list(rel), list(st)
 
 
+def expdiag_batch_iterate_each(b, u0s, Us, max_iters, tols):
+    """Per-instance caps and tolerances; returns (rc, iters[],
+    rel_update[], status[])."""
+    L = load()
+    n = len(u0s)
+    if len(Us) != n or len(max_iters) != n or len(tols) != n:
+        raise ValueError("u0s, Us, max_iters and tols differ in length")
+    pu = (ctypes.c_void_p * n)(*[_ptr(t, name="u0").value for t in u0s])
+    pU = (ctypes.c_void_p * n)(*[_ptr(t, name="U").value for t in Us])
+    caps = (ctypes.c_int * n)(*[int(v) for v in max_iters])
+    tl = (ctypes.c_double * n)(*[float(v) for v in tols])
+    it = (ctypes.c_int * n)()
+    rel = (ctypes.c_double * n)()
+    st = (ctypes.c_int * n)()
+    rc = L.expdiag_batch_iterate_each(b, pu, pU, caps, tl, it, rel, st)
+    if rc < 0 and rc != EXPDIAG_EDIVERGED:
+        raise ExpdiagError(rc, f"{strerror(rc)}: "
+                           f"{L.expdiag_batch_last_error(b).decode()}")
+    return rc, list(it), list(rel), list(st)
+
+
 class Batch:
     """Owns a batch over existing Solvers (which stay owned by the caller)."""
 
@@ -403,6 +443,9 @@ class Batch:
 
     def iterate(self, u0s, Us, max_iter=400, tol=1e-11):
         return expdiag_batch_iterate(self.b, u0s, Us, max_iter, tol)
+
+    def iterate_each(self, u0s, Us, max_iters, tols):
+        return expdiag_batch_iterate_each(self.b, u0s, Us, max_iters, tols)
 
     def close(self):
         if self.b is not None:

@@ -118,6 +118,11 @@ def test_null_handle_calls_are_rejected(lib):
     assert lib.expdiag_iterate(None, None, None, 1, 0.0, None, None) == \
         X.EXPDIAG_EINVAL
     assert lib.expdiag_precond_apply(None, None, None) == X.EXPDIAG_EINVAL
+    assert lib.expdiag_newton_apply(None, None, None, None, None) == \
+        X.EXPDIAG_EINVAL
+    assert lib.expdiag_batch_iterate_each(None, None, None, None, None,
+                                          None, None, None) == \
+        X.EXPDIAG_EINVAL
     assert lib.expdiag_destroy(None) == X.EXPDIAG_OK
 
 

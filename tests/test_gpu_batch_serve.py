@@ -151,15 +151,70 @@ def test_server_continuous_batching():
         assert np.array_equal(Us[k].cpu().numpy(), solo[k]), k
 
 
+def _poll_all(X, srv, count, seconds):
+    done = []
+    t_end = time.time() + seconds
+    while len(done) < count and time.time() < t_end:
+        res, _ = X.expdiag_server_poll(srv)
+        done.extend(res)
+        time.sleep(0.001)
+    return done
+
+
+def test_server_failed_plan_build_reports_and_recovers(monkeypatch):
+    """A launch plan that cannot be built (every plan upload forced to fail
+    from the host, as a failed arena allocation under a full budget would)
+    stops the server from launching for that set: every request comes back
+    with EXPDIAG_EHIP, no slot or byte stays claimed, and once uploads work
+    again the same server solves a new request to its solo result."""
+    import torch
+    from paper_2603_04350_amd import Solver
+    from paper_2603_04350_amd import expdiag as X
+    insts = W.batch(3, seed=5, ns=(16, 32), nts=(8, 16), precision=1)
+    u0s = [_dev(i.u0) for i in insts]
+    Us = [_zeros(i) for i in insts]
+    torch.cuda.synchronize()
+    srv = X.expdiag_server_create(1 << 30, 8)
+    monkeypatch.setenv("EXPDIAG_FAIL_PLAN_UPLOAD", "1")
+    for k, inst in enumerate(insts):
+        prob = X.make_problem(inst.a, inst.c, inst.n1, inst.n2, inst.n3,
+                              inst.precision)
+        X.expdiag_server_submit(srv, inst.shape, inst.Nt, inst.dt,
+                                inst.alpha, inst.scheme, prob, u0s[k],
+                                Us[k], 200, 1e-12)
+    done = _poll_all(X, srv, len(insts), 30)
+    assert len(done) == len(insts)
+    assert all(r["status"] == X.EXPDIAG_EHIP for r in done), done
+    st = X.expdiag_server_stats(srv)
+    assert st["active"] == 0 and st["pending"] == 0
+    assert st["bytes_in_use"] == 0
+    monkeypatch.delenv("EXPDIAG_FAIL_PLAN_UPLOAD")
+    inst = insts[0]
+    U = _zeros(inst)
+    prob = X.make_problem(inst.a, inst.c, inst.n1, inst.n2, inst.n3,
+                          inst.precision)
+    X.expdiag_server_submit(srv, inst.shape, inst.Nt, inst.dt, inst.alpha,
+                            inst.scheme, prob, u0s[0], U, 200, 1e-12)
+    done = _poll_all(X, srv, 1, 30)
+    X.expdiag_server_destroy(srv)
+    assert len(done) == 1 and done[0]["status"] == 0, done
+    with Solver.from_instance(inst) as s:
+        V = _zeros(inst)
+        s.iterate(u0s[0], V, max_iter=200, tol=1e-12)
+    assert np.array_equal(U.cpu().numpy(), V.cpu().numpy())
+
+
 TOL_BENCH = 1e-11  # the benchmark's tolerance on ||S|| / ||U||
 
 
-def test_batched_configuration_full_size_sampled():
+def test_batched_configuration_full_size():
     """The batched configuration at full size, as the benchmark runs it: 256
     Allen-Cahn instances (n in {64, 128, 256}, Nt in {16 .. 128}, alpha in
     {1e-2, 1e-3}, eps ~ U[0.02, 0.1], mixed precision) in one batch.  Every
-    instance converges; the three largest and three smallest windows equal
-    their solo solves bit for bit and sequential stepping to the mixed bar."""
+    instance converges and matches sequential stepping (the oracle) to the
+    mixed bar 1e-10; the three largest and three smallest windows equal
+    their solo solves bit for bit."""
+    from concurrent.futures import ThreadPoolExecutor
     from paper_2603_04350_amd import Batch, Solver
     insts = W.batch(256, seed=0, precision=1)
     solvers = [Solver.from_instance(i, precision=1) for i in insts]
@@ -177,10 +232,22 @@ def test_batched_configuration_full_size_sampled():
         rc1, it1, _ = solvers[k].iterate(_dev(inst.u0), U, max_iter=400,
                                          tol=TOL_BENCH)
         assert it1 == its[k] and np.array_equal(U.cpu().numpy(), got), k
-        ref = O.sequential(O.Setup.from_instance(inst), inst.u0)
-        assert O.rel_err(got, ref) < 1e-10, (k, inst.n, inst.Nt)
     for s in solvers:
         s.close()
+
+    def err_of(k):
+        inst = insts[k]
+        ref = O.sequential(O.Setup.from_instance(inst), inst.u0)
+        return O.rel_err(Us[k].cpu().numpy(), ref)
+
+    with ThreadPoolExecutor(8) as pool:
+        errs = list(pool.map(err_of, range(len(insts))))
+    worst = int(np.argmax(errs))
+    print(f"256 batched instances against sequential stepping: max error "
+          f"{errs[worst]:.2e} (instance {worst}: n {insts[worst].n}, "
+          f"Nt {insts[worst].Nt}, alpha {insts[worst].alpha})")
+    assert max(errs) < 1e-10, [(k, e) for k, e in enumerate(errs)
+                               if e >= 1e-10]
 
 
 def test_served_configuration_full_size_sampled():
