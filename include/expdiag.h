@@ -375,6 +375,32 @@ int expdiag_server_stats(expdiag_server_t s, size_t* bytes_in_use,
 /* Finish every queued request, then stop the thread and free. */
 int expdiag_server_destroy(expdiag_server_t s);
 
+/* ---- No device allocation ---------------------------------------------
+ * For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve
+ * of expdiag_create + expdiag_iterate + expdiag_destroy in one call, with
+ * every device buffer a handle would own and the launch plan's tables
+ * carved from one library-owned device workspace of 128 MiB per GPU
+ * (allocated when the library is loaded, held until the process ends, the
+ * address looked up once per device).  It calls no hipMalloc, hipFree or
+ * hipHostMalloc.  Arguments as expdiag_create (g, Nt, dt, alpha, scheme, p
+ * with gmres_restart = 0, hip_stream) and expdiag_iterate (u0, U,
+ * max_iter, tol, iters, rel_update); results equal those of that pair.
+ * A problem whose buffers do not fit (about 119 MB for 256^2 x 64 in mixed
+ * precision, the largest 2D case that fits) is refused with EINVAL before
+ * the device is touched.  The workspace keeps the last call's contents and
+ * is shared by every call on a device: calls on one device are serialised
+ * by a lock and each synchronises its stream before returning, so calls do
+ * not overlap on a device; a caller enqueueing other work on that stream
+ * must not expect it to run concurrently with this call.  Errors: as
+ * expdiag_create and expdiag_iterate; expdiag_last_error(NULL) gives the
+ * message. */
+int expdiag_iterate_noalloc(const expdiag_grid* g, int Nt, double dt,
+                            double alpha, int scheme,
+                            const expdiag_problem* p, void* hip_stream,
+                            const double* u0, double* U, int max_iter,
+                            double tol, int* iters, double* rel_update);
+
 /* Static description of an error code. */
 const char* expdiag_strerror(int code);
 

@@ -91,6 +91,8 @@ struct Plan {
   char* arena = nullptr;
   char* staging = nullptr;
   size_t cap = 0;
+  // arena and staging provided by the caller: never grown or freed here
+  bool fixed = false;
 };
 
 }  // namespace
@@ -172,6 +174,12 @@ struct expdiag_ctx {
 
   std::string err;
   size_t bytes = 0;
+
+  // device buffers carved from a caller-provided fixed workspace instead of
+  // hipMalloc (the no-allocation entry point); such a handle is never
+  // released with hipFree
+  char* arena = nullptr;
+  size_t arena_cap = 0, arena_off = 0;
 };
 
 namespace {
@@ -939,6 +947,9 @@ int plan_upload(expdiag_ctx* h, Plan& P, hipStream_t st) {
     need += align256(jb) + align256(g.start.size() * sizeof(int)) +
             align256(g.red.size() * sizeof(PassBArgs));
   }
+  if (need > P.cap && P.fixed)
+    return fail(h, EXPDIAG_EINVAL,
+                "launch tables need %zu bytes of a fixed %zu", need, P.cap);
   if (need > P.cap) {
     if (P.arena != nullptr) (void)hipFree(P.arena);
     if (P.staging != nullptr) (void)hipHostFree(P.staging);
@@ -988,7 +999,7 @@ int plan_upload(expdiag_ctx* h, Plan& P, hipStream_t st) {
 void plan_clear(Plan& P, bool keep_arena) {
   P.groups.clear();
   P.uploaded = false;
-  if (!keep_arena) {
+  if (!keep_arena && !P.fixed) {
     if (P.arena != nullptr) (void)hipFree(P.arena);
     if (P.staging != nullptr) (void)hipHostFree(P.staging);
     P.arena = nullptr;
@@ -1568,6 +1579,17 @@ template <typename P>
 int dalloc(expdiag_ctx* h, P** ptr, size_t bytes) {
   void* p = nullptr;
   if (bytes == 0) bytes = 16;
+  if (h->arena != nullptr) {
+    const size_t need = align256(bytes);
+    if (h->arena_off + need > h->arena_cap)
+      return fail(h, EXPDIAG_EINVAL,
+                  "workspace of %zu bytes exceeded (needs more than %zu)",
+                  h->arena_cap, h->arena_off + need);
+    *ptr = reinterpret_cast<P*>(h->arena + h->arena_off);
+    h->arena_off += need;
+    h->bytes += need;
+    return 0;
+  }
   hipError_t e = hipMalloc(&p, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -1779,15 +1801,12 @@ int reinit_params(expdiag_ctx* h, double dt, double alpha, int scheme,
   return build_tables(h);
 }
 
-// light: no iteration plan or graph of its own (handles driven by a batch
-// or the server).
-int create_impl(const expdiag_grid* g, int Nt, double dt, double alpha,
-                int scheme, const expdiag_problem* p, void* hip_stream,
-                expdiag_t* out, bool light) {
-  g_create_err.clear();
-  if (out == nullptr || p == nullptr || g == nullptr)
-    return fail(nullptr, EXPDIAG_EINVAL, "null pointer argument");
-  *out = nullptr;
+// Fill a handle's fields from the arguments (validated) and allocate its
+// device workspace (hipMalloc, or carved from h->arena when set).  On
+// failure the buffers allocated so far stay recorded in h.
+int setup_handle(expdiag_ctx* h, const expdiag_grid* g, int Nt, double dt,
+                 double alpha, int scheme, const expdiag_problem* p,
+                 void* hip_stream) {
   Sizes s{};
   const int gc = check_grid(g, &s);
   if (gc != 0)
@@ -1798,9 +1817,6 @@ int create_impl(const expdiag_grid* g, int Nt, double dt, double alpha,
     s.nh = g->n[g->dim - 1];
     s.Nk = s.Ns;
   }
-
-  expdiag_ctx* h = new (std::nothrow) expdiag_ctx();
-  if (h == nullptr) return fail(nullptr, EXPDIAG_ENOMEM, "host allocation");
   h->dim = g->dim;
   for (int i = 0; i < 3; ++i) h->n[i] = i < g->dim ? g->n[i] : 1;
   h->Nt = Nt;
@@ -1860,6 +1876,29 @@ int create_impl(const expdiag_grid* g, int Nt, double dt, double alpha,
     if (h->nonlinear && h->mixed)
       A(&h->Uphys32, static_cast<size_t>(Nt) * h->Ns * sizeof(float));
   }
+  return rc;
+}
+
+// light: no iteration plan or graph of its own (handles driven by a batch
+// or the server).
+int create_impl(const expdiag_grid* g, int Nt, double dt, double alpha,
+                int scheme, const expdiag_problem* p, void* hip_stream,
+                expdiag_t* out, bool light) {
+  g_create_err.clear();
+  if (out == nullptr || p == nullptr || g == nullptr)
+    return fail(nullptr, EXPDIAG_EINVAL, "null pointer argument");
+  *out = nullptr;
+  {
+    Sizes s{};
+    const int gc = check_grid(g, &s);
+    if (gc != 0)
+      return fail(nullptr, gc,
+                  "grid: dim 1..3, n even, power of two, 4..1024");
+    RCHK(validate_params(Nt, dt, alpha, scheme, p));
+  }
+  expdiag_ctx* h = new (std::nothrow) expdiag_ctx();
+  if (h == nullptr) return fail(nullptr, EXPDIAG_ENOMEM, "host allocation");
+  int rc = setup_handle(h, g, Nt, dt, alpha, scheme, p, hip_stream);
   if (rc == 0) {
     if (hipHostMalloc(&h->h_ctl, sizeof(Ctl)) != hipSuccess ||
         hipHostMalloc(&h->h_mirror, sizeof(Ctl), hipHostMallocMapped) !=
@@ -2185,3 +2224,4 @@ int expdiag_profile_read(expdiag_t h, double* ms, long* launches,
 #include "gmres.inc"
 #include "batch.inc"
 #include "autotune.inc"
+#include "noalloc.inc"

@@ -45,7 +45,7 @@ EXPORTED = (
     "expdiag_server_create", "expdiag_server_submit", "expdiag_server_poll",
     "expdiag_server_stats", "expdiag_server_destroy",
     "expdiag_set_time_variant", "expdiag_get_time_variant",
-    "expdiag_autotune",
+    "expdiag_autotune", "expdiag_iterate_noalloc",
 )
 
 
@@ -146,6 +146,10 @@ def load(path: str = LIB_PATH):
                                        ctypes.POINTER(ci),
                                        ctypes.POINTER(cd)]
     L.expdiag_server_destroy.argtypes = [vp]
+    L.expdiag_iterate_noalloc.argtypes = [ctypes.POINTER(Grid), ci, cd, cd,
+                                          ci, ctypes.POINTER(Problem), vp,
+                                          vp, vp, ci, cd, ctypes.POINTER(ci),
+                                          ctypes.POINTER(cd)]
     L.expdiag_strerror.argtypes = [ci]
     L.expdiag_strerror.restype = ctypes.c_char_p
     L.expdiag_last_error.argtypes = [vp]
@@ -293,6 +297,28 @@ def expdiag_newton_apply(h, u0, U, V, W):
     return _check(load().expdiag_newton_apply(
         h, _ptr(u0, name="u0"), _ptr(U, name="U"), _ptr(V, n, "V"),
         _ptr(W, n, "W")), h)
+
+
+def expdiag_iterate_noalloc(shape, Nt, dt, alpha, scheme, problem: Problem,
+                            u0, U, max_iter, tol, stream=None):
+    """The solve of create + iterate + destroy with no device allocation
+    (the library's fixed workspace); returns (rc, iters, rel_update)."""
+    L = load()
+    g = make_grid(shape)
+    ns = 1
+    for v in shape:
+        ns *= int(v)
+    it = ctypes.c_int(0)
+    rel = ctypes.c_double(0.0)
+    rc = L.expdiag_iterate_noalloc(ctypes.byref(g), int(Nt), float(dt),
+                                   float(alpha), int(scheme),
+                                   ctypes.byref(problem), _stream(stream),
+                                   _ptr(u0, name="u0"),
+                                   _ptr(U, int(Nt) * ns, "U"), int(max_iter),
+                                   float(tol), ctypes.byref(it),
+                                   ctypes.byref(rel))
+    _check(rc, None, ok=(EXPDIAG_OK, EXPDIAG_NOT_CONVERGED))
+    return rc, it.value, rel.value
 
 
 def expdiag_profile_enable(h, mask=0x1F):

@@ -123,6 +123,9 @@ def test_null_handle_calls_are_rejected(lib):
     assert lib.expdiag_batch_iterate_each(None, None, None, None, None,
                                           None, None, None) == \
         X.EXPDIAG_EINVAL
+    assert lib.expdiag_iterate_noalloc(None, 8, 0.1, 1e-2, 1, None, None,
+                                       None, None, 10, 0.0, None, None) == \
+        X.EXPDIAG_EINVAL
     assert lib.expdiag_destroy(None) == X.EXPDIAG_OK
 
 
