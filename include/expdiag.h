@@ -310,7 +310,9 @@ int expdiag_autotune(expdiag_t h, const char* cache_path, int* variant,
  * converged instances drop out, mixed-precision instances switch to the
  * fp64 residual independently, and each result is the one its handle gives
  * alone (same kernels, same per-instance reduction order).  The handles must
- * not be used concurrently outside the batch. */
+ * not be used concurrently outside the batch.  While profiling is enabled on
+ * the batch's first handle (expdiag_profile_enable), the batch's iteration
+ * launches are accounted in that handle's kernel-class profile. */
 typedef struct expdiag_batch* expdiag_batch_t;
 int expdiag_batch_create(const expdiag_t* handles, int count,
                          void* hip_stream, expdiag_batch_t* out);
