@@ -59,7 +59,14 @@ struct EventPair {
   int cls;
 };
 
-enum Kind { K_ROW = 0, K_COL = 1, K_PASSB = 2 };
+// K_X*: boundary-transform stages (entry / exit of a batch): fp64 rows in
+// the group's row mode, fp64 columns in the group's direction, and fp64 ->
+// fp32 copies (a ColJob with `outer` complex elements)
+enum Kind {
+  K_ROW = 0, K_COL = 1, K_PASSB = 2, K_XROW = 3, K_XCOL = 4, K_XNARROW = 5
+};
+bool kind_rows(int k) { return k == K_ROW || k == K_XROW; }
+bool kind_cols(int k) { return k == K_COL || k == K_XCOL || k == K_XNARROW; }
 
 // One launch of a plan: jobs of the same kernel signature.
 struct Group {
@@ -807,16 +814,20 @@ void plan_pass_a(Plan& P, expdiag_ctx* h, const Ctl* ctl, int ph) {
 // instance's fp32 job for the mixed-precision bulk phase and its fp64 job
 // side by side, picked per block from the control block; ti names the fp32
 // job's input type).  For d >= 2 the first stage, the inverse transform of
-// Uh along axis 0, runs in fp64 in both phases (tcode 3) and performs the
-// instance's convergence reduction of the previous iteration (`red`); the
-// bulk phase then reads that fp64 intermediate in the next stage and
-// continues in fp32 through T32.  Returns whether the reduction is hosted
-// (1D pass A is one row stage that depends on the phase: not hosted).
-// Instances without a bulk phase carry their fp64 job in both slots.  A
-// group's byte count is that of the phase the instance spends most
-// iterations in (fp32 when mixed).
+// Uh along axis 0, may perform the instance's convergence reduction of the
+// previous iteration (`red`, when `host`): it then runs in fp64 in both
+// phases (tcode 3; its blocks cannot see the phase that reduction sets),
+// and the bulk phase reads that fp64 intermediate in the next stage before
+// continuing in fp32 through T32.  Not hosted, the first stage picks its
+// phase like the others and writes T32 in the bulk phase (16 bytes less
+// per complex entry in the bulk phase, for one reduction launch after
+// pass B).  Returns whether the reduction is hosted (1D pass A is one row
+// stage that depends on the phase: never hosted).  Instances without a
+// bulk phase carry their fp64 job in both slots.  A group's byte count is
+// that of the phase the instance spends most iterations in (fp32 when
+// mixed).
 bool plan_pass_a_mp(Plan& P, expdiag_ctx* h, const Ctl* ctl,
-                    const PassBArgs& red) {
+                    const PassBArgs& red, bool host) {
   const int d = h->dim;
   const long ns = pass_a_slices(h);
   const long nh2 = 2L * h->nh;
@@ -858,22 +869,30 @@ bool plan_pass_a_mp(Plan& P, expdiag_ctx* h, const Ctl* ctl,
   }
   const int n0 = h->n[0];
   const long in2 = d == 3 ? static_cast<long>(h->n[1]) * h->nh : h->nh;
-  {
+  host = host || !mx;
+  if (host) {
     const ColJob j = make_col(h->Uh, T64, ns, in2, 1.0, ctl, -1);
     Group& g = plan_group(P, 0, K_COL, 3, n0, 1, 0, 0);
     g.cj.push_back(j);
     g.red.push_back(red);
     g.start.push_back(g.start.back() + col_blocks(n0, ns, in2));
     g.bytes += static_cast<double>(ns) * n0 * in2 * 2 * 2 * sizeof(double);
+  } else {
+    col2(0, n0, 1, make_col(h->Uh, T32, ns, in2, 1.0, ctl, -1),
+         make_col(h->Uh, T64, ns, in2, 1.0, ctl, -1), 0);
   }
+  // input type of the next stage's fp32 job: fp64 after the hosted stage
+  const int ti1 = host ? 0 : 1;
+  const void* tin32 = host ? static_cast<const void*>(T64)
+                           : static_cast<const void*>(T32);
   const long rows = ns * (h->Ns / nl);
   if (d == 2) {
-    row2(2, make_row(h, T64, T32, rows, nh2, nh2, sc, ctl, -1),
-         make_row(h, T64, T64, rows, nh2, nh2, sc, ctl, -1), 0);
+    row2(2, make_row(h, tin32, T32, rows, nh2, nh2, sc, ctl, -1),
+         make_row(h, T64, T64, rows, nh2, nh2, sc, ctl, -1), ti1);
   } else {
     const int n1 = h->n[1];
-    col2(1, n1, 1, make_col(T64, T32, ns * n0, h->nh, 1.0, ctl, -1),
-         make_col(T64, T64, ns * n0, h->nh, 1.0, ctl, -1), 0);
+    col2(1, n1, 1, make_col(tin32, T32, ns * n0, h->nh, 1.0, ctl, -1),
+         make_col(T64, T64, ns * n0, h->nh, 1.0, ctl, -1), ti1);
     row2(2, make_row(h, T32, T32, rows, nh2, nh2, sc, ctl, -1),
          make_row(h, T64, T64, rows, nh2, nh2, sc, ctl, -1), 1);
     col2(3, n1, -1, make_col(T32, T32, ns * n0, h->nh, 1.0, ctl, -1),
@@ -881,11 +900,16 @@ bool plan_pass_a_mp(Plan& P, expdiag_ctx* h, const Ctl* ctl,
   }
   col2(4, n0, -1, make_col(T32, N32, ns, in2, 1.0, ctl, -1),
        make_col(T64, N64, ns, in2, 1.0, ctl, -1), 1);
-  return true;
+  return host;
 }
 
 // All launches of one fixed-point iteration of instance h, with control
-// block `ctl` (device) and host mirror `mirror` (device address).
+// block `ctl` (device) and host mirror `mirror` (device address).  A
+// mixed-precision instance takes its convergence reduction as a launch of
+// its own after pass B (its first pass-A stage then writes fp32 in the bulk
+// phase); an fp64 one has it ride on that stage (one launch less per
+// iteration).  The choice depends on the instance only, so a batched
+// instance runs the same kernels on the same data as it does alone.
 void plan_iteration(Plan& P, expdiag_ctx* h, Ctl* ctl, Ctl* mirror,
                     double* hist) {
   PassBArgs a = passb_args(h);
@@ -893,7 +917,8 @@ void plan_iteration(Plan& P, expdiag_ctx* h, Ctl* ctl, Ctl* mirror,
   a.hmirror = mirror;
   a.hist = hist;
   if (h->nonlinear && h->mixed) a.Nh32 = nh_view<float>(h);
-  const bool hosted = h->nonlinear && plan_pass_a_mp(P, h, ctl, a);
+  const bool hosted =
+      h->nonlinear && plan_pass_a_mp(P, h, ctl, a, !h->mixed);
   // pass B variant: 0 radix FFT, 1 dense, 2 EBDF2 dense, 3 EBDF2 radix FFT,
   // 4 radix FFT with complex symbols, 5 the dense kernel of EBDF3..6 (the
   // order read per job), 30 + s the radix FFT kernel of EBDFs (the group
@@ -941,9 +966,9 @@ int plan_upload(expdiag_ctx* h, Plan& P, hipStream_t st) {
                    });
   size_t need = 0;
   for (auto& g : P.groups) {
-    const size_t jb = g.kind == K_ROW   ? g.rj.size() * sizeof(RowJob)
-                      : g.kind == K_COL ? g.cj.size() * sizeof(ColJob)
-                                        : g.pj.size() * sizeof(PassBArgs);
+    const size_t jb = kind_rows(g.kind)   ? g.rj.size() * sizeof(RowJob)
+                      : kind_cols(g.kind) ? g.cj.size() * sizeof(ColJob)
+                                          : g.pj.size() * sizeof(PassBArgs);
     need += align256(jb) + align256(g.start.size() * sizeof(int)) +
             align256(g.red.size() * sizeof(PassBArgs));
   }
@@ -965,10 +990,10 @@ int plan_upload(expdiag_ctx* h, Plan& P, hipStream_t st) {
   for (auto& g : P.groups) {
     size_t jb = 0;
     const void* src = nullptr;
-    if (g.kind == K_ROW) {
+    if (kind_rows(g.kind)) {
       jb = g.rj.size() * sizeof(RowJob);
       src = g.rj.data();
-    } else if (g.kind == K_COL) {
+    } else if (kind_cols(g.kind)) {
       jb = g.cj.size() * sizeof(ColJob);
       src = g.cj.data();
     } else {
@@ -1126,6 +1151,150 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
       return fail(ph, EXPDIAG_EHIP, "plan launch: %s", hipGetErrorString(e));
+  }
+  return 0;
+}
+
+// ------------------------------------------- batched boundary transforms
+// fp64 -> fp32 copies, job j copying `outer` complex elements
+__global__ void narrow_kernel_jt(const ColJob* __restrict__ jobs,
+                                 const int* __restrict__ start, int njobs) {
+  const int i = find_job(start, njobs);
+  const ColJob jb = jobs[i];
+  const long e = static_cast<long>(blockIdx.x - start[i]) * blockDim.x +
+                 threadIdx.x;
+  if (e < jb.outer)
+    static_cast<cx<float>*>(jb.out)[e] =
+        cvt<float>(static_cast<const cx<double>*>(jb.in)[e]);
+}
+
+void plan_xrow(Plan& P, int stage, int M, int mode, const RowJob& j) {
+  Group& g = plan_group(P, stage, K_XROW, 0, M, mode, 0, 0);
+  g.rj.push_back(j);
+  g.start.push_back(g.start.back() + row_blocks(M, j.nrows));
+  g.bytes += row_bytes(M, mode, j.nrows, sizeof(double), sizeof(double));
+}
+
+void plan_xcol(Plan& P, int stage, int L, int S, const ColJob& j) {
+  Group& g = plan_group(P, stage, K_XCOL, 0, L, S, 0, 0);
+  g.cj.push_back(j);
+  g.start.push_back(g.start.back() + col_blocks(L, j.outer, j.inner));
+  g.bytes += static_cast<double>(j.outer) * L * j.inner * 32;
+}
+
+// ns real slices at src -> their half spectra at dst: rows written straight
+// into dst, then the column stages in place there (stages stage0..+2)
+void plan_xfwd(Plan& P, expdiag_ctx* h, int stage0, int rowmode,
+               const double* src, cx<double>* dst, long ns) {
+  const int d = h->dim;
+  const long nh2 = 2L * h->nh;
+  const int nl = h->n[d - 1];
+  plan_xrow(P, stage0, nl / 2, rowmode,
+            make_row(h, src, dst, ns * (h->Ns / nl), nl, nh2, 1.0, nullptr,
+                     -1));
+  if (d == 2) {
+    plan_xcol(P, stage0 + 1, h->n[0], -1,
+              make_col(dst, dst, ns, h->nh, 1.0, nullptr, -1));
+  } else if (d == 3) {
+    plan_xcol(P, stage0 + 1, h->n[1], -1,
+              make_col(dst, dst, ns * h->n[0], h->nh, 1.0, nullptr, -1));
+    plan_xcol(P, stage0 + 2, h->n[0], -1,
+              make_col(dst, dst, ns, static_cast<long>(h->n[1]) * h->nh, 1.0,
+                       nullptr, -1));
+  }
+}
+
+// What expdiag_iterate does before its iterations (prepare_u0 and the
+// forward transform of U), as plan stages 0..3; real states only.
+void plan_entry(Plan& P, expdiag_ctx* h, const double* u0, const double* U) {
+  plan_xfwd(P, h, 0, ROW_R2C, u0, h->u0h, 1);
+  if (h->nonlinear && h->scheme != EXPDIAG_IF1) {
+    plan_xfwd(P, h, 0, ROW_NR2C, u0, h->Nh, 1);
+    if (h->mixed) {
+      Group& g = plan_group(P, 3, K_XNARROW, 0, 0, 0, 0, 0);
+      g.cj.push_back(make_col(h->Nh, nh_view<float>(h), h->Nk, 1, 1.0,
+                              nullptr, -1));
+      g.start.push_back(g.start.back() +
+                        static_cast<int>((h->Nk + 255) / 256));
+    }
+  }
+  plan_xfwd(P, h, 0, ROW_R2C, U, h->Uh, h->Nt);
+}
+
+// inv_slices(h, h->Uh, U, Nt) as plan stages 0..2 (through h->T)
+void plan_exit(Plan& P, expdiag_ctx* h, double* U) {
+  const int d = h->dim;
+  const long nh2 = 2L * h->nh;
+  const int nl = h->n[d - 1];
+  const double sc = 1.0 / static_cast<double>(h->Ns);
+  const long ns = h->Nt;
+  if (d == 1) {
+    plan_xrow(P, 2, nl / 2, ROW_C2R,
+              make_row(h, h->Uh, U, ns, nh2, nl, sc, nullptr, -1));
+    return;
+  }
+  if (d == 2) {
+    plan_xcol(P, 0, h->n[0], 1,
+              make_col(h->Uh, h->T, ns, h->nh, 1.0, nullptr, -1));
+  } else {
+    plan_xcol(P, 0, h->n[0], 1,
+              make_col(h->Uh, h->T, ns, static_cast<long>(h->n[1]) * h->nh,
+                       1.0, nullptr, -1));
+    plan_xcol(P, 1, h->n[1], 1,
+              make_col(h->T, h->T, ns * h->n[0], h->nh, 1.0, nullptr, -1));
+  }
+  plan_xrow(P, 2, nl / 2, ROW_C2R,
+            make_row(h, h->T, U, ns * (h->Ns / nl), nh2, nl, sc, nullptr,
+                     -1));
+}
+
+// Launch the groups of a boundary-transform plan in stage order.
+int plan_launch_x(expdiag_ctx* ph, Plan& P, hipStream_t st,
+                  const cx<double>* tw64) {
+  if (!P.uploaded) return fail(ph, EXPDIAG_EHIP, "plan not uploaded");
+  for (auto& g : P.groups) {
+    const int grid = g.grid();
+    if (grid == 0) continue;
+    const int nj = g.njobs();
+    bool ok = false;
+    if (g.kind == K_XROW) {
+      const RowJob* J = static_cast<const RowJob*>(g.djobs);
+      ok = dispatch_pow2<2, 512>(g.len, [&](auto Mc) {
+        constexpr int MM = decltype(Mc)::value;
+        const dim3 th(RowShape<MM>::THREADS);
+        if (g.mode == ROW_R2C)
+          hipLaunchKernelGGL((row_kernel_jt<MM, ROW_R2C>), dim3(grid), th, 0,
+                             st, J, g.dstart, nj, tw64);
+        else if (g.mode == ROW_NR2C)
+          hipLaunchKernelGGL((row_kernel_jt<MM, ROW_NR2C>), dim3(grid), th,
+                             0, st, J, g.dstart, nj, tw64);
+        else
+          hipLaunchKernelGGL((row_kernel_jt<MM, ROW_C2R>), dim3(grid), th, 0,
+                             st, J, g.dstart, nj, tw64);
+      });
+    } else if (g.kind == K_XCOL) {
+      const ColJob* J = static_cast<const ColJob*>(g.djobs);
+      ok = dispatch_pow2<4, 1024>(g.len, [&](auto Lc) {
+        constexpr int LL = decltype(Lc)::value;
+        const dim3 th(ColShape<LL>::THREADS);
+        if (g.mode == 1)
+          hipLaunchKernelGGL((col_kernel_jt<LL, 1>), dim3(grid), th, 0, st,
+                             J, g.dstart, nj, tw64);
+        else
+          hipLaunchKernelGGL((col_kernel_jt<LL, -1>), dim3(grid), th, 0, st,
+                             J, g.dstart, nj, tw64);
+      });
+    } else if (g.kind == K_XNARROW) {
+      hipLaunchKernelGGL(narrow_kernel_jt, dim3(grid), dim3(256), 0, st,
+                         static_cast<const ColJob*>(g.djobs), g.dstart, nj);
+      ok = true;
+    }
+    if (!ok) return fail(ph, EXPDIAG_EUNSUPPORTED, "transform length %d",
+                         g.len);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+      return fail(ph, EXPDIAG_EHIP, "transform launch: %s",
+                  hipGetErrorString(e));
   }
   return 0;
 }

@@ -355,6 +355,21 @@ __global__ void __launch_bounds__(RowShape<M>::THREADS)
   row_body<T, M, MODE, TI, TO>(jb, blockIdx.x, tw, lds);
 }
 
+// Job-table launch of a boundary-transform stage (entry and exit
+// transforms of a batch): fp64, every job live, job j owning blocks
+// [start[j], start[j+1]).
+template <int M, int MODE>
+__global__ void __launch_bounds__(RowShape<M>::THREADS)
+    row_kernel_jt(const RowJob* __restrict__ jobs,
+                  const int* __restrict__ start, int njobs,
+                  const cx<double>* __restrict__ tw) {
+  __shared__ cx<double> lds[RowShape<M>::RPB * RowShape<M>::LS];
+  const int i = find_job(start, njobs);
+  const RowJob jb = jobs[i];
+  row_body<double, M, MODE, double, double>(jb, blockIdx.x - start[i], tw,
+                                            lds);
+}
+
 // C adjacent columns per workgroup, at least 8 (a 128-byte run of fp64
 // complex per row) while the tile of L*C complex fits 64 KiB of LDS, else
 // 4; for L <= 256 the tile is 32 KiB in fp64, which lets five workgroups
@@ -449,6 +464,19 @@ __global__ void __launch_bounds__(ColShape<L>::THREADS, ColShape<L>::WAVES)
   } else {
     col_body<double, L, S, double, double>(j1, lb, tw64, lds);
   }
+}
+
+// boundary-transform stage (see row_kernel_jt)
+template <int L, int S>
+__global__ void __launch_bounds__(ColShape<L>::THREADS, ColShape<L>::WAVES)
+    col_kernel_jt(const ColJob* __restrict__ jobs,
+                  const int* __restrict__ start, int njobs,
+                  const cx<double>* __restrict__ tw) {
+  __shared__ cx<double> lds[L * ColShape<L>::LS];
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int i = find_job(start, njobs, b);
+  const ColJob jb = jobs[i];
+  col_body<double, L, S, double, double>(jb, b - start[i], tw, lds);
 }
 
 template <typename T, int L, int S, typename TI, typename TO>
