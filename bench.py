@@ -533,6 +533,42 @@ def bench_batch(count, steps, warmup, refs):
 # --------------------------------------------------------------------------
 # Single instances
 # --------------------------------------------------------------------------
+def bench_time_variants(Nts=(8, 16, 32, 64, 128)):
+    """Both time transforms of pass B on the 256^2 Allen-Cahn grid for each
+    Nt, timed by the library's autotuner on one handle (20 preconditioner
+    applies each after warm-up): the radix FFT, and the DFT products on
+    FP64 MFMA with their executed flops (16 Nt^2 per kappa column: two real
+    2Nt x 2Nt products per column) against the FP64 matrix peak; both
+    against HBM (read R, write S: 32 B per complex entry)."""
+    import dataclasses
+    import workloads as W
+    from paper_2603_04350_amd import expdiag as X
+    out = {}
+    for Nt in Nts:
+        inst = dataclasses.replace(W.allen_cahn2d(), Nt=Nt)
+        with X.Solver.from_instance(inst, precision=0) as s:
+            v, us_fft, us_dense = X.expdiag_autotune(s.h)
+        Nk = inst.n * (inst.n // 2 + 1)
+        C = 64 if Nt <= 32 else 2048 // Nt
+        flops = 16 * Nt * Nt * ((Nk + C - 1) // C) * C
+        nbytes = 32 * Nt * Nk
+        row = {"chosen": "dense" if v == 1 else "radix",
+               "radix_us": us_fft, "dense_us": us_dense,
+               "radix_hbm_frac": round(nbytes / (us_fft * 1e-6) / 1e9
+                                       / HBM_PEAK_GBS, 4)}
+        if us_dense > 0:
+            tf = flops / (us_dense * 1e-6) / 1e12
+            row.update({
+                "dense_flops": flops,
+                "dense_TFLOPs": round(tf, 2),
+                "dense_mfma_frac": round(tf / MFMA_F64_PEAK_TFLOPS, 4),
+                "dense_hbm_frac": round(nbytes / (us_dense * 1e-6) / 1e9
+                                        / HBM_PEAK_GBS, 4)})
+        out[f"Nt{Nt}"] = row
+    return {"grid": "256x256 half spectrum (33024 columns), fp64",
+            "per_Nt": out}
+
+
 def bench_single(inst, prec, steps, warmup, ref=None):
     """One instance solved alone: to the run-time rule (timed, `steps`
     solves), then with events on every launch of fixed-count solves (kernel
@@ -1458,6 +1494,8 @@ def main():
     sg["mixed_speedup_time_to_tol"] = (sg["fp64"]["ms_per_solve"]
                                        / sg["mixed"]["ms_per_solve"])
     line["single_256"] = sg
+    _log("time transform variants (radix FFT, DFT on FP64 MFMA)")
+    line["time_transform"] = bench_time_variants()
     _log("1D heat window")
     line["heat1d"] = bench_heat1d(args.steps, refs.get("heat1d"))
     if not args.no_extra:

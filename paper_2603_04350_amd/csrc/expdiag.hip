@@ -320,6 +320,15 @@ bool dense_ok(int Nt) {
 int dense_blocks(long Nk) {
   return static_cast<int>((Nk + DENSE_C - 1) / DENSE_C);
 }
+// blocks of the first-order dense (DFT on MFMA) pass B
+int dft_blocks(int Nt, long Nk) {
+  long b = 0;
+  dispatch_pow2<DENSE_NT_MIN, DENSE_NT_MAX>(Nt, [&](auto Nc) {
+    constexpr int NN = decltype(Nc)::value;
+    b = (Nk + DftShape<NN>::C - 1) / DftShape<NN>::C;
+  });
+  return static_cast<int>(b);
+}
 // Order s of an exponential BDF scheme (EBDF2, EBDF3..EBDF6), else 0.
 int bdf_order(int scheme) {
   if (scheme == EXPDIAG_EBDF2) return 2;
@@ -375,8 +384,10 @@ bool dispatch_bdf_order(int s, F&& f) {
 // once, which nh = 1 gives (kl is then always 0).
 int parseval_nh(const expdiag_ctx* h) { return h->cstate ? 1 : h->nh; }
 int passb_blocks(expdiag_ctx* h) {
-  return h->tvariant == 1 ? dense_blocks(h->Nk)
-                          : passb_blocks_nt(time_len(h), h->Nk);
+  if (h->tvariant == 1)
+    return bdf_order(h->scheme) > 0 ? dense_blocks(h->Nk)
+                                    : dft_blocks(h->Nt, h->Nk);
+  return passb_blocks_nt(time_len(h), h->Nk);
 }
 
 double row_bytes(int M, int mode, long nrows, size_t si, size_t so) {
@@ -546,7 +557,7 @@ int launch_passb1(expdiag_ctx* h, const PassBArgs& a) {
     const bool ok = dispatch_pow2<DENSE_NT_MIN, DENSE_NT_MAX>(h->Nt, [&](auto Nc) {
       constexpr int NN = decltype(Nc)::value;
       hipLaunchKernelGGL((passb_dense_kernel1<NN, PB_PRECOND, double>),
-                         dim3(dense_blocks(h->Nk)), dim3(DENSE_THREADS), 0,
+                         dim3(dft_blocks(NN, h->Nk)), dim3(DENSE_THREADS), 0,
                          h->stream, a);
     });
     if (!ok) return fail(h, EXPDIAG_EUNSUPPORTED, "dense Nt %d", h->Nt);
@@ -2028,7 +2039,9 @@ int setup_handle(expdiag_ctx* h, const expdiag_grid* g, int Nt, double dt,
     A(&h->Wi, 4 * static_cast<size_t>(Nt) * Nt * sizeof(double));
   }
   h->max_partials = std::max(passb_blocks_nt(time_len(h), h->Nk), 1);
-  if (dense_ok(Nt)) h->max_partials = std::max(h->max_partials, dense_blocks(h->Nk));
+  if (dense_ok(Nt))
+    h->max_partials = std::max({h->max_partials, dense_blocks(h->Nk),
+                                dft_blocks(Nt, h->Nk)});
   A(&h->partials, static_cast<size_t>(h->max_partials) * 4 * sizeof(double));
   A(&h->red_out, 8 * sizeof(double));
   A(&h->ctl, sizeof(Ctl));

@@ -20,6 +20,7 @@ CASES = {
     "heat1d_Nt16": (1, 64, 16, 1e-2, 1.0, 0.0, 0, 0, 0, 1),
     "ac2d_Nt8_ragged": (2, 8, 8, 1e-3, 0.0025, 0.0, 1.0, 0, -1.0, 1),
     "ac2d_Nt32": (2, 32, 32, 1e-3, 0.0025, 0.0, 1.0, 0, -1.0, 1),
+    "ac2d_Nt16_tiles": (2, 64, 16, 1e-2, 0.0025, 0.0, 1.0, 0, -1.0, 1),
     "rd2d_etd2_Nt64": (2, 32, 64, 1e-3, 0.1, 0.0, 1.0, 0, -1.0, 2),
     "heat3d_Nt128": (3, 8, 128, 1e-2, 1.0, 0.1, 0, 0, 0, 1),
 }
