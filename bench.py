@@ -378,6 +378,19 @@ def bench_batch(count, steps, warmup, refs):
     solvers = [X.Solver.from_instance(i, precision=1) for i in insts]
     b = X.Batch(solvers)
     setup_s = time.perf_counter() - t0
+    # per-shape tuning (time transform, column width) and graph replay
+    # against plain launches for this batch, measured by the library
+    t0 = time.perf_counter()
+    tune = b.autotune(u0s, Us)
+    tune["seconds"] = time.perf_counter() - t0
+    per_shape = {}
+    for inst, s in zip(insts, solvers):
+        key = f"{inst.n}^2 x Nt{inst.Nt}"
+        if key not in per_shape:
+            tv, cw = X.expdiag_get_tuning(s.h)
+            per_shape[key] = {"time_transform": "dense" if tv else "radix",
+                              "column_width": "2C" if cw else "C"}
+    tune["per_shape"] = per_shape
     # the run-time rule ||S|| / ||U|| <= TOL (what a caller without a
     # reference uses)
     zero(Us)
@@ -389,7 +402,7 @@ def bench_batch(count, steps, warmup, refs):
     torch.cuda.synchronize()
     t_rt = time.perf_counter() - t0
     out = {"instances": n, "total_dof": sum(i.dof for i in insts),
-           "setup_s": setup_s,
+           "setup_s": setup_s, "autotune": tune,
            "run_time_rule": {
                "tol": TOL, "ms_per_solve": 1e3 * t_rt,
                "iters_min_max": [min(its_rt), max(its_rt)],
@@ -1061,6 +1074,7 @@ def _serve_run(times, insts, dev):
           for i in insts]
     torch.cuda.synchronize()
     srv = X.expdiag_server_create(64 << 30, 128)
+    X.expdiag_server_autotune(srv)
     t0 = time.perf_counter()
     done = []
     for k, (ta, inst) in enumerate(zip(times, insts)):

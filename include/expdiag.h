@@ -291,16 +291,27 @@ int expdiag_set_graph(expdiag_t h, int on);
 int expdiag_set_time_variant(expdiag_t h, int variant);
 int expdiag_get_time_variant(expdiag_t h);
 
-/* Autotuner: times both variants of pass B on this handle's shape (its own
- * buffers and stream, 20 launches each after warm-up), keeps the faster and
- * records it in the JSON cache file `cache_path` (nullable) under the key
- * gfx950/d<d>/<n0>x<n1>x<n2>/Nt<Nt>/<fp64|mixed>; a cached entry is used
- * without measuring.  variant, us_fft, us_dense (host, nullable) receive
- * the choice and the per-launch times (us_dense = -1 when not applicable).
- * EBDF and IF1 handles have one variant: it is timed and kept (the other
- * time is -1), and the cache is neither read nor written. */
+/* Autotuner: times, on this handle's shape (its own buffers and stream),
+ * both time transforms of pass B (20 preconditioner applies each after
+ * warm-up) and both widths of the pass-A column workgroups (C or 2C
+ * columns; 10 launches of the plan's column stages each), keeps the faster
+ * of each (an alternative to the default must win by 2%) and applies them.
+ * Decisions are kept in memory for the process and, when cache_path is
+ * non-NULL, in that JSON file under the key
+ * gfx950/d<d>/<n0>x<n1>x<n2>/Nt<Nt>/<fp64|mixed>; a known shape is not
+ * measured again.  variant, us_fft, us_dense (host, nullable) receive the
+ * time-transform choice and its per-launch times (us_dense = -1 when not
+ * applicable).  EBDF and IF1 handles keep their one time transform (timed;
+ * the other time is -1) and are not cached. */
 int expdiag_autotune(expdiag_t h, const char* cache_path, int* variant,
                      double* us_fft, double* us_dense);
+
+/* The handle's choices: time transform (0 radix FFT, 1 dense on MFMA; as
+ * expdiag_set_time_variant) and pass-A column width (0: C, 1: 2C columns
+ * per workgroup; the same transforms, bit for bit).  set() rebuilds the
+ * handle's plan; EINVAL / EUNSUPPORTED as expdiag_set_time_variant. */
+int expdiag_set_tuning(expdiag_t h, int time_variant, int col_wide);
+int expdiag_get_tuning(expdiag_t h, int* time_variant, int* col_wide);
 
 /* ---- Batching: many independent instances in one iteration plan ------
  * Groups `count` handles (any grids, Nt, coefficients, alpha, precision;
@@ -335,6 +346,23 @@ int expdiag_batch_iterate_each(expdiag_batch_t b, const double* const* u0s,
                                const double* tols, int* iters,
                                double* rel_update, int* status);
 const char* expdiag_batch_last_error(expdiag_batch_t b);
+/* Tune a batch: every distinct shape among its handles by expdiag_autotune
+ * (once per shape; the decision is applied to every handle of the shape),
+ * then the batch's plan rebuilt and captured, and three batched iterations
+ * timed as graph replays and three as plain launches on the given inputs
+ * (u0s, Us as in expdiag_batch_iterate; Us is read, not written); the
+ * faster (replay must win by 2%) is kept for the batch's solves.
+ *   shapes      (host, nullable) distinct shapes tuned
+ *   graph_used  (host, nullable) 1 if iterations replay the graph
+ *   ms_graph, ms_launch (host, nullable) ms per batched iteration each way
+ *               (ms_graph = -1 if the capture failed)
+ * Synchronises the stream. */
+int expdiag_batch_autotune(expdiag_batch_t b, const double* const* u0s,
+                           double* const* Us, const char* cache_path,
+                           int* shapes, int* graph_used, double* ms_graph,
+                           double* ms_launch);
+/* 1 if the batch's iterations replay its captured graph, else 0. */
+int expdiag_batch_graph(expdiag_batch_t b);
 
 /* ---- Serving: continuous batching of solve requests -------------------
  * A server owns a host thread that admits submitted requests in arrival
@@ -374,6 +402,10 @@ int expdiag_server_poll(expdiag_server_t s, expdiag_result* out, int cap,
                         int* n, int* outstanding);
 int expdiag_server_stats(expdiag_server_t s, size_t* bytes_in_use,
                          int* active, int* pending, double* busy_seconds);
+/* Tune the handles of requests admitted from now on by their shape
+ * (expdiag_autotune with cache_path, nullable; each shape is measured once
+ * per process). */
+int expdiag_server_autotune(expdiag_server_t s, const char* cache_path);
 /* Finish every queued request, then stop the thread and free. */
 int expdiag_server_destroy(expdiag_server_t s);
 

@@ -71,6 +71,7 @@ bool kind_cols(int k) { return k == K_COL || k == K_XCOL || k == K_XNARROW; }
 // One launch of a plan: jobs of the same kernel signature.
 struct Group {
   int stage, kind, tcode, len, mode, ti, to;  // signature
+  int wide = 0;  // column stages: 1 = the 2C-column workgroup variant
   std::vector<RowJob> rj;
   std::vector<ColJob> cj;
   std::vector<PassBArgs> pj;
@@ -85,8 +86,8 @@ struct Group {
   void* dred = nullptr;
   int grid() const { return start.empty() ? 0 : start.back(); }
   int njobs() const { return static_cast<int>(start.size()) - 1; }
-  std::tuple<int, int, int, int, int, int, int> key() const {
-    return std::make_tuple(stage, kind, tcode, len, mode, ti, to);
+  std::tuple<int, int, int, int, int, int, int, int> key() const {
+    return std::make_tuple(stage, kind, tcode, len, mode, ti, to, wide);
   }
 };
 
@@ -119,6 +120,7 @@ struct expdiag_ctx {
   bool mixed = false;
   int restart_cap = 0;
   int tvariant = 0;  // time transform: 0 radix FFT, 1 dense MFMA GEMM
+  int col_wide = 0;  // pass-A column stages: 1 = 2C-column workgroups
   bool cplx = false;  // complex symbols (advection): E, c1, c2 not real
   // complex state (complex coefficients): physical arrays are complex, the
   // spectral state is the full spectrum (Nk = Ns, nh = n_last)
@@ -297,11 +299,12 @@ int row_blocks(int M, long nrows) {
   });
   return static_cast<int>(b);
 }
-int col_blocks(int L, long outer, long inner) {
+int col_blocks(int L, long outer, long inner, int wide = 0) {
   long b = 0;
   dispatch_pow2<4, 1024>(L, [&](auto Lc) {
     constexpr int LL = decltype(Lc)::value;
-    b = outer * ((inner + ColShape<LL>::C - 1) / ColShape<LL>::C);
+    const long C = wide ? ColShape<LL, 2>::C : ColShape<LL>::C;
+    b = outer * ((inner + C - 1) / C);
   });
   return static_cast<int>(b);
 }
@@ -744,9 +747,10 @@ int prepare_u0(expdiag_ctx* h, const double* u0) {
 
 // ----------------------------------------------------------------- plans
 Group& plan_group(Plan& P, int stage, int kind, int tcode, int len, int mode,
-                  int ti, int to) {
+                  int ti, int to, int wide = 0) {
   for (auto& g : P.groups)
-    if (g.key() == std::make_tuple(stage, kind, tcode, len, mode, ti, to))
+    if (g.key() ==
+        std::make_tuple(stage, kind, tcode, len, mode, ti, to, wide))
       return g;
   Group g{};
   g.stage = stage;
@@ -756,6 +760,7 @@ Group& plan_group(Plan& P, int stage, int kind, int tcode, int len, int mode,
   g.mode = mode;
   g.ti = ti;
   g.to = to;
+  g.wide = wide;
   g.start.push_back(0);
   P.groups.push_back(g);
   return P.groups.back();
@@ -862,12 +867,14 @@ bool plan_pass_a_mp(Plan& P, expdiag_ctx* h, const Ctl* ctl,
                   : row_bytes(M, ROW_FUSED, j64.nrows, sizeof(double),
                               sizeof(double));
   };
+  const int wd = h->col_wide;
   auto col2 = [&](int stage, int L, int S, const ColJob& j32,
                   const ColJob& j64, int ti32) {
-    Group& g = plan_group(P, stage, K_COL, 2, L, S, ti32, 1);
+    Group& g = plan_group(P, stage, K_COL, 2, L, S, ti32, 1, wd);
     g.cj.push_back(mx ? j32 : j64);
     g.cj.push_back(j64);
-    g.start.push_back(g.start.back() + col_blocks(L, j64.outer, j64.inner));
+    g.start.push_back(g.start.back() +
+                      col_blocks(L, j64.outer, j64.inner, wd));
     const double ent = static_cast<double>(j64.outer) * L * j64.inner * 2;
     g.bytes += mx ? ent * ((ti32 == 0 ? sizeof(double) : sizeof(float)) +
                            sizeof(float))
@@ -883,10 +890,10 @@ bool plan_pass_a_mp(Plan& P, expdiag_ctx* h, const Ctl* ctl,
   host = host || !mx;
   if (host) {
     const ColJob j = make_col(h->Uh, T64, ns, in2, 1.0, ctl, -1);
-    Group& g = plan_group(P, 0, K_COL, 3, n0, 1, 0, 0);
+    Group& g = plan_group(P, 0, K_COL, 3, n0, 1, 0, 0, wd);
     g.cj.push_back(j);
     g.red.push_back(red);
-    g.start.push_back(g.start.back() + col_blocks(n0, ns, in2));
+    g.start.push_back(g.start.back() + col_blocks(n0, ns, in2, wd));
     g.bytes += static_cast<double>(ns) * n0 * in2 * 2 * 2 * sizeof(double);
   } else {
     col2(0, n0, 1, make_col(h->Uh, T32, ns, in2, 1.0, ctl, -1),
@@ -1077,31 +1084,39 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st,
       const int nred = static_cast<int>(g.red.size());
       ok = dispatch_pow2<4, 1024>(g.len, [&](auto Lc) {
         constexpr int LL = decltype(Lc)::value;
-        const dim3 th(ColShape<LL>::THREADS);
-        if (g.mode == 1)
-          klaunch(ps, col_kernel_host<LL, 1>, dim3(grid + nred), th, st, J,
-                  g.dstart, nj, RJ, nred, tw64);
+        if (g.wide)
+          klaunch(ps, col_kernel_host<LL, 1, 2>, dim3(grid + nred),
+                  dim3(ColShape<LL, 2>::THREADS), st, J, g.dstart, nj, RJ,
+                  nred, tw64);
         else
-          klaunch(ps, col_kernel_host<LL, -1>, dim3(grid + nred), th, st, J,
-                  g.dstart, nj, RJ, nred, tw64);
+          klaunch(ps, col_kernel_host<LL, 1>, dim3(grid + nred),
+                  dim3(ColShape<LL>::THREADS), st, J, g.dstart, nj, RJ, nred,
+                  tw64);
       });
     } else if (g.kind == K_COL) {
       ProfScope ps(ph, P_COL, g.bytes, true);
       const ColJob* J = static_cast<const ColJob*>(g.djobs);
-      ok = dispatch_pow2<4, 1024>(g.len, [&](auto Lc) {
+      auto run = [&](auto Lc, auto Wc) {
         constexpr int LL = decltype(Lc)::value;
-        const dim3 th(ColShape<LL>::THREADS);
+        constexpr int WW = decltype(Wc)::value;
+        const dim3 th(ColShape<LL, WW>::THREADS);
         // first inverse stage reads the fp64 spectrum; the others read the
         // stage before in the job's own precision
         if (g.mode == 1 && g.ti == 0)
-          klaunch(ps, col_kernel_mp<LL, 1, double>, dim3(grid), th, st, J,
-                  g.dstart, nj, tw32, tw64);
+          klaunch(ps, col_kernel_mp<LL, 1, double, WW>, dim3(grid), th, st,
+                  J, g.dstart, nj, tw32, tw64);
         else if (g.mode == 1)
-          klaunch(ps, col_kernel_mp<LL, 1, float>, dim3(grid), th, st, J,
-                  g.dstart, nj, tw32, tw64);
+          klaunch(ps, col_kernel_mp<LL, 1, float, WW>, dim3(grid), th, st,
+                  J, g.dstart, nj, tw32, tw64);
         else
-          klaunch(ps, col_kernel_mp<LL, -1, float>, dim3(grid), th, st, J,
-                  g.dstart, nj, tw32, tw64);
+          klaunch(ps, col_kernel_mp<LL, -1, float, WW>, dim3(grid), th, st,
+                  J, g.dstart, nj, tw32, tw64);
+      };
+      ok = dispatch_pow2<4, 1024>(g.len, [&](auto Lc) {
+        if (g.wide)
+          run(Lc, std::integral_constant<int, 2>());
+        else
+          run(Lc, std::integral_constant<int, 1>());
       });
     } else {
       const PassBArgs* J = static_cast<const PassBArgs*>(g.djobs);

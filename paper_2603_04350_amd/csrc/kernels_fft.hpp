@@ -375,12 +375,14 @@ __global__ void __launch_bounds__(RowShape<M>::THREADS)
 // 4; for L <= 256 the tile is 32 KiB in fp64, which lets five workgroups
 // share a CU.  WAVES: the waves per SIMD that the LDS of one CU (160 KiB)
 // allows, at most five (the register budget of the launch bounds).
-template <int L>
+// WD = 2: the wide variant of the same transform, 2C columns per workgroup
+// (one of the autotuner's choices).
+template <int L, int WD = 1>
 struct ColShape {
   static constexpr int R = FftShape<L>::R;
   static constexpr int TPL = FftShape<L>::TPL;
   static constexpr int CMIN = L * 8 * 16 <= 65536 ? 8 : 4;
-  static constexpr int C = (256 / TPL) >= CMIN ? 256 / TPL : CMIN;
+  static constexpr int C = WD * ((256 / TPL) >= CMIN ? 256 / TPL : CMIN);
   static constexpr int THREADS = C * TPL;
   static constexpr int LS = C;  // LDS row (complex slots)
   static constexpr int BLOCKS_LDS = 163840 / (L * C * 16);
@@ -401,11 +403,11 @@ struct ColJob {
 // (o, p, c) at (o*L + p)*inner + c.  out = scale * FFT_S(in); in-place safe.
 // A job has outer * ceil(inner / C) blocks; lb < that count.
 // `lds` holds L * LS elements.
-template <typename T, int L, int S, typename TI, typename TO>
+template <typename T, int L, int S, typename TI, typename TO, int WD = 1>
 __device__ __forceinline__ void col_body(const ColJob& jb, int lb,
                                          const cx<T>* __restrict__ tw,
                                          cx<T>* lds) {
-  using SH = ColShape<L>;
+  using SH = ColShape<L, WD>;
   constexpr int R = SH::R;
   constexpr int TPL = SH::TPL;
   constexpr int C = SH::C;
@@ -444,13 +446,14 @@ __device__ __forceinline__ void col_body(const ColJob& jb, int lb,
 // Job-table launch for instances in either precision phase (see
 // row_kernel_mp): jobs[2i] fp32 (input type TI0, fp32 output), jobs[2i + 1]
 // fp64.
-template <int L, int S, typename TI0>
-__global__ void __launch_bounds__(ColShape<L>::THREADS, ColShape<L>::WAVES)
+template <int L, int S, typename TI0, int WD = 1>
+__global__ void __launch_bounds__((ColShape<L, WD>::THREADS),
+                                  (ColShape<L, WD>::WAVES))
     col_kernel_mp(const ColJob* __restrict__ jobs,
                   const int* __restrict__ start, int njobs,
                   const cx<float>* __restrict__ tw32,
                   const cx<double>* __restrict__ tw64) {
-  __shared__ cx<double> lds[L * ColShape<L>::LS];
+  __shared__ cx<double> lds[L * ColShape<L, WD>::LS];
   const int b = xcd_block(blockIdx.x, gridDim.x);
   const int i = find_job(start, njobs, b);
   const int lb = b - start[i];
@@ -459,10 +462,10 @@ __global__ void __launch_bounds__(ColShape<L>::THREADS, ColShape<L>::WAVES)
   if (ph < 0) return;
   if (ph == 0) {
     const ColJob jb = jobs[2 * i];
-    col_body<float, L, S, TI0, float>(jb, lb, tw32,
-                                      reinterpret_cast<cx<float>*>(lds));
+    col_body<float, L, S, TI0, float, WD>(jb, lb, tw32,
+                                          reinterpret_cast<cx<float>*>(lds));
   } else {
-    col_body<double, L, S, double, double>(j1, lb, tw64, lds);
+    col_body<double, L, S, double, double, WD>(j1, lb, tw64, lds);
   }
 }
 

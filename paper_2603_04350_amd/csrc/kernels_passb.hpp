@@ -518,17 +518,18 @@ __global__ void __launch_bounds__(CTL_THREADS)
 // iteration, launched after this one, see the updated state.  A block may
 // still transform an instance whose reduction in this launch finds it done:
 // the result is never read.
-template <int L, int S>
-__global__ void __launch_bounds__(ColShape<L>::THREADS, ColShape<L>::WAVES)
+template <int L, int S, int WD = 1>
+__global__ void __launch_bounds__((ColShape<L, WD>::THREADS),
+                                  (ColShape<L, WD>::WAVES))
     col_kernel_host(const ColJob* __restrict__ jobs,
                     const int* __restrict__ start, int njobs,
                     const PassBArgs* __restrict__ red_jobs, int nred,
                     const cx<double>* __restrict__ tw64) {
-  __shared__ cx<double> lds[L * ColShape<L>::LS];
+  __shared__ cx<double> lds[L * ColShape<L, WD>::LS];
   const int b = xcd_block(blockIdx.x, gridDim.x);
   if (b < nred) {
-    reduce_instance<ColShape<L>::THREADS>(red_jobs[b],
-                                          reinterpret_cast<double*>(lds));
+    reduce_instance<(ColShape<L, WD>::THREADS)>(
+        red_jobs[b], reinterpret_cast<double*>(lds));
     return;
   }
   const int cb = b - nred;
@@ -538,7 +539,7 @@ __global__ void __launch_bounds__(ColShape<L>::THREADS, ColShape<L>::WAVES)
       __hip_atomic_load(&jb.ctl->done, __ATOMIC_RELAXED,
                         __HIP_MEMORY_SCOPE_AGENT))
     return;
-  col_body<double, L, S, double, double>(jb, cb - start[i], tw64, lds);
+  col_body<double, L, S, double, double, WD>(jb, cb - start[i], tw64, lds);
 }
 
 template <int NT, int MODE, typename TN, bool CPLX>

@@ -45,7 +45,10 @@ EXPORTED = (
     "expdiag_server_create", "expdiag_server_submit", "expdiag_server_poll",
     "expdiag_server_stats", "expdiag_server_destroy",
     "expdiag_set_time_variant", "expdiag_get_time_variant",
-    "expdiag_autotune", "expdiag_iterate_noalloc",
+    "expdiag_autotune", "expdiag_iterate_noalloc", "expdiag_get_tuning",
+    "expdiag_set_tuning",
+    "expdiag_batch_autotune", "expdiag_batch_graph",
+    "expdiag_server_autotune",
 )
 
 
@@ -119,7 +122,16 @@ def load(path: str = LIB_PATH):
     L.expdiag_get_time_variant.argtypes = [vp]
     L.expdiag_autotune.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ci),
                                    ctypes.POINTER(cd), ctypes.POINTER(cd)]
+    L.expdiag_get_tuning.argtypes = [vp, ctypes.POINTER(ci),
+                                     ctypes.POINTER(ci)]
+    L.expdiag_set_tuning.argtypes = [vp, ci, ci]
     pp = ctypes.POINTER(vp)
+    L.expdiag_batch_autotune.argtypes = [vp, pp, pp, ctypes.c_char_p,
+                                         ctypes.POINTER(ci),
+                                         ctypes.POINTER(ci),
+                                         ctypes.POINTER(cd),
+                                         ctypes.POINTER(cd)]
+    L.expdiag_batch_graph.argtypes = [vp]
     L.expdiag_batch_create.argtypes = [pp, ci, vp, pp]
     L.expdiag_batch_destroy.argtypes = [vp]
     L.expdiag_batch_iterate.argtypes = [vp, pp, pp, ci, cd,
@@ -146,6 +158,7 @@ def load(path: str = LIB_PATH):
                                        ctypes.POINTER(ci),
                                        ctypes.POINTER(cd)]
     L.expdiag_server_destroy.argtypes = [vp]
+    L.expdiag_server_autotune.argtypes = [vp, ctypes.c_char_p]
     L.expdiag_iterate_noalloc.argtypes = [ctypes.POINTER(Grid), ci, cd, cd,
                                           ci, ctypes.POINTER(Problem), vp,
                                           vp, vp, ci, cd, ctypes.POINTER(ci),
@@ -460,6 +473,29 @@ def expdiag_batch_iterate_each(b, u0s, Us, max_iters, tols):
     return rc, list(it), list(rel), list(st)
 
 
+def expdiag_batch_autotune(b, u0s, Us, cache_path=None):
+    """Returns dict(shapes, graph_used, ms_graph, ms_launch)."""
+    L = load()
+    n = len(u0s)
+    pu = (ctypes.c_void_p * n)(*[_ptr(t, name="u0").value for t in u0s])
+    pU = (ctypes.c_void_p * n)(*[_ptr(t, name="U").value for t in Us])
+    sh, gu = ctypes.c_int(0), ctypes.c_int(0)
+    mg, ml = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    path = None if cache_path is None else str(cache_path).encode()
+    rc = L.expdiag_batch_autotune(b, pu, pU, path, ctypes.byref(sh),
+                                  ctypes.byref(gu), ctypes.byref(mg),
+                                  ctypes.byref(ml))
+    if rc != EXPDIAG_OK:
+        raise ExpdiagError(rc, f"{strerror(rc)}: "
+                           f"{L.expdiag_batch_last_error(b).decode()}")
+    return dict(shapes=sh.value, graph_used=bool(gu.value),
+                ms_graph=mg.value, ms_launch=ml.value)
+
+
+def expdiag_batch_graph(b):
+    return bool(load().expdiag_batch_graph(b))
+
+
 class Batch:
     """Owns a batch over existing Solvers (which stay owned by the caller)."""
 
@@ -472,6 +508,9 @@ class Batch:
 
     def iterate_each(self, u0s, Us, max_iters, tols):
         return expdiag_batch_iterate_each(self.b, u0s, Us, max_iters, tols)
+
+    def autotune(self, u0s, Us, cache_path=None):
+        return expdiag_batch_autotune(self.b, u0s, Us, cache_path)
 
     def close(self):
         if self.b is not None:
@@ -545,6 +584,24 @@ def expdiag_set_time_variant(h, variant):
 
 def expdiag_get_time_variant(h):
     return load().expdiag_get_time_variant(h)
+
+
+def expdiag_get_tuning(h):
+    """Returns (time_variant, col_wide)."""
+    v = ctypes.c_int(0)
+    w = ctypes.c_int(0)
+    _check(load().expdiag_get_tuning(h, ctypes.byref(v), ctypes.byref(w)), h)
+    return v.value, w.value
+
+
+def expdiag_set_tuning(h, time_variant, col_wide):
+    return _check(load().expdiag_set_tuning(h, int(time_variant),
+                                            int(col_wide)), h)
+
+
+def expdiag_server_autotune(s, cache_path=None):
+    path = None if cache_path is None else str(cache_path).encode()
+    return _check(load().expdiag_server_autotune(s, path))
 
 
 def expdiag_autotune(h, cache_path=None):

@@ -298,3 +298,40 @@ def test_served_configuration_full_size_sampled():
             ref = O.sequential(O.Setup.from_instance(inst), inst.u0)
             assert O.rel_err(got, ref) < 1e-10, (k, inst.name)
     assert checked, "no 3D request in the stream"
+
+
+def test_server_autotune_results():
+    """A server that tunes admitted handles by shape: every result equals
+    the solo solve under the same (per-process) tuning and the oracle's
+    sequential stepping at the mixed / fp64 bar."""
+    import torch
+    from paper_2603_04350_amd import Solver
+    from paper_2603_04350_amd import expdiag as X
+    insts = _mix(6, seed=21)
+    u0s = [_dev(i.u0) for i in insts]
+    Us = [_zeros(i) for i in insts]
+    torch.cuda.synchronize()
+    srv = X.expdiag_server_create(1 << 32, 8)
+    X.expdiag_server_autotune(srv)
+    ids = {}
+    for k, inst in enumerate(insts):
+        prob = X.make_problem(inst.a, inst.c, inst.n1, inst.n2, inst.n3,
+                              inst.precision)
+        rid = X.expdiag_server_submit(srv, inst.shape, inst.Nt, inst.dt,
+                                      inst.alpha, inst.scheme, prob, u0s[k],
+                                      Us[k], 300, 1e-12)
+        ids[rid] = k
+    done = _poll_all(X, srv, len(insts), 60)
+    X.expdiag_server_destroy(srv)
+    assert len(done) == len(insts)
+    assert all(r["status"] == 0 for r in done), done
+    for k, inst in enumerate(insts):
+        with Solver.from_instance(inst) as s:
+            X.expdiag_autotune(s.h)  # this shape's decision, from memory
+            V = _zeros(inst)
+            s.iterate(u0s[k], V, max_iter=300, tol=1e-12)
+        got = Us[k].cpu().numpy()
+        assert np.array_equal(V.cpu().numpy(), got), k
+        ref = O.sequential(O.Setup.from_instance(inst), inst.u0)
+        bar = 1e-10 if (inst.precision == 1 and inst.nonlinear) else 1e-12
+        assert O.rel_err(got, ref) < bar, (k, inst.name)

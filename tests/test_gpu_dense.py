@@ -122,3 +122,64 @@ def test_autotune_writes_and_reuses_cache(tmp_path):
         v2, tf2, td2 = X.expdiag_autotune(s.h, cache)
         assert (v2, tf2, td2) == (v, data[key]["us_fft"],
                                   data[key]["us_dense"])
+
+
+@pytest.mark.parametrize("case", ["ac2d_Nt32", "rd2d_etd2_Nt64",
+                                  "heat3d_Nt128"])
+def test_wide_columns_equal_default(case):
+    """The 2C-column workgroups run the same column transforms: a mixed and
+    an fp64 solve give the default's iterate bit for bit."""
+    import torch
+    from paper_2603_04350_amd import expdiag as X
+    from paper_2603_04350_amd import Solver
+    st = _setup(case)
+    u0 = np.random.default_rng([st.n, st.Nt, 5]).uniform(-0.9, 0.9,
+                                                         (st.n,) * st.dim)
+    for prec in (0, 1):
+        out = []
+        for wide in (0, 1):
+            with Solver((st.n,) * st.dim, st.Nt, st.dt, st.alpha, st.scheme,
+                        st.a, st.c, st.n1, st.n2, st.n3, prec) as s:
+                X.expdiag_set_tuning(s.h, 0, wide)
+                assert X.expdiag_get_tuning(s.h) == (0, wide)
+                U = torch.zeros((st.Nt,) + (st.n,) * st.dim,
+                                dtype=torch.float64, device="cuda:0")
+                rc, it, rel = s.iterate(_dev(u0), U, max_iter=300, tol=1e-12)
+                out.append((it, U.cpu().numpy()))
+        assert out[0][0] == out[1][0]
+        assert np.array_equal(out[0][1], out[1][1])
+
+
+def test_batch_autotune_then_solve(tmp_path):
+    """A tuned batch (per-shape choices, graph replay or launches as
+    measured) solves every instance to its solo result under the same
+    tuning, and to the oracle's sequential stepping at the mixed bar."""
+    import torch
+    from paper_2603_04350_amd import Batch, Solver
+    from paper_2603_04350_amd import expdiag as X
+    insts = W.batch(8, seed=4, ns=(32, 64), nts=(16, 32), precision=1)
+    solvers = [Solver.from_instance(i) for i in insts]
+    b = Batch(solvers)
+    u0s = [_dev(i.u0) for i in insts]
+    Us = [torch.zeros((i.Nt,) + i.shape, dtype=torch.float64,
+                      device="cuda:0") for i in insts]
+    info = b.autotune(u0s, Us, tmp_path / "tune.json")
+    shapes = {(i.n, i.Nt) for i in insts}
+    assert info["shapes"] == len(shapes)
+    assert info["ms_launch"] > 0
+    assert info["graph_used"] == X.expdiag_batch_graph(b.b)
+    for U in Us:
+        assert float(U.abs().max()) == 0.0  # autotune reads U only
+    data = json.loads((tmp_path / "tune.json").read_text())
+    assert len(data) == len(shapes)
+    rc, its, rels, sts = b.iterate(u0s, Us, max_iter=300, tol=1e-12)
+    b.close()
+    assert all(s == 0 for s in sts)
+    for k, inst in enumerate(insts):
+        V = torch.zeros_like(Us[k])
+        solvers[k].iterate(u0s[k], V, max_iter=300, tol=1e-12)
+        assert np.array_equal(V.cpu().numpy(), Us[k].cpu().numpy()), k
+        ref = O.sequential(O.Setup.from_instance(inst), inst.u0)
+        assert O.rel_err(Us[k].cpu().numpy(), ref) < 1e-10
+    for s in solvers:
+        s.close()
