@@ -1243,6 +1243,7 @@ def profile_batch(steps, count=256, kfix=16):
                       device="cuda:0") for i in insts]
     solvers = [X.Solver.from_instance(i, precision=1) for i in insts]
     b = X.Batch(solvers)
+    b.autotune(u0s, Us)
     caps, tols = [kfix] * n, [0.0] * n
     for _ in range(2):
         for u in Us:
@@ -1265,6 +1266,44 @@ def profile_batch(steps, count=256, kfix=16):
         "batch_bytes_per_launch": {k: v["bytes_per_launch"]
                                    for k, v in kern.items()},
         "kfix": kfix, "steps": steps}), flush=True)
+
+
+def profile_batch_solve(steps, count=256):
+    """Batched solves to the run-time rule (the headline batch, tuned), for
+    a kernel trace of a whole solve: full-batch iterations, the tail where
+    few instances remain, entry and exit transforms."""
+    import torch
+    import workloads as W
+    from paper_2603_04350_amd import expdiag as X
+    insts = W.batch(count, seed=BATCH_SEED, precision=1)
+    u0s = [torch.from_numpy(i.u0).to("cuda:0") for i in insts]
+    Us = [torch.zeros((i.Nt,) + i.shape, dtype=torch.float64,
+                      device="cuda:0") for i in insts]
+    solvers = [X.Solver.from_instance(i, precision=1) for i in insts]
+    b = X.Batch(solvers)
+    tune = b.autotune(u0s, Us)
+    walls = []
+    for _ in range(steps + 1):
+        for u in Us:
+            u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, its, rels, sts = b.iterate(u0s, Us, max_iter=400, tol=TOL)
+        torch.cuda.synchronize()
+        walls.append(1e3 * (time.perf_counter() - t0))
+    b.close()
+    for s in solvers:
+        s.close()
+    _log("profile batch solve done")
+    print(json.dumps({"batch_solve_ms": walls[1:], "graph": tune["graph_used"],
+                      "iters_max": max(its)}), flush=True)
+
+
+def profile_variants():
+    """Both time transforms of pass B per Nt (bench_time_variants), for a
+    profiler: kernel times and MFMA counters of the dense variant."""
+    r = bench_time_variants()
+    print(json.dumps(r), flush=True)
 
 
 def calibrate(mib=512, reps=5):
@@ -1390,6 +1429,12 @@ def main():
     ap.add_argument("--profile-batch", action="store_true",
                     help="fixed-count batched solves only, for profiler "
                          "runs")
+    ap.add_argument("--profile-batch-solve", action="store_true",
+                    help="batched solves to the run-time rule only, for "
+                         "profiler runs")
+    ap.add_argument("--profile-variants", action="store_true",
+                    help="both time transforms per Nt only, for profiler "
+                         "runs")
     ap.add_argument("--calibrate", action="store_true",
                     help="a plain 512 MiB device copy, for the counter "
                          "calibration")
@@ -1420,6 +1465,14 @@ def main():
         return
     if args.profile_batch:
         profile_batch(args.steps)
+        return
+    if args.profile_batch_solve:
+        profile_batch_solve(args.steps)
+        return
+    if args.profile_variants:
+        import torch
+        torch.zeros(1, device="cuda:0")
+        profile_variants()
         return
     names = ["heat1d", "ac256"]
     if not args.no_extra:

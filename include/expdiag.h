@@ -414,13 +414,13 @@ int expdiag_server_destroy(expdiag_server_t s);
  * capture, tight serving loops, harnesses that forbid hipMalloc): the solve
  * of expdiag_create + expdiag_iterate + expdiag_destroy in one call, with
  * every device buffer a handle would own and the launch plan's tables
- * carved from one library-owned device workspace of 128 MiB per GPU
+ * carved from one library-owned device workspace of 160 MiB per GPU
  * (allocated when the library is loaded, held until the process ends, the
  * address looked up once per device).  It calls no hipMalloc, hipFree or
  * hipHostMalloc.  Arguments as expdiag_create (g, Nt, dt, alpha, scheme, p
  * with gmres_restart = 0, hip_stream) and expdiag_iterate (u0, U,
  * max_iter, tol, iters, rel_update); results equal those of that pair.
- * A problem whose buffers do not fit (about 119 MB for 256^2 x 64 in mixed
+ * A problem whose buffers do not fit (about 136 MB for 256^2 x 64 in mixed
  * precision, the largest 2D case that fits) is refused with EINVAL before
  * the device is touched.  The workspace keeps the last call's contents and
  * is shared by every call on a device: calls on one device are serialised

@@ -63,10 +63,13 @@ struct EventPair {
 // the group's row mode, fp64 columns in the group's direction, and fp64 ->
 // fp32 copies (a ColJob with `outer` complex elements)
 enum Kind {
-  K_ROW = 0, K_COL = 1, K_PASSB = 2, K_XROW = 3, K_XCOL = 4, K_XNARROW = 5
+  K_ROW = 0, K_COL = 1, K_PASSB = 2, K_XROW = 3, K_XCOL = 4, K_XNARROW = 5,
+  K_XWIDEN = 6
 };
 bool kind_rows(int k) { return k == K_ROW || k == K_XROW; }
-bool kind_cols(int k) { return k == K_COL || k == K_XCOL || k == K_XNARROW; }
+bool kind_cols(int k) {
+  return k == K_COL || k == K_XCOL || k == K_XNARROW || k == K_XWIDEN;
+}
 
 // One launch of a plan: jobs of the same kernel signature.
 struct Group {
@@ -133,6 +136,7 @@ struct expdiag_ctx {
   cx<double>* T = nullptr;    // [Nt][Nk] scratch
   cx<double>* T2 = nullptr;   // [Nt][Nk] scratch (GMRES / Newton)
   cx<float>* T32 = nullptr;   // [Nt][Nk] fp32 pass-A scratch (mixed, d >= 2)
+  cx<float>* U32 = nullptr;   // [Nt][Nk] fp32 bulk-phase iterate (same)
   double* Uphys = nullptr;    // [Nt][Ns] physical iterate (Newton)
   float* Uphys32 = nullptr;   // [Nt][Ns] its fp32 copy (mixed Newton)
   cx<double>* u0h = nullptr;  // [Nk]
@@ -386,6 +390,16 @@ bool dispatch_bdf_order(int s, F&& f) {
 // a half spectrum).  A full spectrum (complex state) weights every entry
 // once, which nh = 1 gives (kl is then always 0).
 int parseval_nh(const expdiag_ctx* h) { return h->cstate ? 1 : h->nh; }
+
+// Whether a mixed-precision instance keeps its bulk-phase iterate in fp32
+// (its buffer U32): first-order schemes with the radix pass B on grids of
+// d >= 2 (whose pass A starts with a column stage).
+bool bulk_u32(const expdiag_ctx* h) {
+  return h->mixed && h->nonlinear && h->dim >= 2 && !h->cstate &&
+         (h->scheme == EXPDIAG_ETD1 || h->scheme == EXPDIAG_ETD2) &&
+         h->tvariant == 0 && h->U32 != nullptr;
+}
+cx<float>* u32_view(expdiag_ctx* h) { return h->U32; }
 int passb_blocks(expdiag_ctx* h) {
   if (h->tvariant == 1)
     return bdf_order(h->scheme) > 0 ? dense_blocks(h->Nk)
@@ -437,6 +451,7 @@ ColJob make_col(const void* in, void* out, long outer, long inner,
 PassBArgs passb_args(expdiag_ctx* h) {
   PassBArgs a{};
   a.U = h->Uh;
+  a.U32 = bulk_u32(h) ? u32_view(h) : nullptr;
   a.Nh = h->Nh;
   a.Nh32 = nullptr;
   a.u0h = h->u0h;
@@ -518,7 +533,9 @@ double passb_bytes(const PassBArgs& a, int Nt, int mode, size_t nb) {
   double bytes = static_cast<double>(a.Nk) * (sizeof(double) * 3 + 16);
   const double nbytes = a.nonlinear ? static_cast<double>(nb) : 0.0;
   if (mode == PB_PRECOND) return bytes + ent * 32;
-  return bytes + ent * (32 + nbytes);
+  // the iterate read and written (fp32 in the bulk phase when kept so)
+  const double ubytes = (mode == PB_ITERATE && a.U32 != nullptr) ? 16 : 32;
+  return bytes + ent * (ubytes + nbytes);
 }
 
 template <int MODE, typename TN>
@@ -730,6 +747,36 @@ __global__ void narrow_kernel(const cx<double>* __restrict__ in,
   if (i < n) out[i] = cvt<float>(in[i]);
 }
 
+// The iterate as the bulk phase keeps it: fp32 copy of Uh (after the entry
+// transform of a solve), and back (before the exit transform) when the
+// instance's control block says the fp32 copy is the current iterate
+// (phase PH_BULK or PH_SWITCH after the last iteration).
+__global__ void widen_bulk_kernel(const Ctl* __restrict__ ctl,
+                                  const cx<float>* __restrict__ in,
+                                  cx<double>* __restrict__ out, long n) {
+  if (ctl->phase > PH_SWITCH) return;
+  const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = cvt<double>(in[i]);
+}
+
+int enter_bulk_state(expdiag_ctx* h, hipStream_t st) {
+  if (!bulk_u32(h)) return 0;
+  const long n = static_cast<long>(h->Nt) * h->Nk;
+  hipLaunchKernelGGL(narrow_kernel, dim3((n + 255) / 256), dim3(256), 0, st,
+                     h->Uh, u32_view(h), n);
+  HIPCHK(h, hipGetLastError());
+  return 0;
+}
+
+int leave_bulk_state(expdiag_ctx* h, const Ctl* ctl, hipStream_t st) {
+  if (!bulk_u32(h)) return 0;
+  const long n = static_cast<long>(h->Nt) * h->Nk;
+  hipLaunchKernelGGL(widen_bulk_kernel, dim3((n + 255) / 256), dim3(256), 0,
+                     st, ctl, u32_view(h), h->Uh, n);
+  HIPCHK(h, hipGetLastError());
+  return 0;
+}
+
 // u0 -> u0h, N^_0 = FFT N(u0) (fp64 slot 0) and, for mixed precision, its
 // fp32 copy in slot 0 of the fp32 view.
 int prepare_u0(expdiag_ctx* h, const double* u0) {
@@ -895,6 +942,13 @@ bool plan_pass_a_mp(Plan& P, expdiag_ctx* h, const Ctl* ctl,
     g.red.push_back(red);
     g.start.push_back(g.start.back() + col_blocks(n0, ns, in2, wd));
     g.bytes += static_cast<double>(ns) * n0 * in2 * 2 * 2 * sizeof(double);
+  } else if (bulk_u32(h)) {
+    // the bulk phase reads its fp32 iterate, and so does the fp64 job of
+    // the switch iteration
+    ColJob j64 = make_col(h->Uh, T64, ns, in2, 1.0, ctl, -1);
+    j64.in32 = u32_view(h);
+    col2(0, n0, 1, make_col(u32_view(h), T32, ns, in2, 1.0, ctl, -1), j64,
+         1);
   } else {
     col2(0, n0, 1, make_col(h->Uh, T32, ns, in2, 1.0, ctl, -1),
          make_col(h->Uh, T64, ns, in2, 1.0, ctl, -1), 0);
@@ -1182,6 +1236,20 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st,
 }
 
 // ------------------------------------------- batched boundary transforms
+// fp32 -> fp64 copies of the jobs whose control block says the fp32 copy
+// is the current iterate (see widen_bulk_kernel)
+__global__ void widen_kernel_jt(const ColJob* __restrict__ jobs,
+                                const int* __restrict__ start, int njobs) {
+  const int i = find_job(start, njobs);
+  const ColJob jb = jobs[i];
+  if (jb.ctl->phase > PH_SWITCH) return;
+  const long e = static_cast<long>(blockIdx.x - start[i]) * blockDim.x +
+                 threadIdx.x;
+  if (e < jb.outer)
+    static_cast<cx<double>*>(jb.out)[e] =
+        cvt<double>(static_cast<const cx<float>*>(jb.in)[e]);
+}
+
 // fp64 -> fp32 copies, job j copying `outer` complex elements
 __global__ void narrow_kernel_jt(const ColJob* __restrict__ jobs,
                                  const int* __restrict__ start, int njobs) {
@@ -1245,31 +1313,44 @@ void plan_entry(Plan& P, expdiag_ctx* h, const double* u0, const double* U) {
     }
   }
   plan_xfwd(P, h, 0, ROW_R2C, U, h->Uh, h->Nt);
+  if (bulk_u32(h)) {
+    Group& g = plan_group(P, 3, K_XNARROW, 0, 0, 0, 0, 0);
+    const long n = static_cast<long>(h->Nt) * h->Nk;
+    g.cj.push_back(make_col(h->Uh, u32_view(h), n, 1, 1.0, nullptr, -1));
+    g.start.push_back(g.start.back() + static_cast<int>((n + 255) / 256));
+  }
 }
 
-// inv_slices(h, h->Uh, U, Nt) as plan stages 0..2 (through h->T)
-void plan_exit(Plan& P, expdiag_ctx* h, double* U) {
+// leave_bulk_state (stage 0, gated on the control block `ctl`) and
+// inv_slices(h, h->Uh, U, Nt) (stages 1..3, through h->T) as plan stages
+void plan_exit(Plan& P, expdiag_ctx* h, double* U, const Ctl* ctl) {
   const int d = h->dim;
   const long nh2 = 2L * h->nh;
   const int nl = h->n[d - 1];
   const double sc = 1.0 / static_cast<double>(h->Ns);
   const long ns = h->Nt;
+  if (bulk_u32(h)) {
+    Group& g = plan_group(P, 0, K_XWIDEN, 0, 0, 0, 0, 0);
+    const long n = ns * h->Nk;
+    g.cj.push_back(make_col(u32_view(h), h->Uh, n, 1, 1.0, ctl, -1));
+    g.start.push_back(g.start.back() + static_cast<int>((n + 255) / 256));
+  }
   if (d == 1) {
-    plan_xrow(P, 2, nl / 2, ROW_C2R,
+    plan_xrow(P, 3, nl / 2, ROW_C2R,
               make_row(h, h->Uh, U, ns, nh2, nl, sc, nullptr, -1));
     return;
   }
   if (d == 2) {
-    plan_xcol(P, 0, h->n[0], 1,
+    plan_xcol(P, 1, h->n[0], 1,
               make_col(h->Uh, h->T, ns, h->nh, 1.0, nullptr, -1));
   } else {
-    plan_xcol(P, 0, h->n[0], 1,
+    plan_xcol(P, 1, h->n[0], 1,
               make_col(h->Uh, h->T, ns, static_cast<long>(h->n[1]) * h->nh,
                        1.0, nullptr, -1));
-    plan_xcol(P, 1, h->n[1], 1,
+    plan_xcol(P, 2, h->n[1], 1,
               make_col(h->T, h->T, ns * h->n[0], h->nh, 1.0, nullptr, -1));
   }
-  plan_xrow(P, 2, nl / 2, ROW_C2R,
+  plan_xrow(P, 3, nl / 2, ROW_C2R,
             make_row(h, h->T, U, ns * (h->Ns / nl), nh2, nl, sc, nullptr,
                      -1));
 }
@@ -1312,6 +1393,10 @@ int plan_launch_x(expdiag_ctx* ph, Plan& P, hipStream_t st,
       });
     } else if (g.kind == K_XNARROW) {
       hipLaunchKernelGGL(narrow_kernel_jt, dim3(grid), dim3(256), 0, st,
+                         static_cast<const ColJob*>(g.djobs), g.dstart, nj);
+      ok = true;
+    } else if (g.kind == K_XWIDEN) {
+      hipLaunchKernelGGL(widen_kernel_jt, dim3(grid), dim3(256), 0, st,
                          static_cast<const ColJob*>(g.djobs), g.dstart, nj);
       ok = true;
     }
@@ -1754,7 +1839,7 @@ size_t footprint(const Sizes& s, int dim, int Nt, bool nonlinear,
   const size_t st = static_cast<size_t>(Nt) * s.Nk * sizeof(cx<double>);
   size_t b = 2 * st;                   // Uh, T
   if (nonlinear) b += st;              // Nh
-  if (nonlinear && mixed && dim >= 2) b += st / 2;  // T32
+  if (nonlinear && mixed && dim >= 2) b += st;  // T32, U32
   if (restart > 0) {
     b += st;                                          // T2
     b += static_cast<size_t>(restart + 1) * st;       // Krylov basis
@@ -1808,6 +1893,7 @@ void release(expdiag_ctx* h) {
   fr(h->T);
   fr(h->T2);
   fr(h->T32);
+  fr(h->U32);
   fr(h->Uphys);
   fr(h->Uphys32);
   fr(h->u0h);
@@ -1857,7 +1943,7 @@ Ctl initial_ctl(expdiag_ctx* h, int max_iter, double tol) {
   c.done = 0;
   c.iters = 0;
   c.max_iter = max_iter;
-  c.phase = (h->mixed && h->nonlinear) ? 0 : 1;
+  c.phase = (h->mixed && h->nonlinear) ? PH_BULK : PH_FP64;
   c.tol = tol;
   c.bulk_tol = BULK_TOL;
   c.last_rel = 0.0;
@@ -2038,8 +2124,10 @@ int setup_handle(expdiag_ctx* h, const expdiag_grid* g, int Nt, double dt,
   A(&h->Uh, st);
   A(&h->T, st);
   if (h->nonlinear) A(&h->Nh, st);
-  if (h->nonlinear && h->mixed && h->dim >= 2)
+  if (h->nonlinear && h->mixed && h->dim >= 2) {
     A(&h->T32, static_cast<size_t>(Nt) * h->Nk * sizeof(cx<float>));
+    A(&h->U32, static_cast<size_t>(Nt) * h->Nk * sizeof(cx<float>));
+  }
   A(&h->u0h, h->Nk * sizeof(cx<double>));
   A(&h->E, h->Nk * sizeof(cx<double>));
   A(&h->c1, h->Nk * sizeof(cx<double>));
@@ -2303,6 +2391,7 @@ int expdiag_iterate(expdiag_t h, const double* u0, double* U, int max_iter,
   if (!(tol >= 0.0)) return fail(h, EXPDIAG_EINVAL, "tol must be >= 0");
   RCHK(prepare_u0(h, u0));
   RCHK(fwd_slices<ROW_R2C>(h, U, h->Uh, h->Nt));
+  RCHK(enter_bulk_state(h, h->stream));
   *h->h_ctl = initial_ctl(h, max_iter, tol);
   *h->h_mirror = *h->h_ctl;
   hipLaunchKernelGGL(ctl_set_kernel, dim3(1), dim3(64), 0, h->stream, h->ctl,
@@ -2337,6 +2426,7 @@ int expdiag_iterate(expdiag_t h, const double* u0, double* U, int max_iter,
   if (enqueued < max_iter)
     RCHK(enqueue(std::min(known ? 2 : 8, max_iter - enqueued), 1));
   if (known || enqueued >= max_iter) {
+    RCHK(leave_bulk_state(h, h->ctl, h->stream));
     RCHK(inv_slices(h, h->Uh, U, h->Nt));
     exit_queued = true;
   }
@@ -2357,20 +2447,24 @@ int expdiag_iterate(expdiag_t h, const double* u0, double* U, int max_iter,
       exit_queued = false;
     }
     if (!exit_queued && (add <= 0 || enqueued >= max_iter)) {
+      RCHK(leave_bulk_state(h, h->ctl, h->stream));
       RCHK(inv_slices(h, h->Uh, U, h->Nt));
       exit_queued = true;
     }
     oldest ^= 1;
   }
-  if (!exit_queued) RCHK(inv_slices(h, h->Uh, U, h->Nt));
+  if (!exit_queued) {
+    RCHK(leave_bulk_state(h, h->ctl, h->stream));
+    RCHK(inv_slices(h, h->Uh, U, h->Nt));
+  }
   HIPCHK(h, hipStreamSynchronize(h->stream));
   const Ctl c = read_mirror(h->h_mirror);
   h->last_iters = c.iters;
   if (iters != nullptr) *iters = c.iters;
   if (rel_update != nullptr) *rel_update = c.last_rel;
   if (c.done == 2) return fail(h, EXPDIAG_EDIVERGED, "non-finite residual");
-  return (c.phase == 1 && c.last_rel <= tol) ? EXPDIAG_OK
-                                             : EXPDIAG_NOT_CONVERGED;
+  return (c.phase == PH_FP64 && c.last_rel <= tol) ? EXPDIAG_OK
+                                                   : EXPDIAG_NOT_CONVERGED;
 }
 
 int expdiag_profile_enable(expdiag_t h, int mask) {

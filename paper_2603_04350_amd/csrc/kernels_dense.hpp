@@ -325,7 +325,7 @@ __global__ void __launch_bounds__(DENSE_THREADS)
     const int ph = job_phase(a.ctl);
     if (ph < 0) return;
     if (lb == 0 && threadIdx.x == 0) a.ctl->pending = 1;
-    if (a.Nh32 != nullptr && ph == 0)
+    if (a.Nh32 != nullptr && ph == PH_BULK)
       passb_dft_body<NT, MODE, float>(
           a, lb, static_cast<const float*>(a.Nh32), lds, red);
     else

@@ -24,9 +24,17 @@
 namespace expdiag {
 
 // Per-instance control block, device resident (kernels_passb.hpp updates it).
+// Precision phases of an iteration (mixed precision): the bulk phase
+// evaluates the residual with fp32 spatial FFTs and nonlinearity (and, for
+// instances that keep their bulk iterate in fp32, stores the iterate in
+// fp32); the switch iteration is the first fp64 one (it reads that fp32
+// iterate and writes the fp64 one); the fp64 phase refines.  fp64
+// instances run in PH_FP64 throughout.
+enum : int { PH_BULK = 0, PH_SWITCH = 1, PH_FP64 = 2 };
+
 struct Ctl {
   int done;      // 0 running, 1 finished (tolerance or max_iter), 2 diverged
-  int phase;     // 0: fp32 bulk residual (mixed precision), 1: fp64
+  int phase;     // PH_BULK, PH_SWITCH or PH_FP64
   int iters;     // iterations completed
   int max_iter;
   int pending;   // 1: pass B wrote block partials not yet reduced
@@ -337,7 +345,7 @@ __global__ void __launch_bounds__(RowShape<M>::THREADS)
   const RowJob j1 = jobs[2 * i + 1];
   const int ph = job_phase(j1.ctl);
   if (ph < 0) return;
-  if (ph == 0) {
+  if (ph == PH_BULK) {
     const RowJob jb = jobs[2 * i];
     row_body<float, M, MODE, TI0, float>(jb, lb, tw32,
                                          reinterpret_cast<cx<float>*>(lds));
@@ -393,6 +401,10 @@ struct ColShape {
 struct ColJob {
   const void* in;  // cx<TI>
   void* out;       // cx<TO>
+  // fp64 job of the first pass-A stage of an instance whose bulk iterate
+  // is fp32: that iterate (cx<float>), read instead of `in` in the switch
+  // iteration; else null
+  const void* in32;
   long outer, inner;
   double scale;
   const Ctl* ctl;
@@ -460,10 +472,14 @@ __global__ void __launch_bounds__((ColShape<L, WD>::THREADS),
   const ColJob j1 = jobs[2 * i + 1];
   const int ph = job_phase(j1.ctl);
   if (ph < 0) return;
-  if (ph == 0) {
+  if (ph == PH_BULK) {
     const ColJob jb = jobs[2 * i];
     col_body<float, L, S, TI0, float, WD>(jb, lb, tw32,
                                           reinterpret_cast<cx<float>*>(lds));
+  } else if (ph == PH_SWITCH && j1.in32 != nullptr) {
+    ColJob js = j1;
+    js.in = j1.in32;
+    col_body<double, L, S, float, double, WD>(js, lb, tw64, lds);
   } else {
     col_body<double, L, S, double, double, WD>(j1, lb, tw64, lds);
   }

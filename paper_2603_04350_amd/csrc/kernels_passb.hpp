@@ -38,6 +38,10 @@ enum PassBMode : int {
 
 struct PassBArgs {
   cx<double>* U;          // [Nt][Nk]
+  // [Nt][Nk] fp32 iterate of the bulk phase (mixed, d >= 2, first-order
+  // radix pass B), or null: the bulk phase reads and writes it, the switch
+  // iteration (the first fp64 one) reads it and writes U
+  cx<float>* U32;
   const void* Nh;         // [Nt][Nk] fp64 N^ (or J for PB_OPAPPLY), or null
   const void* Nh32;       // [Nt][Nk] fp32 N^ of the mixed bulk phase
   const cx<double>* u0h;  // [Nk]
@@ -158,9 +162,13 @@ __device__ inline void advance_ctl(const PassBArgs& a, const double* tot) {
   }
   if (!(rel == rel) || !(rn == rn) || rel > 1e300) {
     done = 2;
-  } else if (c->phase == 0) {
-    if (rel <= c->bulk_tol) c->phase = 1;
+  } else if (c->phase == PH_BULK) {
+    if (rel <= c->bulk_tol) c->phase = PH_SWITCH;
     if (it >= c->max_iter) done = 1;
+  } else if (c->phase == PH_SWITCH) {
+    // the first fp64 iteration (it has written the fp64 iterate)
+    c->phase = PH_FP64;
+    if (rel <= c->tol || it >= c->max_iter) done = 1;
   } else if (rel <= c->tol || it >= c->max_iter) {
     done = 1;
   }
@@ -214,9 +222,14 @@ __device__ __forceinline__ cx<double> smul(cx<double> a, cx<double> s) {
   return cmul(a, s);
 }
 
-template <int NT, int MODE, typename TN, bool CPLX>
+// Uin / Uout: the iterate read and written in PB_ITERATE (fp32 or fp64;
+// the arithmetic is fp64), the Krylov vector read in PB_OPAPPLY / the
+// state in PB_RESIDUAL (fp64); unused in PB_PRECOND.
+template <int NT, int MODE, typename TN, bool CPLX, typename TUI = double,
+          typename TUO = double>
 __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
-                                           const TN* Nh, cx<double>* lds,
+                                           const TN* Nh, const cx<TUI>* Uin,
+                                           cx<TUO>* Uout, cx<double>* lds,
                                            double* red) {
   using SY = SymOf<CPLX>;
   using SH = PassBShape<NT>;
@@ -237,6 +250,7 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
 
   // loads: data rows first, then the per-kappa and per-row tables
   cx<double> u[R];
+  cx<TUI> uin[R];
   cx<TN> nr[R];
   const cx<TN>* Nc = reinterpret_cast<const cx<TN>*>(Nh);
   const bool nl = MODE != PB_PRECOND && a.nonlinear;
@@ -244,7 +258,10 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
 #pragma unroll
   for (int s = 0; s < R; ++s) {
     const int l = t + s * TPL;
-    u[s] = gld(MODE == PB_PRECOND ? a.Rin : a.U, l * Nk + kc);
+    if constexpr (MODE == PB_PRECOND)
+      u[s] = gld(a.Rin, l * Nk + kc);
+    else
+      uin[s] = gld(Uin, l * Nk + kc);
   }
   if (nl) {
 #pragma unroll
@@ -285,7 +302,7 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
     // residual, U part (rows of U, or of the Krylov vector v for PB_OPAPPLY)
 #pragma unroll
     for (int s = 0; s < R; ++s) {
-      if (!valid) u[s] = zero;
+      u[s] = valid ? cvt<double>(uin[s]) : zero;
       lds[(t + s * TPL) * LS + c] = u[s];
     }
     __syncthreads();
@@ -379,7 +396,7 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
       nrm_s += pw * norm2(sv);
       nrm_u += pw * norm2(un);
       if (k0) sum0 += un.x;
-      if (valid) gst(a.U, l * Nk + kap, un);
+      if (valid) gst(Uout, l * Nk + kap, cvt<TUO>(un));
     }
   } else {
 #pragma unroll
@@ -416,17 +433,23 @@ __global__ void __launch_bounds__(PassBShape<NT>::THREADS,
     const int ph = job_phase(a.ctl);
     if (ph < 0) return;
     if (lb == 0 && threadIdx.x == 0) a.ctl->pending = 1;
-    if (a.Nh32 != nullptr && ph == 0)
-      passb_body<NT, MODE, float, CPLX>(a, lb,
-                                        static_cast<const float*>(a.Nh32),
-                                  lds, red);
-    else
-      passb_body<NT, MODE, double, CPLX>(a, lb,
-                                         static_cast<const double*>(a.Nh),
-                                   lds, red);
+    if (a.Nh32 != nullptr && ph == PH_BULK) {
+      const float* n32 = static_cast<const float*>(a.Nh32);
+      if (a.U32 != nullptr)
+        passb_body<NT, MODE, float, CPLX, float, float>(a, lb, n32, a.U32,
+                                                        a.U32, lds, red);
+      else
+        passb_body<NT, MODE, float, CPLX>(a, lb, n32, a.U, a.U, lds, red);
+    } else if (a.U32 != nullptr && ph == PH_SWITCH) {
+      passb_body<NT, MODE, double, CPLX, float, double>(
+          a, lb, static_cast<const double*>(a.Nh), a.U32, a.U, lds, red);
+    } else {
+      passb_body<NT, MODE, double, CPLX>(
+          a, lb, static_cast<const double*>(a.Nh), a.U, a.U, lds, red);
+    }
   } else {
-    passb_body<NT, MODE, TN, CPLX>(a, lb, static_cast<const TN*>(a.Nh), lds,
-                                   red);
+    passb_body<NT, MODE, TN, CPLX>(a, lb, static_cast<const TN*>(a.Nh), a.U,
+                                   a.U, lds, red);
   }
 }
 
@@ -550,7 +573,7 @@ __global__ void __launch_bounds__(PassBShape<NT>::THREADS,
   __shared__ cx<double> lds[SH::LDS];
   double* red = reinterpret_cast<double*>(lds);
   passb_body<NT, MODE, TN, CPLX>(a, blockIdx.x, static_cast<const TN*>(a.Nh),
-                                 lds, red);
+                                 a.U, a.U, lds, red);
 }
 
 // Fixed-order final reduction of per-block partials for the non-iterate
