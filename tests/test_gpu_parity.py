@@ -217,3 +217,32 @@ def test_mixed_full_size_allen_cahn():
         rc, it, rel = s.iterate(_dev(inst.u0), U, max_iter=300, tol=1e-11)
     err = O.rel_err(U.cpu().numpy(), ref)
     assert err < 1e-10, (it, rel, err)
+
+
+@pytest.mark.parametrize("case", ["ac2d_etd1", "rd2d_etd2", "ac3d",
+                                  "ac1d_etd2"])
+def test_mixed_bulk_iterates_and_exit(case):
+    """Solves that stop inside the fp32 bulk phase (k = 1..3 iterations):
+    the returned window (the fp32 bulk iterate widened at exit for d >= 2)
+    matches the oracle's fixed-point iterate k to the mixed per-update bar
+    1e-5 (of the iterate's size), and a batch ending in the bulk phase
+    returns the solo window bit for bit."""
+    import torch
+    from paper_2603_04350_amd import Batch
+    st = _setup(case)
+    u0 = _u0(st)
+    _, _, (_, its) = O.fixed_point(st, u0, max_iter=3, tol=0.0, record=True)
+    shape = (st.Nt,) + (st.n,) * st.dim
+    with _solver(st, precision=1) as s:
+        for k in (1, 2, 3):
+            U = torch.zeros(shape, dtype=torch.float64, device="cuda:0")
+            s.iterate(_dev(u0), U, max_iter=k, tol=0.0)
+            got = U.cpu().numpy()
+            assert O.rel_err(got, its[k - 1]) < 1e-5, (k,)
+            assert O.rel_err(got, its[k - 1]) > 0.0
+        solo = got
+        b = Batch([s])
+        V = torch.zeros(shape, dtype=torch.float64, device="cuda:0")
+        b.iterate_each([_dev(u0)], [V], [3], [0.0])
+        b.close()
+    assert np.array_equal(V.cpu().numpy(), solo)
