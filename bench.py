@@ -76,11 +76,22 @@ DEVICE_SOURCES = ("cx.hpp", "fft_core.hpp", "kernels_fft.hpp",
                   "kernels_dense.hpp", "kernels_bdf.hpp")
 
 
-def _src_hash():
-    """Hash of the device-code sources (what the counters depend on)."""
+# the device sources a workload's kernels are built from: its counter
+# record stays valid while these are unchanged
+WORKLOAD_SOURCES = {
+    "batch256_mixed": ("cx.hpp", "fft_core.hpp", "kernels_fft.hpp",
+                       "kernels_passb.hpp", "kernels_dense.hpp"),
+    "single256_fp64": ("cx.hpp", "fft_core.hpp", "kernels_fft.hpp",
+                       "kernels_passb.hpp", "kernels_dense.hpp",
+                       "kernels_bdf.hpp"),
+}
+
+
+def _src_hash(sources=DEVICE_SOURCES):
+    """Hash of device-code sources (what the counters depend on)."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2603_04350_amd", "csrc")
-    for name in DEVICE_SOURCES:
+    for name in sources:
         with open(os.path.join(d, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
@@ -348,7 +359,7 @@ def _classes(X, ms, cnt, by, tm, runs):
 # --------------------------------------------------------------------------
 # Headline: the batched mixed-precision solve
 # --------------------------------------------------------------------------
-def bench_batch(count, steps, warmup, refs):
+def bench_batch(count, steps, warmup, refs, tune_file=None):
     """256 heterogeneous Allen-Cahn instances in one batched plan, mixed
     precision, against the same instances on the plain FP64 single-instance
     path.  With `refs` (the oracle's sequential solutions) every instance
@@ -381,7 +392,7 @@ def bench_batch(count, steps, warmup, refs):
     # per-shape tuning (time transform, column width) and graph replay
     # against plain launches for this batch, measured by the library
     t0 = time.perf_counter()
-    tune = b.autotune(u0s, Us)
+    tune = b.autotune(u0s, Us, tune_file)
     tune["seconds"] = time.perf_counter() - t0
     per_shape = {}
     for inst, s in zip(insts, solvers):
@@ -1228,7 +1239,7 @@ def profile_large(steps):
     print(json.dumps({"event_avg_us_large": out}), flush=True)
 
 
-def profile_batch(steps, count=256, kfix=16):
+def profile_batch(steps, count=256, kfix=17, tune_file=None):
     """Fixed-count batched solves only (every instance `kfix` iterations,
     tol = 0, so every launch does full work), for a profiler wrapped around
     this process: the headline batch.  Prints the event-timed average launch
@@ -1243,7 +1254,7 @@ def profile_batch(steps, count=256, kfix=16):
                       device="cuda:0") for i in insts]
     solvers = [X.Solver.from_instance(i, precision=1) for i in insts]
     b = X.Batch(solvers)
-    b.autotune(u0s, Us)
+    b.autotune(u0s, Us, tune_file)
     caps, tols = [kfix] * n, [0.0] * n
     for _ in range(2):
         for u in Us:
@@ -1268,7 +1279,7 @@ def profile_batch(steps, count=256, kfix=16):
         "kfix": kfix, "steps": steps}), flush=True)
 
 
-def profile_batch_solve(steps, count=256):
+def profile_batch_solve(steps, count=256, tune_file=None):
     """Batched solves to the run-time rule (the headline batch, tuned), for
     a kernel trace of a whole solve: full-batch iterations, the tail where
     few instances remain, entry and exit transforms."""
@@ -1281,7 +1292,7 @@ def profile_batch_solve(steps, count=256):
                       device="cuda:0") for i in insts]
     solvers = [X.Solver.from_instance(i, precision=1) for i in insts]
     b = X.Batch(solvers)
-    tune = b.autotune(u0s, Us)
+    tune = b.autotune(u0s, Us, tune_file)
     walls = []
     for _ in range(steps + 1):
         for u in Us:
@@ -1388,7 +1399,9 @@ def traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, workload,
     except (OSError, ValueError):
         rec = {}
     rec.setdefault("workloads", {})[workload] = {
-        "src_hash": _src_hash(), "fetch_factor": ff, "write_factor": fw,
+        "src_hash": _src_hash(WORKLOAD_SOURCES.get(workload,
+                                                   DEVICE_SOURCES)),
+        "fetch_factor": ff, "write_factor": fw,
         "classes": classes, "kernels": kernels}
     with open(path, "w") as f:
         json.dump(rec, f, indent=1)
@@ -1435,6 +1448,11 @@ def main():
     ap.add_argument("--profile-variants", action="store_true",
                     help="both time transforms per Nt only, for profiler "
                          "runs")
+    ap.add_argument("--tune-file", default=None,
+                    help="the batch's tuning decisions: read from this JSON "
+                         "file where it holds them, measured and written "
+                         "to it otherwise (so that a profiled run can use "
+                         "the decisions of an unprofiled one)")
     ap.add_argument("--calibrate", action="store_true",
                     help="a plain 512 MiB device copy, for the counter "
                          "calibration")
@@ -1464,10 +1482,10 @@ def main():
         profile_large(args.steps)
         return
     if args.profile_batch:
-        profile_batch(args.steps)
+        profile_batch(args.steps, tune_file=args.tune_file)
         return
     if args.profile_batch_solve:
-        profile_batch_solve(args.steps)
+        profile_batch_solve(args.steps, tune_file=args.tune_file)
         return
     if args.profile_variants:
         import torch
@@ -1483,7 +1501,8 @@ def main():
         _log("oracle leg on the host cores (cpu baseline, references)")
         cpu, brefs, refs = oracle_leg(args.batch, args.cpu_iters, names)
     _log(f"batched: {args.batch} instances, mixed, against solo fp64")
-    bt = bench_batch(args.batch, args.steps, args.warmup, brefs)
+    bt = bench_batch(args.batch, args.steps, args.warmup, brefs,
+                     args.tune_file)
     del brefs
     src_hash = _src_hash()
     dom = bt["dominant"]
@@ -1496,7 +1515,8 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": _traffic("batch256_mixed", dom, src_hash),
+        "traffic": _traffic("batch256_mixed", dom,
+                            _src_hash(WORKLOAD_SOURCES["batch256_mixed"])),
         "algorithmic_bytes_per_launch": kd["bytes_per_launch"],
         "avg_launch_us": kd["avg_us"],
         "measured_on": f"fixed-count batched solves "

@@ -538,10 +538,22 @@ double passb_bytes(const PassBArgs& a, int Nt, int mode, size_t nb) {
   return bytes + ent * (ubytes + nbytes);
 }
 
+// Blocks (partial sums) of the single-instance pass B of mode `mode`: the
+// first-order schemes run every mode but the dense-variant PB_PRECOND on
+// the radix kernel.
+int passb1_blocks(expdiag_ctx* h, int mode) {
+  if (bdf_order(h->scheme) == 0 && !(mode == PB_PRECOND && h->tvariant == 1))
+    return passb_blocks_nt(h->Nt, h->Nk);
+  return passb_blocks(h);
+}
+
 template <int MODE, typename TN>
 int launch_passb1(expdiag_ctx* h, const PassBArgs& a) {
   ProfScope ps(h, P_PASSB, passb_bytes(a, h->Nt, MODE, sizeof(cx<TN>)));
-  if (const int s = bdf_order(h->scheme); s > 0) {
+  if constexpr (MODE == PB_PRECRES) {
+    if (bdf_order(h->scheme) > 0)
+      return fail(h, EXPDIAG_EUNSUPPORTED, "fused residual for EBDF");
+  } else if (const int s = bdf_order(h->scheme); s > 0) {
     // radix FFT: one instantiation per order; dense (MFMA-bound either way):
     // order 2 has its own, 3..6 share one that reads s
     bool ok = false;
@@ -1843,6 +1855,9 @@ size_t footprint(const Sizes& s, int dim, int Nt, bool nonlinear,
   if (restart > 0) {
     b += st;                                          // T2
     b += static_cast<size_t>(restart + 1) * st;       // Krylov basis
+    b += static_cast<size_t>((static_cast<long>(Nt) * s.Nk + KRY_PER_BLOCK -
+                              1) / KRY_PER_BLOCK) *
+         (2 * restart + 3) * sizeof(double);  // block partials
     if (nonlinear)
       b += static_cast<size_t>(Nt) * s.Ns * (sizeof(double) + sizeof(float));
   }
@@ -2153,8 +2168,10 @@ int setup_handle(expdiag_ctx* h, const expdiag_grid* g, int Nt, double dt,
     A(&h->T2, st);
     A(&h->V, static_cast<size_t>(h->restart_cap + 1) * st);
     h->kpart_blocks = static_cast<int>(krylov_blocks(Nt * h->Nk));
+    // rows of block partials: up to 2 restart + 1 inner products per
+    // Arnoldi step
     A(&h->kpart, static_cast<size_t>(h->kpart_blocks) *
-                     (h->restart_cap + 2) * sizeof(double));
+                     (2 * h->restart_cap + 3) * sizeof(double));
     A(&h->kdots, 4 * (h->restart_cap + 2) * sizeof(double));
     if (h->nonlinear)
       A(&h->Uphys, static_cast<size_t>(Nt) * h->Ns * sizeof(double));
@@ -2357,7 +2374,7 @@ int expdiag_residual(expdiag_t h, const double* u0, const double* U,
   PassBArgs a = passb_args(h);
   a.Sout = h->T;
   RCHK((launch_passb1<PB_RESIDUAL, double>(h, a)));
-  RCHK(launch_reduce(h, passb_blocks(h)));
+  RCHK(launch_reduce(h, passb1_blocks(h, PB_RESIDUAL)));
   RCHK(inv_slices(h, h->T, R, h->Nt));
   if (rnorm != nullptr) {
     HIPCHK(h, hipMemcpyAsync(h->h_red, h->red_out, 4 * sizeof(double),

@@ -220,6 +220,190 @@ __global__ void __launch_bounds__(KRY_THREADS)
   }
 }
 
+// ---- Arnoldi with delayed reorthogonalisation (one reduction per step) --
+// One pass over the basis V_0..V_{nv-1}, the pending vector u and (unless
+// null) w = op(u): block partials of
+//   rows i < nv: <V_i, u>;   rows nv + i: <V_i, w>;
+//   row 2nv: <u, u>;  row 2nv + 1: <u, w>;  row 2nv + 2: <w, w>
+// and, when w is null, rows i < nv: <V_i, u>, row nv: <u, u>.  The basis
+// goes in groups of KDOT2_GROUP vectors (all their loads in flight before
+// the first product, one block reduction per group); the group after the
+// last basis vector carries the products of u and w.
+constexpr int KDOT2_GROUP = 4;
+
+__global__ void __launch_bounds__(KRY_THREADS)
+    kdot2_kernel(const cx<double>* __restrict__ V, long vstride, int nv,
+                 const cx<double>* __restrict__ u,
+                 const cx<double>* __restrict__ w, long n, long Nk, int nh,
+                 double* __restrict__ part, int ld) {
+  constexpr int NW = KRY_THREADS / 64;
+  constexpr int G = KDOT2_GROUP;
+  constexpr int NV = 2 * G + 1;  // values reduced per group
+  __shared__ double red[NW * NV];
+  const long base = static_cast<long>(blockIdx.x) * KRY_PER_BLOCK;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const bool hw = w != nullptr;
+  cx<double> uv[KRY_PER_THREAD], wv[KRY_PER_THREAD];
+  double pw[KRY_PER_THREAD];
+#pragma unroll
+  for (int q = 0; q < KRY_PER_THREAD; ++q) {
+    const long e = base + threadIdx.x + q * KRY_THREADS;
+    const bool ok = e < n;
+    uv[q] = ok ? u[e] : mk(0.0, 0.0);
+    wv[q] = (ok && hw) ? w[e] : mk(0.0, 0.0);
+    pw[q] = ok ? half_weight(e, Nk, nh) : 0.0;
+  }
+  // slot i < nv: basis vector i; slot nv: the products of u and w
+  for (int i0 = 0; i0 <= nv; i0 += G) {
+    cx<double> x[G][KRY_PER_THREAD];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int i = i0 + g;
+#pragma unroll
+      for (int q = 0; q < KRY_PER_THREAD; ++q) {
+        const long e = base + threadIdx.x + q * KRY_THREADS;
+        x[g][q] = mk(0.0, 0.0);
+        if (i < nv && e < n) x[g][q] = V[i * vstride + e];
+      }
+    }
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int i = i0 + g;
+      if (i < nv) {
+#pragma unroll
+        for (int q = 0; q < KRY_PER_THREAD; ++q) {
+          acc[2 * g] += pw[q] * (x[g][q].x * uv[q].x + x[g][q].y * uv[q].y);
+          acc[2 * g + 1] +=
+              pw[q] * (x[g][q].x * wv[q].x + x[g][q].y * wv[q].y);
+        }
+      } else if (i == nv) {
+#pragma unroll
+        for (int q = 0; q < KRY_PER_THREAD; ++q) {
+          acc[2 * g] += pw[q] * norm2(uv[q]);
+          acc[2 * g + 1] += pw[q] * (uv[q].x * wv[q].x + uv[q].y * wv[q].y);
+          acc[2 * G] += pw[q] * norm2(wv[q]);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1)
+        acc[k] += __shfl_down(acc[k], off, 64);
+    }
+    __syncthreads();  // the previous group's sums have been read
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) red[wid * NV + k] = acc[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      auto sum = [&](int k) {
+        double s = 0.0;
+        for (int q = 0; q < NW; ++q) s += red[q * NV + k];
+        return s;
+      };
+      const long b = blockIdx.x;
+      for (int g = 0; g < G; ++g) {
+        const int i = i0 + g;
+        if (i < nv) {
+          part[static_cast<long>(i) * ld + b] = sum(2 * g);
+          if (hw) part[static_cast<long>(nv + i) * ld + b] = sum(2 * g + 1);
+        } else if (i == nv) {
+          if (hw) {
+            part[static_cast<long>(2 * nv) * ld + b] = sum(2 * g);
+            part[static_cast<long>(2 * nv + 1) * ld + b] = sum(2 * g + 1);
+            part[static_cast<long>(2 * nv + 2) * ld + b] = sum(2 * G);
+          } else {
+            part[static_cast<long>(nv) * ld + b] = sum(2 * g);
+          }
+        }
+      }
+    }
+  }
+}
+
+// The fused update of an Arnoldi step with delayed reorthogonalisation,
+// u = V_j (pending), w = V_{j+1} (= op u):
+//   q_j = (u - sum_{i<j} a_i V_i) / beta,
+//   u'  = w / beta - sum_{i<j} z_i V_i - z_j q_j,
+// q_j overwrites V_j and u' overwrites V_{j+1}.  cf = [a_0..a_{j-1},
+// z_0..z_j, 1/beta] (device, 2j + 2 values, j <= 63).  Per element the
+// terms are added in the order i = 0, 1, ...; two basis vectors' loads
+// are in flight at once, each feeding both sums.
+__global__ void __launch_bounds__(KRY_THREADS)
+    kdcgs_update_kernel(cx<double>* __restrict__ V, long vstride, int j,
+                        const double* __restrict__ coef, long n) {
+  __shared__ double cf[2 * 64 + 2];
+  if (threadIdx.x < 2 * j + 2) cf[threadIdx.x] = coef[threadIdx.x];
+  __syncthreads();
+  const double* ca = cf;
+  const double* cz = cf + j;
+  const double ib = cf[2 * j + 1];
+  const long base = static_cast<long>(blockIdx.x) * KRY_PER_BLOCK;
+  cx<double> uq[KRY_PER_THREAD], wn[KRY_PER_THREAD];
+#pragma unroll
+  for (int q = 0; q < KRY_PER_THREAD; ++q) {
+    const long e = base + threadIdx.x + q * KRY_THREADS;
+    uq[q] = mk(0.0, 0.0);
+    wn[q] = mk(0.0, 0.0);
+    if (e < n) {
+      uq[q] = V[j * vstride + e];
+      wn[q] = V[(j + 1) * vstride + e];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < KRY_PER_THREAD; ++q) wn[q] = wn[q] * ib;
+  int i = 0;
+  for (; i + 1 < j; i += 2) {
+    cx<double> y0[KRY_PER_THREAD], y1[KRY_PER_THREAD];
+#pragma unroll
+    for (int q = 0; q < KRY_PER_THREAD; ++q) {
+      const long e = base + threadIdx.x + q * KRY_THREADS;
+      y0[q] = mk(0.0, 0.0);
+      y1[q] = mk(0.0, 0.0);
+      if (e < n) {
+        y0[q] = V[i * vstride + e];
+        y1[q] = V[(i + 1) * vstride + e];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < KRY_PER_THREAD; ++q) {
+      uq[q] = uq[q] - y0[q] * ca[i];
+      uq[q] = uq[q] - y1[q] * ca[i + 1];
+      wn[q] = wn[q] - y0[q] * cz[i];
+      wn[q] = wn[q] - y1[q] * cz[i + 1];
+    }
+  }
+  if (i < j) {
+    cx<double> y0[KRY_PER_THREAD];
+#pragma unroll
+    for (int q = 0; q < KRY_PER_THREAD; ++q) {
+      const long e = base + threadIdx.x + q * KRY_THREADS;
+      y0[q] = mk(0.0, 0.0);
+      if (e < n) y0[q] = V[i * vstride + e];
+    }
+#pragma unroll
+    for (int q = 0; q < KRY_PER_THREAD; ++q) {
+      uq[q] = uq[q] - y0[q] * ca[i];
+      wn[q] = wn[q] - y0[q] * cz[i];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < KRY_PER_THREAD; ++q) {
+    const long e = base + threadIdx.x + q * KRY_THREADS;
+    const cx<double> qj = uq[q] * ib;
+    const cx<double> un = wn[q] - qj * cz[j];
+    if (e < n) {
+      V[j * vstride + e] = qj;
+      V[(j + 1) * vstride + e] = un;
+    }
+  }
+}
+
 // out = in * s (out may equal in)
 __global__ void __launch_bounds__(KRY_THREADS)
     kscale_kernel(cx<double>* out, const cx<double>* in, double s, long n) {

@@ -34,6 +34,7 @@ enum PassBMode : int {
   PB_PRECOND = 1,   // Sout = Q_alpha^{-1} Rin
   PB_RESIDUAL = 2,  // Sout = R(U)
   PB_OPAPPLY = 3,   // Sout = Q_alpha^{-1} (Q - G'(U)) v, v in U, J in Nh
+  PB_PRECRES = 4,   // Sout = Q_alpha^{-1} R(U), norms of R and of Sout
 };
 
 struct PassBArgs {
@@ -52,7 +53,7 @@ struct PassBArgs {
   const double* igam;     // [Nt]
   const cx<double>* lam;  // [Nt]
   const cx<double>* Rin;  // [Nt][Nk] (PB_PRECOND)
-  cx<double>* Sout;       // [Nt][Nk] (PB_PRECOND / PB_RESIDUAL / PB_OPAPPLY)
+  cx<double>* Sout;       // [Nt][Nk] (every mode but PB_ITERATE)
   double* partials;       // [nblocks][4]
   Ctl* ctl;               // iterate mode: convergence state (else null)
   Ctl* hmirror;           // host-mapped copy of *ctl (nullable)
@@ -224,7 +225,7 @@ __device__ __forceinline__ cx<double> smul(cx<double> a, cx<double> s) {
 
 // Uin / Uout: the iterate read and written in PB_ITERATE (fp32 or fp64;
 // the arithmetic is fp64), the Krylov vector read in PB_OPAPPLY / the
-// state in PB_RESIDUAL (fp64); unused in PB_PRECOND.
+// state in PB_RESIDUAL and PB_PRECRES (fp64); unused in PB_PRECOND.
 template <int NT, int MODE, typename TN, bool CPLX, typename TUI = double,
           typename TUO = double>
 __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,

@@ -2,7 +2,8 @@
 
 Results are compared, not iteration counts, except where a theorem fixes
 the count (finite termination) or bounds it; GPU Arnoldi uses classical
-Gram-Schmidt twice (CGS2), the oracle modified Gram-Schmidt.
+Gram-Schmidt with delayed reorthogonalisation (DCGS2, one reduction per
+step), the oracle modified Gram-Schmidt.
 """
 import numpy as np
 import pytest
