@@ -60,6 +60,62 @@ def test_graph_replay_equals_plain_launches():
         assert np.array_equal(U, outs[0][1])
 
 
+def test_scheduled_batch_solves_equal_solo():
+    """A batch solved a second time runs a schedule predicted from the first
+    solve's counts (launches over just the instances predicted to run); a
+    third solve from other initial values (so the predictions fall short
+    for some instances and over-reach for others) pauses and completes
+    them: every solve equals the solo solves bit for bit."""
+    from paper_2603_04350_amd import Batch, Solver
+    insts = _mix(16, seed=5)
+    solvers = [Solver.from_instance(i) for i in insts]
+    rng = np.random.default_rng(11)
+    u0_sets = [[i.u0 for i in insts], [i.u0 for i in insts],
+               [rng.uniform(-0.9, 0.9, i.u0.shape) * (0.3 + 0.7 * (k % 2))
+                for k, i in enumerate(insts)]]
+    b = Batch(solvers)
+    for u0s_np in u0_sets:
+        solo = []
+        for s, inst, u0 in zip(solvers, insts, u0s_np):
+            U = _zeros(inst)
+            rc, it, rel = s.iterate(_dev(u0), U, max_iter=300, tol=1e-12)
+            solo.append((it, U.cpu().numpy()))
+        Us = [_zeros(i) for i in insts]
+        rc, its, rels, sts = b.iterate([_dev(u) for u in u0s_np], Us,
+                                       max_iter=300, tol=1e-12)
+        for k in range(len(insts)):
+            assert its[k] == solo[k][0], (k, its[k], solo[k][0])
+            assert np.array_equal(Us[k].cpu().numpy(), solo[k][1]), k
+    b.close()
+    for s in solvers:
+        s.close()
+
+
+def test_batch_caps_schedule_equals_solo():
+    """Per-instance caps with tolerance 0 fix every count ahead: the
+    scheduled solve stops each instance at its cap, as solo solves do."""
+    from paper_2603_04350_amd import Batch, Solver
+    insts = _mix(10, seed=6)
+    solvers = [Solver.from_instance(i) for i in insts]
+    caps = [1 + (7 * k) % 23 for k in range(len(insts))]
+    solo = []
+    for s, inst, cap in zip(solvers, insts, caps):
+        U = _zeros(inst)
+        rc, it, rel = s.iterate(_dev(inst.u0), U, max_iter=cap, tol=0.0)
+        assert it == cap
+        solo.append(U.cpu().numpy())
+    b = Batch(solvers)
+    Us = [_zeros(i) for i in insts]
+    rc, its, rels, sts = b.iterate_each([_dev(i.u0) for i in insts], Us,
+                                        caps, [0.0] * len(insts))
+    b.close()
+    assert list(its) == caps
+    for k in range(len(insts)):
+        assert np.array_equal(Us[k].cpu().numpy(), solo[k]), k
+    for s in solvers:
+        s.close()
+
+
 def test_batch_equals_solo_and_oracle():
     from paper_2603_04350_amd import Batch, Solver
     insts = _mix(12)
