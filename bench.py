@@ -1337,25 +1337,39 @@ KERNEL_CLASSES = (("col_kernel_host", "col_fft"), ("col_kernel_mp", "col_fft"),
                   ("ctl_reduce", "reduce"))
 
 
-def _pmc_rows(d, counter):
+def _pmc_rows(d, counter, last_run=False):
     """(kernel name, value) per dispatch of `counter` from a rocprofv3
-    --pmc csv output directory."""
+    --pmc csv output directory, in dispatch order.  last_run: only the
+    dispatches from the last run of consecutive output-zeroing fills on
+    (a profiler mode zeroes its outputs before every solve, so these are
+    the last solve's launches)."""
     rows = []
     for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"),
                           recursive=True):
         with open(path, newline="") as f:
             for r in csv.DictReader(f):
                 if r.get("Counter_Name") == counter:
-                    rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
-    return rows
+                    rows.append((int(r.get("Dispatch_Id") or 0),
+                                 r["Kernel_Name"], float(r["Counter_Value"])))
+    rows.sort(key=lambda x: x[0])
+    if last_run:
+        fills = [i for i, (_, k, _) in enumerate(rows) if "FillFunctor" in k]
+        start = 0
+        for j in range(len(fills) - 1, -1, -1):
+            start = fills[j]
+            if j == 0 or fills[j - 1] != fills[j] - 1:
+                break
+        rows = rows[start:]
+    return [(k, v) for _, k, v in rows]
 
 
 def traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, workload,
-            mib=512, path=None):
+            mib=512, path=None, last_run=False):
     """HBM bytes per launch from two rocprofv3 counter runs (FETCH_SIZE,
-    WRITE_SIZE, KiB per dispatch) of the `workload` profile run, each scaled
-    by what the same counter reads for the calibration copy; merged into
-    profiles/traffic.json under `workload` with the device-source hash, and
+    WRITE_SIZE, KiB per dispatch) of the `workload` profile run (last_run:
+    its last solve only), each scaled by what the same counter reads for the
+    calibration copy; merged into profiles/traffic.json under `workload`
+    with the hash of the device sources its kernels are built from, and
     printed per kernel."""
     copy_kib = mib * 1024.0
 
@@ -1369,7 +1383,7 @@ def traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, workload,
     per = {}
     for counter, d, fac, key in (("FETCH_SIZE", fetch_dir, ff, "read"),
                                  ("WRITE_SIZE", write_dir, fw, "write")):
-        for k, v in _pmc_rows(d, counter):
+        for k, v in _pmc_rows(d, counter, last_run):
             e = per.setdefault(k, {"read": [], "write": []})
             e[key].append(v * 1024.0 * fac)
     kernels = {}
@@ -1448,6 +1462,9 @@ def main():
     ap.add_argument("--profile-variants", action="store_true",
                     help="both time transforms per Nt only, for profiler "
                          "runs")
+    ap.add_argument("--traffic-last-run", action="store_true",
+                    help="with --traffic: count only the profiled run's last "
+                         "solve (after its last zeroing of the outputs)")
     ap.add_argument("--tune-file", default=None,
                     help="the batch's tuning decisions: read from this JSON "
                          "file where it holds them, measured and written "
@@ -1463,7 +1480,7 @@ def main():
                          "into profiles/traffic.json (no GPU)")
     args = ap.parse_args()
     if args.traffic:
-        traffic(*args.traffic)
+        traffic(*args.traffic, last_run=args.traffic_last_run)
         return
     if args.quick:
         args.no_serve = args.no_cpu_baseline = args.no_extra = True

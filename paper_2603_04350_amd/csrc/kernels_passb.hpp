@@ -427,9 +427,12 @@ __global__ void __launch_bounds__(PassBShape<NT>::THREADS,
                 "reduction scratch fits the tile");
   __shared__ cx<double> lds[SH::LDS];
   double* red = reinterpret_cast<double*>(lds);
-  const int j = find_job(start, njobs);
+  // XCD-contiguous tiles: a tile's fp32 rows can be half a 128-byte line
+  // (C = 8 columns at Nt = 128), whose other half the next tile reads
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  const int j = find_job(start, njobs, b);
   const PassBArgs a = jobs[j];  // by value: the kernel stores through a.U
-  const long lb = blockIdx.x - start[j];
+  const long lb = b - start[j];
   if constexpr (MODE == PB_ITERATE) {
     const int ph = job_phase(a.ctl);
     if (ph < 0) return;
@@ -573,8 +576,9 @@ __global__ void __launch_bounds__(PassBShape<NT>::THREADS,
   using SH = PassBShape<NT>;
   __shared__ cx<double> lds[SH::LDS];
   double* red = reinterpret_cast<double*>(lds);
-  passb_body<NT, MODE, TN, CPLX>(a, blockIdx.x, static_cast<const TN*>(a.Nh),
-                                 a.U, a.U, lds, red);
+  passb_body<NT, MODE, TN, CPLX>(a, xcd_block(blockIdx.x, gridDim.x),
+                                 static_cast<const TN*>(a.Nh), a.U, a.U, lds,
+                                 red);
 }
 
 // Fixed-order final reduction of per-block partials for the non-iterate
