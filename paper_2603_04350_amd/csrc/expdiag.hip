@@ -72,6 +72,15 @@ bool kind_cols(int k) {
 }
 
 // One launch of a plan: jobs of the same kernel signature.
+// Algorithmic bytes of one job of an iteration launch in each precision
+// phase (PH_BULK, PH_SWITCH, PH_FP64) of its instance, and the instance's
+// host mirror (profiling resolves a launch's bytes from the phases its
+// instances were in, once the solve has ended).
+struct JobBytes {
+  const Ctl* hm;
+  double b[3];
+};
+
 struct Group {
   int stage, kind, tcode, len, mode, ti, to;  // signature
   int wide = 0;  // column stages: 1 = the 2C-column workgroup variant
@@ -84,6 +93,8 @@ struct Group {
   // ctl_reduce launch right after)
   std::vector<PassBArgs> red;
   double bytes = 0;        // algorithmic bytes of one full launch
+  // per job, when built for an instance with a host mirror (profiling)
+  std::vector<JobBytes> jb;
   void* djobs = nullptr;
   int* dstart = nullptr;
   void* dred = nullptr;
@@ -97,6 +108,9 @@ struct Group {
 struct Plan {
   std::vector<Group> groups;
   bool uploaded = false;
+  // host mirror of the instance whose launches are being added (set by
+  // plan_iteration while it builds; null: no per-phase bytes)
+  const Ctl* cur_hm = nullptr;
   // one device arena (and pinned staging) for every group's job table,
   // grown on demand and reused across rebuilds
   char* arena = nullptr;
@@ -184,6 +198,14 @@ struct expdiag_ctx {
   double prof_ms[NPROF] = {0, 0, 0, 0, 0};
   long prof_cnt[NPROF] = {0, 0, 0, 0, 0};
   double prof_bytes[NPROF] = {0, 0, 0, 0, 0};
+  // iteration launches of the solve being profiled: their index (1-based)
+  // and the per-phase bytes of their jobs, resolved at the solve's end
+  struct PendingBytes {
+    int cls, k;
+    std::vector<JobBytes> jobs;
+  };
+  int prof_iter = 0;
+  std::vector<PendingBytes> prof_pending;
 
   std::string err;
   size_t bytes = 0;
@@ -284,6 +306,50 @@ void klaunch(const ProfScope& ps, void (*kernel)(KArgs...), dim3 grid,
                           args...);
   else
     hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+}
+
+Ctl read_mirror(const Ctl* p);
+
+// Bytes a profiled launch of group g adds now: its static bytes, or, for
+// an iteration launch built with per-phase bytes, none yet (recorded with
+// the launch's iteration index and resolved by prof_resolve).
+double prof_group_bytes(expdiag_ctx* ph, const Group& g, int cls) {
+  if (ph == nullptr || !ph->prof || g.jb.empty()) return g.bytes;
+  ph->prof_pending.push_back({cls, ph->prof_iter, g.jb});
+  return 0.0;
+}
+
+// Start of a profiled solve: iteration launches count from 1 again.
+void prof_begin(expdiag_ctx* ph) {
+  if (ph == nullptr) return;
+  ph->prof_iter = 0;
+  ph->prof_pending.clear();
+}
+
+// End of a profiled solve (stream synchronised, mirrors final): each
+// recorded iteration launch k adds, per job, the bytes of the phase its
+// instance was in at its k-th iteration (bulk through its switch_iter-th
+// iteration, the switch iteration next, fp64 after), nothing once the
+// instance had finished.  Exact when every instance launched runs from the
+// solve's first iteration on (fixed-count solves, compaction of finished
+// instances); an instance a batch schedule paused is counted as if it had
+// run.
+void prof_resolve(expdiag_ctx* ph) {
+  if (ph == nullptr) return;
+  for (const auto& r : ph->prof_pending) {
+    double b = 0;
+    for (const auto& j : r.jobs) {
+      const Ctl c = read_mirror(j.hm);
+      if (r.k > c.iters) continue;
+      const int s = c.switch_iter;
+      const int phase = (s == 0 || r.k <= s) ? PH_BULK
+                        : (r.k == s + 1)    ? PH_SWITCH
+                                            : PH_FP64;
+      b += j.b[phase];
+    }
+    ph->prof_bytes[r.cls] += b;
+  }
+  ph->prof_pending.clear();
 }
 
 template <typename T>
@@ -853,6 +919,26 @@ void plan_passb(Plan& P, int stage, int len, int rows, const PassBArgs& a,
   if (reduce_after) g.red.push_back(a);
   g.start.push_back(g.start.back() + a.nblocks);
   g.bytes += passb_bytes(a, rows, PB_ITERATE, nb);
+  if (P.cur_hm != nullptr) {
+    // per entry: U read and written, N^ read (fp32 in the bulk phase; the
+    // fp32 iterate in the bulk phase and read by the switch iteration)
+    const double base = static_cast<double>(a.Nk) * (sizeof(double) * 3 + 16);
+    const double ent = static_cast<double>(rows) * a.Nk;
+    JobBytes j{P.cur_hm, {0, 0, 0}};
+    if (!a.nonlinear) {
+      j.b[0] = j.b[1] = j.b[2] = base + ent * 32;
+    } else if (a.Nh32 == nullptr) {
+      j.b[0] = j.b[1] = j.b[2] = base + ent * 48;
+    } else if (a.U32 != nullptr) {
+      j.b[0] = base + ent * 24;
+      j.b[1] = base + ent * 40;
+      j.b[2] = base + ent * 48;
+    } else {
+      j.b[0] = base + ent * 40;
+      j.b[1] = j.b[2] = base + ent * 48;
+    }
+    g.jb.push_back(j);
+  }
 }
 
 // pass A of one instance in precision T, gated on phase `ph`
@@ -920,11 +1006,14 @@ bool plan_pass_a_mp(Plan& P, expdiag_ctx* h, const Ctl* ctl,
     g.rj.push_back(mx ? j32 : j64);
     g.rj.push_back(j64);
     g.start.push_back(g.start.back() + row_blocks(M, j64.nrows));
-    g.bytes += mx ? row_bytes(M, ROW_FUSED, j32.nrows,
-                              ti32 == 0 ? sizeof(double) : sizeof(float),
-                              sizeof(float))
-                  : row_bytes(M, ROW_FUSED, j64.nrows, sizeof(double),
-                              sizeof(double));
+    const double b64 =
+        row_bytes(M, ROW_FUSED, j64.nrows, sizeof(double), sizeof(double));
+    const double b32 = row_bytes(
+        M, ROW_FUSED, j32.nrows, ti32 == 0 ? sizeof(double) : sizeof(float),
+        sizeof(float));
+    g.bytes += mx ? b32 : b64;
+    if (P.cur_hm != nullptr)
+      g.jb.push_back({P.cur_hm, {mx ? b32 : b64, b64, b64}});
   };
   const int wd = h->col_wide;
   auto col2 = [&](int stage, int L, int S, const ColJob& j32,
@@ -935,9 +1024,15 @@ bool plan_pass_a_mp(Plan& P, expdiag_ctx* h, const Ctl* ctl,
     g.start.push_back(g.start.back() +
                       col_blocks(L, j64.outer, j64.inner, wd));
     const double ent = static_cast<double>(j64.outer) * L * j64.inner * 2;
-    g.bytes += mx ? ent * ((ti32 == 0 ? sizeof(double) : sizeof(float)) +
-                           sizeof(float))
-                  : ent * 2 * sizeof(double);
+    const double b64 = ent * 2 * sizeof(double);
+    const double b32 =
+        ent * ((ti32 == 0 ? sizeof(double) : sizeof(float)) + sizeof(float));
+    // the switch iteration's first stage reads the fp32 iterate
+    const double bsw =
+        j64.in32 != nullptr ? ent * (sizeof(float) + sizeof(double)) : b64;
+    g.bytes += mx ? b32 : b64;
+    if (P.cur_hm != nullptr)
+      g.jb.push_back({P.cur_hm, {mx ? b32 : b64, mx ? bsw : b64, b64}});
   };
   if (d == 1) {
     row2(2, make_row(h, h->Uh, N32, ns, nh2, nh2, sc, ctl, -1),
@@ -953,7 +1048,10 @@ bool plan_pass_a_mp(Plan& P, expdiag_ctx* h, const Ctl* ctl,
     g.cj.push_back(j);
     g.red.push_back(red);
     g.start.push_back(g.start.back() + col_blocks(n0, ns, in2, wd));
-    g.bytes += static_cast<double>(ns) * n0 * in2 * 2 * 2 * sizeof(double);
+    const double b64 =
+        static_cast<double>(ns) * n0 * in2 * 2 * 2 * sizeof(double);
+    g.bytes += b64;
+    if (P.cur_hm != nullptr) g.jb.push_back({P.cur_hm, {b64, b64, b64}});
   } else if (bulk_u32(h)) {
     // the bulk phase reads its fp32 iterate, and so does the fp64 job of
     // the switch iteration
@@ -995,7 +1093,8 @@ bool plan_pass_a_mp(Plan& P, expdiag_ctx* h, const Ctl* ctl,
 // iteration).  The choice depends on the instance only, so a batched
 // instance runs the same kernels on the same data as it does alone.
 void plan_iteration(Plan& P, expdiag_ctx* h, Ctl* ctl, Ctl* mirror,
-                    double* hist) {
+                    double* hist, const Ctl* host_mirror = nullptr) {
+  P.cur_hm = host_mirror;
   PassBArgs a = passb_args(h);
   a.ctl = ctl;
   a.hmirror = mirror;
@@ -1017,6 +1116,7 @@ void plan_iteration(Plan& P, expdiag_ctx* h, Ctl* ctl, Ctl* mirror,
     variant = 4;
   const int len = variant == 3 || variant > 30 ? time_len(h) : h->Nt;
   plan_passb(P, 5, len, h->Nt, a, sizeof(cx<double>), variant, !hosted);
+  P.cur_hm = nullptr;
 }
 
 // Algorithmic bytes of one iteration of a plan.
@@ -1125,13 +1225,14 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st,
                 const cx<double>* tw64, const cx<float>* tw32) {
   // a plan whose job tables are not on the device is never launched
   if (!P.uploaded) return fail(ph, EXPDIAG_EHIP, "plan not uploaded");
+  if (ph != nullptr && ph->prof) ++ph->prof_iter;
   for (auto& g : P.groups) {
     const int grid = g.grid();
     if (grid == 0) continue;
     const int nj = g.njobs();
     bool ok = false;
     if (g.kind == K_ROW) {
-      ProfScope ps(ph, P_ROW, g.bytes, true);
+      ProfScope ps(ph, P_ROW, prof_group_bytes(ph, g, P_ROW), true);
       const RowJob* J = static_cast<const RowJob*>(g.djobs);
       ok = dispatch_pow2<2, 512>(g.len, [&](auto Mc) {
         constexpr int MM = decltype(Mc)::value;
@@ -1144,7 +1245,7 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st,
                   J, g.dstart, nj, tw32, tw64);
       });
     } else if (g.kind == K_COL && g.tcode == 3) {
-      ProfScope ps(ph, P_COL, g.bytes, true);
+      ProfScope ps(ph, P_COL, prof_group_bytes(ph, g, P_COL), true);
       const ColJob* J = static_cast<const ColJob*>(g.djobs);
       const PassBArgs* RJ = static_cast<const PassBArgs*>(g.dred);
       const int nred = static_cast<int>(g.red.size());
@@ -1160,7 +1261,7 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st,
                   tw64);
       });
     } else if (g.kind == K_COL) {
-      ProfScope ps(ph, P_COL, g.bytes, true);
+      ProfScope ps(ph, P_COL, prof_group_bytes(ph, g, P_COL), true);
       const ColJob* J = static_cast<const ColJob*>(g.djobs);
       auto run = [&](auto Lc, auto Wc) {
         constexpr int LL = decltype(Lc)::value;
@@ -1187,7 +1288,7 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st,
     } else {
       const PassBArgs* J = static_cast<const PassBArgs*>(g.djobs);
       {
-        ProfScope ps(ph, P_PASSB, g.bytes, true);
+        ProfScope ps(ph, P_PASSB, prof_group_bytes(ph, g, P_PASSB), true);
         if (g.tcode == 1) {
           ok = dispatch_pow2<DENSE_NT_MIN, DENSE_NT_MAX>(g.len, [&](auto Nc) {
             constexpr int NN = decltype(Nc)::value;
@@ -2227,7 +2328,7 @@ int create_impl(const expdiag_grid* g, int Nt, double dt, double alpha,
     h->light = true;
   }
   if (rc == 0 && !light) {
-    plan_iteration(h->plan, h, h->ctl, h->d_mirror, h->hist);
+    plan_iteration(h->plan, h, h->ctl, h->d_mirror, h->hist, h->h_mirror);
     rc = plan_upload(h, h->plan, h->cap_stream);
     if (rc == 0 && hipStreamSynchronize(h->cap_stream) != hipSuccess)
       rc = fail(h, EXPDIAG_EHIP, "plan upload");
@@ -2409,6 +2510,7 @@ int expdiag_iterate(expdiag_t h, const double* u0, double* U, int max_iter,
   RCHK(prepare_u0(h, u0));
   RCHK(fwd_slices<ROW_R2C>(h, U, h->Uh, h->Nt));
   RCHK(enter_bulk_state(h, h->stream));
+  prof_begin(h);
   *h->h_ctl = initial_ctl(h, max_iter, tol);
   *h->h_mirror = *h->h_ctl;
   hipLaunchKernelGGL(ctl_set_kernel, dim3(1), dim3(64), 0, h->stream, h->ctl,
@@ -2475,6 +2577,7 @@ int expdiag_iterate(expdiag_t h, const double* u0, double* U, int max_iter,
     RCHK(inv_slices(h, h->Uh, U, h->Nt));
   }
   HIPCHK(h, hipStreamSynchronize(h->stream));
+  prof_resolve(h);
   const Ctl c = read_mirror(h->h_mirror);
   h->last_iters = c.iters;
   if (iters != nullptr) *iters = c.iters;

@@ -38,7 +38,8 @@ struct Ctl {
   int iters;     // iterations completed
   int max_iter;
   int pending;   // 1: pass B wrote block partials not yet reduced
-  int spare;
+  int switch_iter;  // mixed: the iteration after which the bulk phase
+                    // ended (0 while it has not)
   double tol;       // ||S|| / ||U|| target
   double bulk_tol;  // switch from phase 0 to 1 below this
   double last_rel;

@@ -164,7 +164,10 @@ __device__ inline void advance_ctl(const PassBArgs& a, const double* tot) {
   if (!(rel == rel) || !(rn == rn) || rel > 1e300) {
     done = 2;
   } else if (c->phase == PH_BULK) {
-    if (rel <= c->bulk_tol) c->phase = PH_SWITCH;
+    if (rel <= c->bulk_tol) {
+      c->phase = PH_SWITCH;
+      c->switch_iter = it;
+    }
     if (it >= c->max_iter) done = 1;
   } else if (c->phase == PH_SWITCH) {
     // the first fp64 iteration (it has written the fp64 iterate)
@@ -181,6 +184,7 @@ __device__ inline void advance_ctl(const PassBArgs& a, const double* tot) {
     volatile Ctl* m = a.hmirror;
     m->iters = it;
     m->phase = c->phase;
+    m->switch_iter = c->switch_iter;
     m->last_rel = rel;
     m->last_rnorm = rn;
     m->last_unorm = un;
