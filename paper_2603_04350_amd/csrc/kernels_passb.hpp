@@ -109,22 +109,49 @@ struct PassBShape {
 };
 
 // Sum NV doubles over the block; thread 0 writes them to out[0..NV).
+// Sum four doubles over a wavefront.  The first two exchanges halve the
+// values a lane carries (across 32 lanes a lane keeps values {0, 1} or
+// {2, 3} and adds its partner's copies of them; across 16 it keeps one of
+// the two), the last four sum that one value within each group of 16
+// lanes: 7 exchanges of a double instead of 24.  Afterwards every lane of
+// group g = lane / 16 holds the wavefront's total of value g.
+__device__ __forceinline__ double wave_sum4(const double (&a)[4]) {
+  const int lane = threadIdx.x & 63;
+  const bool h32 = (lane & 32) != 0, h16 = (lane & 16) != 0;
+  double k0 = h32 ? a[2] : a[0], k1 = h32 ? a[3] : a[1];
+  const double s0 = h32 ? a[0] : a[2], s1 = h32 ? a[1] : a[3];
+  k0 += __shfl_xor(s0, 32, 64);
+  k1 += __shfl_xor(s1, 32, 64);
+  double k = h16 ? k1 : k0;
+  k += __shfl_xor(h16 ? k0 : k1, 16, 64);
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) k += __shfl_xor(k, off, 64);
+  return k;
+}
+
 template <int NV, int THREADS>
 __device__ __forceinline__ void block_sum(double (&acc)[NV], double* red,
                                           double* out) {
-#pragma unroll
-  for (int j = 0; j < NV; ++j) {
-    double a = acc[j];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
-    acc[j] = a;
-  }
   constexpr int NW = (THREADS + 63) / 64;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) {
+  if constexpr (NV == 4) {
+    static_assert(THREADS % 64 == 0, "whole wavefronts");
+    const double k = wave_sum4(acc);
+    __syncthreads();
+    if ((lane & 15) == 0) red[wid * NV + (lane >> 4)] = k;
+  } else {
 #pragma unroll
-    for (int j = 0; j < NV; ++j) red[wid * NV + j] = acc[j];
+    for (int j = 0; j < NV; ++j) {
+      double a = acc[j];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+      acc[j] = a;
+    }
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < NV; ++j) red[wid * NV + j] = acc[j];
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -253,9 +280,15 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
   const double pw = (!valid) ? 0.0 : ((kl == 0 || kl == a.nh - 1) ? 1.0 : 2.0);
   const cx<double> zero = mk(0.0, 0.0);
 
-  // loads: data rows first, then the per-kappa and per-row tables
+  // loads: data rows first, then the per-kappa and per-row tables.  An
+  // fp32 iterate (the bulk phase) reads row l-1 of its own tile directly
+  // (the block loads those lines anyway, so they come from the caches) in
+  // place of the LDS exchange the fp64 variants make, which saves a trip
+  // through LDS and a barrier where pass B is bound by its LDS traffic.
+  constexpr bool GPREV = std::is_same<TUI, float>::value;
   cx<double> u[R];
   cx<TUI> uin[R];
+  cx<TUI> upin[GPREV ? R : 1];
   cx<TN> nr[R];
   const cx<TN>* Nc = reinterpret_cast<const cx<TN>*>(Nh);
   const bool nl = MODE != PB_PRECOND && a.nonlinear;
@@ -267,6 +300,13 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
       u[s] = gld(a.Rin, l * Nk + kc);
     else
       uin[s] = gld(Uin, l * Nk + kc);
+  }
+  if constexpr (GPREV && MODE != PB_PRECOND) {
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      const int l = t + s * TPL;
+      upin[s] = gld(Uin, (l > 0 ? l - 1 : 0) * Nk + kc);
+    }
   }
   if (nl) {
 #pragma unroll
@@ -308,13 +348,17 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
 #pragma unroll
     for (int s = 0; s < R; ++s) {
       u[s] = valid ? cvt<double>(uin[s]) : zero;
-      lds[(t + s * TPL) * LS + c] = u[s];
+      if constexpr (!GPREV) lds[(t + s * TPL) * LS + c] = u[s];
     }
-    __syncthreads();
+    if constexpr (!GPREV) __syncthreads();
 #pragma unroll
     for (int s = 0; s < R; ++s) {
       const int l = t + s * TPL;
-      const cx<double> prev = (l == 0) ? first : lds[(l - 1) * LS + c];
+      cx<double> prev;
+      if constexpr (GPREV)
+        prev = (l == 0) ? first : (valid ? cvt<double>(upin[s]) : zero);
+      else
+        prev = (l == 0) ? first : lds[(l - 1) * LS + c];
       cx<double> n_cur = zero;
       if (nl && valid && (MODE != PB_OPAPPLY || l >= 1 || a.same_slice))
         n_cur = cvt<double>(nr[s]);
@@ -359,7 +403,9 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
       block_sum<4, SH::THREADS>(acc, red, a.partials + lb * 4);
       return;
     }
-    __syncthreads();
+    // the transform's first exchange may overwrite rows still being read
+    // (uniform condition: a barrier only where the residual used LDS)
+    if (!GPREV || two) __syncthreads();
   }
 
   // step (a): forward time transform with the + sign
