@@ -1958,7 +1958,7 @@ size_t footprint(const Sizes& s, int dim, int Nt, bool nonlinear,
     b += static_cast<size_t>(restart + 1) * st;       // Krylov basis
     b += static_cast<size_t>((static_cast<long>(Nt) * s.Nk + KRY_PER_BLOCK -
                               1) / KRY_PER_BLOCK) *
-         (2 * restart + 3) * sizeof(double);  // block partials
+         (4 * restart + 4) * sizeof(double);  // block partials
     if (nonlinear)
       b += static_cast<size_t>(Nt) * s.Ns * (sizeof(double) + sizeof(float));
   }
@@ -2271,9 +2271,12 @@ int setup_handle(expdiag_ctx* h, const expdiag_grid* g, int Nt, double dt,
     h->kpart_blocks = static_cast<int>(krylov_blocks(Nt * h->Nk));
     // rows of block partials: up to 2 restart + 1 inner products per
     // Arnoldi step
+    // rows of block partials: the inner products of one Arnoldi step (up
+    // to 2 restart + 1 real ones; 4 restart complex ones' parts for a
+    // complex state)
     A(&h->kpart, static_cast<size_t>(h->kpart_blocks) *
-                     (2 * h->restart_cap + 3) * sizeof(double));
-    A(&h->kdots, 4 * (h->restart_cap + 2) * sizeof(double));
+                     (4 * h->restart_cap + 4) * sizeof(double));
+    A(&h->kdots, 8 * (h->restart_cap + 2) * sizeof(double));
     if (h->nonlinear)
       A(&h->Uphys, static_cast<size_t>(Nt) * h->Ns * sizeof(double));
     if (h->nonlinear && h->mixed)
@@ -2307,7 +2310,7 @@ int create_impl(const expdiag_grid* g, int Nt, double dt, double alpha,
         hipHostMalloc(&h->h_mirror, sizeof(Ctl), hipHostMallocMapped) !=
             hipSuccess ||
         hipHostMalloc(&h->h_red, 8 * sizeof(double)) != hipSuccess ||
-        hipHostMalloc(&h->h_kdots, 4 * (h->restart_cap + 2) *
+        hipHostMalloc(&h->h_kdots, 8 * (h->restart_cap + 2) *
                                        sizeof(double)) != hipSuccess)
       rc = fail(h, EXPDIAG_ENOMEM, "pinned host allocation");
   }

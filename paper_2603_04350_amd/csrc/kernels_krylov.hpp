@@ -404,6 +404,207 @@ __global__ void __launch_bounds__(KRY_THREADS)
   }
 }
 
+// ---- Complex Krylov vectors (complex states) ----------------------------
+// A complex state's spectral vector is the full spectrum, and the inner
+// product of the fields it represents is <x, y> = (1/Ns) sum conj(x) y
+// (Parseval weight 1 on every entry): complex, where the real-state
+// kernels above form its real part.
+//
+// kdot2c_kernel: block partials of, with G = KDOT2C_GROUP basis vectors per
+// block reduction,
+//   rows 2i, 2i+1: Re, Im <V_i, u>;  rows 2nv+2i, 2nv+2i+1: Re, Im <V_i, w>;
+//   row 4nv: <u, u>;  rows 4nv+1, 4nv+2: Re, Im <u, w>;  row 4nv+3: <w, w>
+// and, when w is null, rows 2i, 2i+1: <V_i, u>, row 2nv: <u, u>.
+constexpr int KDOT2C_GROUP = 2;
+
+__global__ void __launch_bounds__(KRY_THREADS)
+    kdot2c_kernel(const cx<double>* __restrict__ V, long vstride, int nv,
+                  const cx<double>* __restrict__ u,
+                  const cx<double>* __restrict__ w, long n,
+                  double* __restrict__ part, int ld) {
+  constexpr int NW = KRY_THREADS / 64;
+  constexpr int G = KDOT2C_GROUP;
+  constexpr int NV = 4 * G + 4;  // values reduced per group
+  __shared__ double red[NW * NV];
+  const long base = static_cast<long>(blockIdx.x) * KRY_PER_BLOCK;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const bool hw = w != nullptr;
+  cx<double> uv[KRY_PER_THREAD], wv[KRY_PER_THREAD];
+#pragma unroll
+  for (int q = 0; q < KRY_PER_THREAD; ++q) {
+    const long e = base + threadIdx.x + q * KRY_THREADS;
+    const bool ok = e < n;
+    uv[q] = ok ? u[e] : mk(0.0, 0.0);
+    wv[q] = (ok && hw) ? w[e] : mk(0.0, 0.0);
+  }
+  for (int i0 = 0; i0 <= nv; i0 += G) {
+    cx<double> x[G][KRY_PER_THREAD];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int i = i0 + g;
+#pragma unroll
+      for (int q = 0; q < KRY_PER_THREAD; ++q) {
+        const long e = base + threadIdx.x + q * KRY_THREADS;
+        x[g][q] = mk(0.0, 0.0);
+        if (i < nv && e < n) x[g][q] = V[i * vstride + e];
+      }
+    }
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int i = i0 + g;
+      if (i < nv) {
+#pragma unroll
+        for (int q = 0; q < KRY_PER_THREAD; ++q) {
+          const cx<double> a = x[g][q];
+          acc[4 * g] += a.x * uv[q].x + a.y * uv[q].y;
+          acc[4 * g + 1] += a.x * uv[q].y - a.y * uv[q].x;
+          acc[4 * g + 2] += a.x * wv[q].x + a.y * wv[q].y;
+          acc[4 * g + 3] += a.x * wv[q].y - a.y * wv[q].x;
+        }
+      } else if (i == nv) {
+#pragma unroll
+        for (int q = 0; q < KRY_PER_THREAD; ++q) {
+          acc[4 * G] += norm2(uv[q]);
+          acc[4 * G + 1] += uv[q].x * wv[q].x + uv[q].y * wv[q].y;
+          acc[4 * G + 2] += uv[q].x * wv[q].y - uv[q].y * wv[q].x;
+          acc[4 * G + 3] += norm2(wv[q]);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1)
+        acc[k] += __shfl_down(acc[k], off, 64);
+    }
+    __syncthreads();  // the previous group's sums have been read
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) red[wid * NV + k] = acc[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      auto sum = [&](int k) {
+        double s = 0.0;
+        for (int q = 0; q < NW; ++q) s += red[q * NV + k];
+        return s;
+      };
+      const long b = blockIdx.x;
+      auto put = [&](long row, double v) { part[row * ld + b] = v; };
+      for (int g = 0; g < G; ++g) {
+        const int i = i0 + g;
+        if (i < nv) {
+          put(2 * i, sum(4 * g));
+          put(2 * i + 1, sum(4 * g + 1));
+          if (hw) {
+            put(2 * nv + 2 * i, sum(4 * g + 2));
+            put(2 * nv + 2 * i + 1, sum(4 * g + 3));
+          }
+        } else if (i == nv) {
+          if (hw) {
+            put(4 * nv, sum(4 * G));
+            put(4 * nv + 1, sum(4 * G + 1));
+            put(4 * nv + 2, sum(4 * G + 2));
+            put(4 * nv + 3, sum(4 * G + 3));
+          } else {
+            put(2 * nv, sum(4 * G));
+          }
+        }
+      }
+    }
+  }
+}
+
+// The fused update of a complex Arnoldi step (as kdcgs_update_kernel):
+//   q_j = (u - sum_{i<j} a_i V_i) / beta,
+//   u'  = w / beta - sum_{i<j} z_i V_i - z_j q_j,
+// with complex a_i, z_i: cf = [a_0..a_{j-1}, z_0..z_j] as (re, im) pairs,
+// then 1/beta (device, 4j + 3 values, j <= 63).
+__global__ void __launch_bounds__(KRY_THREADS)
+    kdcgs_updatec_kernel(cx<double>* __restrict__ V, long vstride, int j,
+                         const double* __restrict__ coef, long n) {
+  __shared__ double cf[4 * 64 + 4];
+  for (int k = threadIdx.x; k < 4 * j + 3; k += KRY_THREADS)
+    cf[k] = coef[k];
+  __syncthreads();
+  const cx<double>* ca = reinterpret_cast<const cx<double>*>(cf);
+  const cx<double>* cz = ca + j;
+  const double ib = cf[4 * j + 2];
+  const long base = static_cast<long>(blockIdx.x) * KRY_PER_BLOCK;
+  cx<double> uq[KRY_PER_THREAD], wn[KRY_PER_THREAD];
+#pragma unroll
+  for (int q = 0; q < KRY_PER_THREAD; ++q) {
+    const long e = base + threadIdx.x + q * KRY_THREADS;
+    uq[q] = mk(0.0, 0.0);
+    wn[q] = mk(0.0, 0.0);
+    if (e < n) {
+      uq[q] = V[j * vstride + e];
+      wn[q] = V[(j + 1) * vstride + e];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < KRY_PER_THREAD; ++q) wn[q] = wn[q] * ib;
+  for (int i = 0; i < j; ++i) {
+    cx<double> y[KRY_PER_THREAD];
+#pragma unroll
+    for (int q = 0; q < KRY_PER_THREAD; ++q) {
+      const long e = base + threadIdx.x + q * KRY_THREADS;
+      y[q] = mk(0.0, 0.0);
+      if (e < n) y[q] = V[i * vstride + e];
+    }
+#pragma unroll
+    for (int q = 0; q < KRY_PER_THREAD; ++q) {
+      uq[q] = uq[q] - cmul(y[q], ca[i]);
+      wn[q] = wn[q] - cmul(y[q], cz[i]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < KRY_PER_THREAD; ++q) {
+    const long e = base + threadIdx.x + q * KRY_THREADS;
+    const cx<double> qj = uq[q] * ib;
+    const cx<double> un = wn[q] - cmul(qj, cz[j]);
+    if (e < n) {
+      V[j * vstride + e] = qj;
+      V[(j + 1) * vstride + e] = un;
+    }
+  }
+}
+
+// w += sum_{i<nv} coef_i V_i with complex coefficients (re, im pairs,
+// nv <= 64); per element the terms are added in the order i = 0, 1, ...
+__global__ void __launch_bounds__(KRY_THREADS)
+    kaxpyc_kernel(cx<double>* __restrict__ w, const cx<double>* __restrict__ V,
+                  long vstride, int nv, const double* __restrict__ coef,
+                  long n) {
+  __shared__ double cf[2 * 64];
+  for (int k = threadIdx.x; k < 2 * nv; k += KRY_THREADS) cf[k] = coef[k];
+  __syncthreads();
+  const cx<double>* c = reinterpret_cast<const cx<double>*>(cf);
+  const long base = static_cast<long>(blockIdx.x) * KRY_PER_BLOCK;
+  cx<double> x[KRY_PER_THREAD];
+#pragma unroll
+  for (int q = 0; q < KRY_PER_THREAD; ++q) {
+    const long e = base + threadIdx.x + q * KRY_THREADS;
+    x[q] = e < n ? w[e] : mk(0.0, 0.0);
+  }
+  for (int i = 0; i < nv; ++i) {
+#pragma unroll
+    for (int q = 0; q < KRY_PER_THREAD; ++q) {
+      const long e = base + threadIdx.x + q * KRY_THREADS;
+      const cx<double> y = e < n ? V[i * vstride + e] : mk(0.0, 0.0);
+      x[q] = x[q] + cmul(y, c[i]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < KRY_PER_THREAD; ++q) {
+    const long e = base + threadIdx.x + q * KRY_THREADS;
+    if (e < n) w[e] = x[q];
+  }
+}
+
 // out = in * s (out may equal in)
 __global__ void __launch_bounds__(KRY_THREADS)
     kscale_kernel(cx<double>* out, const cx<double>* in, double s, long n) {
