@@ -94,7 +94,7 @@ extern "C" {
 
 typedef struct expdiag_ctx* expdiag_t;
 
-/* Periodic grid on [0, 2pi)^dim; n[i] a power of two, 4 <= n[i] <= 1024
+/* Periodic grid on [0, 2pi)^dim; n[i] a power of two, 4 <= n[i] <= 4096
  * (n[dim-1] >= 4).  Entries n[dim..2] are ignored. */
 typedef struct {
   int dim;

@@ -50,6 +50,11 @@ using namespace expdiag;
 namespace {
 
 constexpr int HIST_CAP = 4096;
+// grid points per axis: powers of two NMIN..NMAX; row transforms of
+// length NMAX/2 (half spectrum), column transforms of length NMAX; the
+// 2C-column workgroups only up to WIDE_LMAX (LDS)
+constexpr int NMAX = 4096;
+constexpr int WIDE_LMAX = 1024;
 constexpr int NPROF = 5;
 constexpr double BULK_TOL = 1e-6;
 enum ProfClass { P_COL = 0, P_ROW = 1, P_PASSB = 2, P_RED = 3, P_KRY = 4 };
@@ -363,7 +368,7 @@ const cx<T>* twid_table(expdiag_ctx* h) {
 // ------------------------------------------------------- job constructors
 int row_blocks(int M, long nrows) {
   long b = 0;
-  dispatch_pow2<2, 512>(M, [&](auto Mc) {
+  dispatch_pow2<2, NMAX / 2>(M, [&](auto Mc) {
     constexpr int MM = decltype(Mc)::value;
     b = (nrows + RowShape<MM>::RPB - 1) / RowShape<MM>::RPB;
   });
@@ -371,9 +376,10 @@ int row_blocks(int M, long nrows) {
 }
 int col_blocks(int L, long outer, long inner, int wide = 0) {
   long b = 0;
-  dispatch_pow2<4, 1024>(L, [&](auto Lc) {
+  dispatch_pow2<4, NMAX>(L, [&](auto Lc) {
     constexpr int LL = decltype(Lc)::value;
-    const long C = wide ? ColShape<LL, 2>::C : ColShape<LL>::C;
+    const long C = (wide && LL <= WIDE_LMAX) ? ColShape<LL, 2>::C
+                                             : ColShape<LL>::C;
     b = outer * ((inner + C - 1) / C);
   });
   return static_cast<int>(b);
@@ -565,7 +571,7 @@ template <typename T, int MODE, typename TI, typename TO>
 int launch_row1(expdiag_ctx* h, const RowJob& jb) {
   const int M = h->n[h->dim - 1] / 2;
   ProfScope ps(h, P_ROW, row_bytes(M, MODE, jb.nrows, sizeof(TI), sizeof(TO)));
-  bool ok = dispatch_pow2<2, 512>(M, [&](auto Mc) {
+  bool ok = dispatch_pow2<2, NMAX / 2>(M, [&](auto Mc) {
     constexpr int MM = decltype(Mc)::value;
     using S = RowShape<MM>;
     const long blocks = (jb.nrows + S::RPB - 1) / S::RPB;
@@ -581,7 +587,7 @@ template <typename T, int S, typename TI, typename TO>
 int launch_col1(expdiag_ctx* h, int L, const ColJob& jb) {
   ProfScope ps(h, P_COL, static_cast<double>(jb.outer) * L * jb.inner * 2 *
                              (sizeof(TI) + sizeof(TO)));
-  bool ok = dispatch_pow2<4, 1024>(L, [&](auto Lc) {
+  bool ok = dispatch_pow2<4, NMAX>(L, [&](auto Lc) {
     constexpr int LL = decltype(Lc)::value;
     using SH = ColShape<LL>;
     const long tiles = (jb.inner + SH::C - 1) / SH::C;
@@ -695,7 +701,7 @@ int launch_row_c2c(expdiag_ctx* h, const cx<double>* src, cx<double>* dst,
                    long rows, double scale) {
   const int M = h->n[h->dim - 1];
   ProfScope ps(h, P_ROW, static_cast<double>(rows) * M * 32);
-  const bool ok = dispatch_pow2<4, 1024>(M, [&](auto Mc) {
+  const bool ok = dispatch_pow2<4, NMAX>(M, [&](auto Mc) {
     constexpr int MM = decltype(Mc)::value;
     using SH = RowShape<MM>;
     const long blocks = (rows + SH::RPB - 1) / SH::RPB;
@@ -1018,11 +1024,12 @@ bool plan_pass_a_mp(Plan& P, expdiag_ctx* h, const Ctl* ctl,
   const int wd = h->col_wide;
   auto col2 = [&](int stage, int L, int S, const ColJob& j32,
                   const ColJob& j64, int ti32) {
-    Group& g = plan_group(P, stage, K_COL, 2, L, S, ti32, 1, wd);
+    const int wdl = L <= WIDE_LMAX ? wd : 0;
+    Group& g = plan_group(P, stage, K_COL, 2, L, S, ti32, 1, wdl);
     g.cj.push_back(mx ? j32 : j64);
     g.cj.push_back(j64);
     g.start.push_back(g.start.back() +
-                      col_blocks(L, j64.outer, j64.inner, wd));
+                      col_blocks(L, j64.outer, j64.inner, wdl));
     const double ent = static_cast<double>(j64.outer) * L * j64.inner * 2;
     const double b64 = ent * 2 * sizeof(double);
     const double b32 =
@@ -1044,10 +1051,11 @@ bool plan_pass_a_mp(Plan& P, expdiag_ctx* h, const Ctl* ctl,
   host = host || !mx;
   if (host) {
     const ColJob j = make_col(h->Uh, T64, ns, in2, 1.0, ctl, -1);
-    Group& g = plan_group(P, 0, K_COL, 3, n0, 1, 0, 0, wd);
+    const int wd0 = n0 <= WIDE_LMAX ? wd : 0;
+    Group& g = plan_group(P, 0, K_COL, 3, n0, 1, 0, 0, wd0);
     g.cj.push_back(j);
     g.red.push_back(red);
-    g.start.push_back(g.start.back() + col_blocks(n0, ns, in2, wd));
+    g.start.push_back(g.start.back() + col_blocks(n0, ns, in2, wd0));
     const double b64 =
         static_cast<double>(ns) * n0 * in2 * 2 * 2 * sizeof(double);
     g.bytes += b64;
@@ -1234,7 +1242,7 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st,
     if (g.kind == K_ROW) {
       ProfScope ps(ph, P_ROW, prof_group_bytes(ph, g, P_ROW), true);
       const RowJob* J = static_cast<const RowJob*>(g.djobs);
-      ok = dispatch_pow2<2, 512>(g.len, [&](auto Mc) {
+      ok = dispatch_pow2<2, NMAX / 2>(g.len, [&](auto Mc) {
         constexpr int MM = decltype(Mc)::value;
         const dim3 th(RowShape<MM>::THREADS);
         if (g.ti == 0)  // 1D: the fp32 job reads the fp64 spectrum
@@ -1249,13 +1257,16 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st,
       const ColJob* J = static_cast<const ColJob*>(g.djobs);
       const PassBArgs* RJ = static_cast<const PassBArgs*>(g.dred);
       const int nred = static_cast<int>(g.red.size());
-      ok = dispatch_pow2<4, 1024>(g.len, [&](auto Lc) {
+      ok = dispatch_pow2<4, NMAX>(g.len, [&](auto Lc) {
         constexpr int LL = decltype(Lc)::value;
-        if (g.wide)
-          klaunch(ps, col_kernel_host<LL, 1, 2>, dim3(grid + nred),
-                  dim3(ColShape<LL, 2>::THREADS), st, J, g.dstart, nj, RJ,
-                  nred, tw64);
-        else
+        if constexpr (LL <= WIDE_LMAX) {
+          if (g.wide) {
+            klaunch(ps, col_kernel_host<LL, 1, 2>, dim3(grid + nred),
+                    dim3(ColShape<LL, 2>::THREADS), st, J, g.dstart, nj, RJ,
+                    nred, tw64);
+            return;
+          }
+        }
           klaunch(ps, col_kernel_host<LL, 1>, dim3(grid + nred),
                   dim3(ColShape<LL>::THREADS), st, J, g.dstart, nj, RJ, nred,
                   tw64);
@@ -1279,11 +1290,15 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st,
           klaunch(ps, col_kernel_mp<LL, -1, float, WW>, dim3(grid), th, st,
                   J, g.dstart, nj, tw32, tw64);
       };
-      ok = dispatch_pow2<4, 1024>(g.len, [&](auto Lc) {
-        if (g.wide)
-          run(Lc, std::integral_constant<int, 2>());
-        else
-          run(Lc, std::integral_constant<int, 1>());
+      ok = dispatch_pow2<4, NMAX>(g.len, [&](auto Lc) {
+        constexpr int LL = decltype(Lc)::value;
+        if constexpr (LL <= WIDE_LMAX) {
+          if (g.wide) {
+            run(Lc, std::integral_constant<int, 2>());
+            return;
+          }
+        }
+        run(Lc, std::integral_constant<int, 1>());
       });
     } else {
       const PassBArgs* J = static_cast<const PassBArgs*>(g.djobs);
@@ -1479,7 +1494,7 @@ int plan_launch_x(expdiag_ctx* ph, Plan& P, hipStream_t st,
     bool ok = false;
     if (g.kind == K_XROW) {
       const RowJob* J = static_cast<const RowJob*>(g.djobs);
-      ok = dispatch_pow2<2, 512>(g.len, [&](auto Mc) {
+      ok = dispatch_pow2<2, NMAX / 2>(g.len, [&](auto Mc) {
         constexpr int MM = decltype(Mc)::value;
         const dim3 th(RowShape<MM>::THREADS);
         if (g.mode == ROW_R2C)
@@ -1494,7 +1509,7 @@ int plan_launch_x(expdiag_ctx* ph, Plan& P, hipStream_t st,
       });
     } else if (g.kind == K_XCOL) {
       const ColJob* J = static_cast<const ColJob*>(g.djobs);
-      ok = dispatch_pow2<4, 1024>(g.len, [&](auto Lc) {
+      ok = dispatch_pow2<4, NMAX>(g.len, [&](auto Lc) {
         constexpr int LL = decltype(Lc)::value;
         const dim3 th(ColShape<LL>::THREADS);
         if (g.mode == 1)
@@ -1937,7 +1952,7 @@ int check_grid(const expdiag_grid* g, Sizes* sz) {
   long Ns = 1;
   for (int i = 0; i < g->dim; ++i) {
     if (g->n[i] < 4 || (g->n[i] & 1)) return EXPDIAG_EINVAL;
-    if (!is_pow2(g->n[i]) || g->n[i] > 1024) return EXPDIAG_EUNSUPPORTED;
+    if (!is_pow2(g->n[i]) || g->n[i] > NMAX) return EXPDIAG_EUNSUPPORTED;
     Ns *= g->n[i];
   }
   const long nh = g->n[g->dim - 1] / 2 + 1;
@@ -2207,7 +2222,7 @@ int setup_handle(expdiag_ctx* h, const expdiag_grid* g, int Nt, double dt,
   Sizes s{};
   const int gc = check_grid(g, &s);
   if (gc != 0)
-    return fail(nullptr, gc, "grid: dim 1..3, n even, power of two, 4..1024");
+    return fail(nullptr, gc, "grid: dim 1..3, n a power of two, 4..4096");
   RCHK(validate_params(Nt, dt, alpha, scheme, p));
   if (p->complex_state == 1) {
     // the full spectrum: every last-axis index
@@ -2299,7 +2314,7 @@ int create_impl(const expdiag_grid* g, int Nt, double dt, double alpha,
     const int gc = check_grid(g, &s);
     if (gc != 0)
       return fail(nullptr, gc,
-                  "grid: dim 1..3, n even, power of two, 4..1024");
+                  "grid: dim 1..3, n a power of two, 4..4096");
     RCHK(validate_params(Nt, dt, alpha, scheme, p));
   }
   expdiag_ctx* h = new (std::nothrow) expdiag_ctx();

@@ -390,7 +390,9 @@ template <int L, int WD = 1>
 struct ColShape {
   static constexpr int R = FftShape<L>::R;
   static constexpr int TPL = FftShape<L>::TPL;
-  static constexpr int CMIN = L * 8 * 16 <= 65536 ? 8 : 4;
+  // columns per workgroup at least 8 while the tile is at most 64 KiB,
+  // then 4 (up to L = 2048, 128 KiB) and 2 (L = 4096, 128 KiB)
+  static constexpr int CMIN = L * 8 * 16 <= 65536 ? 8 : (L <= 2048 ? 4 : 2);
   static constexpr int C = WD * ((256 / TPL) >= CMIN ? 256 / TPL : CMIN);
   static constexpr int THREADS = C * TPL;
   static constexpr int LS = C;  // LDS row (complex slots)

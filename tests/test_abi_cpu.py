@@ -49,7 +49,7 @@ def _create(lib, shape, Nt, dt, alpha, scheme, prob):
     ((63,), 8, 0.1, 1e-2, 1, X.make_problem(1.0), X.EXPDIAG_EINVAL),
     ((2,), 8, 0.1, 1e-2, 1, X.make_problem(1.0), X.EXPDIAG_EINVAL),
     ((96,), 8, 0.1, 1e-2, 1, X.make_problem(1.0), X.EXPDIAG_EUNSUPPORTED),
-    ((2048,), 8, 0.1, 1e-2, 1, X.make_problem(1.0), X.EXPDIAG_EUNSUPPORTED),
+    ((8192,), 8, 0.1, 1e-2, 1, X.make_problem(1.0), X.EXPDIAG_EUNSUPPORTED),
     ((64,), 1, 0.1, 1e-2, 1, X.make_problem(1.0), X.EXPDIAG_EINVAL),
     ((64,), 12, 0.1, 1e-2, 1, X.make_problem(1.0), X.EXPDIAG_EUNSUPPORTED),
     ((64,), 8, 0.0, 1e-2, 1, X.make_problem(1.0), X.EXPDIAG_EINVAL),

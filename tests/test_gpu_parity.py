@@ -32,6 +32,11 @@ CASES = {
     # the longest columns (512 and 1024 points: 8 and 4 columns per tile)
     "ac2d_n512_Nt4": (2, 512, 4, 1e-3, 1e-4, 0.0, 1.0, 0, -1.0, 1),
     "ac2d_n1024_Nt2": (2, 1024, 2, 1e-2, 1e-5, 0.0, 1.0, 0, -1.0, 2),
+    # the largest grids: 2048- and 4096-point columns (4 and 2 columns per
+    # 128 KiB tile), 1024- and 2048-point half-spectrum rows
+    "ac2d_n2048_Nt2": (2, 2048, 2, 1e-2, 1e-6, 0.0, 1.0, 0, -1.0, 1),
+    "row4096_Nt4": (1, 4096, 4, 1e-2, 1e-6, 0.0, 1.0, 0, -1.0, 2),
+    "heat2d_n4096_Nt2": (2, 4096, 2, 1e-2, 1e-6, 0.1, 0, 0, 0, 1),
 }
 
 
@@ -99,7 +104,13 @@ def test_precond_parity(case):
     assert _rel(S.cpu().numpy(), Sr) < _bar(st)
 
 
-@pytest.mark.parametrize("case", sorted(CASES))
+# the oracle's fixed point on a 4096^2 window takes ~30 s for three
+# iterations: that case is held to the oracle by residual, preconditioner
+# and converged window only
+ITER_CASES = [c for c in sorted(CASES) if c != "heat2d_n4096_Nt2"]
+
+
+@pytest.mark.parametrize("case", ITER_CASES)
 def test_iterates_parity(case):
     import torch
     st = _setup(case)
