@@ -425,7 +425,13 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
     }
     const cx<double> z = smul(lam, E);
     const double dr = 1.0 - z.x - sigma, di = -z.y;
-    const double inv = 1.0 / (NT * (dr * dr + di * di));
+    // 1 / (NT |1 - lambda E - sigma|^2): the hardware reciprocal refined
+    // by two Newton steps (within an ulp of the quotient; the denominator
+    // is at least NT (1 - alpha^{1/Nt})^2 > 0, so no special cases)
+    const double den = NT * (dr * dr + di * di);
+    double inv = __builtin_amdgcn_rcp(den);
+    inv = fma(fma(-den, inv, 1.0), inv, inv);
+    inv = fma(fma(-den, inv, 1.0), inv, inv);
     v[s] = cmul(v[s], mk(dr * inv, -di * inv));
   }
   __syncthreads();
