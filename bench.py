@@ -856,9 +856,11 @@ def bench_ebdf2(steps, warmup, Nt, order=2):
     launches timed with kernel-attached events.  Nt - order + 1 a power of
     two (64 unknown slices for Nt = 63 + order) takes the radix FFT pass B,
     HBM-bound: algorithmic bytes 32 per window entry plus the per-kappa
-    tables.  Nt = 64 takes the dense pass B, one 2Nt x 2Nt real GEMM pair
-    per 16 kappa columns on FP64 MFMA: executed flops 2 * 2 * (2Nt)^2 * 16
-    per block."""
+    tables.  Nt = 64 takes the dense pass B: per block of C kappa columns
+    (C = 64 for Nt <= 32, else 2048 / Nt) two real products of the
+    2Nt x 2Nt block matrix (entries from the table of roots of unity) with
+    the 2Nt x C tile on FP64 MFMA: executed flops 2 * 2 * (2Nt)^2 * C per
+    block."""
     import workloads as W
     inst = W.diffusion2d_ebdf(order, Nt=Nt, T=2.0)
     fp = bench_single(inst, 0, steps, warmup)
@@ -888,7 +890,8 @@ def bench_ebdf2(steps, warmup, Nt, order=2):
     }
     if dense:
         Nk = inst.n * (inst.n // 2 + 1)
-        flops = 2 * 2 * (2 * Nt) ** 2 * 16 * ((Nk + 15) // 16)
+        C = 64 if Nt <= 32 else 2048 // Nt
+        flops = 2 * 2 * (2 * Nt) ** 2 * C * ((Nk + C - 1) // C)
         tflops = flops / (us * 1e-6) / 1e12
         out["passb"]["flops_per_launch"] = flops
         out["passb"]["roofline_mfma"] = {

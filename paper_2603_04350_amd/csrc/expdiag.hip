@@ -164,7 +164,7 @@ struct expdiag_ctx {
   cx<double>* lam = nullptr;                          // [Nt]
   cx<double>* tw64 = nullptr;                         // [TW_N]
   cx<float>* tw32 = nullptr;                          // [TW_N]
-  double *Wf = nullptr, *Wi = nullptr;  // dense time transform [2Nt][2Nt]
+  cx<double>* roots = nullptr;  // e^{+2 pi i j/N}, j < N (EBDF dense transform)
   double* partials = nullptr;                         // [maxblocks][4]
   int max_partials = 0;
   double* red_out = nullptr;  // [8]
@@ -396,9 +396,6 @@ constexpr int DENSE_NT_MIN = 8, DENSE_NT_MAX = 128;
 bool dense_ok(int Nt) {
   return is_pow2(Nt) && Nt >= DENSE_NT_MIN && Nt <= DENSE_NT_MAX;
 }
-int dense_blocks(long Nk) {
-  return static_cast<int>((Nk + DENSE_C - 1) / DENSE_C);
-}
 // blocks of the first-order dense (DFT on MFMA) pass B
 int dft_blocks(int Nt, long Nk) {
   long b = 0;
@@ -474,8 +471,7 @@ bool bulk_u32(const expdiag_ctx* h) {
 cx<float>* u32_view(expdiag_ctx* h) { return h->U32; }
 int passb_blocks(expdiag_ctx* h) {
   if (h->tvariant == 1)
-    return bdf_order(h->scheme) > 0 ? dense_blocks(h->Nk)
-                                    : dft_blocks(h->Nt, h->Nk);
+    return dft_blocks(h->Nt, h->Nk);
   return passb_blocks_nt(time_len(h), h->Nk);
 }
 
@@ -538,8 +534,7 @@ PassBArgs passb_args(expdiag_ctx* h) {
   a.hmirror = nullptr;
   a.hist = nullptr;
   a.tw = h->tw64;
-  a.Wf = h->Wf;
-  a.Wi = h->Wi;
+  a.roots = h->roots;
   a.Nk = h->Nk;
   a.nh = parseval_nh(h);
   a.nonlinear = h->nonlinear ? 1 : 0;
@@ -632,7 +627,7 @@ int launch_passb1(expdiag_ctx* h, const PassBArgs& a) {
     if (h->tvariant == 1) {
       ok = dispatch_pow2<DENSE_NT_MIN, DENSE_NT_MAX>(h->Nt, [&](auto Nc) {
         constexpr int NN = decltype(Nc)::value;
-        const dim3 grid(dense_blocks(h->Nk)), th(DENSE_THREADS);
+        const dim3 grid(dft_blocks(NN, h->Nk)), th(DENSE_THREADS);
         if (s == 2)
           hipLaunchKernelGGL((passb_bdf_kernel1<NN, 2, MODE>), grid, th, 0,
                              h->stream, a);
@@ -1852,33 +1847,11 @@ int build_tables(expdiag_ctx* h) {
     lam[l] = mk<double>(static_cast<double>(root * cs[l]),
                         static_cast<double>(root * sn[l]));
   }
-  if (h->Wf != nullptr) {
-    // [[Re, -Im], [Im, Re]] of Wf[m][l + o] = gamma_l e^{+2 pi i ml/N} / N
-    // and Wi[l + o][m] = gamma_l^{-1} e^{-2 pi i ml/N}, m, l < N; every
-    // other entry zero
-    const int K = 2 * Nt;
-    std::vector<double> wf(static_cast<size_t>(K) * K, 0.0), wi(wf.size(), 0.0);
-    for (int m = 0; m < N; ++m) {
-      for (int l = 0; l < N; ++l) {
-        const int j = static_cast<int>((static_cast<long>(m) * l) % N);
-        const long double g = gl[l];
-        const long double fr = g * cs[j] / N, fi = g * sn[j] / N;
-        const int c = l + o;
-        wf[m * K + c] = static_cast<double>(fr);
-        wf[m * K + Nt + c] = static_cast<double>(-fi);
-        wf[(Nt + m) * K + c] = static_cast<double>(fi);
-        wf[(Nt + m) * K + Nt + c] = static_cast<double>(fr);
-        // Wi row l + o, column m
-        const long double ir = cs[j] / g, ii = -sn[j] / g;
-        wi[c * K + m] = static_cast<double>(ir);
-        wi[c * K + Nt + m] = static_cast<double>(-ii);
-        wi[(Nt + c) * K + m] = static_cast<double>(ii);
-        wi[(Nt + c) * K + Nt + m] = static_cast<double>(ir);
-      }
-    }
-    HIPCHK(h, hipMemcpy(h->Wf, wf.data(), wf.size() * sizeof(double),
-                        hipMemcpyHostToDevice));
-    HIPCHK(h, hipMemcpy(h->Wi, wi.data(), wi.size() * sizeof(double),
+  if (h->roots != nullptr) {
+    std::vector<cx<double>> rt(N);
+    for (int j = 0; j < N; ++j)
+      rt[j] = mk<double>(static_cast<double>(cs[j]), static_cast<double>(sn[j]));
+    HIPCHK(h, hipMemcpy(h->roots, rt.data(), N * sizeof(cx<double>),
                         hipMemcpyHostToDevice));
   }
   h->cplx = complex_symbols(h);
@@ -1981,8 +1954,8 @@ size_t footprint(const Sizes& s, int dim, int Nt, bool nonlinear,
   b += TW_N * (sizeof(cx<double>) + sizeof(cx<float>));
   b += static_cast<size_t>(std::max(std::max(passb_blocks_nt(Nt, s.Nk),
                                              passb_blocks_nt(Nt - 1, s.Nk)),
-                                    dense_blocks(s.Nk))) * 4 * sizeof(double);
-  if (dense_ok(Nt)) b += 8 * static_cast<size_t>(Nt) * Nt * sizeof(double);
+                                    dft_blocks(Nt, s.Nk))) * 4 * sizeof(double);
+  if (dense_ok(Nt)) b += static_cast<size_t>(Nt) * sizeof(cx<double>);
   return b;
 }
 
@@ -2036,8 +2009,7 @@ void release(expdiag_ctx* h) {
   fr(h->lam);
   fr(h->tw64);
   fr(h->tw32);
-  fr(h->Wf);
-  fr(h->Wi);
+  fr(h->roots);
   fr(h->partials);
   fr(h->red_out);
   fr(h->ctl);
@@ -2269,13 +2241,11 @@ int setup_handle(expdiag_ctx* h, const expdiag_grid* g, int Nt, double dt,
   A(&h->tw64, TW_N * sizeof(cx<double>));
   A(&h->tw32, TW_N * sizeof(cx<float>));
   if (dense_ok(Nt)) {
-    A(&h->Wf, 4 * static_cast<size_t>(Nt) * Nt * sizeof(double));
-    A(&h->Wi, 4 * static_cast<size_t>(Nt) * Nt * sizeof(double));
+    A(&h->roots, Nt * sizeof(cx<double>));
   }
   h->max_partials = std::max(passb_blocks_nt(time_len(h), h->Nk), 1);
   if (dense_ok(Nt))
-    h->max_partials = std::max({h->max_partials, dense_blocks(h->Nk),
-                                dft_blocks(Nt, h->Nk)});
+    h->max_partials = std::max(h->max_partials, dft_blocks(Nt, h->Nk));
   A(&h->partials, static_cast<size_t>(h->max_partials) * 4 * sizeof(double));
   A(&h->red_out, 8 * sizeof(double));
   A(&h->ctl, sizeof(Ctl));

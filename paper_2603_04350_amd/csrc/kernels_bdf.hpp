@@ -13,23 +13,22 @@
 // every such term is beta_i E^i E^{l+1-i} u0^, and sum_{i>j} beta_i = q_j
 // below.  R_s^alpha has C_{i-1}^alpha = (C_0^alpha)^i, so steps (a)-(c) on
 // N = Nt - o time points diagonalise it with eigenvalues lambda_m^i:
-//   (a) Y_m = sum_j Wf[m][j] r_{j+o}, Wf[m][j] = gamma_j e^{+2 pi i mj/N}/N
-//   (b) X_m = Y_m / d(lambda_m E), d(z) = 1 - sum_i beta_i z^i
+//   (a) Y_m = sum_j F[m][j] gamma_j r_{j+o}, F[m][j] = e^{+2 pi i mj/N}
+//   (b) X_m = Y_m / (N d(lambda_m E)), d(z) = 1 - sum_i beta_i z^i
 //       = (1 - z) sum_{k<s} q_k z^k, q_k = 1 - sum_{i<=k} beta_i
 //       (d(1) = 0 because the beta_i sum to one; the factored form keeps the
 //       1 - z of low modes free of the large coefficients' rounding)
-//   (c) s_{j+o} = sum_m Wi[j][m] X_m, Wi[j][m] = gamma_j^{-1} e^{-2 pi i mj/N}
+//   (c) s_{j+o} = gamma_j^{-1} sum_m conj(F[m][j]) X_m
 // For s = 2, d(z) = (1 - z)(1 - z/3).
 //
-// Two transforms: the dense complex GEMM of kernels_dense.hpp for Nt a power
-// of two (the host embeds the N x N matrices at row and column offset o of
-// the Nt x Nt real-block operands, so rows < o and frequencies >= N stay
-// zero), and the radix FFT of kernels_passb.hpp when N is a power of two.
+// Two transforms: the DFT products on FP64 MFMA of kernels_dense.hpp for Nt
+// a power of two (the N-point matrix placed at offset o of the Nt-row tile,
+// its entries read from a table of the N roots of unity), and the radix FFT
+// of kernels_passb.hpp when N is a power of two.
 // SC is the order when it is fixed at compile time (the radix kernels of
 // orders 2..4, where the run-time order cost 10-20%); SC = 0 reads it from
 // PassBArgs::bdf_s and unrolls to six (radix orders 5 and 6, which spill
-// when compiled in, and the dense kernels of orders 3..6, bound by the
-// MFMA time transform either way).
+// when compiled in, and the dense kernels of orders 3..6).
 #pragma once
 #include "kernels_dense.hpp"
 
@@ -134,56 +133,88 @@ __device__ __forceinline__ cx<double> bdf_solve(const BdfCoef& cf, int s,
   return cmulc(y, d) * (scale / norm2(d));
 }
 
+// LDS of the dense pass B: operand tile, iterate tile, the start rows'
+// residuals, the roots, lambda, gamma and 1/gamma tables, E of the tile
+template <int NT>
+constexpr int bdf_dft_lds_doubles() {
+  using SH = DftShape<NT>;
+  return 2 * NT * SH::LD + 2 * NT * SH::C + 2 * 5 * SH::C + 2 * NT + 2 * NT +
+         NT + NT + 2 * SH::C;
+}
+
 // MODE: PB_ITERATE (residual, precondition, update U), PB_RESIDUAL
 // (Sout = residual), PB_PRECOND (Sout = P^{-1} Rin, in place allowed),
 // PB_OPAPPLY (Sout = P^{-1} M v for v in U: rows l < o of M v are v_l, rows
 // l >= o are (R_s v)_l with the entries before v_s taken as zero).
-// P = diag(I, R_s^alpha).
+// P = diag(I, R_s^alpha).  A workgroup takes DftShape<NT>::C kappa
+// columns; the residual phase gives each thread whole entries (row l,
+// column c), the products and everything after them the accumulator layout
+// of dft_units_n.
 template <int NT, int SC, int MODE>
 __device__ __forceinline__ void passb_bdf_body(const PassBArgs& a, long lb,
                                                double* lds, double* red) {
+  using SH = DftShape<NT>;
+  using EN = DftEntry<NT>;
+  constexpr int C = SH::C;
+  constexpr int LD = SH::LD;
   constexpr int SMAX = SC > 0 ? SC : 6;
-  constexpr int C = DENSE_C;
-  constexpr int PER = NT * C / DENSE_THREADS > 0 ? NT * C / DENSE_THREADS : 1;
   const int S = SC > 0 ? SC : a.bdf_s;
   const int o = S - 1;
+  const int N = NT - o;
   const BdfCoef cf = load_bdf_coef<SC>(S);
-  double* Bm = lds;                  // [2NT][C]
-  double* Ym = lds + 2 * NT * C;     // [2NT][C]
-  cx<double>* Ut = reinterpret_cast<cx<double>*>(lds + 4 * NT * C);  // [NT][C]
+  double* B = lds;                                              // [2NT][LD]
+  cx<double>* Ut = reinterpret_cast<cx<double>*>(lds + 2 * NT * LD);  // [NT][C]
+  cx<double>* rs = Ut + NT * C;                                 // [5][C]
+  cx<double>* roots = rs + 5 * C;                               // [N]
+  cx<double>* lamc = roots + NT;                                // [N]
+  cx<double>* Ec = lamc + NT;                                   // [C]
+  double* gml = reinterpret_cast<double*>(Ec + C);              // [N]
+  double* igml = gml + NT;                                      // [N]
   const long Nk = a.Nk;
   const long k0 = lb * C;
   const cx<double> zero = mk(0.0, 0.0);
   double nrm_r = 0.0, nrm_s = 0.0, nrm_u = 0.0;
 
+  if constexpr (MODE != PB_RESIDUAL) {
+    for (int j = threadIdx.x; j < N; j += DENSE_THREADS) {
+      roots[j] = gld(a.roots, j);
+      lamc[j] = gld(a.lam, j);
+      gml[j] = gld(a.gam, j);
+      igml[j] = gld(a.igam, j);
+    }
+  }
+  for (int c = threadIdx.x; c < C; c += DENSE_THREADS) {
+    const long kap = k0 + c;
+    Ec[c] = kap < Nk ? gld(a.E, kap) : zero;
+  }
   // 1. rows of U (or v) into LDS: every row's residual needs the s before
   if constexpr (MODE != PB_PRECOND) {
-    for (int e = threadIdx.x; e < NT * C; e += DENSE_THREADS) {
+#pragma unroll
+    for (int p = 0; p < SH::PER; ++p) {
+      const int e = threadIdx.x + p * DENSE_THREADS;
       const int l = e / C, c = e % C;
       const long kap = k0 + c;
       Ut[e] = kap < Nk ? gld(a.U, l * Nk + kap) : zero;
     }
-    __syncthreads();
   }
-  // 2. residual (or operator) rows; this thread keeps its own entries, the
-  //    start rows' being their own preconditioned value
-  cx<double> rk[PER];
+  __syncthreads();
+  // 2. residual (or operator) rows; the unknown rows scaled by gamma as the
+  //    operand of step (a), the start rows' (their own preconditioned
+  //    value) kept aside and zero in the operand
 #pragma unroll
-  for (int p = 0; p < PER; ++p) {
+  for (int p = 0; p < SH::PER; ++p) {
     const int e = threadIdx.x + p * DENSE_THREADS;
-    rk[p] = zero;
-    if (e >= NT * C) break;
     const int l = e / C, c = e % C;
     const long kap = k0 + c;
     const bool valid = kap < Nk;
-    const int kl = static_cast<int>(kap % a.nh);
+    const int kl = static_cast<int>((valid ? kap : 0) % a.nh);
     const double pw = !valid ? 0.0 : ((kl == 0 || kl == a.nh - 1) ? 1.0 : 2.0);
     cx<double> r = zero;
     if (valid) {
       if constexpr (MODE == PB_PRECOND) {
         r = gld(a.Rin, l * Nk + kap);
       } else {
-        const cx<double> E = gld(a.E, kap);
+        const cx<double> E = Ec[c];
         const cx<double> u = Ut[e];
         const int j = l - o;
         // rows l - i (clamped; values, not addresses, are selected)
@@ -203,69 +234,87 @@ __device__ __forceinline__ void passb_bdf_body(const PassBArgs& a, long lb,
         }
       }
     }
-    rk[p] = r;
     nrm_r += pw * norm2(r);
     if constexpr (MODE == PB_RESIDUAL) {
       if (valid) a.Sout[l * Nk + kap] = r;
     } else {
-      Bm[l * C + c] = r.x;
-      Bm[(NT + l) * C + c] = r.y;
+      if (l < o) rs[l * C + c] = r;
+      const double g = l < o ? 0.0 : gml[l >= o ? l - o : 0];
+      B[l * LD + c] = g * r.x;
+      B[(NT + l) * LD + c] = g * r.y;
     }
   }
   if constexpr (MODE != PB_RESIDUAL) {
     __syncthreads();
-    // 3. step (a) on MFMA
-    dense_gemm<NT>(a.Wf, Bm, Ym);
-    __syncthreads();
-    // 4. step (b): the shifted order-s symbol
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int r16 = lane & 15, q = lane >> 4;
+    const double inv_n = 1.0 / static_cast<double>(N);
+    // 3. step (a) on MFMA (frequency m in row m), step (b) in registers;
+    //    rows m >= N of the operand of step (c) are zero
+    dbl4 acc[SH::PP][SH::CC][2];
+    dft_units_n<NT, false>(B, roots, N, 0, N - o, acc);
+    __syncthreads();  // every wave has read B: the X tile replaces it
 #pragma unroll
-    for (int p = 0; p < PER; ++p) {
-      const int e = threadIdx.x + p * DENSE_THREADS;
-      if (e >= NT * C) break;
-      const int m = e / C, c = e % C;
-      const long kap = k0 + c;
-      const cx<double> E = kap < Nk ? gld(a.E, kap) : mk(0.0, 0.0);
-      const cx<double> z = cmul(gld(a.lam, m), E);
-      const cx<double> y = mk(Ym[m * C + c], Ym[(NT + m) * C + c]);
-      const cx<double> x = bdf_solve<SMAX>(cf, S, z, y, 1.0);
-      Bm[m * C + c] = x.x;
-      Bm[(NT + m) * C + c] = x.y;
+    for (int i = 0; i < SH::PP; ++i) {
+      const int p = wave % SH::WP + SH::WP * i;
+#pragma unroll
+      for (int jb = 0; jb < SH::CC; ++jb) {
+        const int c = 16 * (wave / SH::WP + SH::G * jb) + r16;
+#pragma unroll
+        for (int e = 0; e < EN::N; ++e) {
+          const int m = EN::row(p, e, q);
+          cx<double> x = zero;
+          if (m < N)
+            x = bdf_solve<SMAX>(cf, S, cmul(lamc[m], Ec[c]),
+                                EN::get(acc[i][jb], e), inv_n);
+          B[m * LD + c] = x.x;
+          B[(NT + m) * LD + c] = x.y;
+        }
+      }
     }
     __syncthreads();
-    // 5. step (c) on MFMA
-    dense_gemm<NT>(a.Wi, Bm, Ym);
-    __syncthreads();
-    // 6. correction: start rows keep their residual
+    // 4. step (c) on MFMA (time row o + j in row o + j), then 1/gamma and
+    //    the correction; start rows keep their residual
+    dft_units_n<NT, true>(B, roots, N, N - o, 0, acc);
 #pragma unroll
-    for (int p = 0; p < PER; ++p) {
-      const int e = threadIdx.x + p * DENSE_THREADS;
-      if (e >= NT * C) break;
-      const int l = e / C, c = e % C;
-      const long kap = k0 + c;
-      const bool valid = kap < Nk;
-      const int kl = static_cast<int>(kap % a.nh);
-      const double pw =
-          !valid ? 0.0 : ((kl == 0 || kl == a.nh - 1) ? 1.0 : 2.0);
-      const cx<double> sv =
-          l < o ? rk[p] : mk(Ym[l * C + c], Ym[(NT + l) * C + c]);
-      nrm_s += pw * norm2(sv);
-      if constexpr (MODE == PB_ITERATE) {
-        // start rows become E^{l+1} u0^ exactly rather than U_l + residual
-        cx<double> un = Ut[e] + sv;
-        if (l < o)
-          un = valid ? bdf_pow_times<SMAX - 1>(gld(a.E, kap), l + 1,
-                                               gld(a.u0h, kap))
-                     : zero;
-        nrm_u += pw * norm2(un);
-        if (valid) a.U[l * Nk + kap] = un;
-      } else {
-        if (valid) a.Sout[l * Nk + kap] = sv;
+    for (int i = 0; i < SH::PP; ++i) {
+      const int p = wave % SH::WP + SH::WP * i;
+#pragma unroll
+      for (int jb = 0; jb < SH::CC; ++jb) {
+        const int c = 16 * (wave / SH::WP + SH::G * jb) + r16;
+        const long kap = k0 + c;
+        const bool valid = kap < Nk;
+        const int kl = static_cast<int>((valid ? kap : 0) % a.nh);
+        const double pw =
+            !valid ? 0.0 : ((kl == 0 || kl == a.nh - 1) ? 1.0 : 2.0);
+#pragma unroll
+        for (int e = 0; e < EN::N; ++e) {
+          const int l = EN::row(p, e, q);
+          const cx<double> sv =
+              l < o ? rs[(l < o ? l : 0) * C + c]
+                    : EN::get(acc[i][jb], e) * igml[l >= o ? l - o : 0];
+          nrm_s += pw * norm2(sv);
+          if constexpr (MODE == PB_ITERATE) {
+            // start rows become E^{l+1} u0^ exactly rather than U_l +
+            // residual
+            cx<double> un = Ut[l * C + c] + sv;
+            if (l < o)
+              un = valid ? bdf_pow_times<SMAX - 1>(Ec[c], l + 1,
+                                                   gld(a.u0h, kap))
+                         : zero;
+            nrm_u += pw * norm2(un);
+            if (valid) a.U[l * Nk + kap] = un;
+          } else {
+            if (valid) a.Sout[l * Nk + kap] = sv;
+          }
+        }
       }
     }
   }
-  double acc[4] = {nrm_r, nrm_s, nrm_u, 0.0};
+  double accn[4] = {nrm_r, nrm_s, nrm_u, 0.0};
   double tot[4];
-  block_sum<4, DENSE_THREADS>(acc, red, tot);
+  block_sum<4, DENSE_THREADS>(accn, red, tot);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) a.partials[lb * 4 + j] = tot[j];
@@ -277,7 +326,7 @@ template <int NT, int SC>
 __global__ void __launch_bounds__(DENSE_THREADS)
     passb_bdf_kernel(const PassBArgs* __restrict__ jobs,
                      const int* __restrict__ start, int njobs) {
-  __shared__ double lds[dense_lds_doubles<NT>()];
+  __shared__ double lds[bdf_dft_lds_doubles<NT>()];
   __shared__ double red[(DENSE_THREADS / 64) * 4];
   const int j = find_job(start, njobs);
   const PassBArgs a = jobs[j];
@@ -290,7 +339,7 @@ __global__ void __launch_bounds__(DENSE_THREADS)
 template <int NT, int SC, int MODE>
 __global__ void __launch_bounds__(DENSE_THREADS)
     passb_bdf_kernel1(PassBArgs a) {
-  __shared__ double lds[dense_lds_doubles<NT>()];
+  __shared__ double lds[bdf_dft_lds_doubles<NT>()];
   __shared__ double red[(DENSE_THREADS / 64) * 4];
   passb_bdf_body<NT, SC, MODE>(a, blockIdx.x, lds, red);
 }

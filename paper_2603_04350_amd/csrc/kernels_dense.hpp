@@ -3,14 +3,13 @@
 // Same computation as passb_body (kernels_passb.hpp), with steps (a) and
 // (c) of eq. exp_ParaDiag_steps applied as dense complex products on a
 // tile of kappa columns, written as real GEMMs with block matrices
-// [[Re, -Im], [Im, Re]] on v_mfma_f64_16x16x4.  Two forms:
-//   * first-order schemes (passb_dft_body): the Gamma_alpha scaling
-//     pointwise and the DFT matrix read from a table of roots of unity;
-//   * exponential BDFs (dense_gemm, used by kernels_bdf.hpp): the N-point
-//     transform embedded in 2Nt x 2Nt matrices Wf, Wi built on the host,
-//         Wf[m][l] = gamma_l e^{+2 pi i ml/N} / N,
-//         Wi[l][m] = gamma_l^{-1} e^{-2 pi i ml/N}.
-// The pointwise shifted solve sits between the two products.
+// [[Re, -Im], [Im, Re]] on v_mfma_f64_16x16x4.  The Gamma_alpha scaling is
+// applied pointwise and the entries of the DFT matrix come from a table of
+// roots of unity in LDS, so no matrix is stored or read: for first-order
+// schemes the NT-point transform (passb_dft_body below), for the
+// exponential BDFs (kernels_bdf.hpp) the N-point transform of the unknown
+// rows, N = NT - s + 1.  The pointwise shifted solve sits between the two
+// products.
 //
 // MFMA f64 16x16x4 operand layout on gfx950 (64 lanes, checked on the
 // device): A (16x4) lane i holds A[i%16][i/16]; B (4x16) lane i holds
@@ -22,39 +21,7 @@ namespace expdiag {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-constexpr int DENSE_C = 16;        // kappa columns per workgroup
 constexpr int DENSE_THREADS = 256;  // 4 waves
-
-// D (2NT x 16, LDS, row-major, ld 16) = W (2NT x 2NT, global, row-major) *
-// B (2NT x 16, LDS).  Waves split the 16-row output blocks.
-template <int NT>
-__device__ __forceinline__ void dense_gemm(const double* __restrict__ W,
-                                           const double* Bm, double* Dm) {
-  constexpr int K = 2 * NT;
-  constexpr int RB = K / 16;  // 16-row output blocks
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int r = lane & 15, q = lane >> 4;
-  for (int ib = wave; ib < RB; ib += DENSE_THREADS / 64) {
-    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-    const double* wrow = W + (ib * 16 + r) * K;
-#pragma unroll 8
-    for (int ks = 0; ks < K / 4; ++ks) {
-      const double a = wrow[ks * 4 + q];
-      const double b = Bm[(ks * 4 + q) * DENSE_C + r];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) Dm[(ib * 16 + 4 * j + q) * DENSE_C + r] = acc[j];
-  }
-}
-
-// LDS of the EBDF dense pass B (kernels_bdf.hpp): operand, result and
-// window tiles of DENSE_C columns
-template <int NT>
-constexpr int dense_lds_doubles() {
-  return 6 * NT * DENSE_C;
-}
 
 // ---------------------------------------------------------------------
 // First-order schemes: the time transform as DFT products on FP64 MFMA.
@@ -148,6 +115,76 @@ __device__ __forceinline__ void dft_units(
         if constexpr (SH::TILES == 2)
           acc[i][j][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(
               a1, b[j], acc[i][j][1], 0, 0, 0);
+      }
+    }
+  }
+}
+
+// dft_units for an N-point transform (N <= NT, known at run time) placed
+// in the NT-row tile: the complex matrix entry of row R and column K is
+// w^{((R + roff) (K + koff)) mod N}, w = e^{+2 pi i/N} read from roots[N]
+// (conjugated for CONJ).  The caller's offsets keep both factors
+// non-negative (an index i - o of the unknown rows enters as i + N - o,
+// the same exponent mod N); rows and columns outside the transform
+// receive finite entries that a zero operand row or an ignored output
+// masks.  Along a wave's k-steps the column index
+// advances by 4, so each pair's exponent advances by 4 (R + roff) mod N
+// and is kept reduced with one compare.
+template <int NT, bool CONJ>
+__device__ __forceinline__ void dft_units_n(
+    const double* B, const cx<double>* roots, int N, int roff, int koff,
+    dbl4 (&acc)[DftShape<NT>::PP][DftShape<NT>::CC][2]) {
+  using SH = DftShape<NT>;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int r = lane & 15, q = lane >> 4;
+  int idx0[SH::PP], step[SH::PP], pr0[SH::PP], col[SH::CC];
+#pragma unroll
+  for (int i = 0; i < SH::PP; ++i) {
+    const int p = wave % SH::WP + SH::WP * i;
+    const int row0 = 16 * p + r;  // the lane's A row
+    const int am = row0 % NT + roff;
+    pr0[i] = row0 / NT;  // 1 only for the lower half of NT = 8
+    idx0[i] = (am * (q + koff)) % N;
+    step[i] = (4 * am) % N;
+#pragma unroll
+    for (int j = 0; j < SH::CC; ++j) {
+      acc[i][j][0] = dbl4{0.0, 0.0, 0.0, 0.0};
+      acc[i][j][1] = dbl4{0.0, 0.0, 0.0, 0.0};
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < SH::CC; ++j)
+    col[j] = 16 * (wave / SH::WP + SH::G * j) + r;
+  // the real (pc = 0) and imaginary (pc = 1) halves of the operand rows
+#pragma unroll
+  for (int pc = 0; pc < 2; ++pc) {
+    int idx[SH::PP];
+#pragma unroll
+    for (int i = 0; i < SH::PP; ++i) idx[i] = idx0[i];
+#pragma unroll 2
+    for (int ks = 0; ks < NT / 4; ++ks) {
+      const int k = pc * NT + 4 * ks + q;
+      double b[SH::CC];
+#pragma unroll
+      for (int j = 0; j < SH::CC; ++j) b[j] = B[k * SH::LD + col[j]];
+#pragma unroll
+      for (int i = 0; i < SH::PP; ++i) {
+        cx<double> w = roots[idx[i]];
+        if (CONJ) w.y = -w.y;
+        const double a0 = pr0[i] == pc ? w.x : (pr0[i] == 0 ? -w.y : w.y);
+        const double a1 = pc == 1 ? w.x : w.y;
+#pragma unroll
+        for (int j = 0; j < SH::CC; ++j) {
+          acc[i][j][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b[j],
+                                                              acc[i][j][0], 0,
+                                                              0, 0);
+          if constexpr (SH::TILES == 2)
+            acc[i][j][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                a1, b[j], acc[i][j][1], 0, 0, 0);
+        }
+        const int nx = idx[i] + step[i];
+        idx[i] = nx >= N ? nx - N : nx;
       }
     }
   }

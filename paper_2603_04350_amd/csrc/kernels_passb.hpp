@@ -59,8 +59,7 @@ struct PassBArgs {
   Ctl* hmirror;           // host-mapped copy of *ctl (nullable)
   double* hist;           // [max_iter][2] (rel, ||R||) history (nullable)
   const cx<double>* tw;
-  const double* Wf;  // dense time transform [2Nt][2Nt] (dense variant)
-  const double* Wi;
+  const cx<double>* roots;  // e^{+2 pi i j/N}, j < N (EBDF dense transform)
   long Nk;
   int nh;
   int nonlinear;
