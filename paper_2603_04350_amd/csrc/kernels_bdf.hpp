@@ -350,8 +350,8 @@ __global__ void __launch_bounds__(DENSE_THREADS)
 // are window rows j + o).  Rows j - 1 .. j - s of the residual come from the
 // neighbouring threads through the LDS tile; the start rows are handled by
 // the thread with t = 0 of each column.  All of a thread's global loads are
-// issued before any is used (columns past Nk load column Nk - 1 and are
-// masked afterwards).
+// issued before any is used (columns past Nk load column Nk - 1, carry its
+// finite values through, weigh 0 in the norms and store nothing).
 template <int N, int SC, int MODE>
 __device__ __forceinline__ void passb_bdf_fft_body(const PassBArgs& a,
                                                    long lb, cx<double>* lds,
@@ -433,21 +433,17 @@ __device__ __forceinline__ void passb_bdf_fft_body(const PassBArgs& a,
     em = cmul(em, E);
     cx<double> rsm = w[m];
     if constexpr (MODE == PB_ITERATE || MODE == PB_RESIDUAL) rsm = em - w[m];
-    if (!valid) rsm = zero;
     nrm_r += pw * norm2(rsm);
     if constexpr (MODE != PB_RESIDUAL) nrm_s += pw * norm2(rsm);
     if constexpr (MODE == PB_ITERATE) {
-      nrm_u += pw * norm2(valid ? em : zero);
+      nrm_u += pw * norm2(em);
       if (valid) gst(a.U, m * Nk + kap, em);
     } else {
       if (valid) gst(a.Sout, m * Nk + kap, rsm);
     }
   }
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    if (!valid) v[r] = zero;
-    nrm_r += pw * norm2(v[r]);
-  }
+  for (int r = 0; r < R; ++r) nrm_r += pw * norm2(v[r]);
   if constexpr (MODE == PB_RESIDUAL) {
     if (valid) {
 #pragma unroll

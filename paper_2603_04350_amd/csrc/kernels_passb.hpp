@@ -274,7 +274,10 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
   const long Nk = a.Nk;
   const long kap = lb * C + c;
   const bool valid = kap < Nk;
-  const long kc = valid ? kap : Nk - 1;  // in-bounds column for the loads
+  // Columns past Nk load column Nk - 1 (finite values of the same
+  // arithmetic), carry them through unmasked, weigh 0 in the norms (pw) and
+  // store nothing: every column's transform is independent of the others.
+  const long kc = valid ? kap : Nk - 1;
   const int kl = static_cast<int>(kc) % a.nh;
   const double pw = (!valid) ? 0.0 : ((kl == 0 || kl == a.nh - 1) ? 1.0 : 2.0);
   const cx<double> zero = mk(0.0, 0.0);
@@ -338,15 +341,14 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
   if constexpr (MODE == PB_PRECOND) {
 #pragma unroll
     for (int s = 0; s < R; ++s) {
-      const cx<double> r = valid ? u[s] : zero;
-      nrm_r += pw * norm2(r);
-      v[s] = r * gam(s);
+      nrm_r += pw * norm2(u[s]);
+      v[s] = u[s] * gam(s);
     }
   } else {
     // residual, U part (rows of U, or of the Krylov vector v for PB_OPAPPLY)
 #pragma unroll
     for (int s = 0; s < R; ++s) {
-      u[s] = valid ? cvt<double>(uin[s]) : zero;
+      u[s] = cvt<double>(uin[s]);
       if constexpr (!GPREV) lds[(t + s * TPL) * LS + c] = u[s];
     }
     if constexpr (!GPREV) __syncthreads();
@@ -355,11 +357,11 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
       const int l = t + s * TPL;
       cx<double> prev;
       if constexpr (GPREV)
-        prev = (l == 0) ? first : (valid ? cvt<double>(upin[s]) : zero);
+        prev = (l == 0) ? first : cvt<double>(upin[s]);
       else
         prev = (l == 0) ? first : lds[(l - 1) * LS + c];
       cx<double> n_cur = zero;
-      if (nl && valid && (MODE != PB_OPAPPLY || l >= 1 || a.same_slice))
+      if (nl && (MODE != PB_OPAPPLY || l >= 1 || a.same_slice))
         n_cur = cvt<double>(nr[s]);
       // PB_OPAPPLY, (Q - G'(U)) v: v_l - E v_{l-1} - (c1 J_l + c2 J_{l-1})
       // with J_l = FFT[N'(u_{l-1}) v_{l-1}] (J_0 = 0: u_0 is fixed); else
@@ -386,7 +388,6 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
     }
 #pragma unroll
     for (int s = 0; s < R; ++s) {
-      if (!valid) v[s] = zero;  // columns past Nk carry nothing
       nrm_r += pw * norm2(v[s]);
       v[s] = v[s] * gam(s);
     }
