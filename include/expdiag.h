@@ -278,8 +278,9 @@ int expdiag_profile_enable(expdiag_t h, int mask);
 int expdiag_profile_read(expdiag_t h, double* ms, long* launches,
                          double* bytes, long* timed, int nclass);
 
-/* Choose between replaying the captured hipGraph of one iteration (on, the
- * default) and launching the same kernels one by one (off). */
+/* Choose between replaying the captured hipGraph of one iteration (on) and
+ * launching the same kernels one by one (off, the default: on MI355X the
+ * replay measured slower at every iterate size). */
 int expdiag_set_graph(expdiag_t h, int on);
 
 /* Time transform of steps (a) and (c): 0 = radix-8/4/2 FFT along time in

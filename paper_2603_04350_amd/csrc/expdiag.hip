@@ -1122,18 +1122,15 @@ void plan_iteration(Plan& P, expdiag_ctx* h, Ctl* ctl, Ctl* mirror,
   P.cur_hm = nullptr;
 }
 
-// Algorithmic bytes of one iteration of a plan.
-double plan_bytes(const Plan& P) {
-  double b = 0;
-  for (const auto& g : P.groups) b += g.bytes;
-  return b;
-}
-
-// Replaying a captured iteration pays off while launches cost more than
-// the kernels (small iterates); for large ones the captured graph measured
-// slower than plain launches on this GPU (~5 us per iteration of five
-// launches), so it is used only below this size.
-constexpr double GRAPH_MAX_BYTES = 64e6;
+// Whether an iteration replays its captured graph by default.  Measured on
+// this GPU with the host enqueueing iterations ahead of the device, the
+// replay was slower than launching the same kernels one by one at every
+// iterate size, by 3.4-6.5 us per iteration (the 1D 64 x 16 window to the
+// 256^2 x 64 instance, fp64 and mixed), with the kernels' own durations
+// unchanged: the graph stays captured for callers that ask for it
+// (expdiag_set_graph), and a batch measures both on its inputs
+// (expdiag_batch_autotune).
+constexpr bool GRAPH_REPLAY_DEFAULT = false;
 
 size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
@@ -2329,7 +2326,7 @@ int create_impl(const expdiag_grid* g, int Nt, double dt, double alpha,
       h->err.clear();
       (void)hipGetLastError();
     } else {
-      h->use_graph = plan_bytes(h->plan) < GRAPH_MAX_BYTES;
+      h->use_graph = GRAPH_REPLAY_DEFAULT;
     }
   }
   if (rc != 0) {
