@@ -161,9 +161,13 @@ __device__ __forceinline__ void apply_twiddles(cx<T>* a, cx<T> w1) {
 // of this thread's line; element p lives at lds[slot<PAD>(p) * stride].
 // w1 is this stage's base twiddle (unused when NS == 1).  OUT_LDS: also
 // leave the natural-order result in LDS (a barrier follows before anyone
-// reads it).
+// reads it).  PPOFF > 0: two LDS images PPOFF elements apart, exchanges
+// alternating between them starting with image BUF; an exchange then
+// needs only the barrier between its writes and reads, because the next
+// exchange writes the other image and the one after waits behind that
+// exchange's barrier, which every thread reaches only after its reads.
 template <typename T, int L, int R, int S, int NS, bool PAD, bool OUT_LDS,
-          bool WAVE, int ST = 0, bool PRE = false>
+          bool WAVE, int ST = 0, bool PRE = false, int PPOFF = 0, int BUF = 0>
 __device__ __forceinline__ void fft_stages(cx<T> (&v)[R], cx<T> w1,
                                            cx<T>* lds, int stride, int t,
                                            const cx<T>* tw) {
@@ -187,6 +191,7 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[R], cx<T> w1,
         lds[slot<PAD>(t + s * TPL) * stride] = v[s];
     }
   } else {
+    cx<T>* img = lds + BUF * PPOFF;
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       const int b = t + q * TPL;
@@ -199,7 +204,7 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[R], cx<T> w1,
       const int base = (b / NS) * NS * r + k;
 #pragma unroll
       for (int s = 0; s < r; ++s)
-        lds[slot<PAD>(base + s * NS) * stride] = a[s];
+        img[slot<PAD>(base + s * NS) * stride] = a[s];
     }
     // next stage: span NS*r, radix R, one butterfly (index t) per thread;
     // PRE: `tw` holds the stages' base twiddles (forward sign), already in
@@ -213,10 +218,10 @@ __device__ __forceinline__ void fft_stages(cx<T> (&v)[R], cx<T> w1,
       w2 = twid<S>(tw, (t & (NS2 - 1)) << sh2);
     line_sync<WAVE>();
 #pragma unroll
-    for (int s = 0; s < R; ++s) v[s] = lds[slot<PAD>(t + s * TPL) * stride];
-    if constexpr (NS2 * R < L || OUT_LDS) line_sync<WAVE>();
-    fft_stages<T, L, R, S, NS2, PAD, OUT_LDS, WAVE, ST + 1, PRE>(
-        v, w2, lds, stride, t, tw);
+    for (int s = 0; s < R; ++s) v[s] = img[slot<PAD>(t + s * TPL) * stride];
+    if constexpr ((NS2 * R < L && PPOFF == 0) || OUT_LDS) line_sync<WAVE>();
+    fft_stages<T, L, R, S, NS2, PAD, OUT_LDS, WAVE, ST + 1, PRE, PPOFF,
+               (PPOFF > 0 ? 1 - BUF : 0)>(v, w2, lds, stride, t, tw);
   }
 }
 
@@ -275,13 +280,23 @@ __device__ __forceinline__ void fft_line(cx<T> (&v)[R], cx<T>* lds,
 }
 
 // fft_line with the stage twiddles already loaded (fft_stage_twiddles).
-template <typename T, int L, int S, int R>
+// PPOFF > 0: exchanges alternate between two LDS images PPOFF elements
+// apart, the first in image BUF (fft_stages); the transform makes
+// fft_exchanges<L, R>() of them, so a following transform that starts in
+// the other image than the last one written needs no barrier before it.
+template <typename T, int L, int S, int R, int PPOFF = 0, int BUF = 0>
 __device__ __forceinline__ void fft_line_pre(cx<T> (&v)[R], cx<T>* lds,
                                              int stride, int t,
                                              const cx<T>* wst) {
   if constexpr (L > 1)
-    fft_stages<T, L, R, S, 1, false, false, false, 0, true>(
+    fft_stages<T, L, R, S, 1, false, false, false, 0, true, PPOFF, BUF>(
         v, mk<T>(1, 0), lds, stride, t, wst);
+}
+
+// Trips through LDS of a length-L transform with R elements per thread.
+template <int L, int R>
+constexpr int fft_exchanges() {
+  return L > 1 ? fft_stage_count<L, R>() - 1 : 0;
 }
 
 }  // namespace expdiag

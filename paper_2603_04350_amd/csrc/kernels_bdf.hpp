@@ -456,10 +456,12 @@ __device__ __forceinline__ void passb_bdf_fft_body(const PassBArgs& a,
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) v[r] = v[r] * gam(r);
-  if constexpr (MODE != PB_PRECOND) __syncthreads();  // tile reads done
-
-  // step (a): forward time transform with the + sign
-  fft_line_pre<double, N, 1>(v, lds + c, LS, t, wst);
+  // step (a): forward time transform with the + sign; its exchanges
+  // alternate between the two LDS images starting with the second, which
+  // the residual's row reads did not use, and step (c) continues the
+  // alternation (fft_line_pre), so neither needs a barrier before it
+  constexpr int XA = fft_exchanges<N, R>();
+  fft_line_pre<double, N, 1, R, SH::LDS, 1>(v, lds + c, LS, t, wst);
   // step (b): 1/(N d(lambda_m E)), m = t + r TPL
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -475,9 +477,9 @@ __device__ __forceinline__ void passb_bdf_fft_body(const PassBArgs& a,
     }
     v[r] = bdf_solve<SMAX>(cf, S, cmul(lam, E), v[r], 1.0 / N);
   }
-  __syncthreads();
   // step (c): inverse time transform with the - sign, then Gamma^{-1}
-  fft_line_pre<double, N, -1>(v, lds + c, LS, t, wst);
+  fft_line_pre<double, N, -1, R, SH::LDS, (1 + XA) % 2>(v, lds + c, LS, t,
+                                                         wst);
 
   if constexpr (MODE == PB_ITERATE) {
 #pragma unroll
@@ -511,7 +513,7 @@ __global__ void __launch_bounds__(PassBShape<N>::THREADS,
     passb_bdf_fft_kernel(const PassBArgs* __restrict__ jobs,
                          const int* __restrict__ start, int njobs) {
   using SH = PassBShape<N>;
-  __shared__ cx<double> lds[SH::LDS];
+  __shared__ cx<double> lds[2 * SH::LDS];  // two images (fft_line_pre)
   double* red = reinterpret_cast<double*>(lds);
   const int j = find_job(start, njobs);
   const PassBArgs a = jobs[j];
@@ -526,7 +528,7 @@ __global__ void __launch_bounds__(PassBShape<N>::THREADS,
                                   PassBShape<N>::WAVES)
     passb_bdf_fft_kernel1(PassBArgs a) {
   using SH = PassBShape<N>;
-  __shared__ cx<double> lds[SH::LDS];
+  __shared__ cx<double> lds[2 * SH::LDS];  // two images (fft_line_pre)
   double* red = reinterpret_cast<double*>(lds);
   passb_bdf_fft_body<N, SC, MODE>(a, blockIdx.x, lds, red);
 }

@@ -403,13 +403,14 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
       block_sum<4, SH::THREADS>(acc, red, a.partials + lb * 4);
       return;
     }
-    // the transform's first exchange may overwrite rows still being read
-    // (uniform condition: a barrier only where the residual used LDS)
-    if (!GPREV || two) __syncthreads();
   }
 
-  // step (a): forward time transform with the + sign
-  fft_line_pre<double, NT, 1>(v, lds + c, LS, t, wst);
+  // step (a): forward time transform with the + sign.  Its exchanges
+  // alternate between the tile's two LDS images starting with the second,
+  // which the residual did not use, so no barrier precedes it; step (c)
+  // continues the alternation, so none separates the two transforms.
+  constexpr int XA = fft_exchanges<NT, R>();
+  fft_line_pre<double, NT, 1, R, SH::LDS, 1>(v, lds + c, LS, t, wst);
   // step (b): shifted solves, 1/(Nt (1 - lambda_m E)), m = t + s TPL
 #pragma unroll
   for (int s = 0; s < R; ++s) {
@@ -434,13 +435,13 @@ __device__ __forceinline__ void passb_body(const PassBArgs& a, long lb,
     inv = fma(fma(-den, inv, 1.0), inv, inv);
     v[s] = cmul(v[s], mk(dr * inv, -di * inv));
   }
-  __syncthreads();
   // step (c): inverse time transform with the - sign, then Gamma^{-1}.  A
   // fresh copy of the lane index makes it form its LDS addresses anew
   // rather than hold step (a)'s (the same ones) across step (b).
   int t2 = t;
   asm volatile("" : "+v"(t2));
-  fft_line_pre<double, NT, -1>(v, lds + c, LS, t2, wst);
+  fft_line_pre<double, NT, -1, R, SH::LDS, (1 + XA) % 2>(v, lds + c, LS, t2,
+                                                          wst);
 
   double sum0 = 0.0;  // sum_l Re U^_l(kappa = 0), for the IF1 mean Jacobian
   if constexpr (MODE == PB_ITERATE) {
@@ -481,7 +482,7 @@ __global__ void __launch_bounds__(PassBShape<NT>::THREADS,
   using SH = PassBShape<NT>;
   static_assert(SH::LDS * 2 >= ((SH::THREADS + 63) / 64) * 4,
                 "reduction scratch fits the tile");
-  __shared__ cx<double> lds[SH::LDS];
+  __shared__ cx<double> lds[2 * SH::LDS];  // two images (fft_line_pre)
   double* red = reinterpret_cast<double*>(lds);
   // XCD-contiguous tiles: a tile's fp32 rows can be half a 128-byte line
   // (C = 8 columns at Nt = 128), whose other half the next tile reads
@@ -630,7 +631,7 @@ __global__ void __launch_bounds__(PassBShape<NT>::THREADS,
                                   PassBShape<NT>::WAVES)
     passb_kernel1(PassBArgs a) {
   using SH = PassBShape<NT>;
-  __shared__ cx<double> lds[SH::LDS];
+  __shared__ cx<double> lds[2 * SH::LDS];  // two images (fft_line_pre)
   double* red = reinterpret_cast<double*>(lds);
   passb_body<NT, MODE, TN, CPLX>(a, xcd_block(blockIdx.x, gridDim.x),
                                  static_cast<const TN*>(a.Nh), a.U, a.U, lds,
