@@ -283,6 +283,15 @@ int expdiag_profile_read(expdiag_t h, double* ms, long* launches,
  * replay measured slower at every iterate size). */
 int expdiag_set_graph(expdiag_t h, int on);
 
+/* Start this handle's solves (expdiag_iterate, expdiag_gmres,
+ * expdiag_bicgstab) from the all-zero space-time iterate whatever U holds
+ * (on), or from U as passed (off, the default).  With it
+ * on, U is output only: its contents on entry are not read, and the forward
+ * spatial transform of the guess, which would be zero, is replaced by
+ * clearing the spectral iterate.  Results equal those of a solve from a
+ * zeroed U bit for bit.  EINVAL for a null handle. */
+int expdiag_set_zero_guess(expdiag_t h, int on);
+
 /* Time transform of steps (a) and (c): 0 = radix-8/4/2 FFT along time in
  * registers and LDS (any Nt), 1 = dense complex Nt x Nt GEMM on FP64 MFMA
  * (8 <= Nt <= 128).  Both compute the same operator; results agree to
@@ -364,6 +373,12 @@ int expdiag_batch_autotune(expdiag_batch_t b, const double* const* u0s,
                            double* ms_launch);
 /* 1 if the batch's iterations replay its captured graph, else 0. */
 int expdiag_batch_graph(expdiag_batch_t b);
+
+/* expdiag_set_zero_guess for every later solve of a batch
+ * (expdiag_batch_iterate, expdiag_batch_iterate_each): Us are output only
+ * and each instance starts from the all-zero iterate; the handles' own
+ * setting is neither used nor changed.  EINVAL for a null batch. */
+int expdiag_batch_set_zero_guess(expdiag_batch_t b, int on);
 
 /* ---- Serving: continuous batching of solve requests -------------------
  * A server owns a host thread that admits submitted requests in arrival

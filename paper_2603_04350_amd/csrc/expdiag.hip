@@ -69,11 +69,12 @@ struct EventPair {
 // fp32 copies (a ColJob with `outer` complex elements)
 enum Kind {
   K_ROW = 0, K_COL = 1, K_PASSB = 2, K_XROW = 3, K_XCOL = 4, K_XNARROW = 5,
-  K_XWIDEN = 6
+  K_XWIDEN = 6, K_XZERO = 7
 };
 bool kind_rows(int k) { return k == K_ROW || k == K_XROW; }
 bool kind_cols(int k) {
-  return k == K_COL || k == K_XCOL || k == K_XNARROW || k == K_XWIDEN;
+  return k == K_COL || k == K_XCOL || k == K_XNARROW || k == K_XWIDEN ||
+         k == K_XZERO;
 }
 
 // One launch of a plan: jobs of the same kernel signature.
@@ -193,6 +194,8 @@ struct expdiag_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   bool use_graph = true;
+  // solves start from U = 0 whatever U holds (expdiag_set_zero_guess)
+  bool zero_guess = false;
 
   // profiling
   bool prof = false;
@@ -838,6 +841,21 @@ __global__ void widen_bulk_kernel(const Ctl* __restrict__ ctl,
   if (i < n) out[i] = cvt<double>(in[i]);
 }
 
+// n 8-byte words of device memory set to zero by a kernel (a memset node
+// would misbehave where a caller captures the stream into a graph)
+__global__ void zero_words_kernel(double* __restrict__ p, long n) {
+  const long e = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = 0.0;
+}
+
+int zero_words(expdiag_ctx* h, void* p, long n, hipStream_t st) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(zero_words_kernel, dim3((n + 255) / 256), dim3(256), 0,
+                     st, static_cast<double*>(p), n);
+  HIPCHK(h, hipGetLastError());
+  return 0;
+}
+
 int enter_bulk_state(expdiag_ctx* h, hipStream_t st) {
   if (!bulk_u32(h)) return 0;
   const long n = static_cast<long>(h->Nt) * h->Nk;
@@ -854,6 +872,21 @@ int leave_bulk_state(expdiag_ctx* h, const Ctl* ctl, hipStream_t st) {
                      st, ctl, u32_view(h), h->Uh, n);
   HIPCHK(h, hipGetLastError());
   return 0;
+}
+
+// The initial guess as the solve's spectral iterate Uh (and, with `bulk`,
+// its fp32 bulk copy where the instance keeps one): the forward transform
+// of U on h's stream, or, for a solve from U = 0 (`zero`), zeros, which is
+// what that transform would give, without reading U.
+int enter_guess(expdiag_ctx* h, const double* U, bool bulk, bool zero) {
+  const long n = static_cast<long>(h->Nt) * h->Nk;
+  if (zero) {
+    RCHK(zero_words(h, h->Uh, 2 * n, h->stream));
+    if (bulk && bulk_u32(h)) RCHK(zero_words(h, u32_view(h), n, h->stream));
+    return 0;
+  }
+  RCHK(fwd_slices<ROW_R2C>(h, U, h->Uh, h->Nt));
+  return bulk ? enter_bulk_state(h, h->stream) : 0;
 }
 
 // u0 -> u0h, N^_0 = FFT N(u0) (fp64 slot 0) and, for mixed precision, its
@@ -1370,6 +1403,16 @@ __global__ void widen_kernel_jt(const ColJob* __restrict__ jobs,
         cvt<double>(static_cast<const cx<float>*>(jb.in)[e]);
 }
 
+// zeros into job j's `outer` 8-byte words at `out`
+__global__ void zero_kernel_jt(const ColJob* __restrict__ jobs,
+                               const int* __restrict__ start, int njobs) {
+  const int i = find_job(start, njobs);
+  const ColJob jb = jobs[i];
+  const long e = static_cast<long>(blockIdx.x - start[i]) * blockDim.x +
+                 threadIdx.x;
+  if (e < jb.outer) static_cast<double*>(jb.out)[e] = 0.0;
+}
+
 // fp64 -> fp32 copies, job j copying `outer` complex elements
 __global__ void narrow_kernel_jt(const ColJob* __restrict__ jobs,
                                  const int* __restrict__ start, int njobs) {
@@ -1420,7 +1463,11 @@ void plan_xfwd(Plan& P, expdiag_ctx* h, int stage0, int rowmode,
 
 // What expdiag_iterate does before its iterations (prepare_u0 and the
 // forward transform of U), as plan stages 0..3; real states only.
-void plan_entry(Plan& P, expdiag_ctx* h, const double* u0, const double* U) {
+// Entry transforms of one instance as plan stages; `zero`: the solve starts
+// from U = 0, so its spectral iterate (and fp32 bulk copy) are cleared
+// rather than transformed from U (enter_guess)
+void plan_entry(Plan& P, expdiag_ctx* h, const double* u0, const double* U,
+                bool zero) {
   plan_xfwd(P, h, 0, ROW_R2C, u0, h->u0h, 1);
   if (h->nonlinear && h->scheme != EXPDIAG_IF1) {
     plan_xfwd(P, h, 0, ROW_NR2C, u0, h->Nh, 1);
@@ -1432,10 +1479,20 @@ void plan_entry(Plan& P, expdiag_ctx* h, const double* u0, const double* U) {
                         static_cast<int>((h->Nk + 255) / 256));
     }
   }
+  const long n = static_cast<long>(h->Nt) * h->Nk;
+  if (zero) {
+    Group& g = plan_group(P, 3, K_XZERO, 0, 0, 0, 0, 0);
+    g.cj.push_back(make_col(nullptr, h->Uh, 2 * n, 1, 1.0, nullptr, -1));
+    g.start.push_back(g.start.back() + static_cast<int>((2 * n + 255) / 256));
+    if (bulk_u32(h)) {
+      g.cj.push_back(make_col(nullptr, u32_view(h), n, 1, 1.0, nullptr, -1));
+      g.start.push_back(g.start.back() + static_cast<int>((n + 255) / 256));
+    }
+    return;
+  }
   plan_xfwd(P, h, 0, ROW_R2C, U, h->Uh, h->Nt);
   if (bulk_u32(h)) {
     Group& g = plan_group(P, 3, K_XNARROW, 0, 0, 0, 0, 0);
-    const long n = static_cast<long>(h->Nt) * h->Nk;
     g.cj.push_back(make_col(h->Uh, u32_view(h), n, 1, 1.0, nullptr, -1));
     g.start.push_back(g.start.back() + static_cast<int>((n + 255) / 256));
   }
@@ -1517,6 +1574,10 @@ int plan_launch_x(expdiag_ctx* ph, Plan& P, hipStream_t st,
       ok = true;
     } else if (g.kind == K_XWIDEN) {
       hipLaunchKernelGGL(widen_kernel_jt, dim3(grid), dim3(256), 0, st,
+                         static_cast<const ColJob*>(g.djobs), g.dstart, nj);
+      ok = true;
+    } else if (g.kind == K_XZERO) {
+      hipLaunchKernelGGL(zero_kernel_jt, dim3(grid), dim3(256), 0, st,
                          static_cast<const ColJob*>(g.djobs), g.dstart, nj);
       ok = true;
     }
@@ -2372,6 +2433,12 @@ int expdiag_set_graph(expdiag_t h, int on) {
   return EXPDIAG_OK;
 }
 
+int expdiag_set_zero_guess(expdiag_t h, int on) {
+  if (h == nullptr) return EXPDIAG_EINVAL;
+  h->zero_guess = on != 0;
+  return EXPDIAG_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -2493,8 +2560,7 @@ int expdiag_iterate(expdiag_t h, const double* u0, double* U, int max_iter,
     return fail(h, EXPDIAG_EINVAL, "max_iter must be 1..%d", HIST_CAP);
   if (!(tol >= 0.0)) return fail(h, EXPDIAG_EINVAL, "tol must be >= 0");
   RCHK(prepare_u0(h, u0));
-  RCHK(fwd_slices<ROW_R2C>(h, U, h->Uh, h->Nt));
-  RCHK(enter_bulk_state(h, h->stream));
+  RCHK(enter_guess(h, U, true, h->zero_guess));
   prof_begin(h);
   *h->h_ctl = initial_ctl(h, max_iter, tol);
   *h->h_mirror = *h->h_ctl;

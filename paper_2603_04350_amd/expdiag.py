@@ -48,7 +48,8 @@ EXPORTED = (
     "expdiag_autotune", "expdiag_iterate_noalloc", "expdiag_get_tuning",
     "expdiag_set_tuning",
     "expdiag_batch_autotune", "expdiag_batch_graph",
-    "expdiag_server_autotune",
+    "expdiag_server_autotune", "expdiag_set_zero_guess",
+    "expdiag_batch_set_zero_guess",
 )
 
 
@@ -118,6 +119,8 @@ def load(path: str = LIB_PATH):
                                        ctypes.POINTER(cd),
                                        ctypes.POINTER(ctypes.c_long), ci]
     L.expdiag_set_graph.argtypes = [vp, ci]
+    L.expdiag_set_zero_guess.argtypes = [vp, ci]
+    L.expdiag_batch_set_zero_guess.argtypes = [vp, ci]
     L.expdiag_set_time_variant.argtypes = [vp, ci]
     L.expdiag_get_time_variant.argtypes = [vp]
     L.expdiag_autotune.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ci),
@@ -404,6 +407,9 @@ class Solver:
     def iterate(self, u0, U, max_iter=200, tol=1e-11):
         return expdiag_iterate(self.h, u0, U, max_iter, tol)
 
+    def set_zero_guess(self, on=True):
+        return expdiag_set_zero_guess(self.h, on)
+
     def gmres(self, u0, U, restart=20, max_iter=400, tol=1e-10):
         return expdiag_gmres(self.h, u0, U, restart, max_iter, tol)
 
@@ -416,6 +422,10 @@ class Solver:
 
 def expdiag_set_graph(h, on=True):
     return _check(load().expdiag_set_graph(h, 1 if on else 0), h)
+
+
+def expdiag_set_zero_guess(h, on=True):
+    return _check(load().expdiag_set_zero_guess(h, 1 if on else 0), h)
 
 
 # -- batching -----------------------------------------------------------------
@@ -496,6 +506,13 @@ def expdiag_batch_graph(b):
     return bool(load().expdiag_batch_graph(b))
 
 
+def expdiag_batch_set_zero_guess(b, on=True):
+    rc = load().expdiag_batch_set_zero_guess(b, 1 if on else 0)
+    if rc != EXPDIAG_OK:
+        raise ExpdiagError(rc, strerror(rc))
+    return rc
+
+
 class Batch:
     """Owns a batch over existing Solvers (which stay owned by the caller)."""
 
@@ -511,6 +528,9 @@ class Batch:
 
     def autotune(self, u0s, Us, cache_path=None):
         return expdiag_batch_autotune(self.b, u0s, Us, cache_path)
+
+    def set_zero_guess(self, on=True):
+        return expdiag_batch_set_zero_guess(self.b, on)
 
     def close(self):
         if self.b is not None:

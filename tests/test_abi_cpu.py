@@ -126,6 +126,8 @@ def test_null_handle_calls_are_rejected(lib):
     assert lib.expdiag_iterate_noalloc(None, 8, 0.1, 1e-2, 1, None, None,
                                        None, None, 10, 0.0, None, None) == \
         X.EXPDIAG_EINVAL
+    assert lib.expdiag_set_zero_guess(None, 1) == X.EXPDIAG_EINVAL
+    assert lib.expdiag_batch_set_zero_guess(None, 1) == X.EXPDIAG_EINVAL
     assert lib.expdiag_destroy(None) == X.EXPDIAG_OK
 
 
