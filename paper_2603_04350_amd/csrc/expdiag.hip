@@ -124,6 +124,11 @@ struct Plan {
   size_t cap = 0;
   // arena and staging provided by the caller: never grown or freed here
   bool fixed = false;
+  // the pass-B groups' convergence reductions as one list on the device,
+  // reduced by one launch after the last pass-B group of an iteration
+  void* dred_pb = nullptr;
+  int nred_pb = 0;
+  double red_pb_bytes = 0;
 };
 
 }  // namespace
@@ -1225,12 +1230,30 @@ int plan_upload(expdiag_ctx* h, Plan& P, hipStream_t st) {
     g.dstart = reinterpret_cast<int*>(P.arena + off);
     off += align256(sb);
     g.dred = nullptr;
-    if (!g.red.empty()) {
+    if (!g.red.empty() && g.kind != K_PASSB) {
       const size_t rb = g.red.size() * sizeof(PassBArgs);
       std::memcpy(P.staging + off, g.red.data(), rb);
       g.dred = P.arena + off;
       off += align256(rb);
     }
+  }
+  // the pass-B groups' reductions in one list (the space the per-group
+  // sizes above reserved covers it)
+  P.dred_pb = nullptr;
+  P.nred_pb = 0;
+  P.red_pb_bytes = 0;
+  size_t rb_pb = 0;
+  for (auto& g : P.groups) {
+    if (g.kind != K_PASSB || g.red.empty()) continue;
+    const size_t rb = g.red.size() * sizeof(PassBArgs);
+    std::memcpy(P.staging + off + rb_pb, g.red.data(), rb);
+    rb_pb += rb;
+    P.nred_pb += static_cast<int>(g.red.size());
+    P.red_pb_bytes += static_cast<double>(g.grid()) * 32;
+  }
+  if (rb_pb > 0) {
+    P.dred_pb = P.arena + off;
+    off += align256(rb_pb);
   }
   HIPCHK(h, hipMemcpyAsync(P.arena, P.staging, off, hipMemcpyHostToDevice, st));
   P.uploaded = true;
@@ -1369,21 +1392,24 @@ int plan_launch(expdiag_ctx* ph, Plan& P, hipStream_t st,
           });
         }
       }
-      if (ok && !g.red.empty()) {
-        hipError_t e0 = hipGetLastError();
-        if (e0 != hipSuccess)
-          return fail(ph, EXPDIAG_EHIP, "plan launch: %s",
-                      hipGetErrorString(e0));
-        const int nred = static_cast<int>(g.red.size());
-        ProfScope pr(ph, P_RED, static_cast<double>(grid) * 32, true);
-        klaunch(pr, ctl_reduce_kernel, dim3(nred), dim3(CTL_THREADS), st,
-                static_cast<const PassBArgs*>(g.dred), nred);
-      }
     }
     if (!ok) return fail(ph, EXPDIAG_EUNSUPPORTED, "plan length %d", g.len);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
       return fail(ph, EXPDIAG_EHIP, "plan launch: %s", hipGetErrorString(e));
+  }
+  // the reductions that follow pass B (mixed instances, whose next first
+  // stage reads the phase; instances with no pass A) in one launch after
+  // the last pass-B group: pass B is the plan's last stage and every
+  // instance has its pass B in exactly one group
+  if (P.nred_pb > 0) {
+    ProfScope pr(ph, P_RED, P.red_pb_bytes, true);
+    klaunch(pr, ctl_reduce_kernel, dim3(P.nred_pb), dim3(CTL_THREADS), st,
+            static_cast<const PassBArgs*>(P.dred_pb), P.nred_pb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+      return fail(ph, EXPDIAG_EHIP, "reduce launch: %s",
+                  hipGetErrorString(e));
   }
   return 0;
 }
