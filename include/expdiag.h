@@ -217,7 +217,9 @@ int expdiag_iterate(expdiag_t h, const double* u0, double* U, int max_iter,
  * set to A^m u0 first); for
  * nonlinear problems, Newton's method on R(U) = 0 whose correction
  * equations (Q - G'(U)) d = R(U) are solved by the same preconditioned
- * GMRES with forcing term min(1e-3, ||R_j|| / ||R_0||).
+ * GMRES with Eisenstat and Walker's forcing terms (choice 2: eta_0 = 0.1,
+ * eta_k = 0.9 (||R_k|| / ||R_{k-1}||)^2 capped at 0.1, their safeguard,
+ * and eta_k >= tol ||R_0|| / (2 ||R_k||)).
  *   restart   Krylov space size, 1 <= restart <= gmres_restart of create
  *   max_iter  cap on total GMRES iterations
  *   tol       linear: ||Q_alpha^{-1}(f - QU)|| <= tol ||Q_alpha^{-1} f||;
