@@ -354,6 +354,9 @@ void prof_resolve(expdiag_ctx* ph) {
     for (const auto& j : r.jobs) {
       const Ctl c = read_mirror(j.hm);
       if (r.k > c.iters) continue;
+      // the first iteration of a solve from zero skips its pass A
+      if (r.k == 1 && c.zstart && (r.cls == P_COL || r.cls == P_ROW))
+        continue;
       const int s = c.switch_iter;
       const int phase = (s == 0 || r.k <= s) ? PH_BULK
                         : (r.k == s + 1)    ? PH_SWITCH
@@ -879,15 +882,46 @@ int leave_bulk_state(expdiag_ctx* h, const Ctl* ctl, hipStream_t st) {
   return 0;
 }
 
+// Whether a fixed-point solve from U = 0 may skip its first pass A: the
+// first-order exponential schemes take N at U's slices only into slots
+// 1..Nt-1 of N^ (slot 0 is N(u_0)), and N(0) = 0.
+bool zero_start_ok(const expdiag_ctx* h) {
+  return h->nonlinear &&
+         (h->scheme == EXPDIAG_ETD1 || h->scheme == EXPDIAG_ETD2);
+}
+
+// Slot region [offset, count) in words of N^ that the first pass B of a
+// solve from U = 0 reads for U's slices: fp32 slots 1..Nt-1 in the bulk
+// phase of a mixed instance (the fp32 view shares the allocation's second
+// half, so fp64 slots are left alone), else fp64 slots 1..Nt-1.
+void zero_start_region(expdiag_ctx* h, void** p, long* words) {
+  const long n1 = static_cast<long>(h->Nt - 1) * h->Nk;
+  if (h->mixed) {
+    *p = nh_view<float>(h) + h->Nk;
+    *words = n1;
+  } else {
+    *p = h->Nh + h->Nk;
+    *words = 2 * n1;
+  }
+}
+
 // The initial guess as the solve's spectral iterate Uh (and, with `bulk`,
 // its fp32 bulk copy where the instance keeps one): the forward transform
 // of U on h's stream, or, for a solve from U = 0 (`zero`), zeros, which is
-// what that transform would give, without reading U.
+// what that transform would give, without reading U; with `bulk` and a
+// scheme that allows it, also the N^ rows the first pass B reads, so that
+// the first iteration's pass A can be skipped (Ctl::zstart).
 int enter_guess(expdiag_ctx* h, const double* U, bool bulk, bool zero) {
   const long n = static_cast<long>(h->Nt) * h->Nk;
   if (zero) {
     RCHK(zero_words(h, h->Uh, 2 * n, h->stream));
     if (bulk && bulk_u32(h)) RCHK(zero_words(h, u32_view(h), n, h->stream));
+    if (bulk && zero_start_ok(h)) {
+      void* p = nullptr;
+      long w = 0;
+      zero_start_region(h, &p, &w);
+      RCHK(zero_words(h, p, w, h->stream));
+    }
     return 0;
   }
   RCHK(fwd_slices<ROW_R2C>(h, U, h->Uh, h->Nt));
@@ -1508,11 +1542,18 @@ void plan_entry(Plan& P, expdiag_ctx* h, const double* u0, const double* U,
   const long n = static_cast<long>(h->Nt) * h->Nk;
   if (zero) {
     Group& g = plan_group(P, 3, K_XZERO, 0, 0, 0, 0, 0);
-    g.cj.push_back(make_col(nullptr, h->Uh, 2 * n, 1, 1.0, nullptr, -1));
-    g.start.push_back(g.start.back() + static_cast<int>((2 * n + 255) / 256));
-    if (bulk_u32(h)) {
-      g.cj.push_back(make_col(nullptr, u32_view(h), n, 1, 1.0, nullptr, -1));
-      g.start.push_back(g.start.back() + static_cast<int>((n + 255) / 256));
+    auto add = [&](void* p, long words) {
+      g.cj.push_back(make_col(nullptr, p, words, 1, 1.0, nullptr, -1));
+      g.start.push_back(g.start.back() +
+                        static_cast<int>((words + 255) / 256));
+    };
+    add(h->Uh, 2 * n);
+    if (bulk_u32(h)) add(u32_view(h), n);
+    if (zero_start_ok(h)) {
+      void* p = nullptr;
+      long w = 0;
+      zero_start_region(h, &p, &w);
+      add(p, w);
     }
     return;
   }
@@ -2589,6 +2630,7 @@ int expdiag_iterate(expdiag_t h, const double* u0, double* U, int max_iter,
   RCHK(enter_guess(h, U, true, h->zero_guess));
   prof_begin(h);
   *h->h_ctl = initial_ctl(h, max_iter, tol);
+  h->h_ctl->zstart = h->zero_guess && zero_start_ok(h) ? 1 : 0;
   *h->h_mirror = *h->h_ctl;
   hipLaunchKernelGGL(ctl_set_kernel, dim3(1), dim3(64), 0, h->stream, h->ctl,
                      *h->h_ctl);

@@ -361,7 +361,10 @@ __global__ void __launch_bounds__(DENSE_THREADS)
   if constexpr (MODE == PB_ITERATE) {
     const int ph = job_phase(a.ctl);
     if (ph < 0) return;
-    if (lb == 0 && threadIdx.x == 0) a.ctl->pending = 1;
+    if (lb == 0 && threadIdx.x == 0) {
+      a.ctl->pending = 1;
+      a.ctl->zstart = 0;  // the next pass A computes again
+    }
     if (a.Nh32 != nullptr && ph == PH_BULK)
       passb_dft_body<NT, MODE, float>(
           a, lb, static_cast<const float*>(a.Nh32), lds, red);

@@ -35,6 +35,10 @@ enum : int { PH_BULK = 0, PH_SWITCH = 1, PH_FP64 = 2 };
 struct Ctl {
   int done;      // 0 running, 1 finished (tolerance or max_iter), 2 diverged
   int phase;     // PH_BULK, PH_SWITCH or PH_FP64
+  // 1 until the first pass B of a solve from the all-zero iterate: its
+  // N^ rows of U's slices are zero (cleared at entry, as N(0) = 0), so that
+  // iteration's pass-A stages have nothing to compute
+  int zstart;
   int iters;     // iterations completed
   int max_iter;
   int pending;   // 1: pass B wrote block partials not yet reduced
@@ -55,6 +59,16 @@ __device__ __forceinline__ int job_phase(const Ctl* c) {
   typedef int i2 __attribute__((ext_vector_type(2)));
   const i2 dp = gld(reinterpret_cast<const i2*>(c), 0);  // {done, phase}
   return dp.x ? -1 : dp.y;
+}
+
+// job_phase for a pass-A stage of an iteration: also -1 while the
+// instance's first iteration from the all-zero iterate has not reached its
+// pass B (Ctl::zstart), whose N^ rows the entry has already zeroed
+__device__ __forceinline__ int job_phase_a(const Ctl* c) {
+  if (c == nullptr) return 1;
+  typedef int i4 __attribute__((ext_vector_type(4)));
+  const i4 d = gld(reinterpret_cast<const i4*>(c), 0);  // {done, phase, zstart}
+  return (d.x || d.z) ? -1 : d.y;
 }
 
 // Values a thread has just issued loads for, marked as modified by an
@@ -344,7 +358,7 @@ __global__ void __launch_bounds__(RowShape<M>::THREADS)
   const int i = find_job(start, njobs);
   const long lb = blockIdx.x - start[i];
   const RowJob j1 = jobs[2 * i + 1];
-  const int ph = job_phase(j1.ctl);
+  const int ph = job_phase_a(j1.ctl);
   if (ph < 0) return;
   if (ph == PH_BULK) {
     const RowJob jb = jobs[2 * i];
@@ -473,7 +487,7 @@ __global__ void __launch_bounds__((ColShape<L, WD>::THREADS),
   const int i = find_job(start, njobs, b);
   const int lb = b - start[i];
   const ColJob j1 = jobs[2 * i + 1];
-  const int ph = job_phase(j1.ctl);
+  const int ph = job_phase_a(j1.ctl);
   if (ph < 0) return;
   if (ph == PH_BULK) {
     const ColJob jb = jobs[2 * i];

@@ -493,7 +493,10 @@ __global__ void __launch_bounds__(PassBShape<NT>::THREADS,
   if constexpr (MODE == PB_ITERATE) {
     const int ph = job_phase(a.ctl);
     if (ph < 0) return;
-    if (lb == 0 && threadIdx.x == 0) a.ctl->pending = 1;
+    if (lb == 0 && threadIdx.x == 0) {
+      a.ctl->pending = 1;
+      a.ctl->zstart = 0;  // the next pass A computes again
+    }
     if (a.Nh32 != nullptr && ph == PH_BULK) {
       const float* n32 = static_cast<const float*>(a.Nh32);
       if (a.U32 != nullptr)
@@ -620,8 +623,10 @@ __global__ void __launch_bounds__((ColShape<L, WD>::THREADS),
   const int i = find_job(start, njobs, cb);
   const ColJob jb = jobs[i];
   if (jb.ctl != nullptr &&
-      __hip_atomic_load(&jb.ctl->done, __ATOMIC_RELAXED,
-                        __HIP_MEMORY_SCOPE_AGENT))
+      (__hip_atomic_load(&jb.ctl->done, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT) ||
+       __hip_atomic_load(&jb.ctl->zstart, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT)))
     return;
   col_body<double, L, S, double, double, WD>(jb, cb - start[i], tw64, lds);
 }
