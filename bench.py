@@ -1312,9 +1312,10 @@ def profile_batch(steps, count=256, kfix=17, tune_file=None):
 
 
 def profile_batch_solve(steps, count=256, tune_file=None):
-    """Batched solves to the run-time rule (the headline batch, tuned), for
-    a kernel trace of a whole solve: full-batch iterations, the tail where
-    few instances remain, entry and exit transforms."""
+    """Batched solves to the run-time rule (the headline batch, tuned, from
+    U = 0 with the zero-guess option as the headline's solves), for a kernel
+    trace of a whole solve: full-batch iterations, the tail where few
+    instances remain, entry and exit transforms."""
     import torch
     import workloads as W
     from paper_2603_04350_amd import expdiag as X
@@ -1325,10 +1326,11 @@ def profile_batch_solve(steps, count=256, tune_file=None):
     solvers = [X.Solver.from_instance(i, precision=1) for i in insts]
     b = X.Batch(solvers)
     tune = b.autotune(u0s, Us, tune_file)
+    b.set_zero_guess(True)
+    mark = torch.zeros(1, device="cuda:0")
     walls = []
     for _ in range(steps + 1):
-        for u in Us:
-            u.zero_()
+        mark.add_(1.0)  # one small kernel ahead of each solve in the trace
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rc, its, rels, sts = b.iterate(u0s, Us, max_iter=400, tol=TOL)
