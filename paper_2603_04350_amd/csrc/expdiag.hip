@@ -831,10 +831,22 @@ cx<T>* nh_view(expdiag_ctx* h) {
   }
 }
 
+// Elementwise boundary kernels (copies between precisions, clearing): 256
+// threads per block, each thread XPT elements 256 apart, so a block covers
+// XPB consecutive elements (far fewer blocks than one element per thread,
+// whose launch rate, not memory, bounded these kernels)
+constexpr int XPT = 8;
+constexpr int XPB = 256 * XPT;
+int xblocks(long n) { return static_cast<int>((n + XPB - 1) / XPB); }
+
 __global__ void narrow_kernel(const cx<double>* __restrict__ in,
                               cx<float>* __restrict__ out, long n) {
-  const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = cvt<float>(in[i]);
+  const long b = static_cast<long>(blockIdx.x) * XPB + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < XPT; ++k) {
+    const long i = b + k * 256;
+    if (i < n) out[i] = cvt<float>(in[i]);
+  }
 }
 
 // The iterate as the bulk phase keeps it: fp32 copy of Uh (after the entry
@@ -845,21 +857,29 @@ __global__ void widen_bulk_kernel(const Ctl* __restrict__ ctl,
                                   const cx<float>* __restrict__ in,
                                   cx<double>* __restrict__ out, long n) {
   if (ctl->phase > PH_SWITCH) return;
-  const long i = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = cvt<double>(in[i]);
+  const long b = static_cast<long>(blockIdx.x) * XPB + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < XPT; ++k) {
+    const long i = b + k * 256;
+    if (i < n) out[i] = cvt<double>(in[i]);
+  }
 }
 
 // n 8-byte words of device memory set to zero by a kernel (a memset node
 // would misbehave where a caller captures the stream into a graph)
 __global__ void zero_words_kernel(double* __restrict__ p, long n) {
-  const long e = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e < n) p[e] = 0.0;
+  const long b = static_cast<long>(blockIdx.x) * XPB + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < XPT; ++k) {
+    const long e = b + k * 256;
+    if (e < n) p[e] = 0.0;
+  }
 }
 
 int zero_words(expdiag_ctx* h, void* p, long n, hipStream_t st) {
   if (n <= 0) return 0;
-  hipLaunchKernelGGL(zero_words_kernel, dim3((n + 255) / 256), dim3(256), 0,
-                     st, static_cast<double*>(p), n);
+  hipLaunchKernelGGL(zero_words_kernel, dim3(xblocks(n)), dim3(256), 0, st,
+                     static_cast<double*>(p), n);
   HIPCHK(h, hipGetLastError());
   return 0;
 }
@@ -867,7 +887,7 @@ int zero_words(expdiag_ctx* h, void* p, long n, hipStream_t st) {
 int enter_bulk_state(expdiag_ctx* h, hipStream_t st) {
   if (!bulk_u32(h)) return 0;
   const long n = static_cast<long>(h->Nt) * h->Nk;
-  hipLaunchKernelGGL(narrow_kernel, dim3((n + 255) / 256), dim3(256), 0, st,
+  hipLaunchKernelGGL(narrow_kernel, dim3(xblocks(n)), dim3(256), 0, st,
                      h->Uh, u32_view(h), n);
   HIPCHK(h, hipGetLastError());
   return 0;
@@ -876,8 +896,8 @@ int enter_bulk_state(expdiag_ctx* h, hipStream_t st) {
 int leave_bulk_state(expdiag_ctx* h, const Ctl* ctl, hipStream_t st) {
   if (!bulk_u32(h)) return 0;
   const long n = static_cast<long>(h->Nt) * h->Nk;
-  hipLaunchKernelGGL(widen_bulk_kernel, dim3((n + 255) / 256), dim3(256), 0,
-                     st, ctl, u32_view(h), h->Uh, n);
+  hipLaunchKernelGGL(widen_bulk_kernel, dim3(xblocks(n)), dim3(256), 0, st,
+                     ctl, u32_view(h), h->Uh, n);
   HIPCHK(h, hipGetLastError());
   return 0;
 }
@@ -936,7 +956,7 @@ int prepare_u0(expdiag_ctx* h, const double* u0) {
   if (!h->nonlinear || h->scheme == EXPDIAG_IF1) return 0;
   RCHK(fwd_slices<ROW_NR2C>(h, u0, h->Nh, 1));
   if (h->mixed) {
-    hipLaunchKernelGGL(narrow_kernel, dim3((h->Nk + 255) / 256), dim3(256), 0,
+    hipLaunchKernelGGL(narrow_kernel, dim3(xblocks(h->Nk)), dim3(256), 0,
                        h->stream, h->Nh, nh_view<float>(h), h->Nk);
     HIPCHK(h, hipGetLastError());
   }
@@ -1456,11 +1476,14 @@ __global__ void widen_kernel_jt(const ColJob* __restrict__ jobs,
   const int i = find_job(start, njobs);
   const ColJob jb = jobs[i];
   if (jb.ctl->phase > PH_SWITCH) return;
-  const long e = static_cast<long>(blockIdx.x - start[i]) * blockDim.x +
-                 threadIdx.x;
-  if (e < jb.outer)
-    static_cast<cx<double>*>(jb.out)[e] =
-        cvt<double>(static_cast<const cx<float>*>(jb.in)[e]);
+  const long b = static_cast<long>(blockIdx.x - start[i]) * XPB + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < XPT; ++k) {
+    const long e = b + k * 256;
+    if (e < jb.outer)
+      static_cast<cx<double>*>(jb.out)[e] =
+          cvt<double>(static_cast<const cx<float>*>(jb.in)[e]);
+  }
 }
 
 // zeros into job j's `outer` 8-byte words at `out`
@@ -1468,9 +1491,12 @@ __global__ void zero_kernel_jt(const ColJob* __restrict__ jobs,
                                const int* __restrict__ start, int njobs) {
   const int i = find_job(start, njobs);
   const ColJob jb = jobs[i];
-  const long e = static_cast<long>(blockIdx.x - start[i]) * blockDim.x +
-                 threadIdx.x;
-  if (e < jb.outer) static_cast<double*>(jb.out)[e] = 0.0;
+  const long b = static_cast<long>(blockIdx.x - start[i]) * XPB + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < XPT; ++k) {
+    const long e = b + k * 256;
+    if (e < jb.outer) static_cast<double*>(jb.out)[e] = 0.0;
+  }
 }
 
 // fp64 -> fp32 copies, job j copying `outer` complex elements
@@ -1478,11 +1504,14 @@ __global__ void narrow_kernel_jt(const ColJob* __restrict__ jobs,
                                  const int* __restrict__ start, int njobs) {
   const int i = find_job(start, njobs);
   const ColJob jb = jobs[i];
-  const long e = static_cast<long>(blockIdx.x - start[i]) * blockDim.x +
-                 threadIdx.x;
-  if (e < jb.outer)
-    static_cast<cx<float>*>(jb.out)[e] =
-        cvt<float>(static_cast<const cx<double>*>(jb.in)[e]);
+  const long b = static_cast<long>(blockIdx.x - start[i]) * XPB + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < XPT; ++k) {
+    const long e = b + k * 256;
+    if (e < jb.outer)
+      static_cast<cx<float>*>(jb.out)[e] =
+          cvt<float>(static_cast<const cx<double>*>(jb.in)[e]);
+  }
 }
 
 void plan_xrow(Plan& P, int stage, int M, int mode, const RowJob& j) {
@@ -1536,7 +1565,7 @@ void plan_entry(Plan& P, expdiag_ctx* h, const double* u0, const double* U,
       g.cj.push_back(make_col(h->Nh, nh_view<float>(h), h->Nk, 1, 1.0,
                               nullptr, -1));
       g.start.push_back(g.start.back() +
-                        static_cast<int>((h->Nk + 255) / 256));
+                        xblocks(h->Nk));
     }
   }
   const long n = static_cast<long>(h->Nt) * h->Nk;
@@ -1545,7 +1574,7 @@ void plan_entry(Plan& P, expdiag_ctx* h, const double* u0, const double* U,
     auto add = [&](void* p, long words) {
       g.cj.push_back(make_col(nullptr, p, words, 1, 1.0, nullptr, -1));
       g.start.push_back(g.start.back() +
-                        static_cast<int>((words + 255) / 256));
+                        xblocks(words));
     };
     add(h->Uh, 2 * n);
     if (bulk_u32(h)) add(u32_view(h), n);
@@ -1561,7 +1590,7 @@ void plan_entry(Plan& P, expdiag_ctx* h, const double* u0, const double* U,
   if (bulk_u32(h)) {
     Group& g = plan_group(P, 3, K_XNARROW, 0, 0, 0, 0, 0);
     g.cj.push_back(make_col(h->Uh, u32_view(h), n, 1, 1.0, nullptr, -1));
-    g.start.push_back(g.start.back() + static_cast<int>((n + 255) / 256));
+    g.start.push_back(g.start.back() + xblocks(n));
   }
 }
 
@@ -1577,7 +1606,7 @@ void plan_exit(Plan& P, expdiag_ctx* h, double* U, const Ctl* ctl) {
     Group& g = plan_group(P, 0, K_XWIDEN, 0, 0, 0, 0, 0);
     const long n = ns * h->Nk;
     g.cj.push_back(make_col(u32_view(h), h->Uh, n, 1, 1.0, ctl, -1));
-    g.start.push_back(g.start.back() + static_cast<int>((n + 255) / 256));
+    g.start.push_back(g.start.back() + xblocks(n));
   }
   if (d == 1) {
     plan_xrow(P, 3, nl / 2, ROW_C2R,
