@@ -171,8 +171,9 @@ def test_rd2d_full_size_newton_gmres():
     precision (fp32 Jacobian products, fp64 residual and time
     diagonalisation).  The window is held against sequential ETD2 stepping
     in fp64 at the mixed-mode bar 1e-10.  Newton stops on the residual,
-    ||R_j|| <= tol ||R_0||, and the error is about the residual's size
-    (1.3e-10 at tol 1e-10), so the solve runs to tol 1e-11."""
+    ||R_j|| <= tol ||R_0||, and the error is about the residual's size (a
+    stop at 1e-10 can land just above the bar), so the solve runs to tol
+    1e-11."""
     import torch
     from paper_2603_04350_amd import Solver
     inst = W.rd2d()
