@@ -568,8 +568,9 @@ def bench_time_variants(Nts=(8, 16, 32, 64, 128)):
     """Both time transforms of pass B on the 256^2 Allen-Cahn grid for each
     Nt, timed by the library's autotuner on one handle (20 preconditioner
     applies each after warm-up): the radix FFT, and the DFT products on
-    FP64 MFMA with their executed flops (16 Nt^2 per kappa column: two real
-    2Nt x 2Nt products per column) against the FP64 matrix peak; both
+    FP64 MFMA with their executed flops (16 Nt^2 per kappa column: the
+    2Nt x 2Nt real form of each of the two Nt-point DFTs, its entries read
+    from a table of roots of unity) against the FP64 matrix peak; both
     against HBM (read R, write S: 32 B per complex entry)."""
     import dataclasses
     import workloads as W
