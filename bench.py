@@ -1546,7 +1546,7 @@ def main():
     if args.quick:
         args.no_serve = args.no_cpu_baseline = args.no_extra = True
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))

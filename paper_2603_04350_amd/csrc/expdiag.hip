@@ -2227,7 +2227,7 @@ const char* expdiag_strerror(int code) {
     case EXPDIAG_EDIVERGED:
       return "iteration diverged (non-finite residual)";
     case EXPDIAG_EUNSUPPORTED:
-      return "size not supported by this build";
+      return "size not supported by the library";
     default:
       return "unknown error code";
   }
