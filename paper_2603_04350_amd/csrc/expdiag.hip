@@ -934,7 +934,11 @@ void zero_start_region(expdiag_ctx* h, void** p, long* words) {
 int enter_guess(expdiag_ctx* h, const double* U, bool bulk, bool zero) {
   const long n = static_cast<long>(h->Nt) * h->Nk;
   if (zero) {
-    RCHK(zero_words(h, h->Uh, 2 * n, h->stream));
+    // an instance that keeps the fp32 bulk iterate reads Uh only after
+    // writing all of it (the switch iteration's pass B, or the exit's
+    // widening of the fp32 iterate when the solve stops before that)
+    if (!(bulk && bulk_u32(h)))
+      RCHK(zero_words(h, h->Uh, 2 * n, h->stream));
     if (bulk && bulk_u32(h)) RCHK(zero_words(h, u32_view(h), n, h->stream));
     if (bulk && zero_start_ok(h)) {
       void* p = nullptr;
@@ -1553,8 +1557,9 @@ void plan_xfwd(Plan& P, expdiag_ctx* h, int stage0, int rowmode,
 // What expdiag_iterate does before its iterations (prepare_u0 and the
 // forward transform of U), as plan stages 0..3; real states only.
 // Entry transforms of one instance as plan stages; `zero`: the solve starts
-// from U = 0, so its spectral iterate (and fp32 bulk copy) are cleared
-// rather than transformed from U (enter_guess)
+// from U = 0, so its spectral iterate (or its fp32 bulk copy, where the
+// instance keeps one) is cleared rather than transformed from U
+// (enter_guess)
 void plan_entry(Plan& P, expdiag_ctx* h, const double* u0, const double* U,
                 bool zero) {
   plan_xfwd(P, h, 0, ROW_R2C, u0, h->u0h, 1);
@@ -1576,8 +1581,12 @@ void plan_entry(Plan& P, expdiag_ctx* h, const double* u0, const double* U,
       g.start.push_back(g.start.back() +
                         xblocks(words));
     };
-    add(h->Uh, 2 * n);
-    if (bulk_u32(h)) add(u32_view(h), n);
+    // (Uh of an instance that keeps the fp32 bulk iterate is written
+    // before it is read: enter_guess)
+    if (bulk_u32(h))
+      add(u32_view(h), n);
+    else
+      add(h->Uh, 2 * n);
     if (zero_start_ok(h)) {
       void* p = nullptr;
       long w = 0;
