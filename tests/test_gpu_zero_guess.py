@@ -139,3 +139,53 @@ def test_batch_from_zero_guess_equals_zeroed_Us():
     b.close()
     for s in solvers:
         s.close()
+
+
+def test_zero_guess_solve_stopped_before_the_fp64_phase():
+    """A mixed instance that keeps its bulk iterate in fp32 is not given a
+    cleared fp64 iterate by the zero-guess entry: the switch iteration writes
+    all of it, or, when max_iter stops the solve in the bulk phase or at the
+    switch, the exit widens the fp32 iterate into it.  Every cap from 1 to 12
+    iterations (the fp64 phase starts within them), after a solve that left
+    its converged fp64 iterate in the handle, against the same capped solve
+    from a zeroed U."""
+    from paper_2603_04350_amd import Solver
+    inst, prec = SINGLE["ac2d_mixed_bulk_fp32"]
+    u0 = _dev(inst.u0)
+    with Solver.from_instance(inst, precision=prec) as s:
+        for cap in range(1, 13):
+            s.set_zero_guess(False)
+            U = _full(_shape(inst), 0.0)
+            rc, it, rel = s.iterate(u0, U, max_iter=cap, tol=1e-12)
+            ref = U.cpu().numpy()
+            s.iterate(u0, _full(_shape(inst), 0.0), max_iter=200, tol=1e-12)
+            s.set_zero_guess(True)
+            U = _full(_shape(inst), float("nan"))
+            assert s.iterate(u0, U, max_iter=cap, tol=1e-12) == (rc, it, rel)
+            assert np.array_equal(U.cpu().numpy(), ref), cap
+
+
+def test_batch_zero_guess_stopped_before_the_fp64_phase():
+    """The batch form of the test above: mixed instances capped at 1 to 8
+    iterations each, after a batch solve that left converged fp64 iterates
+    in every handle."""
+    from paper_2603_04350_amd import Batch, Solver
+    insts = W.batch(8, seed=5, ns=(16, 32), nts=(8, 16), precision=1)
+    solvers = [Solver.from_instance(i) for i in insts]
+    u0s = [_dev(i.u0) for i in insts]
+    b = Batch(solvers)
+    caps = [1 + k for k in range(len(insts))]
+    tols = [0.0] * len(insts)
+    Us = [_full(_shape(i), 0.0) for i in insts]
+    out = b.iterate_each(u0s, Us, caps, tols)
+    ref = [U.cpu().numpy() for U in Us]
+    b.iterate(u0s, [_full(_shape(i), 0.0) for i in insts], max_iter=200,
+              tol=1e-12)
+    b.set_zero_guess(True)
+    Us = [_full(_shape(i), float("nan")) for i in insts]
+    assert b.iterate_each(u0s, Us, caps, tols) == out
+    for k, U in enumerate(Us):
+        assert np.array_equal(U.cpu().numpy(), ref[k]), k
+    b.close()
+    for s in solvers:
+        s.close()
