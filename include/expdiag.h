@@ -290,9 +290,11 @@ int expdiag_set_graph(expdiag_t h, int on);
  * (on), or from U as passed (off, the default).  With it
  * on, U is output only: its contents on entry are not read, and the forward
  * spatial transform of the guess, which would be zero, is replaced by
- * clearing the spectral iterate; for nonlinear ETD1/ETD2 fixed-point solves
- * the first iteration's nonlinear term N(0) = 0 is cleared likewise and its
- * spatial transforms are skipped.  Results equal those of a solve from a
+ * clearing the spectral iterate the solve starts from (for a mixed-precision
+ * fixed-point solve that starts in the fp32 bulk phase, the fp32 copy; the
+ * fp64 iterate is written before it is read); for nonlinear ETD1/ETD2
+ * fixed-point solves the first iteration's nonlinear term N(0) = 0 is
+ * cleared likewise and its spatial transforms are skipped.  Results equal those of a solve from a
  * zeroed U bit for bit.  EINVAL for a null handle. */
 int expdiag_set_zero_guess(expdiag_t h, int on);
 
